@@ -1,0 +1,228 @@
+/*
+ * emrt.h -- C ABI of the gfx950 dynamic EM ray tracer.
+ *
+ * The library implements the data-parallel hot path of Wang & Manocha,
+ * "Dynamic EM Ray Tracing for Large Urban Scenes with Multiple Receivers"
+ * (2023): shooting-and-bouncing rays from transmitters through LBVHs over
+ * static buildings and moving vehicles (Section II-A: direct, reflected and
+ * diffracted rays, a BVH updated between frames), receiver capture,
+ * revalidation of cached paths across frames (Section III-B: the path cache /
+ * "visibility hash table" with deletion), and per-receiver sums of complex
+ * field, power, delay and Doppler (Section III-C Eq (3); Section V-D: mean
+ * Doppler shift and RMS Doppler spread).
+ *
+ * Conventions
+ *   - Every call returns an emrt status: EMRT_OK (0), a warning (> 0) or an
+ *     error (< 0).  emrt_last_error() gives the message of the last error.
+ *   - All work is enqueued on the context's HIP stream (emrt_set_stream).
+ *     Calls return without waiting for the GPU unless their name contains
+ *     "read", "sync", "size" or "export", or they are emrt_set_scene /
+ *     emrt_cache_import (which read back counts).
+ *   - Memory: the caller owns every buffer.  The library never allocates
+ *     device memory: it carves one caller-allocated workspace
+ *     (emrt_workspace_size / emrt_bind_workspace).  Arrays marked "device"
+ *     are device pointers read or written in stream order; the caller keeps
+ *     them alive and unmodified until the stream has passed the call.
+ *     Arrays marked "host" are copied before the call returns.
+ *   - A context is used from one host thread at a time.
+ *   - Positions in metres, velocities in m/s, frequencies in Hz, delays in s,
+ *     powers in W; complex numbers are (re, im) double pairs; time factor
+ *     exp(+j w t), permittivity eps_r = eps' - j eps'' (imaginary part <= 0).
+ */
+#ifndef EMRT_H
+#define EMRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    EMRT_OK = 0,
+    EMRT_W_PATHS_TRUNCATED = 1, /* a link had more paths than the path-list capacity */
+    EMRT_W_CACHE_FULL = 2,      /* path table / candidate / path capacity reached: results incomplete */
+    EMRT_E_INVALID = -1,        /* bad argument or malformed input */
+    EMRT_E_STATE = -2,          /* call out of order (e.g. step before scene) */
+    EMRT_E_WORKSPACE = -3,      /* workspace missing or too small */
+    EMRT_E_HIP = -4,            /* HIP runtime error */
+    EMRT_E_UNSUPPORTED = -5,    /* configuration outside the supported range */
+    EMRT_E_DEVICE_FLAG = -6     /* a kernel reported bad input (non-finite transform, ...) */
+};
+
+enum { EMRT_ANT_ISO_V = 0, EMRT_ANT_DIPOLE = 1 };
+
+typedef struct emrt_ctx emrt_ctx;
+
+/* Configuration (host struct, copied by emrt_ctx_create).  Readings of the
+ * paper (which fixes none of these): launch on a Fibonacci sphere,
+ * reception-sphere radius k_rx * sqrt(4 pi / N) * unfolded length, no power
+ * threshold, first-order edge diffraction for receivers within
+ * diff_max_leg_m of the diffraction point. */
+typedef struct emrt_config {
+    int32_t n_freq;             /* 1..4 */
+    double freq_hz[4];          /* carrier frequencies evaluated on the same paths */
+    int32_t max_reflections;    /* K, 0..5 */
+    int32_t diffraction;        /* 0/1: first-order edge diffraction */
+    int32_t rays_per_tx;        /* N launch directions per transmitter, >= 1 */
+    double rx_sphere_k;         /* reception-sphere constant k_rx (default 1.0) */
+    double diff_max_leg_m;      /* max edge-to-receiver distance (default 250) */
+    double tx_power_w;          /* transmit power (default 100 W = 50 dBm, Section IV) */
+    int32_t antenna_mode;       /* transmit antenna: EMRT_ANT_ISO_V (Section IV) or EMRT_ANT_DIPOLE */
+    int32_t path_cap_per_link;  /* default path-list capacity per link (emrt_read_paths) */
+    int64_t path_capacity;      /* max candidate keys per frame and cached paths (default 4 Mi) */
+    int64_t table_capacity;     /* path-table slots, rounded up to a power of two (default 4 x path_capacity) */
+} emrt_config;
+
+/* Fill *cfg with the defaults above (one 28 GHz carrier, K = 3, no
+ * diffraction, 10,000 rays per transmitter). */
+void emrt_config_default(emrt_config* cfg);
+
+/* Sizes that fix the workspace layout. */
+typedef struct emrt_sizes {
+    int64_t n_verts, n_tris, n_faces, n_objects; /* scene arrays */
+    int32_t n_tx, n_rx;                          /* transmitters and receivers per frame */
+} emrt_sizes;
+
+/* Create / destroy a context.  Errors: EMRT_E_INVALID (NULL or out-of-range
+ * config), EMRT_E_UNSUPPORTED (K > 5, n_freq > 4). */
+int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out);
+int32_t emrt_ctx_destroy(emrt_ctx* ctx);
+
+/* Bytes of device workspace for the given sizes (host call, no GPU work). */
+int32_t emrt_workspace_size(emrt_ctx* ctx, const emrt_sizes* sizes, size_t* bytes);
+/* Bind a caller-allocated device workspace of at least emrt_workspace_size()
+ * bytes (256-byte aligned).  The library carves all of its device state from
+ * it; it stays owned by the caller and must outlive the context's work.
+ * Errors: EMRT_E_WORKSPACE (too small / NULL), EMRT_E_INVALID (sizes). */
+int32_t emrt_bind_workspace(emrt_ctx* ctx, void* device_ptr, size_t bytes);
+/* Stream for all subsequent work (a hipStream_t; NULL = default stream). */
+int32_t emrt_set_stream(emrt_ctx* ctx, void* hip_stream);
+
+/* Scene (Section IV: buildings and moving vehicles as triangle meshes, no
+ * penetration).  A face is a set of coplanar triangles of one object and one
+ * material, the unit of reflection and of path keys; triangles are wound
+ * counter-clockwise seen from outside (used to find convex wedge edges).
+ * Vertices of dynamic objects are in the object's local frame. */
+typedef struct emrt_scene_desc {
+    int64_t n_verts, n_tris, n_faces, n_objects;
+    const float* verts;            /* device [n_verts][3] */
+    const int32_t* tris;           /* device [n_tris][3] vertex indices */
+    const int32_t* tri_face;       /* device [n_tris] face of each triangle */
+    const int32_t* face_object;    /* device [n_faces] */
+    const int32_t* face_material;  /* device [n_faces] */
+    const uint8_t* object_dynamic; /* device [n_objects] 1 = moves with a per-frame transform */
+    int32_t n_materials;           /* <= 256 */
+    const double* material_eps;    /* host [n_materials][2] relative permittivity (re, im) */
+} emrt_scene_desc;
+/* Upload and preprocess a scene: index checks, face planes and triangle lists,
+ * wedge edges, the static LBVH.  Synchronises.  Errors: EMRT_E_INVALID
+ * (sizes differ from the workspace's, index out of range, degenerate or
+ * non-finite triangle), EMRT_E_STATE (no workspace). */
+int32_t emrt_set_scene(emrt_ctx* ctx, const emrt_scene_desc* scene);
+/* Replace the permittivity table without touching geometry (host array). */
+int32_t emrt_set_materials(emrt_ctx* ctx, const double* material_eps, int32_t n_materials);
+
+/* Per-frame state (Section III-A/C: moving objects and receivers; the base
+ * station is static by default, but transmitter velocities are honoured).
+ * All arrays are device pointers, copied into the workspace in stream order. */
+typedef struct emrt_frame_desc {
+    int64_t frame;
+    double t_s;
+    int32_t n_tx, n_rx;        /* must equal the workspace sizes */
+    const double* obj_xform;   /* [n_dynamic][3][4] row-major rigid transforms, dynamic objects in id order */
+    const double* obj_vel;     /* [n_dynamic][3] translational velocity */
+    const double* tx_pos;      /* [n_tx][3] */
+    const double* tx_vel;      /* [n_tx][3] */
+    const double* tx_orient;   /* [n_tx][2] dipole (theta, phi), rad; ignored for ISO_V */
+    const double* rx_pos;      /* [n_rx][3] */
+    const double* rx_vel;      /* [n_rx][3] */
+} emrt_frame_desc;
+int32_t emrt_set_frame(emrt_ctx* ctx, const emrt_frame_desc* frame);
+
+/* Run one frame.  discover = 1: launch rays from every transmitter, bounce
+ * them, capture receivers and edges, merge the discovered keys with the cache
+ * (Section II-A path caching); discover = 0: revalidate the cached keys only
+ * (Section III-B).  Both then validate every key exactly plus line of sight
+ * for every link, evaluate the fields and reduce per link; invalid keys are
+ * dropped from the cache.  Errors: EMRT_E_STATE (no scene / frame). */
+int32_t emrt_step(emrt_ctx* ctx, int32_t discover);
+
+/* Channel outputs of the last step.  Device buffers, any may be NULL.  Links
+ * are ordered tx-major: link = tx * n_rx + rx.  Frequency-dependent arrays
+ * are [n_freq][n_links]. */
+typedef struct emrt_channel_view {
+    double* H;        /* [n_freq][n_links][2] complex gain sum */
+    double* P_coh;    /* [n_freq][n_links] P_tx |H|^2 */
+    double* P_inc;    /* [n_freq][n_links] P_tx sum |a|^2 */
+    double* tau_mean; /* [n_freq][n_links] power-weighted mean delay */
+    double* tau_rms;  /* [n_freq][n_links] RMS delay spread */
+    double* fd_mean;  /* [n_freq][n_links] mean Doppler shift (Section V-D) */
+    double* fd_rms;   /* [n_freq][n_links] RMS Doppler spread (Section V-D) */
+    int32_t* n_paths; /* [n_links] */
+    uint32_t* flags;  /* [n_links] bit 0: line of sight present */
+} emrt_channel_view;
+int32_t emrt_read_channels(emrt_ctx* ctx, const emrt_channel_view* view);
+
+/* Path lists of the last step, per link ordered by key (tx, rx, type, order,
+ * ids).  Device buffers [n_links][cap][...], any may be NULL except count.
+ * Returns EMRT_W_PATHS_TRUNCATED (after synchronising) when some link has
+ * more than cap paths; the channel sums always use every path. */
+typedef struct emrt_path_view {
+    int32_t cap;
+    int32_t* key;     /* [n_links][cap][9] tx, rx, type (0 LoS, 1 specular, 2 diffraction), order, id0..id4 */
+    int32_t* tri_ids; /* [n_links][cap][5] triangle of each reflection point */
+    double* a;        /* [n_links][cap][n_freq][2] complex gain */
+    double* tau;      /* [n_links][cap] delay */
+    double* fd;       /* [n_links][cap][n_freq] Doppler shift */
+    float* angles;    /* [n_links][cap][4] departure az, el; arrival az, el (rad) */
+    int32_t* count;   /* [n_links] paths written */
+} emrt_path_view;
+int32_t emrt_read_paths(emrt_ctx* ctx, const emrt_path_view* view);
+
+/* Triangle hit per bounce of the last discovery step for launch directions
+ * ray_ids (device [n]) of transmitter tx: out device [n][K+1], -1 miss,
+ * -2 not traced (the ray ended earlier). */
+int32_t emrt_debug_ray_records(emrt_ctx* ctx, int32_t tx, const int32_t* ray_ids, int32_t n, int32_t* out);
+
+/* Path cache (checkpoint / resume): the valid non-line-of-sight keys after
+ * the last step, rows of 9 int32 as in emrt_path_view.key.  size and export
+ * synchronise; import replaces the cache (device rows). */
+int32_t emrt_cache_size(emrt_ctx* ctx, int64_t* n_keys);
+int32_t emrt_cache_export(emrt_ctx* ctx, int32_t* keys, int64_t cap, int64_t* n_keys);
+int32_t emrt_cache_import(emrt_ctx* ctx, const int32_t* keys, int64_t n_keys);
+
+/* Counters of the last step (synchronises). */
+typedef struct emrt_stats {
+    int64_t rays_per_bounce[7]; /* live rays entering bounce b */
+    int64_t n_candidates;       /* keys validated besides line of sight */
+    int64_t n_valid;            /* valid paths including line of sight */
+    int64_t n_cache;            /* cache size after the step */
+    int64_t node_visits;        /* traversal counters (when stats are enabled) */
+    int64_t tri_tests;
+    int64_t segments;
+    int64_t captures;
+    int64_t n_static_tris, n_dynamic_tris, n_edges;
+    uint32_t device_flags;
+    double bounce_ms;           /* summed kernel time of the bounce launches (when timing is enabled) */
+    int32_t bounce_launches;
+    double validate_ms;         /* kernel time of the validation launch (when timing is enabled) */
+} emrt_stats;
+int32_t emrt_read_stats(emrt_ctx* ctx, emrt_stats* out);
+/* Optional instrumentation: stats = count traversal work (slower), timing =
+ * HIP events around the bounce and validation launches. */
+int32_t emrt_set_instrumentation(emrt_ctx* ctx, int32_t stats, int32_t timing);
+
+/* Wait for the context's stream; reports device-side flags of the work so
+ * far: EMRT_W_CACHE_FULL (capacity reached) or EMRT_E_DEVICE_FLAG. */
+int32_t emrt_sync(emrt_ctx* ctx);
+
+const char* emrt_status_string(int32_t status);
+/* Copy the last error message (NUL-terminated, truncated to len). */
+int32_t emrt_last_error(emrt_ctx* ctx, char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMRT_H */

@@ -1,0 +1,741 @@
+// api.hip -- the C ABI (include/emrt.h): context, workspace carving and the
+// per-frame pipeline.  All device state lives in one caller-owned workspace;
+// every launch goes to the context's stream and a frame needs no host round
+// trip (element counts stay on the device).
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/emrt.h"
+#include "emrt_dev.h"
+#include "emrt_launch.h"
+
+using namespace emrt;
+
+namespace {
+
+constexpr int kMaxMaterials = 256;
+constexpr int kNumCounters = 64;
+// counter slots (u64)
+constexpr int C_RAYS = 0;      // [0..7] live rays entering bounce b
+constexpr int C_WORK = 8;      // [8..15] work counters per bounce
+constexpr int C_NCAND = 16;
+constexpr int C_NVALID = 17;
+constexpr int C_NCACHE = 18;   // [18, 19] cache sizes (double buffer)
+constexpr int C_STATS = 20;    // [20..23]
+constexpr int C_TRUNC = 24;    // path-list truncation flag
+constexpr int C_SCRATCH = 32;  // ints for set_scene
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    bool measure;
+    explicit Carver(char* b) : base(b), measure(b == nullptr) {}
+    template <class T>
+    T* take(long long n) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = measure ? nullptr : (T*)(base + off);
+        off += sizeof(T) * (size_t)(n > 0 ? n : 1);
+        return p;
+    }
+};
+
+int64_t pow2_at_least(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int bits_for(long long n) {
+    int b = 1;
+    while ((1LL << b) < n) b++;
+    return b;
+}
+
+}  // namespace
+
+struct emrt_ctx {
+    emrt_config cfg{};
+    emrt_sizes sz{};
+    bool sized = false, bound = false, scene_set = false, frame_set = false, stepped = false, discovered = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int stats_on = 0, timing_on = 0;
+    std::vector<hipEvent_t> ev;  // timing events
+    int ev_used = 0;
+    int ev_bounce = 0;  // events of bounce launches recorded in the last step
+    bool ev_valid = false;
+
+    // derived sizes
+    long long n_total = 0, n_links = 0, P = 0, table_slots = 0, vcap = 0, bcap = 0;
+    int K = 0, nf = 1, e_words = 1, E_cap = 0;
+
+    SceneDev S{};
+    Tree st, dy, rxt, edt;
+    TriP *st_prims = nullptr, *dy_prims = nullptr;
+    float4 *rx_prims = nullptr, *edge_prims = nullptr;
+    float *box_st = nullptr, *box_dy = nullptr, *box_rx = nullptr, *box_ed = nullptr;
+    BuildTemp tmp{};
+    RaySoA rays[2]{};
+    int* hitlog = nullptr;
+    uint32_t* dir_perm = nullptr;
+    unsigned long long* ctr = nullptr;
+    unsigned long long* table = nullptr;
+    KeyRec* cand = nullptr;
+    KeyRec* cache[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint32_t* illum = nullptr;
+    ValidPaths vp{};
+    unsigned long long *sk0 = nullptr, *sk1 = nullptr;
+    uint32_t *sv0 = nullptr, *sv1 = nullptr;
+    void* sort_tmp = nullptr;
+    uint32_t* order = nullptr;
+    int *link_start = nullptr, *link_end = nullptr;
+    uint32_t *link_cnt = nullptr, *link_off = nullptr, *scan_tmp = nullptr;
+    double* chan = nullptr;
+    double *f_tx = nullptr, *f_txv = nullptr, *f_txo = nullptr, *f_rx = nullptr, *f_rxv = nullptr, *f_xf = nullptr,
+           *f_ov = nullptr;
+    double* mat = nullptr;
+    std::vector<double> mat_host;
+    uint32_t* flags = nullptr;
+    uint32_t* scene_scratch = nullptr;
+    int *obj_off = nullptr, *obj_faces = nullptr;
+    uint8_t* obj_dyn = nullptr;
+    uint32_t flag_accum = 0;
+    int64_t frame_idx = -1;
+    hipError_t pending = hipSuccess;  // first error of an unchecked async call
+};
+
+#define HC(expr)                                                         \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess && c->pending == hipSuccess) c->pending = e_; \
+    } while (0)
+
+static int32_t fail(emrt_ctx* c, int32_t code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+static int32_t hip_check(emrt_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess && c && c->pending != hipSuccess) {
+        e = c->pending;
+        c->pending = hipSuccess;
+    }
+    if (e == hipSuccess) return EMRT_OK;
+    return fail(c, EMRT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------ layout ----
+static void layout(emrt_ctx* c, Carver& cv) {
+    const emrt_sizes& z = c->sz;
+    long long V = z.n_verts, T = z.n_tris, F = z.n_faces, O = z.n_objects;
+    SceneDev& S = c->S;
+    S.verts_local_copy = cv.take<float>(3 * V);
+    S.verts = cv.take<float>(3 * V);
+    S.tris = cv.take<int>(3 * T);
+    S.tri_face = cv.take<int>(T);
+    S.face_object = cv.take<int>(F);
+    S.face_material = cv.take<int>(F);
+    S.face_dyn = cv.take<int>(F);
+    S.vert_dyn = cv.take<int>(V);
+    S.obj_rank = cv.take<int>(O);
+    S.plane = cv.take<double>(4 * F);
+    S.face_first = cv.take<int>(F);
+    S.face_off = cv.take<int>(F + 1);
+    S.face_tris = cv.take<int>(T);
+    S.tris_static = cv.take<int>(T);
+    S.tris_dynamic = cv.take<int>(T);
+    S.edge_i = cv.take<int>(2 * 6 * (long long)c->E_cap);
+    S.edge_n = cv.take<double>(2 * (long long)c->E_cap);
+    c->obj_dyn = cv.take<uint8_t>(O);
+    c->obj_off = cv.take<int>(O + 1);
+    c->obj_faces = cv.take<int>(F);
+    long long big = std::max(std::max(T, O), F);
+    c->scene_scratch = cv.take<uint32_t>(3 * big + 16 + (long long)scan_temp_bytes(big) / 4 + 64);
+    // trees: worst case every triangle in one tree
+    auto tree = [&](Tree& t, long long n) {
+        long long ni = n > 1 ? n - 1 : 1;
+        t.nodes = cv.take<BNode>(ni);
+        t.leaf_parent = cv.take<int>(n);
+        t.counters = cv.take<uint32_t>(ni);
+        t.perm = cv.take<uint32_t>(n);
+        t.cap = (int)n;
+    };
+    tree(c->st, T);
+    tree(c->dy, T);
+    tree(c->rxt, z.n_rx);
+    tree(c->edt, c->E_cap);
+    c->st_prims = cv.take<TriP>(T);
+    c->dy_prims = cv.take<TriP>(T);
+    c->rx_prims = cv.take<float4>(z.n_rx);
+    c->edge_prims = cv.take<float4>(2LL * c->E_cap);
+    c->box_st = cv.take<float>(6 * T);
+    c->box_dy = cv.take<float>(6 * T);
+    c->box_rx = cv.take<float>(6LL * z.n_rx);
+    c->box_ed = cv.take<float>(6LL * c->E_cap);
+    char* bt = cv.take<char>((long long)build_temp_bytes(c->bcap));
+    if (!cv.measure) carve_build_temp(bt, c->bcap, c->tmp);
+    for (int k = 0; k < 2; k++) {
+        RaySoA& r = c->rays[k];
+        r.ox = cv.take<float>(c->n_total); r.oy = cv.take<float>(c->n_total); r.oz = cv.take<float>(c->n_total);
+        r.dx = cv.take<float>(c->n_total); r.dy = cv.take<float>(c->n_total); r.dz = cv.take<float>(c->n_total);
+        r.L = cv.take<float>(c->n_total);
+        r.id = cv.take<uint32_t>(c->n_total);
+        r.prev = cv.take<int>(c->n_total);
+    }
+    c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
+    c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
+    c->ctr = cv.take<unsigned long long>(kNumCounters);
+    c->table = cv.take<unsigned long long>(c->table_slots);
+    c->cand = cv.take<KeyRec>(c->P);
+    c->cache[0] = cv.take<KeyRec>(c->P);
+    c->cache[1] = cv.take<KeyRec>(c->P);
+    c->illum = cv.take<uint32_t>((long long)z.n_tx * c->e_words);
+    ValidPaths& vp = c->vp;
+    vp.cap = c->vcap;
+    vp.key = cv.take<KeyRec>(c->vcap);
+    vp.tri = cv.take<int>(5 * c->vcap);
+    vp.a = cv.take<double>(2LL * c->nf * c->vcap);
+    vp.tau = cv.take<double>(c->vcap);
+    vp.fd = cv.take<double>((long long)c->nf * c->vcap);
+    vp.ang = cv.take<float4>(c->vcap);
+    c->sk0 = cv.take<unsigned long long>(c->vcap);
+    c->sk1 = cv.take<unsigned long long>(c->vcap);
+    c->sv0 = cv.take<uint32_t>(c->vcap);
+    c->sv1 = cv.take<uint32_t>(c->vcap);
+    c->sort_tmp = cv.take<char>((long long)radix_temp_bytes(c->vcap));
+    c->link_start = cv.take<int>(c->n_links);
+    c->link_end = cv.take<int>(c->n_links);
+    c->link_cnt = cv.take<uint32_t>(c->n_links);
+    c->link_off = cv.take<uint32_t>(c->n_links);
+    c->scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(c->n_links) / 4 + 16);
+    c->chan = cv.take<double>(8LL * c->nf * c->n_links + c->n_links + 8);
+    c->f_tx = cv.take<double>(3LL * z.n_tx);
+    c->f_txv = cv.take<double>(3LL * z.n_tx);
+    c->f_txo = cv.take<double>(2LL * z.n_tx);
+    c->f_rx = cv.take<double>(3LL * z.n_rx);
+    c->f_rxv = cv.take<double>(3LL * z.n_rx);
+    c->f_xf = cv.take<double>(12 * O);
+    c->f_ov = cv.take<double>(3 * O);
+    c->mat = cv.take<double>(2 * kMaxMaterials);
+    c->flags = cv.take<uint32_t>(16);
+    if (!cv.measure) c->vp.count = c->ctr + C_NVALID;
+}
+
+static void derive(emrt_ctx* c) {
+    const emrt_sizes& z = c->sz;
+    c->K = c->cfg.max_reflections;
+    c->nf = c->cfg.n_freq;
+    c->n_total = (long long)z.n_tx * c->cfg.rays_per_tx;
+    c->n_links = (long long)z.n_tx * z.n_rx;
+    c->P = c->cfg.path_capacity;
+    c->table_slots = pow2_at_least(std::max<int64_t>(c->cfg.table_capacity, 1024));
+    c->vcap = c->n_links + c->P;
+    c->E_cap = (int)std::min<long long>(3LL * z.n_faces + 16, (1LL << 24) - 1);
+    c->e_words = (c->E_cap + 31) / 32;
+    long long b = std::max<long long>({z.n_tris, (long long)c->E_cap, (long long)z.n_rx, (long long)c->cfg.rays_per_tx,
+                                       z.n_faces, z.n_objects, 16LL});
+    c->bcap = b;
+}
+
+// ---------------------------------------------------------------- ABI ----
+extern "C" {
+
+void emrt_config_default(emrt_config* cfg) {
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->n_freq = 1;
+    cfg->freq_hz[0] = 28e9;
+    cfg->max_reflections = 3;
+    cfg->diffraction = 0;
+    cfg->rays_per_tx = 10000;
+    cfg->rx_sphere_k = 1.0;
+    cfg->diff_max_leg_m = 250.0;
+    cfg->tx_power_w = 100.0;
+    cfg->antenna_mode = EMRT_ANT_ISO_V;
+    cfg->path_cap_per_link = 64;
+    cfg->path_capacity = 4LL << 20;
+    cfg->table_capacity = 0;
+}
+
+int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
+    if (!cfg || !out) return EMRT_E_INVALID;
+    *out = nullptr;
+    if (cfg->n_freq < 1 || cfg->n_freq > 4 || cfg->max_reflections < 0 || cfg->max_reflections > 5)
+        return EMRT_E_UNSUPPORTED;
+    if (cfg->rays_per_tx < 1 || !(cfg->rx_sphere_k > 0) || !(cfg->diff_max_leg_m >= 0) || cfg->path_capacity < 1 ||
+        cfg->path_capacity > (1LL << 31) || cfg->antenna_mode < 0 || cfg->antenna_mode > 1)
+        return EMRT_E_INVALID;
+    for (int i = 0; i < cfg->n_freq; i++)
+        if (!(cfg->freq_hz[i] > 0)) return EMRT_E_INVALID;
+    emrt_ctx* c = new emrt_ctx();
+    c->cfg = *cfg;
+    if (c->cfg.table_capacity <= 0) c->cfg.table_capacity = 4 * c->cfg.path_capacity;
+    if (c->cfg.path_cap_per_link <= 0) c->cfg.path_cap_per_link = 64;
+    *out = c;
+    return EMRT_OK;
+}
+
+int32_t emrt_ctx_destroy(emrt_ctx* c) {
+    if (!c) return EMRT_E_INVALID;
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+    return EMRT_OK;
+}
+
+int32_t emrt_workspace_size(emrt_ctx* c, const emrt_sizes* s, size_t* bytes) {
+    if (!c || !s || !bytes) return fail(c, EMRT_E_INVALID, "null argument");
+    if (s->n_verts < 3 || s->n_tris < 1 || s->n_faces < 1 || s->n_objects < 1 || s->n_tx < 1 || s->n_rx < 1)
+        return fail(c, EMRT_E_INVALID, "sizes must be positive");
+    if (s->n_tris >= (1LL << 31) || s->n_verts >= (1LL << 31) || s->n_tx > 4095 || s->n_rx >= (1 << 26))
+        return fail(c, EMRT_E_UNSUPPORTED, "scene too large (n_tx <= 4095, n_rx < 2^26, n_tris < 2^31)");
+    if ((long long)s->n_tx * c->cfg.rays_per_tx >= (1LL << 32))
+        return fail(c, EMRT_E_UNSUPPORTED, "n_tx * rays_per_tx must be below 2^32");
+    c->sz = *s;
+    c->sized = true;
+    derive(c);
+    Carver cv(nullptr);
+    layout(c, cv);
+    *bytes = cv.off + 256;
+    return EMRT_OK;
+}
+
+int32_t emrt_bind_workspace(emrt_ctx* c, void* ptr, size_t bytes) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->sized) return fail(c, EMRT_E_STATE, "call emrt_workspace_size first");
+    if (!ptr) return fail(c, EMRT_E_WORKSPACE, "null workspace");
+    Carver m(nullptr);
+    layout(c, m);
+    char* base = (char*)(((uintptr_t)ptr + 255) & ~(uintptr_t)255);
+    size_t need = m.off + (size_t)(base - (char*)ptr);
+    if (bytes < need) return fail(c, EMRT_E_WORKSPACE, "workspace too small");
+    Carver cv(base);
+    layout(c, cv);
+    c->ws = (char*)ptr;
+    c->ws_bytes = bytes;
+    c->bound = true;
+    c->scene_set = c->frame_set = c->stepped = false;
+    fill_u64(c->ctr, 0ULL, kNumCounters, c->stream);
+    fill_u32(c->flags, 0u, 16, c->stream);
+    return EMRT_OK;
+}
+
+int32_t emrt_set_stream(emrt_ctx* c, void* s) {
+    if (!c) return EMRT_E_INVALID;
+    c->stream = (hipStream_t)s;
+    return EMRT_OK;
+}
+
+int32_t emrt_set_materials(emrt_ctx* c, const double* eps, int32_t M) {
+    if (!c || !eps || M < 1 || M > kMaxMaterials) return fail(c, EMRT_E_INVALID, "bad material table");
+    if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace");
+    for (int i = 0; i < 2 * M; i++)
+        if (!std::isfinite(eps[i])) return fail(c, EMRT_E_INVALID, "non-finite permittivity");
+    c->mat_host.assign(eps, eps + 2 * M);
+    c->S.M = M;
+    return hip_check(c, hipMemcpyAsync(c->mat, c->mat_host.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice,
+                                       c->stream), "material upload");
+}
+
+static int32_t sync_read(emrt_ctx* c, void* dst, const void* src, size_t n) {
+    hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_check(c, e, "device read");
+}
+
+int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
+    if (!c || !d) return EMRT_E_INVALID;
+    if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace bound");
+    const emrt_sizes& z = c->sz;
+    if (d->n_verts != z.n_verts || d->n_tris != z.n_tris || d->n_faces != z.n_faces || d->n_objects != z.n_objects)
+        return fail(c, EMRT_E_INVALID, "scene sizes differ from the workspace sizes");
+    if (!d->verts || !d->tris || !d->tri_face || !d->face_object || !d->face_material || !d->object_dynamic)
+        return fail(c, EMRT_E_INVALID, "null scene array");
+    int32_t rc = emrt_set_materials(c, d->material_eps, d->n_materials);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    SceneDev& S = c->S;
+    S.V = (int)z.n_verts; S.T = (int)z.n_tris; S.F = (int)z.n_faces; S.O = (int)z.n_objects;
+    S.E_cap = c->E_cap;
+    HC(hipMemcpyAsync(S.verts_local_copy, d->verts, sizeof(float) * 3 * z.n_verts, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(S.verts, d->verts, sizeof(float) * 3 * z.n_verts, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(S.tris, d->tris, sizeof(int) * 3 * z.n_tris, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(S.tri_face, d->tri_face, sizeof(int) * z.n_tris, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(S.face_object, d->face_object, sizeof(int) * z.n_faces, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(S.face_material, d->face_material, sizeof(int) * z.n_faces, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(c->obj_dyn, d->object_dynamic, z.n_objects, hipMemcpyDeviceToDevice, st));
+    fill_u32(c->flags, 0u, 16, st);
+    scene_check(S, c->obj_dyn, c->flags, st);
+    uint32_t fl = 0;
+    if ((rc = sync_read(c, &fl, c->flags, sizeof(fl)))) return rc;
+    if (fl & FLAG_BAD_INPUT)
+        return fail(c, EMRT_E_INVALID, "scene: index out of range, degenerate or non-finite triangle");
+    int* counts = (int*)(c->ctr + C_SCRATCH);
+    scene_prepare(S, c->obj_dyn, c->scene_scratch, counts, c->tmp, st);
+    int cnt[2] = {0, 0};
+    if ((rc = sync_read(c, cnt, counts, sizeof(cnt)))) return rc;
+    S.O_d = cnt[0];
+    S.T_s = cnt[1];
+    S.T_d = S.T - S.T_s;
+    int E = scene_edges(S, c->obj_off, c->obj_faces, counts + 4, c->tmp, st);
+    if (E < 0) return fail(c, EMRT_E_UNSUPPORTED, "too many wedge edges");
+    // edges on dynamic objects
+    S.E_dyn = 0;
+    // static tree (world == local for static vertices)
+    scene_planes(S, st);
+    tri_boxes(S, S.tris_static, S.T_s, c->box_st, st);
+    bvh_build(c->box_st, S.T_s, c->st, c->tmp, st);
+    tri_prims(S, S.tris_static, c->st, c->st_prims, st);
+    c->dy.n = 0;
+    ray_order(c->cfg.rays_per_tx, c->dir_perm, c->tmp, st);
+    // empty cache
+    fill_u64(c->ctr, 0ULL, kNumCounters, st);
+    c->cur = 0;
+    c->scene_set = true;
+    c->frame_set = c->stepped = c->discovered = false;
+    c->frame_idx = -1;
+    return hip_check(c, hipStreamSynchronize(st), "set_scene");
+}
+
+int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
+    if (!c || !f) return EMRT_E_INVALID;
+    if (!c->scene_set) return fail(c, EMRT_E_STATE, "set_scene first");
+    if (f->n_tx != c->sz.n_tx || f->n_rx != c->sz.n_rx) return fail(c, EMRT_E_INVALID, "n_tx / n_rx differ from sizes");
+    if (!f->tx_pos || !f->rx_pos || !f->tx_vel || !f->rx_vel) return fail(c, EMRT_E_INVALID, "null frame array");
+    if (c->S.O_d > 0 && (!f->obj_xform || !f->obj_vel)) return fail(c, EMRT_E_INVALID, "dynamic objects need transforms");
+    hipStream_t st = c->stream;
+    int ntx = c->sz.n_tx, nrx = c->sz.n_rx;
+    HC(hipMemcpyAsync(c->f_tx, f->tx_pos, sizeof(double) * 3 * ntx, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(c->f_txv, f->tx_vel, sizeof(double) * 3 * ntx, hipMemcpyDeviceToDevice, st));
+    if (f->tx_orient) HC(hipMemcpyAsync(c->f_txo, f->tx_orient, sizeof(double) * 2 * ntx, hipMemcpyDeviceToDevice, st));
+    else fill_u64((unsigned long long*)c->f_txo, 0ULL, 2LL * ntx, st);
+    HC(hipMemcpyAsync(c->f_rx, f->rx_pos, sizeof(double) * 3 * nrx, hipMemcpyDeviceToDevice, st));
+    HC(hipMemcpyAsync(c->f_rxv, f->rx_vel, sizeof(double) * 3 * nrx, hipMemcpyDeviceToDevice, st));
+    if (c->S.O_d > 0) {
+        HC(hipMemcpyAsync(c->f_xf, f->obj_xform, sizeof(double) * 12 * c->S.O_d, hipMemcpyDeviceToDevice, st));
+        HC(hipMemcpyAsync(c->f_ov, f->obj_vel, sizeof(double) * 3 * c->S.O_d, hipMemcpyDeviceToDevice, st));
+    }
+    c->frame_set = true;
+    c->frame_idx = f->frame;
+    return hip_check(c, hipGetLastError(), "set_frame");
+}
+
+int32_t emrt_set_instrumentation(emrt_ctx* c, int32_t stats, int32_t timing) {
+    if (!c) return EMRT_E_INVALID;
+    c->stats_on = stats ? 1 : 0;
+    c->timing_on = timing ? 1 : 0;
+    if (c->timing_on && c->ev.empty()) {
+        c->ev.resize(16);
+        for (auto& e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(c, EMRT_E_HIP, "event create");
+    }
+    return EMRT_OK;
+}
+
+static PathArgs path_args(emrt_ctx* c) {
+    PathArgs a{};
+    a.s = c->S;
+    a.f.n_tx = c->sz.n_tx;
+    a.f.n_rx = c->sz.n_rx;
+    a.f.tx_pos = c->f_tx; a.f.tx_vel = c->f_txv; a.f.tx_orient = c->f_txo;
+    a.f.rx_pos = c->f_rx; a.f.rx_vel = c->f_rxv; a.f.obj_vel = c->f_ov;
+    a.st = c->st.view(); a.dy = c->dy.view();
+    a.st_prims = c->st_prims; a.dy_prims = c->dy_prims;
+    a.mat_eps = c->mat;
+    a.nf = c->nf;
+    for (int i = 0; i < EMRT_NF; i++) a.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
+    a.ant_mode = c->cfg.antenna_mode;
+    a.diff_max_leg = c->cfg.diff_max_leg_m;
+    a.out = c->vp;
+    a.flags = c->flags;
+    return a;
+}
+
+int32_t emrt_step(emrt_ctx* c, int32_t discover) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->scene_set || !c->frame_set) return fail(c, EMRT_E_STATE, "set_scene and set_frame first");
+    hipStream_t st = c->stream;
+    SceneDev& S = c->S;
+    const int K = c->K;
+    // counters: keep the cache sizes, clear the rest
+    fill_u64(c->ctr + C_RAYS, 0ULL, C_NCACHE - C_RAYS, st);
+    fill_u64(c->ctr + C_STATS, 0ULL, kNumCounters - C_STATS, st);
+    c->ev_used = 0;
+    c->ev_bounce = 0;
+    // ---- frame geometry (Section II-A: BVH updated between frames)
+    scene_world(S, c->f_xf, c->flags, st);
+    scene_planes(S, st);
+    if (S.T_d > 0) {
+        tri_boxes(S, S.tris_dynamic, S.T_d, c->box_dy, st);
+        if (discover || c->dy.n != S.T_d) bvh_build(c->box_dy, S.T_d, c->dy, c->tmp, st);
+        else bvh_refit(c->box_dy, c->dy, st);
+        tri_prims(S, S.tris_dynamic, c->dy, c->dy_prims, st);
+    }
+    rx_boxes(c->f_rx, c->sz.n_rx, c->box_rx, st);
+    bvh_build(c->box_rx, c->sz.n_rx, c->rxt, c->tmp, st);
+    rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
+    bool diff = c->cfg.diffraction && S.E > 0;
+    if (diff) {
+        edge_boxes(S, c->box_ed, st);
+        bvh_build(c->box_ed, S.E, c->edt, c->tmp, st);
+        edge_prims(S, c->edt, c->edge_prims, st);
+    }
+    KeySrc src{c->hitlog, S.tri_face, c->cache[c->cur], c->n_total, c->cfg.rays_per_tx};
+    PathArgs pa = path_args(c);
+    const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
+    if (discover) {
+        fill_u64(c->table, 0ULL, c->table_slots, st);
+        fill_u32((uint32_t*)c->hitlog, 0xFFFFFFFEu, (long long)(K + 1) * c->n_total, st);
+        if (diff) fill_u32(c->illum, 0u, (long long)c->sz.n_tx * c->e_words, st);
+        cache_insert(c->table, mask, c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, src, c->flags, st);
+        raygen(c->f_tx, c->sz.n_tx, c->cfg.rays_per_tx, c->dir_perm, c->rays[0], c->ctr + C_RAYS, st);
+        BounceArgs b{};
+        b.K = K;
+        b.n_total = c->n_total;
+        b.rays_per_tx = c->cfg.rays_per_tx;
+        b.st = c->st.view(); b.dy = c->dy.view();
+        b.st_prims = c->st_prims; b.dy_prims = c->dy_prims;
+        b.plane = S.plane;
+        b.rxt = c->rxt.view();
+        b.rx_prims = c->rx_prims;
+        b.alpha_k = (float)(c->cfg.rx_sphere_k * sqrt(4.0 * kPi / (double)c->cfg.rays_per_tx));
+        b.diffraction = diff ? 1 : 0;
+        b.edt = c->edt.view();
+        b.edge_prims = c->edge_prims;
+        b.illum = c->illum;
+        b.e_words = c->e_words;
+        b.table = c->table;
+        b.mask = mask;
+        b.src = src;
+        b.hitlog = c->hitlog;
+        b.flags = c->flags;
+        b.stats = c->ctr + C_STATS;
+        long long g = (c->n_total + 255) / 256;
+        int grid = (int)std::min<long long>(std::max<long long>(g, 1), 2048);
+        for (int k = 0; k <= K; k++) {
+            b.b = k;
+            b.in = c->rays[k & 1];
+            b.out = c->rays[(k + 1) & 1];
+            b.n_in = c->ctr + C_RAYS + k;
+            b.n_out = c->ctr + C_RAYS + k + 1;
+            b.work = (unsigned int*)(c->ctr + C_WORK + k);
+            if (c->timing_on && c->ev_used + 2 <= (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+            bounce(b, c->stats_on != 0, grid, st);
+            if (c->timing_on && c->ev_used + 1 <= (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+        }
+        c->ev_bounce = c->ev_used;
+        if (diff) diff_candidates(pa, c->illum, c->e_words, c->rxt.view(), c->rx_prims, c->table, mask, src, st);
+        table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags, st);
+        pa.cand = c->cand;
+        pa.n_cand = c->ctr + C_NCAND;
+        c->discovered = true;
+    } else {
+        pa.cand = c->cache[c->cur];
+        pa.n_cand = c->ctr + C_NCACHE + c->cur;
+    }
+    // ---- exact validation + fields (Sections II-A, III-B, III-C)
+    int ev0 = c->ev_used;
+    if (c->timing_on && c->ev_used + 2 <= (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+    validate_eval(pa, c->n_links, c->P, st);
+    if (c->timing_on && ev0 + 1 < (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+    // ---- per-link reduction (Section V-D statistics)
+    link_keys(c->vp, c->sz.n_rx, c->sk0, c->sv0, st);
+    int which = radix_sort(c->sk0, c->sv0, c->sk1, c->sv1, (const long long*)c->vp.count, c->vcap, bits_for(c->n_links),
+                           c->sort_tmp, st);
+    unsigned long long* skeys = which ? c->sk1 : c->sk0;
+    c->order = which ? c->sv1 : c->sv0;
+    link_ranges(skeys, c->vp.count, c->vcap, c->link_start, c->link_end, c->n_links, st);
+    link_reduce(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->nf, c->cfg.tx_power_w, c->chan, st);
+    // ---- next cache: valid non-LoS keys in link/key order
+    int nxt = 1 - c->cur;
+    cache_counts(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->link_cnt, st);
+    exclusive_scan(c->link_cnt, c->link_off, c->n_links, c->scan_tmp, (uint32_t*)(c->ctr + C_NCACHE + nxt), st);
+    fill_u32(((uint32_t*)(c->ctr + C_NCACHE + nxt)) + 1, 0u, 1, st);  // high word of the u64 count
+    cache_write(c->vp, c->order, c->link_start, c->link_end, c->link_off, c->n_links, c->cache[nxt], st);
+    c->cur = nxt;
+    c->stepped = true;
+    c->ev_valid = c->timing_on != 0;
+    return hip_check(c, hipGetLastError(), "step");
+}
+
+int32_t emrt_sync(emrt_ctx* c) {
+    if (!c) return EMRT_E_INVALID;
+    uint32_t fl = 0;
+    if (c->bound) {
+        int32_t rc = sync_read(c, &fl, c->flags, sizeof(fl));
+        if (rc) return rc;
+    } else {
+        return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    }
+    c->flag_accum |= fl;
+    if (fl & (FLAG_BAD_INPUT | FLAG_NONFINITE)) return fail(c, EMRT_E_DEVICE_FLAG, "non-finite or invalid frame input");
+    if (fl & (FLAG_TABLE_FULL | FLAG_CAND_CAP | FLAG_PATH_CAP))
+        return fail(c, EMRT_W_CACHE_FULL, "capacity reached (path table, candidates or paths): results incomplete");
+    return EMRT_OK;
+}
+
+}  // extern "C"
+
+// channel copy into caller layout
+__global__ void k_read_channels(const double* chan, long long n_links, int nf, double* H, double* Pc, double* Pi,
+                                double* tm, double* tr, double* fm, double* fr, int32_t* np, uint32_t* fl) {
+    long long n = n_links * nf;
+    const int* ci = (const int*)(chan + 8 * n);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double* c = chan + 8 * i;
+        if (H) { H[2 * i] = c[0]; H[2 * i + 1] = c[1]; }
+        if (Pc) Pc[i] = c[2];
+        if (Pi) Pi[i] = c[3];
+        if (tm) tm[i] = c[4];
+        if (tr) tr[i] = c[5];
+        if (fm) fm[i] = c[6];
+        if (fr) fr[i] = c[7];
+        if (i < n_links) {
+            if (np) np[i] = ci[2 * i];
+            if (fl) fl[i] = ci[2 * i + 1] ? 1u : 0u;
+        }
+    }
+}
+
+__global__ void k_trunc_flag(const int* start, const int* end, long long n_links, int cap, unsigned long long* flag) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_links; i += (long long)gridDim.x * blockDim.x) {
+        if (start[i] >= 0 && end[i] - start[i] > cap) atomicOr(flag, 1ULL);
+    }
+}
+
+extern "C" {
+
+int32_t emrt_read_channels(emrt_ctx* c, const emrt_channel_view* v) {
+    if (!c || !v) return EMRT_E_INVALID;
+    if (!c->stepped) return fail(c, EMRT_E_STATE, "no step yet");
+    long long n = c->n_links * c->nf;
+    int g = (int)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_read_channels, dim3(std::max(g, 1)), dim3(256), 0, c->stream, c->chan, c->n_links, c->nf,
+                       v->H, v->P_coh, v->P_inc, v->tau_mean, v->tau_rms, v->fd_mean, v->fd_rms, v->n_paths,
+                       v->flags);
+    return emrt_sync(c);
+}
+
+int32_t emrt_read_paths(emrt_ctx* c, const emrt_path_view* v) {
+    if (!c || !v || v->cap < 1 || !v->count) return fail(c, EMRT_E_INVALID, "bad path view");
+    if (!c->stepped) return fail(c, EMRT_E_STATE, "no step yet");
+    path_gather(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->nf, v->cap, v->key, v->tri_ids, v->a,
+                v->tau, v->fd, v->angles, v->count, c->stream);
+    fill_u64(c->ctr + C_TRUNC, 0ULL, 1, c->stream);
+    int g = (int)std::min<long long>((c->n_links + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_trunc_flag, dim3(std::max(g, 1)), dim3(256), 0, c->stream, c->link_start, c->link_end,
+                       c->n_links, v->cap, c->ctr + C_TRUNC);
+    unsigned long long tr = 0;
+    int32_t rc = sync_read(c, &tr, c->ctr + C_TRUNC, sizeof(tr));
+    if (rc) return rc;
+    rc = emrt_sync(c);
+    if (rc) return rc;
+    return tr ? EMRT_W_PATHS_TRUNCATED : EMRT_OK;
+}
+
+int32_t emrt_debug_ray_records(emrt_ctx* c, int32_t tx, const int32_t* ray_ids, int32_t n, int32_t* out) {
+    if (!c || (n > 0 && (!ray_ids || !out)) || tx < 0 || tx >= c->sz.n_tx) return fail(c, EMRT_E_INVALID, "bad arguments");
+    if (!c->discovered) return fail(c, EMRT_E_STATE, "no discovery step yet");
+    debug_rays(c->hitlog, c->n_total, c->K, tx, c->cfg.rays_per_tx, ray_ids, n, out, c->stream);
+    return hip_check(c, hipGetLastError(), "debug_ray_records");
+}
+
+int32_t emrt_cache_size(emrt_ctx* c, int64_t* n) {
+    if (!c || !n) return EMRT_E_INVALID;
+    if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace");
+    unsigned long long v = 0;
+    int32_t rc = sync_read(c, &v, c->ctr + C_NCACHE + c->cur, sizeof(v));
+    *n = (int64_t)std::min<unsigned long long>(v, (unsigned long long)c->P);
+    return rc;
+}
+
+int32_t emrt_cache_export(emrt_ctx* c, int32_t* keys, int64_t cap, int64_t* n) {
+    if (!c || !n) return EMRT_E_INVALID;
+    int64_t m = 0;
+    int32_t rc = emrt_cache_size(c, &m);
+    if (rc) return rc;
+    *n = m;
+    if (m > cap) return fail(c, EMRT_E_INVALID, "export buffer too small");
+    if (m > 0 && !keys) return fail(c, EMRT_E_INVALID, "null export buffer");
+    keys_export(c->cache[c->cur], m, keys, c->stream);
+    return hip_check(c, hipStreamSynchronize(c->stream), "cache_export");
+}
+
+int32_t emrt_cache_import(emrt_ctx* c, const int32_t* keys, int64_t n) {
+    if (!c || n < 0 || (n > 0 && !keys)) return EMRT_E_INVALID;
+    if (!c->scene_set) return fail(c, EMRT_E_STATE, "set_scene first");
+    if (n > c->P) return fail(c, EMRT_E_INVALID, "more keys than path_capacity");
+    keys_import(keys, n, c->cache[c->cur], c->stream);
+    unsigned long long v = (unsigned long long)n;
+    HC(hipMemcpyAsync(c->ctr + C_NCACHE + c->cur, &v, sizeof(v), hipMemcpyHostToDevice, c->stream));
+    return hip_check(c, hipStreamSynchronize(c->stream), "cache_import");
+}
+
+int32_t emrt_read_stats(emrt_ctx* c, emrt_stats* o) {
+    if (!c || !o) return EMRT_E_INVALID;
+    if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace");
+    unsigned long long h[kNumCounters];
+    int32_t rc = sync_read(c, h, c->ctr, sizeof(h));
+    if (rc) return rc;
+    uint32_t fl = 0;
+    if ((rc = sync_read(c, &fl, c->flags, sizeof(fl)))) return rc;
+    memset(o, 0, sizeof(*o));
+    for (int b = 0; b < 7; b++) o->rays_per_bounce[b] = b <= c->K ? (int64_t)h[C_RAYS + b] : 0;
+    o->n_candidates = (int64_t)h[C_NCAND];
+    o->n_valid = (int64_t)h[C_NVALID];
+    o->n_cache = (int64_t)h[C_NCACHE + c->cur];
+    o->node_visits = (int64_t)h[C_STATS + 0];
+    o->tri_tests = (int64_t)h[C_STATS + 1];
+    o->segments = (int64_t)h[C_STATS + 2];
+    o->captures = (int64_t)h[C_STATS + 3];
+    o->n_static_tris = c->S.T_s;
+    o->n_dynamic_tris = c->S.T_d;
+    o->n_edges = c->S.E;
+    o->device_flags = fl | c->flag_accum;
+    if (c->ev_valid && c->ev_used >= 2) {
+        int nb = c->ev_bounce;
+        double tb = 0;
+        int launches = 0;
+        for (int i = 0; i + 1 < nb && i + 1 < c->ev_used; i += 2) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) { tb += ms; launches++; }
+        }
+        o->bounce_ms = tb;
+        o->bounce_launches = launches;
+        int vi = c->ev_used - 2;
+        float ms = 0;
+        if (vi >= 0 && hipEventElapsedTime(&ms, c->ev[vi], c->ev[vi + 1]) == hipSuccess) o->validate_ms = ms;
+    }
+    return EMRT_OK;
+}
+
+const char* emrt_status_string(int32_t s) {
+    switch (s) {
+        case EMRT_OK: return "ok";
+        case EMRT_W_PATHS_TRUNCATED: return "warning: path list truncated";
+        case EMRT_W_CACHE_FULL: return "warning: capacity reached, results incomplete";
+        case EMRT_E_INVALID: return "invalid argument";
+        case EMRT_E_STATE: return "call out of order";
+        case EMRT_E_WORKSPACE: return "workspace missing or too small";
+        case EMRT_E_HIP: return "HIP error";
+        case EMRT_E_UNSUPPORTED: return "unsupported configuration";
+        case EMRT_E_DEVICE_FLAG: return "device reported invalid input";
+        default: return "unknown status";
+    }
+}
+
+int32_t emrt_last_error(emrt_ctx* c, char* buf, size_t len) {
+    if (!c || !buf || len == 0) return EMRT_E_INVALID;
+    size_t n = std::min(len - 1, c->err.size());
+    memcpy(buf, c->err.data(), n);
+    buf[n] = 0;
+    return EMRT_OK;
+}
+
+}  // extern "C"

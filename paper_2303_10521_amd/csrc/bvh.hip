@@ -1,0 +1,246 @@
+// bvh.hip -- linear BVH over arbitrary primitive boxes.
+//
+// Build: 63-bit Morton codes of box centroids (21 bits per axis over the
+// centroid bounds), LSD radix sort, Karras-style hierarchy emission
+// (T. Karras, "Maximizing parallelism in the construction of BVHs, octrees
+// and k-d trees", HPG 2012) with ties between equal codes broken by the sorted
+// index, then a bottom-up refit.  Each internal node stores both child boxes,
+// its parent link and the split axis (the Morton bit at which its range
+// splits), which the traversal uses to visit the near child first.
+// Refit: one thread per leaf climbs towards the root; the second thread to
+// arrive at a node (device-scope atomic counter) merges the two child boxes
+// and continues, so every node is written exactly once per refit.
+// Paper: Section II-A (a BVH updated between frames), Section III-A (only
+// subtrees change within a trajectory segment).
+#include "emrt_dev.h"
+#include "emrt_launch.h"
+
+namespace emrt {
+
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+    u = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ unsigned long long split3(uint32_t a) {
+    unsigned long long x = a & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+__global__ void k_init_bounds(uint32_t* b) {
+    int t = threadIdx.x;
+    if (t < 3) b[t] = 0xFFFFFFFFu;
+    else if (t < 6) b[t] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_bounds(const float* box, int n, uint32_t* b) {
+    __shared__ uint32_t sh[6];
+    if (threadIdx.x < 3) sh[threadIdx.x] = 0xFFFFFFFFu;
+    else if (threadIdx.x < 6) sh[threadIdx.x] = 0u;
+    __syncthreads();
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float* p = box + 6 * (long long)i;
+        for (int c = 0; c < 3; c++) {
+            float m = 0.5f * (p[c] + p[3 + c]);
+            atomicMin(&sh[c], f2ord(m));
+            atomicMax(&sh[3 + c], f2ord(m));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) atomicMin(&b[threadIdx.x], sh[threadIdx.x]);
+    else if (threadIdx.x < 6) atomicMax(&b[threadIdx.x], sh[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) k_morton(const float* box, int n, const uint32_t* b, unsigned long long* codes,
+                                                uint32_t* vals) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* p = box + 6 * (long long)i;
+    uint32_t q[3];
+    for (int c = 0; c < 3; c++) {
+        float lo = ord2f(b[c]), hi = ord2f(b[3 + c]);
+        float m = 0.5f * (p[c] + p[3 + c]);
+        float e = hi - lo;
+        float u = e > 0.0f ? (m - lo) / e : 0.5f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        q[c] = (uint32_t)(u * 2097151.0f);
+    }
+    codes[i] = (split3(q[0]) << 2) | (split3(q[1]) << 1) | split3(q[2]);
+    vals[i] = (uint32_t)i;
+}
+
+__device__ __forceinline__ int kdelta(const unsigned long long* c, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    unsigned long long a = c[i], b = c[j];
+    if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+    return __clzll((long long)(a ^ b));
+}
+
+__global__ void __launch_bounds__(256) k_emit(const unsigned long long* codes, const uint32_t* sorted, int n,
+                                              BNode* nodes, int* leaf_parent, uint32_t* perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = sorted[i];
+    if (n == 1 && i == 0) {
+        BNode nd;
+        nd.a = make_float4(INFINITY, INFINITY, INFINITY, -INFINITY);
+        nd.b = make_float4(-INFINITY, -INFINITY, INFINITY, INFINITY);
+        nd.c = make_float4(INFINITY, -INFINITY, -INFINITY, -INFINITY);
+        nd.m = make_int4((int)EMRT_LEAF, (int)EMRT_LEAF, -1, 0);
+        nodes[0] = nd;
+        leaf_parent[0] = 0;
+        return;
+    }
+    if (i >= n - 1) return;
+    int d = (kdelta(codes, n, i, i + 1) - kdelta(codes, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = kdelta(codes, n, i, i - d);
+    int lmax = 2;
+    while (kdelta(codes, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (kdelta(codes, n, i, i + (l + t) * d) > dmin) l += t;
+    int j = i + l * d;
+    int dnode = kdelta(codes, n, i, j);
+    int s = 0;
+    int t = l;
+    do {
+        t = (t + 1) / 2;
+        if (kdelta(codes, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int gamma = i + s * d + (d < 0 ? -1 : 0);
+    int lo = i < j ? i : j, hi = i < j ? j : i;
+    int left = (lo == gamma) ? (int)(EMRT_LEAF | (uint32_t)gamma) : gamma;
+    int right = (hi == gamma + 1) ? (int)(EMRT_LEAF | (uint32_t)(gamma + 1)) : gamma + 1;
+    int axis = 0;
+    if (dnode < 64) {
+        int bit = 63 - dnode;
+        int r = bit % 3;
+        axis = r == 2 ? 0 : (r == 1 ? 1 : 2);
+    }
+    int* m = (int*)&nodes[i].m;
+    m[0] = left;
+    m[1] = right;
+    m[3] = axis;
+    if (i == 0) m[2] = -1;
+    if (lo == gamma) leaf_parent[gamma] = i;
+    else ((int*)&nodes[gamma].m)[2] = i;
+    if (hi == gamma + 1) leaf_parent[gamma + 1] = (int)((uint32_t)i | EMRT_SIDE);
+    else ((int*)&nodes[gamma + 1].m)[2] = (int)((uint32_t)i | EMRT_SIDE);
+}
+
+__device__ __forceinline__ float aload(const float* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256) k_refit(const float* box, const uint32_t* perm, int n, BNode* nodes,
+                                               const int* leaf_parent, uint32_t* counters) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const float* p = box + 6 * (long long)perm[l];
+    float lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[3], p[4], p[5]};
+    uint32_t par = (uint32_t)leaf_parent[l];
+    while (true) {
+        int idx = (int)(par & 0x7FFFFFFFu);
+        int side = (int)(par >> 31);
+        float* nb = (float*)&nodes[idx];
+        float* dst = nb + (side ? 6 : 0);
+        for (int c = 0; c < 3; c++) {
+            __hip_atomic_store(dst + c, lo[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(dst + 3 + c, hi[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        uint32_t old = atomicAdd(&counters[idx], 1u);
+        if (old == 0u) return;
+        __threadfence();
+        const float* o = nb + (side ? 0 : 6);
+        for (int c = 0; c < 3; c++) {
+            lo[c] = fminf(lo[c], aload(o + c));
+            hi[c] = fmaxf(hi[c], aload(o + 3 + c));
+        }
+        if (idx == 0) return;
+        par = (uint32_t)__hip_atomic_load(&((int*)&nodes[idx].m)[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sah(const BNode* nodes, int n_int, double* out) {
+    __shared__ double sh[256];
+    double s = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_int; i += gridDim.x * blockDim.x) {
+        BNode nd = nodes[i];
+        float ex = nd.a.w - nd.a.x, ey = nd.b.x - nd.a.y, ez = nd.b.y - nd.a.z;
+        if (ex >= 0) s += 2.0 * ((double)ex * ey + (double)ey * ez + (double)ez * ex);
+        ex = nd.c.y - nd.b.z; ey = nd.c.z - nd.b.w; ez = nd.c.w - nd.c.x;
+        if (ex >= 0) s += 2.0 * ((double)ex * ey + (double)ey * ez + (double)ez * ex);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, sh[0]);
+}
+
+size_t build_temp_bytes(long long cap) {
+    if (cap < 1) cap = 1;
+    size_t b = 0;
+    b += 2 * sizeof(unsigned long long) * (size_t)cap;
+    b += 2 * sizeof(uint32_t) * (size_t)cap;
+    b += 64;
+    b += radix_temp_bytes(cap);
+    return b + 5 * 256;
+}
+
+static char* align256(char* p) { return (char*)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
+
+void carve_build_temp(void* base, long long cap, BuildTemp& t) {
+    if (cap < 1) cap = 1;
+    char* p = align256((char*)base);
+    t.k0 = (unsigned long long*)p; p = align256(p + sizeof(unsigned long long) * cap);
+    t.k1 = (unsigned long long*)p; p = align256(p + sizeof(unsigned long long) * cap);
+    t.v0 = (uint32_t*)p; p = align256(p + sizeof(uint32_t) * cap);
+    t.v1 = (uint32_t*)p; p = align256(p + sizeof(uint32_t) * cap);
+    t.bounds = (uint32_t*)p; p = align256(p + 64);
+    t.radix = p;
+}
+
+void bvh_build(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st) {
+    tree.n = n;
+    if (n <= 0) return;
+    int g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, tmp.bounds);
+    hipLaunchKernelGGL(k_bounds, dim3(g), dim3(256), 0, st, box6, n, tmp.bounds);
+    hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, st, box6, n, tmp.bounds, tmp.k0, tmp.v0);
+    int which = radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, nullptr, n, 63, tmp.radix, st);
+    const unsigned long long* codes = which ? tmp.k1 : tmp.k0;
+    const uint32_t* vals = which ? tmp.v1 : tmp.v0;
+    hipLaunchKernelGGL(k_emit, dim3(g), dim3(256), 0, st, codes, vals, n, tree.nodes, tree.leaf_parent, tree.perm);
+    bvh_refit(box6, tree, st);
+}
+
+void bvh_refit(const float* box6, Tree& tree, hipStream_t st) {
+    int n = tree.n;
+    if (n <= 0) return;
+    fill_u32(tree.counters, 0u, n > 1 ? n - 1 : 1, st);
+    hipLaunchKernelGGL(k_refit, dim3((n + 255) / 256), dim3(256), 0, st, box6, tree.perm, n, tree.nodes,
+                       tree.leaf_parent, tree.counters);
+}
+
+void bvh_sah(const Tree& tree, double* out, hipStream_t st) {
+    int n_int = tree.n > 1 ? tree.n - 1 : 1;
+    if (tree.n <= 0) return;
+    int g = (n_int + 255) / 256;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_sah, dim3(g), dim3(256), 0, st, tree.nodes, n_int, out);
+}
+
+}  // namespace emrt

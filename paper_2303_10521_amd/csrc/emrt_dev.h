@@ -1,0 +1,463 @@
+// emrt_dev.h -- device-side data layouts and inline helpers of the gfx950
+// dynamic SBR EM ray tracer (Wang & Manocha 2023, Sections II-A, III-B/C).
+//
+// Layouts (all device memory, coalesced SoA where threads stream):
+//   BNode  64 B  internal node of a binary LBVH; both child boxes inline so a
+//                node visit is four 16-byte loads; leaves are primitives.
+//   TriP   48 B  triangle in leaf order: v0.xyz|tri id, v1.xyz|face, v2.xyz
+//   KeyRec 32 B  path key: tx, rx, type|order<<8, ids[5] (faces or edge)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define EMRT_LEAF 0x80000000u
+#define EMRT_SIDE 0x80000000u
+#define EMRT_KMAX 5
+#define EMRT_NF 4
+
+namespace emrt {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC0 = 299792458.0;
+
+// --------------------------------------------------------------------------
+// structures
+// --------------------------------------------------------------------------
+struct __attribute__((aligned(16))) BNode {
+    float4 a;  // lmin.x lmin.y lmin.z lmax.x
+    float4 b;  // lmax.y lmax.z rmin.x rmin.y
+    float4 c;  // rmin.z rmax.x rmax.y rmax.z
+    int4 m;    // left, right (EMRT_LEAF|slot for leaves), parent|side<<31, split axis
+};
+
+struct __attribute__((aligned(16))) TriP {
+    float4 v0;  // w = tri id (int bits)
+    float4 v1;  // w = face id (int bits)
+    float4 v2;
+};
+
+struct KeyRec {
+    int tx, rx, to;  // to = type | order << 8
+    int ids[5];
+};
+
+enum { KT_LOS = 0, KT_SPEC = 1, KT_DIFF = 2 };
+
+// device status flags (read back on sync)
+enum : uint32_t {
+    FLAG_TABLE_FULL = 1u << 0,
+    FLAG_CAND_CAP = 1u << 1,
+    FLAG_PATH_CAP = 1u << 2,
+    FLAG_BAD_INPUT = 1u << 3,
+    FLAG_NONFINITE = 1u << 4,
+    FLAG_EDGE_CAP = 1u << 5,
+};
+
+struct Bvh {
+    const BNode* nodes;
+    int n_prims;  // 0: empty tree
+};
+
+// --------------------------------------------------------------------------
+// float / double vectors
+// --------------------------------------------------------------------------
+struct dv3 { double x, y, z; };
+__device__ __forceinline__ dv3 d3(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ dv3 operator+(dv3 a, dv3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ dv3 operator-(dv3 a, dv3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ dv3 operator*(dv3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double dot(dv3 a, dv3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ dv3 cross(dv3 a, dv3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double len(dv3 a) { return sqrt(dot(a, a)); }
+__device__ __forceinline__ dv3 unit(dv3 a) { return a * (1.0 / len(a)); }
+__device__ __forceinline__ dv3 ldd3(const double* p) { return {p[0], p[1], p[2]}; }
+__device__ __forceinline__ dv3 ldf3(const float* p) { return {(double)p[0], (double)p[1], (double)p[2]}; }
+
+// --------------------------------------------------------------------------
+// complex double
+// --------------------------------------------------------------------------
+struct cd { double re, im; };
+__device__ __forceinline__ cd C(double r, double i = 0.0) { return {r, i}; }
+__device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd operator*(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd operator*(cd a, double s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    // Smith's algorithm
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, den = b.re + b.im * r;
+        return {(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+    }
+    double r = b.re / b.im, den = b.im + b.re * r;
+    return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+}
+__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ double cabsd(cd a) { return hypot(a.re, a.im); }
+__device__ __forceinline__ cd cexpi(double ph) { double s, c; sincos(ph, &s, &c); return {c, s}; }
+// principal square root (Re >= 0)
+__device__ __forceinline__ cd csqrtd(cd z) {
+    double r = hypot(z.re, z.im);
+    if (r == 0.0) return {0.0, 0.0};
+    if (z.re >= 0.0) {
+        double t = sqrt(0.5 * (r + z.re));
+        return {t, z.im / (2.0 * t)};
+    }
+    double t = sqrt(0.5 * (r - z.re));
+    return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// --------------------------------------------------------------------------
+// path keys and the open-addressing table
+//   table slot (u64): 0 empty;
+//     1<<62 | order<<59 | rx<<32 | ray       ray capture (order 1..7, rx < 2^27)
+//     2<<62 | cache index                     key copied from the path cache
+//     3<<62 | tx<<50 | edge<<26 | rx          diffraction candidate
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+}
+__device__ __forceinline__ uint64_t key_hash(int tx, int rx, int to, const int* ids) {
+    uint64_t h = mix64(((uint64_t)(uint32_t)tx << 32) ^ (uint64_t)(uint32_t)rx ^ 0x9E3779B97F4A7C15ULL);
+    h = mix64(h ^ (uint64_t)(uint32_t)to);
+    int type = to & 0xff, order = to >> 8;
+    int n = type == KT_SPEC ? order : (type == KT_DIFF ? 1 : 0);
+    for (int j = 0; j < n; j++) h = mix64(h ^ ((uint64_t)(uint32_t)ids[j] + 0x632BE59BD9B4E019ULL * (uint64_t)(j + 1)));
+    return h;
+}
+__device__ __forceinline__ uint64_t ref_ray(int order, int rx, uint32_t ray) {
+    return (1ULL << 62) | ((uint64_t)order << 59) | ((uint64_t)rx << 32) | (uint64_t)ray;
+}
+__device__ __forceinline__ uint64_t ref_cache(uint32_t idx) { return (2ULL << 62) | (uint64_t)idx; }
+__device__ __forceinline__ uint64_t ref_diff(int tx, int e, int rx) {
+    return (3ULL << 62) | ((uint64_t)tx << 50) | ((uint64_t)e << 26) | (uint64_t)rx;
+}
+
+// Context needed to expand a table reference into its key.
+struct KeySrc {
+    const int* hitlog;     // [K+1][n_total] triangle id per bounce
+    const int* tri_face;   // [T]
+    const KeyRec* cache;   // previous cache
+    long long n_total;     // rays in the launch
+    int rays_per_tx;
+};
+
+__device__ __forceinline__ void expand_ref(uint64_t ref, const KeySrc& s, KeyRec& k) {
+    uint32_t tag = (uint32_t)(ref >> 62);
+    if (tag == 1) {
+        uint32_t ray = (uint32_t)ref;
+        int order = (int)((ref >> 59) & 7);
+        k.tx = (int)(ray / (uint32_t)s.rays_per_tx);
+        k.rx = (int)((ref >> 32) & 0x7FFFFFF);
+        k.to = KT_SPEC | (order << 8);
+        for (int j = 0; j < 5; j++)
+            k.ids[j] = j < order ? s.tri_face[s.hitlog[(long long)j * s.n_total + ray]] : -1;
+    } else if (tag == 2) {
+        k = s.cache[(uint32_t)(ref & 0x3FFFFFFFFFFFFFFFULL)];
+    } else {
+        k.tx = (int)((ref >> 50) & 0xFFF);
+        k.rx = (int)(ref & 0x3FFFFFF);
+        k.to = KT_DIFF | (1 << 8);
+        k.ids[0] = (int)((ref >> 26) & 0xFFFFFF);
+        for (int j = 1; j < 5; j++) k.ids[j] = -1;
+    }
+}
+
+__device__ __forceinline__ bool key_eq(const KeyRec& a, const KeyRec& b) {
+    if (a.tx != b.tx || a.rx != b.rx || a.to != b.to) return false;
+    for (int j = 0; j < 5; j++)
+        if (a.ids[j] != b.ids[j]) return false;
+    return true;
+}
+
+// lexicographic (tx, rx, type, order, ids) -- the within-link path order
+__device__ __forceinline__ bool key_less(const KeyRec& a, const KeyRec& b) {
+    if (a.tx != b.tx) return a.tx < b.tx;
+    if (a.rx != b.rx) return a.rx < b.rx;
+    int ta = a.to & 0xff, tb = b.to & 0xff;
+    if (ta != tb) return ta < tb;
+    int oa = a.to >> 8, ob = b.to >> 8;
+    if (oa != ob) return oa < ob;
+    for (int j = 0; j < 5; j++)
+        if (a.ids[j] != b.ids[j]) return a.ids[j] < b.ids[j];
+    return false;
+}
+
+// Insert `ref` whose expanded key is `mine` with hash h.  Returns 1 when
+// inserted, 0 when an equal key is present, -1 when the table is full.
+// Lock-free: a slot is claimed by one 64-bit CAS holding the whole
+// reference, whose key data were written before this kernel started.
+__device__ __forceinline__ int table_insert(unsigned long long* table, uint64_t mask, uint64_t ref, const KeyRec& mine,
+                                            uint64_t h, const KeySrc& src) {
+    uint64_t slot = h & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        unsigned long long cur = __hip_atomic_load(&table[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0ULL) {
+            unsigned long long prev = atomicCAS(&table[slot], 0ULL, (unsigned long long)ref);
+            if (prev == 0ULL) return 1;
+            cur = prev;
+        }
+        if (cur == ref) return 0;
+        KeyRec other;
+        expand_ref(cur, src, other);
+        if (key_eq(other, mine)) return 0;
+        slot = (slot + 1) & mask;
+    }
+    return -1;
+}
+
+// --------------------------------------------------------------------------
+// rays: precomputation for the slab test and the watertight triangle test
+// (Woop, Benthin & Wald, "Watertight ray/triangle intersection", JCGT 2013)
+// --------------------------------------------------------------------------
+struct RayPre {
+    float ox, oy, oz;
+    float dx, dy, dz;
+    float ix, iy, iz;  // 1/d (zero components replaced by +-1e-30)
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+    int neg_x, neg_y, neg_z;
+};
+
+__device__ __forceinline__ float nz(float v) { return v != 0.0f ? v : 1e-30f; }
+
+__device__ __forceinline__ RayPre ray_pre(float ox, float oy, float oz, float dx, float dy, float dz) {
+    RayPre r;
+    r.ox = ox; r.oy = oy; r.oz = oz;
+    r.dx = dx; r.dy = dy; r.dz = dz;
+    r.ix = 1.0f / nz(dx);
+    r.iy = 1.0f / nz(dy);
+    r.iz = 1.0f / nz(dz);
+    r.neg_x = dx < 0.0f; r.neg_y = dy < 0.0f; r.neg_z = dz < 0.0f;
+    float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    float dkz = kz == 0 ? dx : (kz == 1 ? dy : dz);
+    if (dkz < 0.0f) { int t = kx; kx = ky; ky = t; }
+    float dkx = kx == 0 ? dx : (kx == 1 ? dy : dz);
+    float dky = ky == 0 ? dx : (ky == 1 ? dy : dz);
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.Sx = dkx / dkz;
+    r.Sy = dky / dkz;
+    r.Sz = 1.0f / dkz;
+    return r;
+}
+
+__device__ __forceinline__ float sel3(int k, float x, float y, float z) { return k == 0 ? x : (k == 1 ? y : z); }
+
+// Conservative slab test (Ize, "Robust BVH ray traversal", JCGT 2013): far
+// distance scaled by 1 + 2 gamma_3 so rounding never rejects a box that the
+// exact ray touches.  Returns the entry distance through tn.
+__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, const RayPre& r,
+                                     float tmin, float tmax, float& tn) {
+    float t0x = (lx - r.ox) * r.ix, t1x = (hx - r.ox) * r.ix;
+    float t0y = (ly - r.oy) * r.iy, t1y = (hy - r.oy) * r.iy;
+    float t0z = (lz - r.oz) * r.iz, t1z = (hz - r.oz) * r.iz;
+    float a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.0000003576278687f;
+    tn = a;
+    return a <= fminf(b, tmax);
+}
+
+// Watertight ray/triangle test, two-sided; hit when t > 0.  Edge functions
+// are evaluated without contraction so neighbouring triangles see exactly
+// opposite values on a shared edge; zero edge functions are re-evaluated in
+// double.
+__device__ __forceinline__ bool tri_hit(const TriP& p, const RayPre& r, float& t_out) {
+#pragma clang fp contract(off)
+    float Ax0 = p.v0.x - r.ox, Ay0 = p.v0.y - r.oy, Az0 = p.v0.z - r.oz;
+    float Bx0 = p.v1.x - r.ox, By0 = p.v1.y - r.oy, Bz0 = p.v1.z - r.oz;
+    float Cx0 = p.v2.x - r.ox, Cy0 = p.v2.y - r.oy, Cz0 = p.v2.z - r.oz;
+    float Akz = sel3(r.kz, Ax0, Ay0, Az0), Bkz = sel3(r.kz, Bx0, By0, Bz0), Ckz = sel3(r.kz, Cx0, Cy0, Cz0);
+    float Ax = sel3(r.kx, Ax0, Ay0, Az0) - r.Sx * Akz;
+    float Ay = sel3(r.ky, Ax0, Ay0, Az0) - r.Sy * Akz;
+    float Bx = sel3(r.kx, Bx0, By0, Bz0) - r.Sx * Bkz;
+    float By = sel3(r.ky, Bx0, By0, Bz0) - r.Sy * Bkz;
+    float Cx = sel3(r.kx, Cx0, Cy0, Cz0) - r.Sx * Ckz;
+    float Cy = sel3(r.ky, Cx0, Cy0, Cz0) - r.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        double u = (double)Cx * (double)By - (double)Cy * (double)Bx;
+        double v = (double)Ax * (double)Cy - (double)Ay * (double)Cx;
+        double w = (double)Bx * (double)Ay - (double)By * (double)Ax;
+        U = (float)u; V = (float)v; W = (float)w;
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = U + V + W;
+    if (det == 0.0f) return false;
+    float Az = r.Sz * Akz, Bz = r.Sz * Bkz, Cz = r.Sz * Ckz;
+    float T = U * Az + V * Bz + W * Cz;
+    float t = T / det;
+    if (!(t > 0.0f)) return false;
+    t_out = t;
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// stackless traversal over parent links
+//
+// State per ray: the current internal node and what is left to do there:
+//   0 test the first child, 1 test the second child, 2 climb to the parent,
+//   3 just climbed back from child `came` (decides between 1 and 2).
+// A node is loaded once when entered and once more when climbed back to.
+// Closest-hit and shadow traversal visit the near child first (the child on
+// the ray's side of the Morton split axis); the all-leaves queries go left
+// first.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ BNode ld_node(const BNode* n, int i) { return n[i]; }
+
+__device__ __forceinline__ void child_box(const BNode& nd, int side, float& lx, float& ly, float& lz, float& hx,
+                                          float& hy, float& hz, int& child) {
+    if (side == 0) { lx = nd.a.x; ly = nd.a.y; lz = nd.a.z; hx = nd.a.w; hy = nd.b.x; hz = nd.b.y; child = nd.m.x; }
+    else { lx = nd.b.z; ly = nd.b.w; lz = nd.c.x; hx = nd.c.y; hy = nd.c.z; hz = nd.c.w; child = nd.m.y; }
+}
+
+__device__ __forceinline__ int near_side(const BNode& nd, const RayPre& r) {
+    int axis = nd.m.w & 3;
+    return axis == 0 ? r.neg_x : (axis == 1 ? r.neg_y : r.neg_z);
+}
+
+// Generic driver.  test(nd, side, child) returns true to descend into `child`
+// (an internal node); it handles leaves itself and returns false for them.
+// ordered: visit the near child first.  Returns early when stop() is true.
+template <bool ORDERED, class Test, class Stop>
+__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Stop stop) {
+    int cur = 0, state = 0, came = 0;
+    while (true) {
+        BNode nd = ld_node(nodes, cur);
+        int first = ORDERED ? near_side(nd, r) : 0;
+        if (state == 3) state = (came == first) ? 1 : 2;
+        bool descended = false;
+        if (state == 0) {
+            int child;
+            float lx, ly, lz, hx, hy, hz;
+            child_box(nd, first, lx, ly, lz, hx, hy, hz, child);
+            if (test(lx, ly, lz, hx, hy, hz, child)) { cur = child; descended = true; }
+            else state = 1;
+            if (stop()) return;
+        }
+        if (!descended && state == 1) {
+            int child;
+            float lx, ly, lz, hx, hy, hz;
+            child_box(nd, 1 - first, lx, ly, lz, hx, hy, hz, child);
+            if (test(lx, ly, lz, hx, hy, hz, child)) { cur = child; state = 0; descended = true; }
+            else state = 2;
+            if (stop()) return;
+        }
+        if (descended) continue;
+        if (cur == 0) return;
+        uint32_t pz = (uint32_t)nd.m.z;
+        came = (int)(pz >> 31);
+        cur = (int)(pz & 0x7FFFFFFFu);
+        state = ORDERED ? 3 : (came ? 2 : 1);
+    }
+}
+
+struct NoStop { __device__ bool operator()() const { return false; } };
+
+// Closest hit among triangles not on face `skip_face`.  best_t / best_tri /
+// best_face carry the current best (ties broken by the lowest triangle id),
+// so the result does not depend on the tree or the visiting order.
+template <bool STATS>
+__device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, int skip_face,
+                                            float& best_t, int& best_tri, int& best_face, unsigned& n_nodes,
+                                            unsigned& n_tris) {
+    if (bvh.n_prims <= 0) return;
+    if (STATS) n_nodes++;
+    traverse<true>(bvh.nodes, r,
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
+            float tn;
+            if (!slab(lx, ly, lz, hx, hy, hz, r, 0.0f, best_t, tn)) return false;
+            if (!((uint32_t)child & EMRT_LEAF)) { if (STATS) n_nodes++; return true; }
+            TriP p = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
+            if (STATS) n_tris++;
+            int face = __float_as_int(p.v1.w);
+            float t;
+            if (face != skip_face && tri_hit(p, r, t)) {
+                int id = __float_as_int(p.v0.w);
+                if (t < best_t || (t == best_t && id < best_tri)) { best_t = t; best_tri = id; best_face = face; }
+            }
+            return false;
+        },
+        NoStop());
+}
+
+// Any hit on the open segment t in (0, tmax) among triangles not on faces
+// xa / xb (shadow rays of path validation).
+__device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, float tmax, int xa, int xb) {
+    if (bvh.n_prims <= 0) return false;
+    bool found = false;
+    traverse<true>(bvh.nodes, r,
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
+            float tn;
+            if (!slab(lx, ly, lz, hx, hy, hz, r, 0.0f, tmax, tn)) return false;
+            if (!((uint32_t)child & EMRT_LEAF)) return true;
+            TriP p = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
+            int face = __float_as_int(p.v1.w);
+            float t;
+            if (face != xa && face != xb && tri_hit(p, r, t) && t < tmax) found = true;
+            return false;
+        },
+        [&]() { return found; });
+    return found;
+}
+
+// Visit every leaf whose box, inflated by `grow`, meets the ray on [0, tmax].
+template <class Leaf>
+__device__ __forceinline__ void all_hits(const Bvh& bvh, const RayPre& r, float tmax, float grow, Leaf leaf) {
+    if (bvh.n_prims <= 0) return;
+    traverse<false>(bvh.nodes, r,
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
+            float tn;
+            if (!slab(lx - grow, ly - grow, lz - grow, hx + grow, hy + grow, hz + grow, r, 0.0f, tmax, tn)) return false;
+            if (!((uint32_t)child & EMRT_LEAF)) return true;
+            leaf((int)((uint32_t)child & ~EMRT_LEAF));
+            return false;
+        },
+        NoStop());
+}
+
+// Visit every leaf whose box overlaps the query box [ql, qh].
+template <class Leaf>
+__device__ __forceinline__ void box_query(const Bvh& bvh, float qlx, float qly, float qlz, float qhx, float qhy,
+                                          float qhz, Leaf leaf) {
+    if (bvh.n_prims <= 0) return;
+    RayPre dummy{};
+    traverse<false>(bvh.nodes, dummy,
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
+            bool ov = lx <= qhx && hx >= qlx && ly <= qhy && hy >= qly && lz <= qhz && hz >= qlz;
+            if (!ov) return false;
+            if (!((uint32_t)child & EMRT_LEAF)) return true;
+            leaf((int)((uint32_t)child & ~EMRT_LEAF));
+            return false;
+        },
+        NoStop());
+}
+
+// wave helpers (wave64)
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ uint64_t ballot64(bool p) { return (uint64_t)__ballot(p); }
+__device__ __forceinline__ int prefix_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+// one atomic per wave: returns this lane's slot in a compacted output
+__device__ __forceinline__ long long wave_append(unsigned long long* counter, bool keep) {
+    uint64_t m = ballot64(keep);
+    int cnt = __popcll(m);
+    unsigned long long base = 0;
+    int leader = __ffsll((long long)m) - 1;
+    if (cnt > 0 && lane_id() == leader) base = atomicAdd(counter, (unsigned long long)cnt);
+    base = __shfl(base, leader < 0 ? 0 : leader);
+    return keep ? (long long)(base + (unsigned long long)prefix_below(m)) : -1;
+}
+
+}  // namespace emrt

@@ -1,0 +1,197 @@
+// emrt_launch.h -- host-side launch interface between the library's
+// translation units (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "emrt_dev.h"
+
+namespace emrt {
+
+// ------------------------------------------------------------ sort.hip ----
+size_t scan_temp_bytes(long long n);
+void exclusive_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* temp, uint32_t* grand, hipStream_t st);
+size_t radix_temp_bytes(long long cap);
+int radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1, const long long* n_dev,
+               long long cap, int nbits, void* temp, hipStream_t st);
+void fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
+void fill_u64(unsigned long long* p, unsigned long long v, long long n, hipStream_t st);
+void iota_u32(uint32_t* p, long long n, hipStream_t st);
+
+// ------------------------------------------------------------- bvh.hip ----
+// A binary LBVH over n primitives given as float boxes [n][6] (lo, hi).
+struct Tree {
+    BNode* nodes = nullptr;       // [max(n-1, 1)]
+    int* leaf_parent = nullptr;   // [n] parent | side << 31
+    uint32_t* counters = nullptr; // [max(n-1, 1)] refit arrival counters
+    uint32_t* perm = nullptr;     // [n] leaf slot -> primitive index
+    int n = 0;
+    int cap = 0;
+    Bvh view() const { return Bvh{nodes, n}; }
+};
+// scratch for a build of up to `cap` primitives
+struct BuildTemp {
+    unsigned long long* k0;
+    unsigned long long* k1;
+    uint32_t* v0;
+    uint32_t* v1;
+    uint32_t* bounds;  // [8]
+    void* radix;
+};
+size_t build_temp_bytes(long long cap);
+void carve_build_temp(void* base, long long cap, BuildTemp& t);
+void bvh_build(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st);
+void bvh_refit(const float* box6, Tree& tree, hipStream_t st);
+// extra tree statistics: surface-area sum of internal nodes (device double)
+void bvh_sah(const Tree& tree, double* out, hipStream_t st);
+
+// ----------------------------------------------------------- scene.hip ----
+struct SceneDev {
+    int V, T, F, O, M;
+    const float* verts_local;   // [V][3] caller's array, copied at set_scene
+    float* verts_local_copy;    // [V][3]
+    float* verts;               // [V][3] world vertices of the current frame
+    int* tris;                  // [T][3]
+    int* tri_face;              // [T]
+    int* face_object;           // [F]
+    int* face_material;         // [F]
+    int* face_dyn;              // [F] dynamic-object rank or -1
+    int* vert_dyn;              // [V]
+    int* obj_rank;              // [O] dynamic rank or -1
+    double* plane;              // [F][4]
+    int* face_first;            // [F] lowest triangle id
+    int* face_off;              // [F+1]
+    int* face_tris;             // [T] sorted by (face, tri)
+    int* tris_static;           // [T_s]
+    int* tris_dynamic;          // [T_d]
+    int T_s, T_d, O_d;
+    // wedge edges
+    int E, E_cap;
+    int* edge_i;                // [E][6] va, vb, f0, fn, w0, wn
+    double* edge_n;             // [E]
+    int E_dyn;                  // edges on dynamic objects
+};
+
+// validate indices; returns flags via device word
+void scene_check(const SceneDev& s, const uint8_t* object_dynamic, uint32_t* flags, hipStream_t st);
+void scene_prepare(SceneDev& s, const uint8_t* object_dynamic, uint32_t* scratch_u32, int* counts_dev,
+                   const BuildTemp& tmp, hipStream_t st);
+int scene_edges(SceneDev& s, int* obj_off, int* obj_faces, int* counter, const BuildTemp& tmp, hipStream_t st);
+void scene_world(const SceneDev& s, const double* xform, uint32_t* flags, hipStream_t st);
+void scene_planes(const SceneDev& s, hipStream_t st);
+void tri_boxes(const SceneDev& s, const int* list, int n, float* box6, hipStream_t st);
+void tri_prims(const SceneDev& s, const int* list, const Tree& tree, TriP* prims, hipStream_t st);
+void edge_boxes(const SceneDev& s, float* box6, hipStream_t st);
+void edge_prims(const SceneDev& s, const Tree& tree, float4* prims, hipStream_t st);
+void rx_boxes(const double* rx_pos, int n_rx, float* box6, hipStream_t st);
+void rx_prims(const double* rx_pos, const Tree& tree, float4* prims, hipStream_t st);
+
+// ----------------------------------------------------------- trace.hip ----
+struct RaySoA {
+    float *ox, *oy, *oz, *dx, *dy, *dz, *L;
+    uint32_t* id;
+    int* prev;
+};
+
+struct BounceArgs {
+    RaySoA in, out;
+    const unsigned long long* n_in;
+    unsigned long long* n_out;
+    unsigned int* work;
+    int b, K;
+    long long n_total;
+    int rays_per_tx;
+    // scene
+    Bvh st, dy;
+    const TriP* st_prims;
+    const TriP* dy_prims;
+    const double* plane;
+    // receivers
+    Bvh rxt;
+    const float4* rx_prims;
+    float alpha_k;  // k_rx * sqrt(4 pi / N)
+    float4 rx_root_lo, rx_root_hi;  // unused when the tree is read on device
+    // edges
+    int diffraction;
+    Bvh edt;
+    const float4* edge_prims;  // [E][2]
+    uint32_t* illum;           // [N_tx][E_words]
+    int e_words;
+    // path table
+    unsigned long long* table;
+    unsigned long long mask;
+    KeySrc src;
+    int* hitlog;
+    uint32_t* flags;
+    unsigned long long* stats;  // [4] node visits, triangle tests, segments, captures (STATS only)
+};
+void ray_order(int N, uint32_t* perm, const BuildTemp& tmp, hipStream_t st);
+void raygen(const double* tx_pos, int n_tx, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
+            hipStream_t st);
+void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
+void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ray_ids, int n, int* out,
+                hipStream_t st);
+
+// ----------------------------------------------------------- paths.hip ----
+struct FrameDev {
+    int n_tx, n_rx;
+    const double* tx_pos;   // [N_tx][3]
+    const double* tx_vel;
+    const double* tx_orient;  // [N_tx][2]
+    const double* rx_pos;
+    const double* rx_vel;
+    const double* obj_vel;  // [O_d][3]
+};
+
+struct ValidPaths {
+    KeyRec* key;
+    int* tri;        // [cap][5]
+    double* a;       // [cap][nf][2]
+    double* tau;     // [cap]
+    double* fd;      // [cap][nf]
+    float4* ang;     // [cap]
+    unsigned long long* count;
+    long long cap;
+};
+
+struct PathArgs {
+    SceneDev s;
+    FrameDev f;
+    Bvh st, dy;
+    const TriP* st_prims;
+    const TriP* dy_prims;
+    const double* mat_eps;  // [M][2]
+    int nf;
+    double freq[EMRT_NF];
+    int ant_mode;
+    double diff_max_leg;
+    // inputs
+    const KeyRec* cand;
+    const unsigned long long* n_cand;
+    ValidPaths out;
+    uint32_t* flags;
+};
+
+void cache_insert(unsigned long long* table, unsigned long long mask, const KeyRec* cache,
+                  const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags, hipStream_t st);
+void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, Bvh rxt, const float4* rx_prims,
+                     unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
+void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
+                   unsigned long long* n_cand, long long cap, uint32_t* flags, hipStream_t st);
+void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, hipStream_t st);
+void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st);
+void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
+                 int* cnt, long long n_links, hipStream_t st);
+void link_reduce(const ValidPaths& vp, uint32_t* order, const int* start, const int* cnt, long long n_links, int nf,
+                 double p_tx, double* chan, hipStream_t st);
+void cache_counts(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, long long n_links,
+                  uint32_t* per_link, hipStream_t st);
+void cache_write(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, const uint32_t* off,
+                 long long n_links, KeyRec* cache, hipStream_t st);
+void path_gather(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, long long n_links,
+                 int nf, int cap, int32_t* key, int32_t* tri, double* a, double* tau, double* fd, float* ang,
+                 int32_t* count, hipStream_t st);
+void keys_export(const KeyRec* cache, long long n, int32_t* out, hipStream_t st);
+void keys_import(const int32_t* in, long long n, KeyRec* cache, hipStream_t st);
+
+}  // namespace emrt

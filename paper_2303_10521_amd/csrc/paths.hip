@@ -1,0 +1,706 @@
+// paths.hip -- path cache, exact path validation, field evaluation and the
+// per-receiver channel sums.
+//
+// Section II-A: propagation paths are cached to exploit temporal coherence;
+// Section III-B: valid paths stay in the cache ("visibility hash table") and
+// are deleted once invalid.  Every frame the cached keys (and, on discovery
+// frames, the keys found by the rays) are rebuilt exactly: image method over
+// the face planes for reflections, Keller's law for first-order edge
+// diffraction, float32 shadow rays through the LBVHs for every leg.
+// Fields are evaluated in double (Fresnel reflection of the tracked
+// polarisation, UTD for diffraction), with the delay and the Doppler shift of
+// Section III-C (Eq (3) generalised to moving interaction points) and the
+// power-weighted mean Doppler shift / RMS Doppler spread of Section V-D.
+#include "emrt_dev.h"
+#include "emrt_launch.h"
+
+namespace emrt {
+
+#define GRID_STRIDE(i, n) for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+static int grid_for(long long n, int block = 256, int cap = 8192) {
+    long long g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ------------------------------------------------------------- tables ----
+__global__ void k_cache_insert(unsigned long long* table, unsigned long long mask, const KeyRec* cache,
+                               const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags) {
+    long long n = (long long)*n_cache;
+    if (n > cap) n = cap;
+    GRID_STRIDE(c, n) {
+        KeyRec k = cache[c];
+        uint64_t h = key_hash(k.tx, k.rx, k.to, k.ids);
+        if (table_insert(table, mask, ref_cache((uint32_t)c), k, h, src) < 0) atomicOr(flags, FLAG_TABLE_FULL);
+    }
+}
+
+void cache_insert(unsigned long long* table, unsigned long long mask, const KeyRec* cache,
+                  const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_cache_insert, dim3(grid_for(cap)), dim3(256), 0, st, table, mask, cache, n_cache, cap, src,
+                       flags);
+}
+
+__global__ void __launch_bounds__(256) k_table_compact(const unsigned long long* table, unsigned long long n_slots,
+                                                       KeySrc src, KeyRec* cand, unsigned long long* n_cand,
+                                                       long long cap, uint32_t* flags) {
+    // every lane of a wave runs the same number of iterations (ballot below)
+    unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    unsigned long long start = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long iters = (n_slots + stride - 1) / stride;
+    for (unsigned long long it = 0; it < iters; it++) {
+        unsigned long long i = start + it * stride;
+        unsigned long long ref = i < n_slots ? table[i] : 0ULL;
+        long long pos = wave_append(n_cand, ref != 0ULL);
+        if (pos >= 0) {
+            if (pos < cap) {
+                KeyRec k;
+                expand_ref(ref, src, k);
+                cand[pos] = k;
+            } else {
+                atomicOr(flags, FLAG_CAND_CAP);
+            }
+        }
+    }
+}
+
+void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
+                   unsigned long long* n_cand, long long cap, uint32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_table_compact, dim3(grid_for((long long)n_slots)), dim3(256), 0, st, table, n_slots, src,
+                       cand, n_cand, cap, flags);
+}
+
+// ------------------------------------------------------------ geometry ----
+__device__ __forceinline__ dv3 vert(const SceneDev& s, int v) { return ldf3(s.verts + 3 * (long long)v); }
+
+__device__ __forceinline__ dv3 mirror(dv3 p, const double* pl) {
+    dv3 n = d3(pl[0], pl[1], pl[2]);
+    return p - n * (2.0 * (dot(n, p) - pl[3]));
+}
+
+// point-in-triangle after dropping the dominant normal axis (edges inside)
+__device__ __forceinline__ bool in_tri(dv3 p, dv3 a, dv3 b, dv3 c) {
+    dv3 n = cross(b - a, c - a);
+    double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
+    double P0, P1, A0, A1, B0, B1, C0, C1;
+    if (az >= ax && az >= ay) { P0 = p.x; P1 = p.y; A0 = a.x; A1 = a.y; B0 = b.x; B1 = b.y; C0 = c.x; C1 = c.y; }
+    else if (ay >= ax) { P0 = p.z; P1 = p.x; A0 = a.z; A1 = a.x; B0 = b.z; B1 = b.x; C0 = c.z; C1 = c.x; }
+    else { P0 = p.y; P1 = p.z; A0 = a.y; A1 = a.z; B0 = b.y; B1 = b.z; C0 = c.y; C1 = c.z; }
+    double w0 = (B0 - P0) * (C1 - P1) - (B1 - P1) * (C0 - P0);
+    double w1 = (C0 - P0) * (A1 - P1) - (C1 - P1) * (A0 - P0);
+    double w2 = (A0 - P0) * (B1 - P1) - (A1 - P1) * (B0 - P0);
+    return (w0 >= 0 && w1 >= 0 && w2 >= 0) || (w0 <= 0 && w1 <= 0 && w2 <= 0);
+}
+
+// lowest triangle id of face f containing p, or -1
+__device__ __forceinline__ int face_contains(const SceneDev& s, int f, dv3 p) {
+    int found = -1;
+    for (int q = s.face_off[f]; q < s.face_off[f + 1]; q++) {
+        int t = s.face_tris[q];
+        if (found >= 0 && t > found) break;  // face_tris is sorted by id
+        if (in_tri(p, vert(s, s.tris[3 * t]), vert(s, s.tris[3 * t + 1]), vert(s, s.tris[3 * t + 2]))) found = t;
+    }
+    return found;
+}
+
+// float32 shadow ray over the open segment p0 -> p1
+__device__ __forceinline__ bool occluded(const PathArgs& a, dv3 p0, dv3 p1, int xa, int xb) {
+    dv3 d = p1 - p0;
+    RayPre r = ray_pre((float)p0.x, (float)p0.y, (float)p0.z, (float)d.x, (float)d.y, (float)d.z);
+    if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb)) return true;
+    return any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb);
+}
+
+struct Wedge {
+    dv3 P0, e, t0, n0;
+    double len, n;
+    int f0, fn;
+};
+
+__device__ __forceinline__ Wedge wedge_of(const SceneDev& s, int e) {
+    const int* row = s.edge_i + 6 * (long long)e;
+    Wedge w;
+    w.P0 = vert(s, row[0]);
+    dv3 ev = vert(s, row[1]) - w.P0;
+    w.len = len(ev);
+    w.e = ev * (1.0 / w.len);
+    dv3 r0 = vert(s, row[4]) - w.P0, rn = vert(s, row[5]) - w.P0;
+    w.t0 = unit(r0 - w.e * dot(r0, w.e));
+    dv3 tn = unit(rn - w.e * dot(rn, w.e));
+    dv3 n0 = cross(w.e, w.t0);
+    if (dot(n0, tn) > 0) n0 = n0 * -1.0;
+    w.n0 = n0;
+    w.n = s.edge_n[e];
+    w.f0 = row[2];
+    w.fn = row[3];
+    return w;
+}
+
+__device__ __forceinline__ double wedge_angle(const Wedge& w, dv3 p) {
+    dv3 v = p - w.P0;
+    double ph = atan2(dot(v, w.n0), dot(v, w.t0));
+    if (ph < 0) ph += 2.0 * kPi;
+    return ph;
+}
+
+// Keller point (equal angles with the edge) strictly inside the edge, both
+// ends in the exterior wedge, receiver leg within diff_max_leg.
+__device__ __forceinline__ bool keller(const Wedge& w, dv3 s, dv3 r, double max_leg, dv3& Q) {
+    double zs = dot(s - w.P0, w.e), zr = dot(r - w.P0, w.e);
+    double rs = len(s - w.P0 - w.e * zs), rr = len(r - w.P0 - w.e * zr);
+    if (!(rs + rr > 0)) return false;
+    double zq = zs + (zr - zs) * rs / (rs + rr);
+    if (!(zq > 0.0 && zq < w.len)) return false;
+    Q = w.P0 + w.e * zq;
+    double php = wedge_angle(w, s), ph = wedge_angle(w, r);
+    double lim = w.n * kPi;
+    if (!(php > 0 && php < lim && ph > 0 && ph < lim)) return false;
+    return len(Q - r) <= max_leg;
+}
+
+// -------------------------------------------------------- diffraction ----
+__global__ void __launch_bounds__(128) k_diff_cand(PathArgs a, const uint32_t* illum, int e_words, Bvh rxt,
+                                                   const float4* rx_prims, unsigned long long* table,
+                                                   unsigned long long mask, KeySrc src) {
+    long long n = (long long)a.f.n_tx * a.s.E;
+    GRID_STRIDE(k, n) {
+        int tx = (int)(k / a.s.E), e = (int)(k - (long long)tx * a.s.E);
+        if (!(illum[(long long)tx * e_words + (e >> 5)] & (1u << (e & 31)))) continue;
+        Wedge w = wedge_of(a.s, e);
+        dv3 s = ldd3(a.f.tx_pos + 3 * tx);
+        dv3 P1 = w.P0 + w.e * w.len;
+        float g = (float)a.diff_max_leg + 1.0f;
+        float qlx = (float)fmin(w.P0.x, P1.x) - g, qly = (float)fmin(w.P0.y, P1.y) - g, qlz = (float)fmin(w.P0.z, P1.z) - g;
+        float qhx = (float)fmax(w.P0.x, P1.x) + g, qhy = (float)fmax(w.P0.y, P1.y) + g, qhz = (float)fmax(w.P0.z, P1.z) + g;
+        box_query(rxt, qlx, qly, qlz, qhx, qhy, qhz, [&](int slot) {
+            int rx = __float_as_int(rx_prims[slot].w);
+            dv3 r = ldd3(a.f.rx_pos + 3 * rx);
+            dv3 Q;
+            if (!keller(w, s, r, a.diff_max_leg, Q)) return;
+            KeyRec key;
+            key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
+            key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
+            uint64_t h = key_hash(key.tx, key.rx, key.to, key.ids);
+            if (table_insert(table, mask, ref_diff(tx, e, rx), key, h, src) < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
+        });
+    }
+}
+
+void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, Bvh rxt, const float4* rx_prims,
+                     unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st) {
+    long long n = (long long)a.f.n_tx * a.s.E;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_diff_cand, dim3(grid_for(n, 128)), dim3(128), 0, st, a, illum, e_words, rxt, rx_prims, table,
+                       mask, src);
+}
+
+// -------------------------------------------------------------- fields ----
+// Fresnel reflection coefficients for relative permittivity eps (eps' - j eps'',
+// time factor exp(+j w t)) at incidence cosine c, principal square root.
+__device__ __forceinline__ void fresnel(cd eps, double c, cd& te, cd& tm) {
+    cd rt = csqrtd(eps - C(1.0 - c * c));
+    te = cdiv(C(c) - rt, C(c) + rt);
+    cd ec = eps * c;
+    tm = cdiv(ec - rt, ec + rt);
+}
+
+// erfcx(w) = exp(w^2) erfc(w) on w = exp(j pi/4) v, v >= 0: power series of
+// erf for v < 2.5 (Abramowitz & Stegun 7.1.5), Laplace continued fraction
+// (A&S 7.1.14) by the modified Lentz method otherwise.
+__device__ cd erfcx_diag(double v) {
+    const double h = 0.70710678118654752440;
+    cd w = C(v * h, v * h);
+    if (v < 2.5) {
+        cd w2 = w * w;
+        cd term = w, sum = w;
+        for (int n = 1; n < 400; n++) {
+            term = term * (w2 * (-1.0 / (double)n));
+            cd add = term * (1.0 / (double)(2 * n + 1));
+            sum = sum + add;
+            if (cabsd(add) < 1e-18 * (cabsd(sum) + 1e-300)) break;
+        }
+        cd erfc_w = C(1.0) - sum * (2.0 / sqrt(kPi));
+        return cexpi(v * v) * erfc_w;  // exp(w^2), w^2 = j v^2
+    }
+    const double tiny = 1e-300;
+    cd f = w, Cc = w, D = C(0.0);
+    for (int n = 1; n < 5000; n++) {
+        double an = 0.5 * n;
+        D = w + D * an;
+        if (cabsd(D) < tiny) D = C(tiny);
+        Cc = w + cdiv(C(an), Cc);
+        if (cabsd(Cc) < tiny) Cc = C(tiny);
+        D = cdiv(C(1.0), D);
+        cd delta = Cc * D;
+        f = f * delta;
+        if (cabsd(delta - C(1.0)) < 1e-16) break;
+    }
+    return cdiv(C(1.0), f * sqrt(kPi));
+}
+
+// UTD transition function F(X) = e^{j pi/4} sqrt(pi X) erfcx(e^{j pi/4} sqrt X)
+// (Kouyoumjian & Pathak 1974), X >= 0.
+__device__ cd utd_F(double X) {
+    if (X <= 0) return C(0.0);
+    const double h = 0.70710678118654752440;
+    return C(h, h) * erfcx_diag(sqrt(X)) * sqrt(kPi * X);
+}
+
+// cot((pi + sg beta)/(2n)) F(kL a^{sg}(beta)), with the boundary limit
+// n e^{j pi/4} [sqrt(2 pi kL) sgn(eps) - 2 kL eps e^{j pi/4}] for |eps| < 1e-4.
+__device__ cd utd_term(double sg, double beta, double n, double kL) {
+    double N = rint((beta + sg * kPi) / (2.0 * kPi * n));
+    double eps = kPi + sg * (beta - 2.0 * kPi * n * N);
+    const double h = 0.70710678118654752440;
+    if (fabs(eps) < 1e-4) {
+        double sgn = eps > 0 ? 1.0 : (eps < 0 ? -1.0 : 0.0);
+        cd e4 = C(h, h);
+        return e4 * (C(sqrt(2.0 * kPi * kL) * sgn) - e4 * (2.0 * kL * eps)) * n;
+    }
+    double c = cos((2.0 * kPi * n * N - beta) * 0.5);
+    double x = (kPi + sg * beta) / (2.0 * n);
+    return utd_F(kL * 2.0 * c * c) * (cos(x) / sin(x));
+}
+
+// Kouyoumjian-Pathak coefficient with the Luebbers lossy-face factors
+// (R_0 of the 0-face at incidence cosine sin(beta0)|sin phi'|, R_n of the
+// n-face at sin(beta0)|sin(n pi - phi)|; TE for soft, TM for hard).
+__device__ void utd_D(double n, double k, double L, double beta0, double php, double ph, cd eps0, cd epsn, cd& Ds,
+                      cd& Dh) {
+    double sb = sin(beta0);
+    const double h = 0.70710678118654752440;
+    cd Cc = C(-h, h) * (1.0 / (2.0 * n * sqrt(2.0 * kPi * k) * sb));  // -e^{-j pi/4} / (...)
+    double kL = k * L;
+    cd t1 = utd_term(+1, ph - php, n, kL);
+    cd t2 = utd_term(-1, ph - php, n, kL);
+    cd t3 = utd_term(+1, ph + php, n, kL);
+    cd t4 = utd_term(-1, ph + php, n, kL);
+    cd r0te, r0tm, rnte, rntm;
+    fresnel(eps0, sb * fabs(sin(php)), r0te, r0tm);
+    fresnel(epsn, sb * fabs(sin(n * kPi - ph)), rnte, rntm);
+    Ds = Cc * (t1 + t2 + rnte * t3 + r0te * t4);
+    Dh = Cc * (t1 + t2 + rntm * t3 + r0tm * t4);
+}
+
+// transmit / receive polarisation: vertical iso (mode 0) or short dipole along
+// (theta, phi) (mode 1)
+__device__ __forceinline__ dv3 antenna(int mode, dv3 k, double th, double ph) {
+    if (mode == 1) {
+        double st, ct, sp, cp;
+        sincos(th, &st, &ct);
+        sincos(ph, &sp, &cp);
+        dv3 u = d3(st * cp, st * sp, ct);
+        return (u - k * dot(u, k)) * sqrt(1.5);
+    }
+    dv3 e = d3(0, 0, 1) - k * k.z;
+    if (len(e) < 1e-12) e = d3(1, 0, 0) - k * k.x;
+    return unit(e);
+}
+
+__device__ __forceinline__ cd phase(double L, double lam) {
+    double x = L / lam;
+    return cexpi(-2.0 * kPi * (x - rint(x)));
+}
+
+struct CV { cd x, y, z; };
+__device__ __forceinline__ cd cdot(dv3 a, const CV& b) { return b.x * a.x + b.y * a.y + b.z * a.z; }
+
+__global__ void __launch_bounds__(128) k_validate(PathArgs a, long long n_links, long long cap_cand) {
+    long long nc = (long long)*a.n_cand;
+    if (nc > cap_cand) nc = cap_cand;
+    long long n = n_links + nc;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long iters = (n + stride - 1) / stride;
+    const SceneDev& S = a.s;
+    for (long long it = 0; it < iters; it++) {
+        long long q = start + it * stride;
+        bool ok = q < n;
+        KeyRec key;
+        if (ok) {
+            if (q < n_links) {
+                key.tx = (int)(q / a.f.n_rx);
+                key.rx = (int)(q - (long long)key.tx * a.f.n_rx);
+                key.to = KT_LOS;
+                for (int j = 0; j < 5; j++) key.ids[j] = -1;
+            } else {
+                key = a.cand[q - n_links];
+            }
+        }
+        int type = key.to & 0xff, order = key.to >> 8;
+        if (ok) {
+            // keys may come from an imported cache: reject anything out of range
+            bool good = key.tx >= 0 && key.tx < a.f.n_tx && key.rx >= 0 && key.rx < a.f.n_rx;
+            if (type == KT_SPEC) {
+                good = good && order >= 1 && order <= EMRT_KMAX;
+                for (int j = 0; j < EMRT_KMAX; j++)
+                    if (j < order && !(key.ids[j] >= 0 && key.ids[j] < S.F)) good = false;
+            } else if (type == KT_DIFF) {
+                good = good && order == 1 && key.ids[0] >= 0 && key.ids[0] < S.E;
+            } else if (type != KT_LOS) {
+                good = false;
+            }
+            ok = good;
+        }
+        dv3 s = ok ? ldd3(a.f.tx_pos + 3 * key.tx) : d3(0, 0, 0);
+        dv3 r = ok ? ldd3(a.f.rx_pos + 3 * key.rx) : d3(0, 0, 1);
+        dv3 P[7];
+        int tri[5] = {-1, -1, -1, -1, -1};
+        int np = 0;
+        Wedge w;
+        if (ok) {
+            if (type == KT_LOS) {
+                P[0] = s; P[1] = r; np = 2;
+                if (occluded(a, s, r, -1, -1)) ok = false;
+            } else if (type == KT_SPEC) {
+                dv3 img[6];
+                img[0] = s;
+                for (int i = 1; i <= order; i++) img[i] = mirror(img[i - 1], S.plane + 4 * (long long)key.ids[i - 1]);
+                dv3 cur = r;
+                for (int i = order; i >= 1 && ok; i--) {
+                    const double* pl = S.plane + 4 * (long long)key.ids[i - 1];
+                    dv3 nrm = d3(pl[0], pl[1], pl[2]);
+                    dv3 dv = img[i] - cur;
+                    double den = dot(nrm, dv);
+                    if (den == 0.0) { ok = false; break; }
+                    double tt = (pl[3] - dot(nrm, cur)) / den;
+                    if (!(tt > 0.0 && tt < 1.0)) { ok = false; break; }
+                    cur = cur + dv * tt;
+                    P[i] = cur;
+                    int t = face_contains(S, key.ids[i - 1], cur);
+                    if (t < 0) { ok = false; break; }
+                    tri[i - 1] = t;
+                }
+                if (ok) {
+                    P[0] = s;
+                    P[order + 1] = r;
+                    np = order + 2;
+                    for (int i = 0; i <= order && ok; i++) {
+                        int xa = i >= 1 ? key.ids[i - 1] : -1;
+                        int xb = i + 1 <= order ? key.ids[i] : -1;
+                        if (occluded(a, P[i], P[i + 1], xa, xb)) ok = false;
+                    }
+                }
+            } else if (type == KT_DIFF) {
+                w = wedge_of(S, key.ids[0]);
+                dv3 Q;
+                if (!keller(w, s, r, a.diff_max_leg, Q)) ok = false;
+                else {
+                    P[0] = s; P[1] = Q; P[2] = r; np = 3;
+                    if (occluded(a, s, Q, w.f0, w.fn) || occluded(a, Q, r, w.f0, w.fn)) ok = false;
+                }
+            }
+        }
+        long long pos = wave_append(a.out.count, ok);
+        if (!ok) continue;
+        if (pos >= a.out.cap) { atomicOr(a.flags, FLAG_PATH_CAP); continue; }
+        // ------------------------------------------------------- fields
+        dv3 vt = ldd3(a.f.tx_vel + 3 * key.tx), vr = ldd3(a.f.rx_vel + 3 * key.rx);
+        double th = a.f.tx_orient[2 * key.tx], phi = a.f.tx_orient[2 * key.tx + 1];
+        dv3 kk[6];
+        double L = 0.0;
+        for (int i = 0; i + 1 < np; i++) {
+            dv3 dv = P[i + 1] - P[i];
+            double l = len(dv);
+            L += l;
+            kk[i] = dv * (1.0 / l);
+        }
+        dv3 k0 = kk[0], kK = kk[np - 2];
+        double dop = dot(kK, vr) - dot(k0, vt);
+        cd amp[EMRT_NF];
+        if (type != KT_DIFF) {
+            for (int i = 1; i + 1 < np; i++) {
+                int od = S.face_dyn[key.ids[i - 1]];
+                if (od >= 0) dop += dot(kk[i - 1] - kk[i], ldd3(a.f.obj_vel + 3 * (long long)od));
+            }
+            dv3 e0 = antenna(a.ant_mode, k0, th, phi);
+            dv3 er = antenna(0, kK, 0, 0);
+            for (int fi = 0; fi < a.nf; fi++) {
+                double lam = kC0 / a.freq[fi];
+                CV E = {C(e0.x), C(e0.y), C(e0.z)};
+                for (int i = 1; i + 1 < np; i++) {
+                    int f = key.ids[i - 1];
+                    const double* pl = S.plane + 4 * (long long)f;
+                    dv3 nrm = d3(pl[0], pl[1], pl[2]);
+                    dv3 ki = kk[i - 1], ko = kk[i];
+                    if (dot(nrm, ki) > 0) nrm = nrm * -1.0;
+                    double c = -dot(ki, nrm);
+                    dv3 sv = cross(ki, nrm);
+                    if (len(sv) < 1e-12) {
+                        sv = cross(nrm, d3(0, 0, 1));
+                        if (len(sv) < 1e-12) sv = cross(nrm, d3(1, 0, 0));
+                    }
+                    sv = unit(sv);
+                    dv3 pin = cross(sv, ki), pout = cross(sv, ko);
+                    int m = S.face_material[f];
+                    cd te, tm;
+                    fresnel(C(a.mat_eps[2 * m], a.mat_eps[2 * m + 1]), c, te, tm);
+                    cd es = cdot(sv, E) * te, ep = cdot(pin, E) * tm;
+                    E.x = es * sv.x + ep * pout.x;
+                    E.y = es * sv.y + ep * pout.y;
+                    E.z = es * sv.z + ep * pout.z;
+                }
+                amp[fi] = cdot(er, E) * phase(L, lam) * (lam / (4.0 * kPi * L));
+            }
+        } else {
+            int od = S.face_dyn[w.f0];
+            if (od >= 0) dop += dot(kk[0] - kk[1], ldd3(a.f.obj_vel + 3 * (long long)od));
+            double sp = len(P[1] - P[0]), sd = len(P[2] - P[1]);
+            dv3 si = kk[0], so = kk[1];
+            double cb = fmin(1.0, fmax(-1.0, dot(si, w.e)));
+            double beta0 = acos(cb);
+            double php = wedge_angle(w, s), ph = wedge_angle(w, r);
+            double sb = sin(beta0);
+            double Lp = sd * sp * sb * sb / (sd + sp);
+            dv3 fp = unit(cross(w.e, si)) * -1.0, bp = cross(fp, si);
+            dv3 fo = unit(cross(w.e, so)), bo = cross(fo, so);
+            int m0 = S.face_material[w.f0], mn = S.face_material[w.fn];
+            dv3 et = antenna(a.ant_mode, si, th, phi);
+            dv3 er = antenna(0, so, 0, 0);
+            double spread = (1.0 / sp) * sqrt(sp / (sd * (sd + sp)));
+            for (int fi = 0; fi < a.nf; fi++) {
+                double lam = kC0 / a.freq[fi];
+                double k = 2.0 * kPi / lam;
+                cd Ds, Dh;
+                utd_D(w.n, k, Lp, beta0, php, ph, C(a.mat_eps[2 * m0], a.mat_eps[2 * m0 + 1]),
+                      C(a.mat_eps[2 * mn], a.mat_eps[2 * mn + 1]), Ds, Dh);
+                cd fld = Ds * (-dot(er, bo) * dot(bp, et)) - Dh * (dot(er, fo) * dot(fp, et));
+                amp[fi] = fld * phase(L, lam) * (lam / (4.0 * kPi) * spread);
+            }
+        }
+        ValidPaths& o = a.out;
+        o.key[pos] = key;
+        for (int j = 0; j < 5; j++) o.tri[5 * pos + j] = tri[j];
+        for (int fi = 0; fi < a.nf; fi++) {
+            double lam = kC0 / a.freq[fi];
+            o.a[2 * (pos * a.nf + fi)] = amp[fi].re;
+            o.a[2 * (pos * a.nf + fi) + 1] = amp[fi].im;
+            o.fd[pos * a.nf + fi] = -dop / lam;
+        }
+        o.tau[pos] = L / kC0;
+        float aod_az = (float)atan2(k0.y, k0.x), aod_el = (float)asin(fmin(1.0, fmax(-1.0, k0.z)));
+        float aoa_az = (float)atan2(-kK.y, -kK.x), aoa_el = (float)asin(fmin(1.0, fmax(-1.0, -kK.z)));
+        o.ang[pos] = make_float4(aod_az, aod_el, aoa_az, aoa_el);
+    }
+}
+
+void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, hipStream_t st) {
+    long long n = n_links + cap_cand;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
+}
+
+// ----------------------------------------------------------- per link ----
+__global__ void k_link_keys(ValidPaths vp, int n_rx, unsigned long long* keys, uint32_t* vals) {
+    long long n = (long long)*vp.count;
+    if (n > vp.cap) n = vp.cap;
+    GRID_STRIDE(i, n) {
+        KeyRec k = vp.key[i];
+        keys[i] = (unsigned long long)((long long)k.tx * n_rx + k.rx);
+        vals[i] = (uint32_t)i;
+    }
+}
+
+void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st) {
+    hipLaunchKernelGGL(k_link_keys, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, n_rx, keys, vals);
+}
+
+__global__ void k_link_init(int* start, int* end, long long n_links) {
+    GRID_STRIDE(i, n_links) { start[i] = -1; end[i] = -1; }
+}
+
+__global__ void k_link_ranges(const unsigned long long* key, const unsigned long long* n_dev, long long cap, int* start,
+                              int* end) {
+    long long n = (long long)*n_dev;
+    if (n > cap) n = cap;
+    GRID_STRIDE(i, n) {
+        unsigned long long L = key[i];
+        if (i == 0 || key[i - 1] != L) start[L] = (int)i;
+        if (i == n - 1 || key[i + 1] != L) end[L] = (int)(i + 1);
+    }
+}
+
+void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
+                 int* end, long long n_links, hipStream_t st) {
+    hipLaunchKernelGGL(k_link_init, dim3(grid_for(n_links)), dim3(256), 0, st, start, end, n_links);
+    hipLaunchKernelGGL(k_link_ranges, dim3(grid_for(cap)), dim3(256), 0, st, sorted_keys, n, cap, start, end);
+}
+
+// One thread per link: order the link's paths by key (insertion sort; the
+// sums then run in a fixed order, so results are bit-reproducible), then
+//   H = sum a, P_coh = P_tx |H|^2, P_inc = P_tx sum |a|^2,
+//   power-weighted mean and RMS of delay and Doppler (weights |a|^2).
+// chan[(f * n_links + link) * 8 + {H.re, H.im, P_coh, P_inc, tau_mean,
+// tau_rms, fd_mean, fd_rms}]; chan_i[link * 2 + {n_paths, los}].
+__global__ void k_link_reduce(ValidPaths vp, uint32_t* order, const int* start, const int* end, long long n_links,
+                              int nf, double p_tx, double* chan, int* chan_i) {
+    GRID_STRIDE(Lk, n_links) {
+        int s = start[Lk], e = end[Lk];
+        if (s < 0) {
+            for (int f = 0; f < nf; f++)
+                for (int c = 0; c < 8; c++) chan[((long long)f * n_links + Lk) * 8 + c] = 0.0;
+            chan_i[2 * Lk] = 0;
+            chan_i[2 * Lk + 1] = 0;
+            continue;
+        }
+        for (int i = s + 1; i < e; i++) {
+            uint32_t v = order[i];
+            KeyRec kv = vp.key[v];
+            int j = i - 1;
+            while (j >= s && key_less(kv, vp.key[order[j]])) {
+                order[j + 1] = order[j];
+                j--;
+            }
+            order[j + 1] = v;
+        }
+        int los = (vp.key[order[s]].to & 0xff) == KT_LOS ? 1 : 0;
+        for (int f = 0; f < nf; f++) {
+            double hr = 0, hi = 0, sw = 0, st_ = 0, sf = 0;
+            for (int i = s; i < e; i++) {
+                long long p = order[i];
+                double ar = vp.a[2 * (p * nf + f)], ai = vp.a[2 * (p * nf + f) + 1];
+                double wgt = ar * ar + ai * ai;
+                hr += ar;
+                hi += ai;
+                sw += wgt;
+                st_ += wgt * vp.tau[p];
+                sf += wgt * vp.fd[p * nf + f];
+            }
+            double tm = sw > 0 ? st_ / sw : 0.0, fm = sw > 0 ? sf / sw : 0.0;
+            double vt = 0, vf = 0;
+            for (int i = s; i < e; i++) {
+                long long p = order[i];
+                double ar = vp.a[2 * (p * nf + f)], ai = vp.a[2 * (p * nf + f) + 1];
+                double wgt = ar * ar + ai * ai;
+                double dt = vp.tau[p] - tm, df = vp.fd[p * nf + f] - fm;
+                vt += wgt * dt * dt;
+                vf += wgt * df * df;
+            }
+            double* c = chan + ((long long)f * n_links + Lk) * 8;
+            c[0] = hr;
+            c[1] = hi;
+            c[2] = p_tx * (hr * hr + hi * hi);
+            c[3] = p_tx * sw;
+            c[4] = tm;
+            c[5] = sw > 0 ? sqrt(vt / sw) : 0.0;
+            c[6] = fm;
+            c[7] = sw > 0 ? sqrt(vf / sw) : 0.0;
+        }
+        chan_i[2 * Lk] = e - s;
+        chan_i[2 * Lk + 1] = los;
+    }
+}
+
+void link_reduce(const ValidPaths& vp, uint32_t* order, const int* start, const int* end, long long n_links, int nf,
+                 double p_tx, double* chan, hipStream_t st) {
+    int* chan_i = (int*)(chan + (long long)nf * n_links * 8);
+    hipLaunchKernelGGL(k_link_reduce, dim3(grid_for(n_links, 128)), dim3(128), 0, st, vp, order, start, end, n_links,
+                       nf, p_tx, chan, chan_i);
+}
+
+__global__ void k_cache_counts(ValidPaths vp, const uint32_t* order, const int* start, const int* end,
+                               long long n_links, uint32_t* per_link) {
+    GRID_STRIDE(Lk, n_links) {
+        int s = start[Lk], e = end[Lk];
+        uint32_t c = 0;
+        if (s >= 0) {
+            c = (uint32_t)(e - s);
+            if ((vp.key[order[s]].to & 0xff) == KT_LOS) c--;
+        }
+        per_link[Lk] = c;
+    }
+}
+
+void cache_counts(const ValidPaths& vp, const uint32_t* order, const int* start, const int* end, long long n_links,
+                  uint32_t* per_link, hipStream_t st) {
+    hipLaunchKernelGGL(k_cache_counts, dim3(grid_for(n_links)), dim3(256), 0, st, vp, order, start, end, n_links,
+                       per_link);
+}
+
+__global__ void k_cache_write(ValidPaths vp, const uint32_t* order, const int* start, const int* end,
+                              const uint32_t* off, long long n_links, KeyRec* cache) {
+    GRID_STRIDE(Lk, n_links) {
+        int s = start[Lk], e = end[Lk];
+        if (s < 0) continue;
+        uint32_t o = off[Lk];
+        for (int i = s; i < e; i++) {
+            KeyRec k = vp.key[order[i]];
+            if ((k.to & 0xff) == KT_LOS) continue;
+            cache[o++] = k;
+        }
+    }
+}
+
+void cache_write(const ValidPaths& vp, const uint32_t* order, const int* start, const int* end, const uint32_t* off,
+                 long long n_links, KeyRec* cache, hipStream_t st) {
+    hipLaunchKernelGGL(k_cache_write, dim3(grid_for(n_links)), dim3(256), 0, st, vp, order, start, end, off, n_links,
+                       cache);
+}
+
+__global__ void k_path_gather(ValidPaths vp, const uint32_t* order, const int* start, const int* end,
+                              long long n_links, int nf, int cap, int32_t* key, int32_t* tri, double* a, double* tau,
+                              double* fd, float* ang, int32_t* count) {
+    GRID_STRIDE(Lk, n_links) {
+        int s = start[Lk], e = end[Lk];
+        int n = s < 0 ? 0 : e - s;
+        int m = n < cap ? n : cap;
+        if (count) count[Lk] = m;
+        for (int j = 0; j < m; j++) {
+            long long p = order[s + j];
+            long long o = Lk * cap + j;
+            KeyRec k = vp.key[p];
+            if (key) {
+                int32_t* kr = key + 9 * o;
+                kr[0] = k.tx; kr[1] = k.rx; kr[2] = k.to & 0xff; kr[3] = k.to >> 8;
+                for (int q = 0; q < 5; q++) kr[4 + q] = k.ids[q];
+            }
+            if (tri) for (int q = 0; q < 5; q++) tri[5 * o + q] = vp.tri[5 * p + q];
+            if (a) for (int f = 0; f < nf; f++) {
+                a[2 * (o * nf + f)] = vp.a[2 * (p * nf + f)];
+                a[2 * (o * nf + f) + 1] = vp.a[2 * (p * nf + f) + 1];
+            }
+            if (tau) tau[o] = vp.tau[p];
+            if (fd) for (int f = 0; f < nf; f++) fd[o * nf + f] = vp.fd[p * nf + f];
+            if (ang) {
+                float4 g = vp.ang[p];
+                ang[4 * o] = g.x; ang[4 * o + 1] = g.y; ang[4 * o + 2] = g.z; ang[4 * o + 3] = g.w;
+            }
+        }
+    }
+}
+
+void path_gather(const ValidPaths& vp, const uint32_t* order, const int* start, const int* end, long long n_links,
+                 int nf, int cap, int32_t* key, int32_t* tri, double* a, double* tau, double* fd, float* ang,
+                 int32_t* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_path_gather, dim3(grid_for(n_links)), dim3(256), 0, st, vp, order, start, end, n_links, nf,
+                       cap, key, tri, a, tau, fd, ang, count);
+}
+
+__global__ void k_keys_export(const KeyRec* c, long long n, int32_t* out) {
+    GRID_STRIDE(i, n) {
+        KeyRec k = c[i];
+        int32_t* r = out + 9 * i;
+        r[0] = k.tx; r[1] = k.rx; r[2] = k.to & 0xff; r[3] = k.to >> 8;
+        for (int q = 0; q < 5; q++) r[4 + q] = k.ids[q];
+    }
+}
+
+__global__ void k_keys_import(const int32_t* in, long long n, KeyRec* c) {
+    GRID_STRIDE(i, n) {
+        const int32_t* r = in + 9 * i;
+        KeyRec k;
+        k.tx = r[0]; k.rx = r[1]; k.to = r[2] | (r[3] << 8);
+        for (int q = 0; q < 5; q++) k.ids[q] = r[4 + q];
+        c[i] = k;
+    }
+}
+
+void keys_export(const KeyRec* cache, long long n, int32_t* out, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_keys_export, dim3(grid_for(n)), dim3(256), 0, st, cache, n, out);
+}
+void keys_import(const int32_t* in, long long n, KeyRec* cache, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_keys_import, dim3(grid_for(n)), dim3(256), 0, st, in, n, cache);
+}
+
+}  // namespace emrt

@@ -1,0 +1,260 @@
+// trace.hip -- shooting and bouncing rays from the transmitters.
+//
+// Section II-A: the engine traces direct, reflected and diffracted rays
+// through a BVH and caches the propagation paths it finds.  Here each
+// transmitter launches N rays on a Fibonacci sphere; every bounce is one
+// launch of k_bounce, a persistent kernel whose waves pull 64-ray chunks
+// from a device counter.  Per ray and bounce it
+//   1. finds the closest hit in the static and the dynamic LBVH (stackless,
+//      near child first, watertight triangle test, previous face excluded,
+//      ties to the lowest triangle id),
+//   2. records the hit triangle in the per-bounce hit log,
+//   3. captures receivers whose reception sphere (radius k alpha (L + s),
+//      alpha = sqrt(4 pi / N)) the segment crosses, inserting the path key
+//      (tx, rx, face sequence) into the lock-free path table,
+//   4. on the first segment, marks wedge edges that the ray passes within
+//      k alpha s of (diffraction candidates),
+//   5. reflects specularly and appends the surviving ray to the next
+//      bounce's buffer with one atomic per wave (ballot + mbcnt prefix).
+#include "emrt_dev.h"
+#include "emrt_launch.h"
+
+namespace emrt {
+
+__device__ __forceinline__ void fib_dir(long long i, int N, float& x, float& y, float& z) {
+    const double ga = kPi * (3.0 - sqrt(5.0));
+    double zz = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
+    double r = sqrt(1.0 - zz * zz);
+    double ph = (double)i * ga;
+    double s, c;
+    sincos(ph, &s, &c);
+    x = (float)(r * c);
+    y = (float)(r * s);
+    z = (float)zz;
+}
+
+// Morton code of each launch direction, so that neighbouring threads trace
+// neighbouring directions (the launch index still identifies the ray).
+__global__ void k_dir_codes(int N, unsigned long long* codes, uint32_t* vals) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float x, y, z;
+    fib_dir(i, N, x, y, z);
+    auto q = [](float v) { return (uint32_t)(fminf(fmaxf(0.5f * (v + 1.0f), 0.0f), 1.0f) * 2097151.0f); };
+    auto split3 = [](uint32_t a) {
+        unsigned long long x = a & 0x1fffffu;
+        x = (x | x << 32) & 0x1f00000000ffffULL;
+        x = (x | x << 16) & 0x1f0000ff0000ffULL;
+        x = (x | x << 8) & 0x100f00f00f00f00fULL;
+        x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+        x = (x | x << 2) & 0x1249249249249249ULL;
+        return x;
+    };
+    codes[i] = (split3(q(x)) << 2) | (split3(q(y)) << 1) | split3(q(z));
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_copy_perm(const uint32_t* in, uint32_t* out, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+void ray_order(int N, uint32_t* perm, const BuildTemp& tmp, hipStream_t st) {
+    int g = (N + 255) / 256;
+    hipLaunchKernelGGL(k_dir_codes, dim3(g), dim3(256), 0, st, N, tmp.k0, tmp.v0);
+    int which = radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, nullptr, N, 63, tmp.radix, st);
+    hipLaunchKernelGGL(k_copy_perm, dim3(g), dim3(256), 0, st, which ? tmp.v1 : tmp.v0, perm, N);
+}
+
+__global__ void __launch_bounds__(256) k_raygen(const double* tx_pos, int n_tx, int N, const uint32_t* perm,
+                                                RaySoA out, unsigned long long* n_out) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)n_tx * N;
+    if (k == 0) *n_out = (unsigned long long)total;
+    if (k >= total) return;
+    int tx = (int)(k / N);
+    int t = (int)(k - (long long)tx * N);
+    uint32_t i = perm[t];
+    float x, y, z;
+    fib_dir(i, N, x, y, z);
+    out.ox[k] = (float)tx_pos[3 * tx];
+    out.oy[k] = (float)tx_pos[3 * tx + 1];
+    out.oz[k] = (float)tx_pos[3 * tx + 2];
+    out.dx[k] = x;
+    out.dy[k] = y;
+    out.dz[k] = z;
+    out.L[k] = 0.0f;
+    out.id[k] = (uint32_t)tx * (uint32_t)N + i;
+    out.prev[k] = -1;
+}
+
+void raygen(const double* tx_pos, int n_tx, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
+            hipStream_t st) {
+    long long total = (long long)n_tx * N;
+    long long g = (total + 255) / 256;
+    hipLaunchKernelGGL(k_raygen, dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, st, tx_pos, n_tx, N, perm, out, n_out);
+}
+
+// far bound of the distance from o to any point of a tree's root box
+__device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, float oz) {
+    BNode nd = t.nodes[0];
+    float lx = fminf(nd.a.x, nd.b.z), ly = fminf(nd.a.y, nd.b.w), lz = fminf(nd.a.z, nd.c.x);
+    float hx = fmaxf(nd.a.w, nd.c.y), hy = fmaxf(nd.b.x, nd.c.z), hz = fmaxf(nd.b.y, nd.c.w);
+    float dx = fmaxf(fabsf(lx - ox), fabsf(hx - ox));
+    float dy = fmaxf(fabsf(ly - oy), fabsf(hy - oy));
+    float dz = fmaxf(fabsf(lz - oz), fabsf(hz - oz));
+    return sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1.0f;
+}
+
+template <bool STATS>
+__global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
+    const int lane = lane_id();
+    const unsigned long long n_in = *a.n_in;
+    const int b = a.b;
+    unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
+    while (true) {
+        unsigned int chunk = 0;
+        if (lane == 0) chunk = atomicAdd(a.work, 1u);
+        chunk = __shfl(chunk, 0);
+        unsigned long long base = (unsigned long long)chunk * 64ULL;
+        if (base >= n_in) break;
+        unsigned long long i = base + (unsigned long long)lane;
+        bool act = i < n_in;
+        float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, L = 0;
+        uint32_t id = 0;
+        int prev = -1;
+        if (act) {
+            ox = a.in.ox[i]; oy = a.in.oy[i]; oz = a.in.oz[i];
+            dx = a.in.dx[i]; dy = a.in.dy[i]; dz = a.in.dz[i];
+            L = a.in.L[i];
+            id = a.in.id[i];
+            prev = a.in.prev[i];
+        }
+        RayPre r = ray_pre(ox, oy, oz, dx, dy, dz);
+        float best_t = INFINITY;
+        int best_tri = 0x7FFFFFFF, best_face = -1;
+        if (act) {
+            if (STATS) s_seg++;
+            closest_hit<STATS>(a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
+            closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
+        }
+        bool hit = act && best_tri != 0x7FFFFFFF;
+        if (act) a.hitlog[(long long)b * a.n_total + id] = hit ? best_tri : -1;
+        float t_end = hit ? best_t : INFINITY;
+
+        // receiver capture on segments after at least one reflection
+        if (act && b >= 1 && a.rxt.n_prims > 0) {
+            float tcap = fminf(t_end, root_far(a.rxt, ox, oy, oz));
+            float grow = a.alpha_k * (L + tcap);
+            KeyRec mine;
+            bool have = false;
+            uint64_t h = 0;
+            all_hits(a.rxt, r, tcap, grow, [&](int slot) {
+                float4 p = a.rx_prims[slot];
+                float wx = p.x - ox, wy = p.y - oy, wz = p.z - oz;
+                float s = wx * dx + wy * dy + wz * dz;
+                if (!(s > 0.0f && s < t_end)) return;
+                float rho2 = wx * wx + wy * wy + wz * wz - s * s;
+                float rs = a.alpha_k * (L + s);
+                if (!(rho2 < rs * rs)) return;
+                int rx = __float_as_int(p.w);
+                if (!have) {
+                    mine.tx = (int)(id / (uint32_t)a.rays_per_tx);
+                    mine.to = KT_SPEC | (b << 8);
+                    for (int j = 0; j < 5; j++)
+                        mine.ids[j] = j < b ? a.src.tri_face[a.hitlog[(long long)j * a.n_total + id]] : -1;
+                    have = true;
+                }
+                mine.rx = rx;
+                h = key_hash(mine.tx, mine.rx, mine.to, mine.ids);
+                int res = table_insert(a.table, a.mask, ref_ray(b, rx, id), mine, h, a.src);
+                if (res < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
+                if (STATS) s_cap++;
+            });
+        }
+
+        // edge capture on the first segment
+        if (act && b == 0 && a.diffraction && a.edt.n_prims > 0) {
+            float tcap = fminf(t_end, root_far(a.edt, ox, oy, oz));
+            float grow = a.alpha_k * tcap;
+            int tx = (int)(id / (uint32_t)a.rays_per_tx);
+            all_hits(a.edt, r, tcap, grow, [&](int slot) {
+                float4 P0 = a.edge_prims[2 * slot], P1 = a.edge_prims[2 * slot + 1];
+                float ex = P1.x - P0.x, ey = P1.y - P0.y, ez = P1.z - P0.z;
+                float wx = ox - P0.x, wy = oy - P0.y, wz = oz - P0.z;
+                float aa = dx * dx + dy * dy + dz * dz;
+                float bb = dx * ex + dy * ey + dz * ez;
+                float cc = ex * ex + ey * ey + ez * ez;
+                float dd = dx * wx + dy * wy + dz * wz;
+                float ee = ex * wx + ey * wy + ez * wz;
+                float den = aa * cc - bb * bb;
+                if (!(den > 1e-12f * aa * cc)) return;
+                float s = (bb * ee - cc * dd) / den;
+                float u = (aa * ee - bb * dd) / den;
+                if (!(s > 0.0f && s < t_end && u > 0.0f && u < 1.0f)) return;
+                float qx = ox + s * dx - (P0.x + u * ex);
+                float qy = oy + s * dy - (P0.y + u * ey);
+                float qz = oz + s * dz - (P0.z + u * ez);
+                float re = a.alpha_k * s;
+                if (!(qx * qx + qy * qy + qz * qz < re * re)) return;
+                int e = __float_as_int(P0.w);
+                uint32_t* w = a.illum + (long long)tx * a.e_words + (e >> 5);
+                uint32_t bit = 1u << (e & 31);
+                if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(w, bit);
+            });
+        }
+
+        // specular reflection about the face plane
+        bool alive = hit && b < a.K;
+        float nox = 0, noy = 0, noz = 0, ndx = 0, ndy = 0, ndz = 0;
+        if (alive) {
+            const double* pl = a.plane + 4 * (long long)best_face;
+            float nx = (float)pl[0], ny = (float)pl[1], nzv = (float)pl[2];
+            nox = ox + best_t * dx;
+            noy = oy + best_t * dy;
+            noz = oz + best_t * dz;
+            float dn = 2.0f * (dx * nx + dy * ny + dz * nzv);
+            ndx = dx - dn * nx;
+            ndy = dy - dn * ny;
+            ndz = dz - dn * nzv;
+        }
+        long long o = wave_append(a.n_out, alive);
+        if (alive) {
+            a.out.ox[o] = nox; a.out.oy[o] = noy; a.out.oz[o] = noz;
+            a.out.dx[o] = ndx; a.out.dy[o] = ndy; a.out.dz[o] = ndz;
+            a.out.L[o] = L + best_t;
+            a.out.id[o] = id;
+            a.out.prev[o] = best_face;
+        }
+    }
+    if (STATS) {
+        unsigned long long v[4] = {s_nodes, s_tris, s_seg, s_cap};
+        for (int k = 0; k < 4; k++) {
+            unsigned long long x = v[k];
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+            if (lane == 0 && x) atomicAdd(&a.stats[k], x);
+        }
+    }
+}
+
+void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {
+    if (stats) hipLaunchKernelGGL(k_bounce<true>, dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_bounce<false>, dim3(grid), dim3(256), 0, st, a);
+}
+
+__global__ void k_debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ids, int n,
+                             int* out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int i = ids[k];
+    for (int b = 0; b <= K; b++)
+        out[(long long)k * (K + 1) + b] = (i >= 0 && i < N) ? hitlog[(long long)b * n_total + (long long)tx * N + i] : -3;
+}
+
+void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ray_ids, int n, int* out,
+                hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_debug_rays, dim3((n + 255) / 256), dim3(256), 0, st, hitlog, n_total, K, tx, N,
+                                  ray_ids, n, out);
+}
+
+}  // namespace emrt

@@ -1,0 +1,212 @@
+"""Python binding of the emrt C ABI: argument marshalling onto torch device
+tensors.  Every step of the method runs in the HIP library; this module only
+allocates device buffers (torch), passes pointers and reads results back."""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+class EmrtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"emrt status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _dev(a, dtype, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device).contiguous()
+
+
+class Tracer:
+    """One emrt context bound to one scene, n_tx transmitters and n_rx receivers.
+
+    ``scene`` provides ``verts, tris, tri_face, face_object, face_material,
+    object_dynamic, materials`` (numpy or torch); ``config`` keys mirror
+    ``emrt_config`` (freq_hz list, max_reflections, diffraction, rays_per_tx,
+    rx_sphere_k, diff_max_leg_m, tx_power_w, antenna_mode, path_cap_per_link,
+    path_capacity, table_capacity).
+    """
+
+    def __init__(self, scene, n_tx: int, n_rx: int, device: str = "cuda", **config):
+        self.lib = A.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RuntimeError("the emrt library runs on the GPU only")
+        cfg = A.Config()
+        self.lib.emrt_config_default(ctypes.byref(cfg))
+        freqs = list(config.pop("freq_hz", [28e9]))
+        cfg.n_freq = len(freqs)
+        for i, f in enumerate(freqs[:4]):
+            cfg.freq_hz[i] = float(f)
+        for k, v in config.items():
+            if not hasattr(cfg, k):
+                raise TypeError(f"unknown config key {k}")
+            setattr(cfg, k, v)
+        self.cfg = cfg
+        self.freqs = freqs
+        self.n_tx, self.n_rx = int(n_tx), int(n_rx)
+        self.n_links = self.n_tx * self.n_rx
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.emrt_ctx_create(ctypes.byref(cfg), ctypes.byref(ctx)), None)
+        self.ctx = ctx
+        sz = A.Sizes(len(scene.verts), len(scene.tris), len(scene.face_object), len(scene.object_dynamic),
+                     self.n_tx, self.n_rx)
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.emrt_workspace_size(self.ctx, ctypes.byref(sz), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._check(self.lib.emrt_set_stream(self.ctx, ctypes.c_void_p(self.stream.cuda_stream)))
+        self._check(self.lib.emrt_bind_workspace(self.ctx, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
+        self.set_scene(scene)
+        self._frame_refs = None
+
+    # ------------------------------------------------------------------ util
+    def _check(self, st: int, ctx=0) -> int:
+        if st < 0:
+            msg = A.load().emrt_status_string(st).decode()
+            if ctx is not None:
+                buf = ctypes.create_string_buffer(512)
+                self.lib.emrt_last_error(self.ctx, buf, 512)
+                msg = buf.value.decode() or msg
+            raise EmrtError(st, msg)
+        return st
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.emrt_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- scene
+    def set_scene(self, sc) -> None:
+        d = self.device
+        self._scene_refs = dict(
+            verts=_dev(sc.verts, torch.float32, d), tris=_dev(sc.tris, torch.int32, d),
+            tri_face=_dev(sc.tri_face, torch.int32, d), face_object=_dev(sc.face_object, torch.int32, d),
+            face_material=_dev(sc.face_material, torch.int32, d), object_dynamic=_dev(sc.object_dynamic, torch.uint8, d),
+        )
+        mats = np.asarray(sc.materials, np.complex128)
+        self._mat_host = np.ascontiguousarray(np.stack([mats.real, mats.imag], 1), np.float64)
+        r = self._scene_refs
+        desc = A.SceneDesc(len(sc.verts), len(sc.tris), len(sc.face_object), len(sc.object_dynamic),
+                           _ptr(r["verts"]), _ptr(r["tris"]), _ptr(r["tri_face"]), _ptr(r["face_object"]),
+                           _ptr(r["face_material"]), _ptr(r["object_dynamic"]), len(mats),
+                           self._mat_host.ctypes.data)
+        self.n_dynamic = int(np.asarray(sc.object_dynamic).sum())
+        self._check(self.lib.emrt_set_scene(self.ctx, ctypes.byref(desc)))
+
+    def set_materials(self, eps: Sequence[complex]) -> None:
+        e = np.asarray(eps, np.complex128)
+        self._mat_host = np.ascontiguousarray(np.stack([e.real, e.imag], 1), np.float64)
+        self._check(self.lib.emrt_set_materials(self.ctx, self._mat_host.ctypes.data, len(e)))
+
+    def set_frame(self, fr, frame_index: int = 0) -> None:
+        d = self.device
+        nd = max(self.n_dynamic, 1)
+        xf = np.zeros((nd, 3, 4)) if np.asarray(fr.obj_xform).size == 0 else fr.obj_xform
+        ov = np.zeros((nd, 3)) if np.asarray(fr.obj_vel).size == 0 else fr.obj_vel
+        refs = dict(
+            xf=_dev(xf, torch.float64, d), ov=_dev(ov, torch.float64, d), tx=_dev(fr.tx_pos, torch.float64, d),
+            txv=_dev(fr.tx_vel, torch.float64, d), txo=_dev(fr.tx_orient, torch.float64, d),
+            rx=_dev(fr.rx_pos, torch.float64, d), rxv=_dev(fr.rx_vel, torch.float64, d),
+        )
+        desc = A.FrameDesc(int(frame_index), float(getattr(fr, "t", 0.0)), self.n_tx, self.n_rx, _ptr(refs["xf"]),
+                           _ptr(refs["ov"]), _ptr(refs["tx"]), _ptr(refs["txv"]), _ptr(refs["txo"]),
+                           _ptr(refs["rx"]), _ptr(refs["rxv"]))
+        self._check(self.lib.emrt_set_frame(self.ctx, ctypes.byref(desc)))
+        self._frame_refs = refs  # kept alive until the next frame (stream order)
+
+    def step(self, discover: bool = True) -> int:
+        return self._check(self.lib.emrt_step(self.ctx, 1 if discover else 0))
+
+    def sync(self) -> int:
+        return self._check(self.lib.emrt_sync(self.ctx))
+
+    # --------------------------------------------------------------- outputs
+    def channels(self) -> Dict[str, torch.Tensor]:
+        nf, nl, d = len(self.freqs), self.n_links, self.device
+        out = {
+            "H": torch.empty((nf, nl, 2), dtype=torch.float64, device=d),
+            "P_coh": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "P_inc": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "tau_mean": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "tau_rms": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "fd_mean": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "fd_rms": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "n_paths": torch.empty((nl,), dtype=torch.int32, device=d),
+            "flags": torch.empty((nl,), dtype=torch.int32, device=d),
+        }
+        v = A.ChannelView(*(_ptr(out[k]) for k in ("H", "P_coh", "P_inc", "tau_mean", "tau_rms", "fd_mean", "fd_rms",
+                                                   "n_paths", "flags")))
+        self._check(self.lib.emrt_read_channels(self.ctx, ctypes.byref(v)))
+        out["H"] = torch.view_as_complex(out["H"])
+        return out
+
+    def paths(self, cap: Optional[int] = None) -> Dict[str, torch.Tensor]:
+        cap = int(cap or self.cfg.path_cap_per_link)
+        nf, nl, d = len(self.freqs), self.n_links, self.device
+        out = {
+            "key": torch.empty((nl, cap, 9), dtype=torch.int32, device=d),
+            "tri_ids": torch.empty((nl, cap, 5), dtype=torch.int32, device=d),
+            "a": torch.empty((nl, cap, nf, 2), dtype=torch.float64, device=d),
+            "tau": torch.empty((nl, cap), dtype=torch.float64, device=d),
+            "fd": torch.empty((nl, cap, nf), dtype=torch.float64, device=d),
+            "angles": torch.empty((nl, cap, 4), dtype=torch.float32, device=d),
+            "count": torch.empty((nl,), dtype=torch.int32, device=d),
+        }
+        v = A.PathView(cap, *(_ptr(out[k]) for k in ("key", "tri_ids", "a", "tau", "fd", "angles", "count")))
+        st = self._check(self.lib.emrt_read_paths(self.ctx, ctypes.byref(v)))
+        out["truncated"] = st == A.EMRT_W_PATHS_TRUNCATED
+        out["a"] = torch.view_as_complex(out["a"])
+        return out
+
+    def flat_paths(self, cap: Optional[int] = None) -> Dict[str, np.ndarray]:
+        """All paths of the last step as flat host arrays (keys in link, key order)."""
+        p = self.paths(cap)
+        cnt = p["count"].cpu().numpy()
+        mask = np.arange(p["key"].shape[1])[None, :] < cnt[:, None]
+        res = {k: p[k].cpu().numpy()[mask] for k in ("key", "tri_ids", "a", "tau", "fd", "angles")}
+        res["truncated"] = p["truncated"]
+        return res
+
+    def debug_rays(self, tx: int, ray_ids) -> np.ndarray:
+        ids = _dev(ray_ids, torch.int32, self.device)
+        out = torch.empty((len(ids), int(self.cfg.max_reflections) + 1), dtype=torch.int32, device=self.device)
+        self._check(self.lib.emrt_debug_ray_records(self.ctx, int(tx), _ptr(ids), len(ids), _ptr(out)))
+        return out.cpu().numpy()
+
+    def cache_export(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        self._check(self.lib.emrt_cache_size(self.ctx, ctypes.byref(n)))
+        buf = torch.empty((max(n.value, 1), 9), dtype=torch.int32, device=self.device)
+        self._check(self.lib.emrt_cache_export(self.ctx, _ptr(buf), n.value, ctypes.byref(n)))
+        return buf[: n.value].cpu().numpy()
+
+    def cache_import(self, keys) -> None:
+        k = _dev(np.asarray(keys, np.int32).reshape(-1, 9), torch.int32, self.device)
+        self._check(self.lib.emrt_cache_import(self.ctx, _ptr(k), len(k)))
+
+    def set_instrumentation(self, stats: bool = False, timing: bool = False) -> None:
+        self._check(self.lib.emrt_set_instrumentation(self.ctx, int(stats), int(timing)))
+
+    def stats(self) -> Dict[str, object]:
+        s = A.Stats()
+        self._check(self.lib.emrt_read_stats(self.ctx, ctypes.byref(s)))
+        return {f: (list(getattr(s, f)) if f == "rays_per_bounce" else getattr(s, f)) for f, _ in A.Stats._fields_}
