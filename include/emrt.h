@@ -205,13 +205,15 @@ typedef struct emrt_stats {
     int64_t captures;
     int64_t n_static_tris, n_dynamic_tris, n_edges;
     uint32_t device_flags;
-    double bounce_ms;           /* summed kernel time of the bounce launches (when timing is enabled) */
+    double bounce_ms;           /* summed time of the bounce launches since timing was enabled */
     int32_t bounce_launches;
-    double validate_ms;         /* kernel time of the validation launch (when timing is enabled) */
+    double validate_ms;         /* summed time of the validation stage (construct, shadow, fields) */
+    int32_t validate_launches;
 } emrt_stats;
 int32_t emrt_read_stats(emrt_ctx* ctx, emrt_stats* out);
 /* Optional instrumentation: stats = count traversal work (slower), timing =
- * HIP events around the bounce and validation launches. */
+ * HIP events around the bounce launches and the validation stage, summed over
+ * the steps since this call (which resets the sums). */
 int32_t emrt_set_instrumentation(emrt_ctx* ctx, int32_t stats, int32_t timing);
 
 /* Wait for the context's stream; reports device-side flags of the work so

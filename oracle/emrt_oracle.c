@@ -677,8 +677,8 @@ int32_t orc_validate(int32_t T, const float* tv, const int32_t* tri_face, const 
         if (type == 0) {
             if (occluded(T, tv, tri_face, s, r, -1, -1, &amb)) ok = 0;
         } else if (type == 1) {
-            v3 img[6];
-            v3 x[6];
+            v3 img[6];  /* Tx and its images through up to 5 faces */
+            v3 x[7];    /* Tx, up to 5 reflection points, Rx */
             img[0] = s;
             for (int i = 1; i <= order; i++) {
                 int32_t f = key[3 + i];

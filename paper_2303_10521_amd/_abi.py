@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("rays_per_bounce", c_i64 * 7), ("n_candidates", c_i64), ("n_valid", c_i64), ("n_cache", c_i64),
                 ("node_visits", c_i64), ("tri_tests", c_i64), ("segments", c_i64), ("captures", c_i64),
                 ("n_static_tris", c_i64), ("n_dynamic_tris", c_i64), ("n_edges", c_i64), ("device_flags", c_u32),
-                ("bounce_ms", c_f64), ("bounce_launches", c_i32), ("validate_ms", c_f64)]
+                ("bounce_ms", c_f64), ("bounce_launches", c_i32), ("validate_ms", c_f64),
+                ("validate_launches", c_i32)]
 
 
 # name -> (restype, argtypes)

@@ -27,6 +27,7 @@ constexpr int C_NVALID = 17;
 constexpr int C_NCACHE = 18;   // [18, 19] cache sizes (double buffer)
 constexpr int C_STATS = 20;    // [20..23]
 constexpr int C_TRUNC = 24;    // path-list truncation flag
+constexpr int C_NLEGS = 25;    // shadow legs of the step
 constexpr int C_SCRATCH = 32;  // ints for set_scene
 
 struct Carver {
@@ -66,10 +67,17 @@ struct emrt_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int stats_on = 0, timing_on = 0;
-    std::vector<hipEvent_t> ev;  // timing events
-    int ev_used = 0;
-    int ev_bounce = 0;  // events of bounce launches recorded in the last step
-    bool ev_valid = false;
+    // kernel timing: two event sets used by alternate steps, read lazily so
+    // consecutive steps never wait for each other
+    struct EventSet {
+        hipEvent_t ev[16];
+        int used = 0, bounce_end = 0;
+        bool pending = false;
+    } evs[2];
+    bool ev_created = false;
+    int ev_parity = 0;
+    double t_bounce_ms = 0, t_validate_ms = 0;
+    int t_bounce_n = 0, t_validate_n = 0;
 
     // derived sizes
     long long n_total = 0, n_links = 0, P = 0, table_slots = 0, vcap = 0, bcap = 0;
@@ -91,6 +99,9 @@ struct emrt_ctx {
     int cur = 0;
     uint32_t* illum = nullptr;
     ValidPaths vp{};
+    LegBuf legs{};
+    uint8_t* kstate = nullptr;
+    uint32_t* occl = nullptr;
     unsigned long long *sk0 = nullptr, *sk1 = nullptr;
     uint32_t *sv0 = nullptr, *sv1 = nullptr;
     void* sort_tmp = nullptr;
@@ -210,6 +221,15 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->sv0 = cv.take<uint32_t>(c->vcap);
     c->sv1 = cv.take<uint32_t>(c->vcap);
     c->sort_tmp = cv.take<char>((long long)radix_temp_bytes(c->vcap));
+    LegBuf& lg = c->legs;
+    lg.cap = 3 * c->vcap;
+    lg.ox = cv.take<float>(lg.cap); lg.oy = cv.take<float>(lg.cap); lg.oz = cv.take<float>(lg.cap);
+    lg.dx = cv.take<float>(lg.cap); lg.dy = cv.take<float>(lg.cap); lg.dz = cv.take<float>(lg.cap);
+    lg.xa = cv.take<int>(lg.cap);
+    lg.xb = cv.take<int>(lg.cap);
+    lg.key = cv.take<uint32_t>(lg.cap);
+    c->kstate = cv.take<uint8_t>(c->vcap);
+    c->occl = cv.take<uint32_t>(c->vcap);
     c->link_start = cv.take<int>(c->n_links);
     c->link_end = cv.take<int>(c->n_links);
     c->link_cnt = cv.take<uint32_t>(c->n_links);
@@ -284,7 +304,9 @@ int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
 
 int32_t emrt_ctx_destroy(emrt_ctx* c) {
     if (!c) return EMRT_E_INVALID;
-    for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->ev_created)
+        for (auto& set : c->evs)
+            for (auto e : set.ev) (void)hipEventDestroy(e);
     delete c;
     return EMRT_OK;
 }
@@ -426,15 +448,45 @@ int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
     return hip_check(c, hipGetLastError(), "set_frame");
 }
 
+static void ev_flush(emrt_ctx* c, emrt_ctx::EventSet& set) {
+    if (!set.pending) return;
+    set.pending = false;
+    if (set.used == 0 || hipEventSynchronize(set.ev[set.used - 1]) != hipSuccess) return;
+    for (int i = 0; i + 1 < set.bounce_end; i += 2) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, set.ev[i], set.ev[i + 1]) == hipSuccess) { c->t_bounce_ms += ms; c->t_bounce_n++; }
+    }
+    if (set.used - set.bounce_end >= 2) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, set.ev[set.bounce_end], set.ev[set.bounce_end + 1]) == hipSuccess) {
+            c->t_validate_ms += ms;
+            c->t_validate_n++;
+        }
+    }
+}
+
+static void ev_record(emrt_ctx* c) {
+    if (!c->timing_on) return;
+    auto& set = c->evs[c->ev_parity];
+    if (set.used < 16) HC(hipEventRecord(set.ev[set.used++], c->stream));
+}
+
 int32_t emrt_set_instrumentation(emrt_ctx* c, int32_t stats, int32_t timing) {
     if (!c) return EMRT_E_INVALID;
     c->stats_on = stats ? 1 : 0;
     c->timing_on = timing ? 1 : 0;
-    if (c->timing_on && c->ev.empty()) {
-        c->ev.resize(16);
-        for (auto& e : c->ev)
-            if (hipEventCreate(&e) != hipSuccess) return fail(c, EMRT_E_HIP, "event create");
+    if (c->timing_on && !c->ev_created) {
+        for (auto& set : c->evs)
+            for (auto& e : set.ev)
+                if (hipEventCreate(&e) != hipSuccess) return fail(c, EMRT_E_HIP, "event create");
+        c->ev_created = true;
     }
+    for (auto& set : c->evs) {
+        ev_flush(c, set);
+        set.used = set.bounce_end = 0;
+    }
+    c->t_bounce_ms = c->t_validate_ms = 0;
+    c->t_bounce_n = c->t_validate_n = 0;
     return EMRT_OK;
 }
 
@@ -453,6 +505,10 @@ static PathArgs path_args(emrt_ctx* c) {
     a.ant_mode = c->cfg.antenna_mode;
     a.diff_max_leg = c->cfg.diff_max_leg_m;
     a.out = c->vp;
+    a.legs = c->legs;
+    a.legs.count = c->ctr + C_NLEGS;
+    a.state = c->kstate;
+    a.occl = c->occl;
     a.flags = c->flags;
     return a;
 }
@@ -466,8 +522,12 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
     // counters: keep the cache sizes, clear the rest
     fill_u64(c->ctr + C_RAYS, 0ULL, C_NCACHE - C_RAYS, st);
     fill_u64(c->ctr + C_STATS, 0ULL, kNumCounters - C_STATS, st);
-    c->ev_used = 0;
-    c->ev_bounce = 0;
+    fill_u32(c->flags, 0u, 16, st);  // device flags report this step only
+    if (c->timing_on) {
+        auto& set = c->evs[c->ev_parity];
+        ev_flush(c, set);
+        set.used = set.bounce_end = 0;
+    }
     // ---- frame geometry (Section II-A: BVH updated between frames)
     scene_world(S, c->f_xf, c->flags, st);
     scene_planes(S, st);
@@ -525,11 +585,11 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
             b.n_in = c->ctr + C_RAYS + k;
             b.n_out = c->ctr + C_RAYS + k + 1;
             b.work = (unsigned int*)(c->ctr + C_WORK + k);
-            if (c->timing_on && c->ev_used + 2 <= (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+            ev_record(c);
             bounce(b, c->stats_on != 0, grid, st);
-            if (c->timing_on && c->ev_used + 1 <= (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+            ev_record(c);
         }
-        c->ev_bounce = c->ev_used;
+        c->evs[c->ev_parity].bounce_end = c->evs[c->ev_parity].used;
         if (diff) diff_candidates(pa, c->illum, c->e_words, c->rxt.view(), c->rx_prims, c->table, mask, src, st);
         table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags, st);
         pa.cand = c->cand;
@@ -540,10 +600,9 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
         pa.n_cand = c->ctr + C_NCACHE + c->cur;
     }
     // ---- exact validation + fields (Sections II-A, III-B, III-C)
-    int ev0 = c->ev_used;
-    if (c->timing_on && c->ev_used + 2 <= (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+    ev_record(c);
     validate_eval(pa, c->n_links, c->P, st);
-    if (c->timing_on && ev0 + 1 < (int)c->ev.size()) HC(hipEventRecord(c->ev[c->ev_used++], st));
+    ev_record(c);
     // ---- per-link reduction (Section V-D statistics)
     link_keys(c->vp, c->sz.n_rx, c->sk0, c->sv0, st);
     int which = radix_sort(c->sk0, c->sv0, c->sk1, c->sv1, (const long long*)c->vp.count, c->vcap, bits_for(c->n_links),
@@ -560,7 +619,10 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
     cache_write(c->vp, c->order, c->link_start, c->link_end, c->link_off, c->n_links, c->cache[nxt], st);
     c->cur = nxt;
     c->stepped = true;
-    c->ev_valid = c->timing_on != 0;
+    if (c->timing_on) {
+        c->evs[c->ev_parity].pending = true;
+        c->ev_parity ^= 1;
+    }
     return hip_check(c, hipGetLastError(), "step");
 }
 
@@ -698,20 +760,11 @@ int32_t emrt_read_stats(emrt_ctx* c, emrt_stats* o) {
     o->n_dynamic_tris = c->S.T_d;
     o->n_edges = c->S.E;
     o->device_flags = fl | c->flag_accum;
-    if (c->ev_valid && c->ev_used >= 2) {
-        int nb = c->ev_bounce;
-        double tb = 0;
-        int launches = 0;
-        for (int i = 0; i + 1 < nb && i + 1 < c->ev_used; i += 2) {
-            float ms = 0;
-            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) { tb += ms; launches++; }
-        }
-        o->bounce_ms = tb;
-        o->bounce_launches = launches;
-        int vi = c->ev_used - 2;
-        float ms = 0;
-        if (vi >= 0 && hipEventElapsedTime(&ms, c->ev[vi], c->ev[vi + 1]) == hipSuccess) o->validate_ms = ms;
-    }
+    for (auto& set : c->evs) ev_flush(c, set);
+    o->bounce_ms = c->t_bounce_ms;
+    o->bounce_launches = c->t_bounce_n;
+    o->validate_ms = c->t_validate_ms;
+    o->validate_launches = c->t_validate_n;
     return EMRT_OK;
 }
 

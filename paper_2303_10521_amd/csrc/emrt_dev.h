@@ -222,7 +222,7 @@ struct RayPre {
     float ix, iy, iz;  // 1/d (zero components replaced by +-1e-30)
     int kx, ky, kz;
     float Sx, Sy, Sz;
-    int neg_x, neg_y, neg_z;
+    int negmask;  // bit k set when d[k] < 0
 };
 
 __device__ __forceinline__ float nz(float v) { return v != 0.0f ? v : 1e-30f; }
@@ -234,7 +234,7 @@ __device__ __forceinline__ RayPre ray_pre(float ox, float oy, float oz, float dx
     r.ix = 1.0f / nz(dx);
     r.iy = 1.0f / nz(dy);
     r.iz = 1.0f / nz(dz);
-    r.neg_x = dx < 0.0f; r.neg_y = dy < 0.0f; r.neg_z = dz < 0.0f;
+    r.negmask = (dx < 0.0f ? 1 : 0) | (dy < 0.0f ? 2 : 0) | (dz < 0.0f ? 4 : 0);
     float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
     int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
     int kx = kz + 1 == 3 ? 0 : kz + 1;
@@ -323,7 +323,7 @@ __device__ __forceinline__ void child_box(const BNode& nd, int side, float& lx, 
 
 __device__ __forceinline__ int near_side(const BNode& nd, const RayPre& r) {
     int axis = nd.m.w & 3;
-    return axis == 0 ? r.neg_x : (axis == 1 ? r.neg_y : r.neg_z);
+    return (r.negmask >> axis) & 1;
 }
 
 // Generic driver.  test(nd, side, child) returns true to descend into `child`

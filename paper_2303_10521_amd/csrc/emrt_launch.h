@@ -154,8 +154,20 @@ struct ValidPaths {
     long long cap;
 };
 
+// shadow rays of the keys under validation (one per leg)
+struct LegBuf {
+    float *ox, *oy, *oz, *dx, *dy, *dz;
+    int *xa, *xb;
+    uint32_t* key;
+    unsigned long long* count;
+    long long cap;
+};
+
 struct PathArgs {
     SceneDev s;
+    LegBuf legs;
+    uint8_t* state;   // [n_links + cap_cand] 1 = constructed
+    uint32_t* occl;   // [n_links + cap_cand] 1 = a leg is blocked
     FrameDev f;
     Bvh st, dy;
     const TriP* st_prims;

@@ -307,7 +307,188 @@ __device__ __forceinline__ cd phase(double L, double lam) {
 struct CV { cd x, y, z; };
 __device__ __forceinline__ cd cdot(dv3 a, const CV& b) { return b.x * a.x + b.y * a.y + b.z * a.z; }
 
-__global__ void __launch_bounds__(128) k_validate(PathArgs a, long long n_links, long long cap_cand) {
+// Geometry of one path key.  Points: P[0] = Tx, P[1..order] reflection
+// points (or P[1] = Keller point), R = Rx; leg i runs from P[i] to P[i+1]
+// (R for the last leg).  Loops run to the compile-time bound so every array
+// index is a constant and the arrays stay in registers.
+struct Built {
+    dv3 P[EMRT_KMAX + 2];
+    dv3 R;
+    int order, type, np;  // np = number of points including Tx and Rx
+    int tri[EMRT_KMAX];
+    Wedge w;
+};
+
+__device__ __forceinline__ bool key_in_range(const PathArgs& a, const KeyRec& key) {
+    int type = key.to & 0xff, order = key.to >> 8;
+    bool good = key.tx >= 0 && key.tx < a.f.n_tx && key.rx >= 0 && key.rx < a.f.n_rx;
+    if (type == KT_SPEC) {
+        good = good && order >= 1 && order <= EMRT_KMAX;
+#pragma unroll
+        for (int j = 0; j < EMRT_KMAX; j++)
+            if (j < order && !(key.ids[j] >= 0 && key.ids[j] < a.s.F)) good = false;
+    } else if (type == KT_DIFF) {
+        good = good && order == 1 && key.ids[0] >= 0 && key.ids[0] < a.s.E;
+    } else if (type != KT_LOS) {
+        good = false;
+    }
+    return good;
+}
+
+// Exact construction (everything except occlusion):
+//   line of sight: the segment Tx -> Rx;
+//   specular (image method): images s_k = mirror(s_{k-1}, plane f_k), then
+//   back from Rx, x_k = segment(x_{k+1} -> s_k) meets plane f_k at a
+//   parameter in (0, 1) and lies in a triangle of f_k (lowest id reported);
+//   diffraction: Keller point strictly inside the edge, both ends in the
+//   exterior wedge, receiver leg within diff_max_leg.
+__device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, Built& g) {
+    const SceneDev& S = a.s;
+    g.type = key.to & 0xff;
+    g.order = key.to >> 8;
+    dv3 s = ldd3(a.f.tx_pos + 3 * key.tx);
+    g.R = ldd3(a.f.rx_pos + 3 * key.rx);
+    g.P[0] = s;
+#pragma unroll
+    for (int j = 0; j < EMRT_KMAX; j++) g.tri[j] = -1;
+    if (g.type == KT_LOS) {
+        g.np = 2;
+        return true;
+    }
+    if (g.type == KT_DIFF) {
+        g.np = 3;
+        g.w = wedge_of(S, key.ids[0]);
+        return keller(g.w, s, g.R, a.diff_max_leg, g.P[1]);
+    }
+    const int order = g.order;
+    g.np = order + 2;
+    dv3 img[EMRT_KMAX + 1];
+    img[0] = s;
+#pragma unroll
+    for (int i = 1; i <= EMRT_KMAX; i++)
+        if (i <= order) img[i] = mirror(img[i - 1], S.plane + 4 * (long long)key.ids[i - 1]);
+    dv3 cur = g.R;
+#pragma unroll
+    for (int i = EMRT_KMAX; i >= 1; i--) {
+        if (i > order) continue;
+        const double* pl = S.plane + 4 * (long long)key.ids[i - 1];
+        dv3 nrm = d3(pl[0], pl[1], pl[2]);
+        dv3 dv = img[i] - cur;
+        double den = dot(nrm, dv);
+        if (den == 0.0) return false;
+        double tt = (pl[3] - dot(nrm, cur)) / den;
+        if (!(tt > 0.0 && tt < 1.0)) return false;
+        cur = cur + dv * tt;
+        g.P[i] = cur;
+        int t = face_contains(S, key.ids[i - 1], cur);
+        if (t < 0) return false;
+        g.tri[i - 1] = t;
+    }
+    return true;
+}
+
+// endpoints and excluded faces of leg i (compile-time i)
+template <int I>
+__device__ __forceinline__ void leg_of(const Built& g, const KeyRec& key, dv3& p0, dv3& p1, int& xa, int& xb) {
+    p0 = g.P[I];
+    p1 = (I + 2 == g.np) ? g.R : g.P[I + 1 <= EMRT_KMAX + 1 ? I + 1 : EMRT_KMAX + 1];
+    if (g.type == KT_DIFF) {
+        xa = g.w.f0;
+        xb = g.w.fn;
+    } else if (g.type == KT_SPEC) {
+        xa = I >= 1 ? key.ids[I >= 1 ? I - 1 : 0] : -1;
+        xb = I + 1 <= g.order ? key.ids[I < EMRT_KMAX ? I : EMRT_KMAX - 1] : -1;
+    } else {
+        xa = xb = -1;
+    }
+}
+
+__device__ __forceinline__ KeyRec key_at(const PathArgs& a, long long q, long long n_links) {
+    KeyRec key;
+    if (q < n_links) {
+        key.tx = (int)(q / a.f.n_rx);
+        key.rx = (int)(q - (long long)key.tx * a.f.n_rx);
+        key.to = KT_LOS;
+#pragma unroll
+        for (int j = 0; j < 5; j++) key.ids[j] = -1;
+    } else {
+        key = a.cand[q - n_links];
+    }
+    return key;
+}
+
+template <int I>
+__device__ __forceinline__ void emit_leg(const PathArgs& a, const Built& g, const KeyRec& key, bool ok, uint32_t q) {
+    bool has = ok && I + 1 < g.np;
+    long long pos = wave_append(a.legs.count, has);
+    if (!has) return;
+    if (pos >= a.legs.cap) { atomicOr(a.flags, FLAG_PATH_CAP); a.state[q] = 0; return; }
+    dv3 p0, p1;
+    int xa, xb;
+    leg_of<I>(g, key, p0, p1, xa, xb);
+    dv3 d = p1 - p0;
+    a.legs.ox[pos] = (float)p0.x; a.legs.oy[pos] = (float)p0.y; a.legs.oz[pos] = (float)p0.z;
+    a.legs.dx[pos] = (float)d.x; a.legs.dy[pos] = (float)d.y; a.legs.dz[pos] = (float)d.z;
+    a.legs.xa[pos] = xa;
+    a.legs.xb[pos] = xb;
+    a.legs.key[pos] = q;
+}
+
+// Phase 1: exact construction of every key (line of sight for every link,
+// then the candidates); surviving keys emit their legs as shadow rays.
+__global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links, long long cap_cand) {
+    long long nc = (long long)*a.n_cand;
+    if (nc > cap_cand) nc = cap_cand;
+    long long n = n_links + nc;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long iters = (n + stride - 1) / stride;
+    for (long long it = 0; it < iters; it++) {
+        long long q = start + it * stride;
+        bool ok = q < n;
+        KeyRec key;
+        Built g;
+        g.np = 0;
+        if (ok) {
+            key = key_at(a, q, n_links);
+            ok = key_in_range(a, key) && construct(a, key, g);
+            a.state[q] = ok ? (uint8_t)1 : (uint8_t)0;
+            a.occl[q] = 0u;
+        }
+        emit_leg<0>(a, g, key, ok, (uint32_t)q);
+        emit_leg<1>(a, g, key, ok, (uint32_t)q);
+        emit_leg<2>(a, g, key, ok, (uint32_t)q);
+        emit_leg<3>(a, g, key, ok, (uint32_t)q);
+        emit_leg<4>(a, g, key, ok, (uint32_t)q);
+        emit_leg<5>(a, g, key, ok, (uint32_t)q);
+    }
+}
+
+// Phase 2: float32 shadow rays over the open legs (t in (0, 1)), static and
+// dynamic LBVH; a blocked leg marks its key occluded.
+__global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
+    long long n = (long long)*a.legs.count;
+    if (n > a.legs.cap) n = a.legs.cap;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        uint32_t q = a.legs.key[i];
+        if (a.occl[q]) continue;
+        RayPre r = ray_pre(a.legs.ox[i], a.legs.oy[i], a.legs.oz[i], a.legs.dx[i], a.legs.dy[i], a.legs.dz[i]);
+        int xa = a.legs.xa[i], xb = a.legs.xb[i];
+        if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb) || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb))
+            a.occl[q] = 1u;
+    }
+}
+
+// Phase 3: fields of the unoccluded keys (double precision).
+//   Specular: E = e_tx(k_0); at each bounce, with the face normal n turned
+//   against the incident k_{i-1}: s = normalize(k_{i-1} x n) (normal
+//   incidence: normalize(n x z), else normalize(n x x)), p_in = s x k_{i-1},
+//   p_out = s x k_i, E <- Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out;
+//   a = lambda / (4 pi L) (e_rx(k_K).E) exp(-j 2 pi frac(L / lambda)).
+//   Diffraction: a = lambda/(4 pi) (1/s') sqrt(s'/(s (s + s'))) e_rx.(D e_tx)
+//   exp(-j 2 pi frac((s + s')/lambda)), D = -b0 b0' D_s - ph ph' D_h.
+//   Delay L / c; Doppler -(1/lambda)[k_K.v_rx - k_0.v_tx + sum (k_{i-1} - k_i).v_obj].
+__global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, long long cap_cand) {
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     long long n = n_links + nc;
@@ -317,110 +498,53 @@ __global__ void __launch_bounds__(128) k_validate(PathArgs a, long long n_links,
     const SceneDev& S = a.s;
     for (long long it = 0; it < iters; it++) {
         long long q = start + it * stride;
-        bool ok = q < n;
+        bool ok = q < n && a.state[q] && !a.occl[q];
         KeyRec key;
+        Built g;
         if (ok) {
-            if (q < n_links) {
-                key.tx = (int)(q / a.f.n_rx);
-                key.rx = (int)(q - (long long)key.tx * a.f.n_rx);
-                key.to = KT_LOS;
-                for (int j = 0; j < 5; j++) key.ids[j] = -1;
-            } else {
-                key = a.cand[q - n_links];
-            }
-        }
-        int type = key.to & 0xff, order = key.to >> 8;
-        if (ok) {
-            // keys may come from an imported cache: reject anything out of range
-            bool good = key.tx >= 0 && key.tx < a.f.n_tx && key.rx >= 0 && key.rx < a.f.n_rx;
-            if (type == KT_SPEC) {
-                good = good && order >= 1 && order <= EMRT_KMAX;
-                for (int j = 0; j < EMRT_KMAX; j++)
-                    if (j < order && !(key.ids[j] >= 0 && key.ids[j] < S.F)) good = false;
-            } else if (type == KT_DIFF) {
-                good = good && order == 1 && key.ids[0] >= 0 && key.ids[0] < S.E;
-            } else if (type != KT_LOS) {
-                good = false;
-            }
-            ok = good;
-        }
-        dv3 s = ok ? ldd3(a.f.tx_pos + 3 * key.tx) : d3(0, 0, 0);
-        dv3 r = ok ? ldd3(a.f.rx_pos + 3 * key.rx) : d3(0, 0, 1);
-        dv3 P[7];
-        int tri[5] = {-1, -1, -1, -1, -1};
-        int np = 0;
-        Wedge w;
-        if (ok) {
-            if (type == KT_LOS) {
-                P[0] = s; P[1] = r; np = 2;
-                if (occluded(a, s, r, -1, -1)) ok = false;
-            } else if (type == KT_SPEC) {
-                dv3 img[6];
-                img[0] = s;
-                for (int i = 1; i <= order; i++) img[i] = mirror(img[i - 1], S.plane + 4 * (long long)key.ids[i - 1]);
-                dv3 cur = r;
-                for (int i = order; i >= 1 && ok; i--) {
-                    const double* pl = S.plane + 4 * (long long)key.ids[i - 1];
-                    dv3 nrm = d3(pl[0], pl[1], pl[2]);
-                    dv3 dv = img[i] - cur;
-                    double den = dot(nrm, dv);
-                    if (den == 0.0) { ok = false; break; }
-                    double tt = (pl[3] - dot(nrm, cur)) / den;
-                    if (!(tt > 0.0 && tt < 1.0)) { ok = false; break; }
-                    cur = cur + dv * tt;
-                    P[i] = cur;
-                    int t = face_contains(S, key.ids[i - 1], cur);
-                    if (t < 0) { ok = false; break; }
-                    tri[i - 1] = t;
-                }
-                if (ok) {
-                    P[0] = s;
-                    P[order + 1] = r;
-                    np = order + 2;
-                    for (int i = 0; i <= order && ok; i++) {
-                        int xa = i >= 1 ? key.ids[i - 1] : -1;
-                        int xb = i + 1 <= order ? key.ids[i] : -1;
-                        if (occluded(a, P[i], P[i + 1], xa, xb)) ok = false;
-                    }
-                }
-            } else if (type == KT_DIFF) {
-                w = wedge_of(S, key.ids[0]);
-                dv3 Q;
-                if (!keller(w, s, r, a.diff_max_leg, Q)) ok = false;
-                else {
-                    P[0] = s; P[1] = Q; P[2] = r; np = 3;
-                    if (occluded(a, s, Q, w.f0, w.fn) || occluded(a, Q, r, w.f0, w.fn)) ok = false;
-                }
-            }
+            key = key_at(a, q, n_links);
+            ok = construct(a, key, g);
         }
         long long pos = wave_append(a.out.count, ok);
         if (!ok) continue;
         if (pos >= a.out.cap) { atomicOr(a.flags, FLAG_PATH_CAP); continue; }
-        // ------------------------------------------------------- fields
         dv3 vt = ldd3(a.f.tx_vel + 3 * key.tx), vr = ldd3(a.f.rx_vel + 3 * key.rx);
         double th = a.f.tx_orient[2 * key.tx], phi = a.f.tx_orient[2 * key.tx + 1];
-        dv3 kk[6];
+        // unit directions of the legs and the unfolded length
+        dv3 kk[EMRT_KMAX + 1];
         double L = 0.0;
-        for (int i = 0; i + 1 < np; i++) {
-            dv3 dv = P[i + 1] - P[i];
+#pragma unroll
+        for (int i = 0; i <= EMRT_KMAX; i++) {
+            if (i + 1 >= g.np) break;
+            dv3 p1 = (i + 2 == g.np) ? g.R : g.P[i + 1 <= EMRT_KMAX + 1 ? i + 1 : EMRT_KMAX + 1];
+            dv3 dv = p1 - g.P[i];
             double l = len(dv);
             L += l;
             kk[i] = dv * (1.0 / l);
         }
-        dv3 k0 = kk[0], kK = kk[np - 2];
+        const int nlegs = g.np - 1;
+        dv3 k0 = kk[0];
+        dv3 kK = kk[0];
+#pragma unroll
+        for (int i = 1; i <= EMRT_KMAX; i++)
+            if (i == nlegs - 1) kK = kk[i];
         double dop = dot(kK, vr) - dot(k0, vt);
         cd amp[EMRT_NF];
-        if (type != KT_DIFF) {
-            for (int i = 1; i + 1 < np; i++) {
+        if (g.type != KT_DIFF) {
+            dv3 e0 = antenna(a.ant_mode, k0, th, phi);
+            dv3 er = antenna(0, kK, 0, 0);
+#pragma unroll
+            for (int i = 1; i <= EMRT_KMAX; i++) {
+                if (i > g.order || g.type == KT_LOS) break;
                 int od = S.face_dyn[key.ids[i - 1]];
                 if (od >= 0) dop += dot(kk[i - 1] - kk[i], ldd3(a.f.obj_vel + 3 * (long long)od));
             }
-            dv3 e0 = antenna(a.ant_mode, k0, th, phi);
-            dv3 er = antenna(0, kK, 0, 0);
             for (int fi = 0; fi < a.nf; fi++) {
                 double lam = kC0 / a.freq[fi];
                 CV E = {C(e0.x), C(e0.y), C(e0.z)};
-                for (int i = 1; i + 1 < np; i++) {
+#pragma unroll
+                for (int i = 1; i <= EMRT_KMAX; i++) {
+                    if (i > g.order || g.type == KT_LOS) break;
                     int f = key.ids[i - 1];
                     const double* pl = S.plane + 4 * (long long)f;
                     dv3 nrm = d3(pl[0], pl[1], pl[2]);
@@ -445,13 +569,14 @@ __global__ void __launch_bounds__(128) k_validate(PathArgs a, long long n_links,
                 amp[fi] = cdot(er, E) * phase(L, lam) * (lam / (4.0 * kPi * L));
             }
         } else {
+            const Wedge& w = g.w;
             int od = S.face_dyn[w.f0];
             if (od >= 0) dop += dot(kk[0] - kk[1], ldd3(a.f.obj_vel + 3 * (long long)od));
-            double sp = len(P[1] - P[0]), sd = len(P[2] - P[1]);
+            double sp = len(g.P[1] - g.P[0]), sd = len(g.R - g.P[1]);
             dv3 si = kk[0], so = kk[1];
             double cb = fmin(1.0, fmax(-1.0, dot(si, w.e)));
             double beta0 = acos(cb);
-            double php = wedge_angle(w, s), ph = wedge_angle(w, r);
+            double php = wedge_angle(w, g.P[0]), ph = wedge_angle(w, g.R);
             double sb = sin(beta0);
             double Lp = sd * sp * sb * sb / (sd + sp);
             dv3 fp = unit(cross(w.e, si)) * -1.0, bp = cross(fp, si);
@@ -472,7 +597,8 @@ __global__ void __launch_bounds__(128) k_validate(PathArgs a, long long n_links,
         }
         ValidPaths& o = a.out;
         o.key[pos] = key;
-        for (int j = 0; j < 5; j++) o.tri[5 * pos + j] = tri[j];
+#pragma unroll
+        for (int j = 0; j < 5; j++) o.tri[5 * pos + j] = g.tri[j];
         for (int fi = 0; fi < a.nf; fi++) {
             double lam = kC0 / a.freq[fi];
             o.a[2 * (pos * a.nf + fi)] = amp[fi].re;
@@ -488,7 +614,9 @@ __global__ void __launch_bounds__(128) k_validate(PathArgs a, long long n_links,
 
 void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, hipStream_t st) {
     long long n = n_links + cap_cand;
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
+    hipLaunchKernelGGL(k_construct, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
+    hipLaunchKernelGGL(k_shadow, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_fields, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
 }
 
 // ----------------------------------------------------------- per link ----

@@ -1,0 +1,367 @@
+"""HIP path vs the FP64 oracle, through the C ABI.
+
+Levels of comparison:
+  * per ray: triangle id per bounce, bit-exact on rays the oracle marks robust
+    (every decision farther than its margin from a boundary);
+  * per link: path-key sets equal except keys the oracle marks ambiguous;
+  * per path and per link: gain, delay and Doppler within the tolerances of
+    tests/parity.py.
+The toy city is compared in full; the district and the 2x2 km city run at
+their full sizes in the benchmark's launch configuration and are compared on
+sampled rays, sampled keys and sampled links that the oracle computes one by
+one.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from synth import city  # noqa: E402
+from tests import parity as P  # noqa: E402
+from tests.oracle_util import static_frame  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _tracer(sc, w, **kw):
+    from paper_2303_10521_amd import Tracer
+
+    args = dict(freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections, rays_per_tx=w.rays_per_tx,
+                diffraction=int(w.diffraction), path_capacity=1 << 22)
+    args.update(kw)
+    return Tracer(sc, sc.n_tx, sc.n_rx, **args)
+
+
+# ---------------------------------------------------------------- toy city
+@pytest.fixture(scope="module")
+def toy():
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    tr = _tracer(sc, w, path_capacity=1 << 16)
+    tr.set_frame(fr)
+    tr.step(True)
+    assert tr.sync() == 0
+    out = dict(w=w, sc=sc, fr=fr, tr=tr,
+               hits=tr.debug_rays(0, np.arange(w.rays_per_tx)),
+               paths=tr.flat_paths(), ch=P.gpu_channels_np(tr.channels()))
+    os_ = O.OracleScene(sc)
+    out["os"] = os_
+    out["ref"] = O.run_frame(os_, fr, w.rays_per_tx, w.max_reflections, w.freqs_hz)
+    yield out
+    tr.close()
+
+
+def test_toy_interaction_sequences_bit_exact(toy):
+    t0 = toy["ref"].traces[0]
+    n_rob, mm_rob, mm_all = P.compare_hitlogs(toy["hits"], t0.hit_tri, t0.robust)
+    assert n_rob >= 0.98 * len(t0.robust)
+    assert mm_rob == 0
+    assert mm_all <= len(t0.robust) - n_rob
+
+
+def test_toy_path_sets(toy):
+    ref = toy["ref"]
+    g = P.keyset(toy["paths"]["key"])
+    unamb = P.keyset(ref.keys[~ref.ambiguous & ref.robust])
+    assert unamb <= g
+    extra = np.array(sorted(g - P.keyset(ref.keys)), np.int32).reshape(-1, 9)
+    if len(extra):
+        valid, amb, _, _ = O.validate(toy["os"], toy["os"].geometry(toy["fr"].obj_xform), extra,
+                                      toy["fr"].tx_pos, toy["fr"].rx_pos)
+        assert np.all(valid | amb)
+    assert len(extra) <= max(1, len(g) // 50)
+
+
+def test_toy_path_values_and_triangles(toy):
+    ref, p = toy["ref"], toy["paths"]
+    gi = {tuple(int(x) for x in k): i for i, k in enumerate(p["key"])}
+    n = 0
+    for j, k in enumerate(ref.keys):
+        i = gi.get(tuple(int(x) for x in k))
+        if i is None:
+            continue
+        n += 1
+        assert abs(p["a"][i, 0] - ref.a[j, 0]) <= 1e-8 * abs(ref.a[j, 0])
+        assert abs(p["tau"][i] - ref.tau[j]) <= P.TAU_REL * ref.tau[j]
+        assert abs(p["fd"][i, 0] - ref.fd[j, 0]) <= P.FD_ABS
+        if not ref.ambiguous[j]:
+            assert np.array_equal(p["tri_ids"][i], ref.tri_ids[j])
+    assert n >= 0.95 * len(ref.keys)
+
+
+def test_toy_channels(toy):
+    ref = toy["ref"]
+    g = toy["ch"]
+    links = np.arange(toy["sc"].n_rx)
+    assert not P.channel_ok(g, ref.channels, links, 100.0)
+    assert np.array_equal(g["n_paths"], ref.channels["n_paths"])
+    assert np.array_equal(g["flags"] & 1, ref.channels["los"].astype(np.int32))
+
+
+def test_toy_deterministic_and_cached_frame(toy):
+    tr, fr = toy["tr"], toy["fr"]
+    tr.set_frame(fr)
+    tr.step(True)
+    again = P.gpu_channels_np(tr.channels())
+    for k in again:
+        assert np.array_equal(again[k], toy["ch"][k]), k
+    tr.step(False)  # static scene: the cache reproduces the same channels
+    cached = P.gpu_channels_np(tr.channels())
+    for k in cached:
+        assert np.array_equal(cached[k], toy["ch"][k]), k
+
+
+# ------------------------------------------------ district at full size
+@pytest.fixture(scope="module")
+def district():
+    w = city.workload("district")
+    sc = w.scene
+    tr = _tracer(sc, w, path_capacity=1 << 23)
+    frames = [sc.frame(i * w.frame_dt) for i in range(4)]
+    out = dict(w=w, sc=sc, tr=tr, frames=frames, os=O.OracleScene(sc))
+    tr.set_frame(frames[0], 0)
+    tr.step(True)
+    assert tr.sync() == 0
+    out["hits"] = {t: tr.debug_rays(t, np.arange(t, w.rays_per_tx, 509)) for t in range(sc.n_tx)}
+    out["paths"] = tr.flat_paths(cap=256)
+    out["ch"] = P.gpu_channels_np(tr.channels())
+    out["cache0"] = tr.cache_export()
+    yield out
+    tr.close()
+
+
+def test_district_sampled_rays_bit_exact(district):
+    w, sc, fr = district["w"], district["sc"], district["frames"][0]
+    os_ = district["os"]
+    g = os_.geometry(fr.obj_xform)
+    tot = 0
+    for t in range(sc.n_tx):
+        ids = np.arange(t, w.rays_per_tx, 509, dtype=np.int32)
+        res = O.trace(os_, g, fr.tx_pos[t], w.rays_per_tx, ids, w.max_reflections, fr.rx_pos, 1.0, True, True)
+        n_rob, mm_rob, _ = P.compare_hitlogs(district["hits"][t], res.hit_tri, res.robust)
+        assert mm_rob == 0
+        assert n_rob >= 0.95 * len(ids)
+        tot += len(ids)
+    assert tot > 7000
+
+
+def test_district_paths_exact_in_oracle(district):
+    """Sampled GPU paths (specular and diffraction) validate in the oracle with
+    the same triangles, gains, delays and Doppler shifts."""
+    fr = district["frames"][0]
+    os_ = district["os"]
+    p = district["paths"]
+    assert not p["truncated"]
+    keys = p["key"]
+    rng = np.random.default_rng(0)
+    types = keys[:, 2]
+    assert (types == 2).sum() > 100 and (types == 1).sum() > 100
+    pick = np.concatenate([rng.choice(np.nonzero(types == t)[0], min(400, (types == t).sum()), replace=False)
+                           for t in (0, 1, 2)])
+    g = os_.geometry(fr.obj_xform)
+    valid, amb, tri, pts = O.validate(os_, g, keys[pick], fr.tx_pos, fr.rx_pos)
+    assert np.all(valid | amb)
+    assert valid.mean() > 0.99
+    ok = valid & ~amb
+    a, tau, fd, aod, aoa = O.evaluate(os_, g, keys[pick][ok], pts[ok], fr, district["w"].freqs_hz)
+    ga = p["a"][pick][ok]
+    assert np.all(np.abs(ga - a) <= 1e-8 * np.abs(a))
+    assert np.all(np.abs(p["tau"][pick][ok] - tau) <= P.TAU_REL * tau)
+    assert np.all(np.abs(p["fd"][pick][ok] - fd) <= P.FD_ABS)
+    spec = keys[pick][ok][:, 2] == 1
+    assert np.array_equal(p["tri_ids"][pick][ok][spec], tri[ok][spec])
+
+
+def test_district_channel_sums(district):
+    """Per-link sums over the GPU's path set equal the oracle's sums over the
+    same keys (sampled links, every path of the link)."""
+    fr = district["frames"][0]
+    os_ = district["os"]
+    sc = district["sc"]
+    p = district["paths"]
+    link = p["key"][:, 0] * sc.n_rx + p["key"][:, 1]
+    rng = np.random.default_rng(1)
+    links = rng.choice(np.unique(link), 150, replace=False)
+    sel = np.isin(link, links)
+    keys = p["key"][sel]
+    g = os_.geometry(fr.obj_xform)
+    valid, amb, tri, pts = O.validate(os_, g, keys, fr.tx_pos, fr.rx_pos)
+    assert np.all(valid | amb)
+    a, tau, fd, _, _ = O.evaluate(os_, g, keys, pts, fr, district["w"].freqs_hz)
+    ref = O.reduce_links(keys, a, tau, fd, sc.n_tx, sc.n_rx)
+    # links with an ambiguous path are excluded (their oracle sum is undefined here)
+    amb_links = set(link[sel][amb].tolist())
+    check = np.array([L for L in links if L not in amb_links])
+    assert len(check) > 100
+    assert not P.channel_ok(district["ch"], ref, check, 100.0)
+
+
+def test_district_discovery_covers_oracle_subset(district):
+    """Keys the oracle discovers robustly from a launch subset (every 53rd ray
+    of every transmitter) and validates unambiguously are all in the GPU set,
+    which traces every ray."""
+    w, sc, fr = district["w"], district["sc"], district["frames"][0]
+    os_ = district["os"]
+    ids = np.arange(0, w.rays_per_tx, 53, dtype=np.int32)
+    ref = O.run_frame(os_, fr, w.rays_per_tx, w.max_reflections, w.freqs_hz, ray_ids=ids, diffraction=False)
+    spec = (ref.keys[:, 2] == 1) & ref.robust & ~ref.ambiguous
+    want = P.keyset(ref.keys[spec])
+    assert len(want) > 40
+    assert want <= P.keyset(district["paths"]["key"])
+
+
+def test_district_cached_frames_revalidate(district):
+    """Cached frames keep only keys that are valid at the new geometry
+    (deletion of invalid paths), never add keys, and agree with the oracle's
+    validation of the same cache."""
+    tr, os_, w = district["tr"], district["os"], district["w"]
+    prev = P.keyset(district["cache0"])
+    for f in (1, 2, 3):
+        fr = district["frames"][f]
+        tr.set_frame(fr, f)
+        tr.step(False)
+        assert tr.sync() == 0
+        cache = tr.cache_export()
+        cur = P.keyset(cache)
+        assert cur <= prev
+        dropped = np.array(sorted(prev - cur), np.int32).reshape(-1, 9)
+        g = os_.geometry(fr.obj_xform)
+        if len(dropped):
+            valid, amb, _, _ = O.validate(os_, g, dropped, fr.tx_pos, fr.rx_pos)
+            assert np.all(~valid | amb)
+        rng = np.random.default_rng(f)
+        keep = cache[rng.choice(len(cache), min(600, len(cache)), replace=False)]
+        valid, amb, _, _ = O.validate(os_, g, keep, fr.tx_pos, fr.rx_pos)
+        assert np.all(valid | amb)
+        prev = cur
+    # restore frame 0 state for other tests
+    tr.set_frame(district["frames"][0], 0)
+    tr.step(True)
+
+
+def test_district_resume_from_exported_cache(district):
+    """Checkpoint / resume: a fresh context that imports the exported cache
+    produces the same cached-frame channels as the original context."""
+    w, sc = district["w"], district["sc"]
+    tr = district["tr"]
+    fr1 = district["frames"][1]
+    tr.set_frame(district["frames"][0], 0)
+    tr.step(True)
+    keys = tr.cache_export()
+    tr.set_frame(fr1, 1)
+    tr.step(False)
+    a = P.gpu_channels_np(tr.channels())
+    tr2 = _tracer(sc, w, path_capacity=1 << 23)
+    tr2.cache_import(keys)
+    tr2.set_frame(fr1, 1)
+    tr2.step(False)
+    b = P.gpu_channels_np(tr2.channels())
+    tr2.close()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+# ------------------------------------------- 2x2 km city at full size
+def test_city_full_size_sampled():
+    """The benchmark workload (16 Tx x 1M rays, K = 5, diffraction, 10k Rx,
+    two carriers): sampled rays bit-exact and sampled paths exact."""
+    w = city.workload("city")
+    sc = w.scene
+    tr = _tracer(sc, w, path_capacity=1 << 23)
+    fr = sc.frame(0.0)
+    tr.set_frame(fr, 0)
+    tr.step(True)
+    assert tr.sync() == 0
+    st = tr.stats()
+    assert st["n_edges"] == 36800 and st["rays_per_bounce"][0] == 16_000_000
+    os_ = O.OracleScene(sc)
+    g = os_.geometry(fr.obj_xform)
+    for t in (0, 7, 15):
+        ids = np.arange(t, w.rays_per_tx, 8191, dtype=np.int32)
+        hits = tr.debug_rays(t, ids)
+        res = O.trace(os_, g, fr.tx_pos[t], w.rays_per_tx, ids, w.max_reflections, fr.rx_pos, 1.0, True, True)
+        n_rob, mm_rob, _ = P.compare_hitlogs(hits, res.hit_tri, res.robust)
+        assert mm_rob == 0 and n_rob >= 0.9 * len(ids)
+    p = tr.flat_paths(cap=128)
+    rng = np.random.default_rng(3)
+    pick = rng.choice(len(p["key"]), 300, replace=False)
+    valid, amb, tri, pts = O.validate(os_, g, p["key"][pick], fr.tx_pos, fr.rx_pos)
+    assert np.all(valid | amb)
+    ok = valid & ~amb
+    a, tau, fd, _, _ = O.evaluate(os_, g, p["key"][pick][ok], pts[ok], fr, w.freqs_hz)
+    assert np.all(np.abs(p["a"][pick][ok] - a) <= 1e-8 * np.abs(a))
+    assert np.all(np.abs(p["fd"][pick][ok] - fd) <= P.FD_ABS)
+    tr.close()
+
+
+# -------------------------------------------------------------- edge cases
+def test_no_reflections_only_line_of_sight():
+    w = city.workload("toy")
+    sc = w.scene
+    tr = _tracer(sc, w, max_reflections=0, path_capacity=1 << 12)
+    fr = sc.frame(0.0)
+    tr.set_frame(fr)
+    tr.step(True)
+    p = tr.flat_paths()
+    assert np.all(p["key"][:, 2] == 0)
+    ref = O.run_frame(O.OracleScene(sc), fr, w.rays_per_tx, 0, w.freqs_hz)
+    assert P.keyset(p["key"]) == P.keyset(ref.keys)
+    tr.close()
+
+
+def test_single_ray_single_receiver_and_truncation():
+    sc = city.tiny_ground_wall(wall_x=50.0)
+    sc1 = city.with_static_rx(sc, np.array([[30.0, 20.0, 6.0]]))
+    from paper_2303_10521_amd import Tracer
+
+    tr = Tracer(sc1, 1, 1, freq_hz=[28e9], max_reflections=2, rays_per_tx=1, path_capacity=64)
+    fr = static_frame([[0.0, 0.0, 10.0]], [[30.0, 20.0, 6.0]])
+    tr.set_frame(fr)
+    tr.step(True)
+    p = tr.flat_paths()
+    assert P.keyset(p["key"]) == {(0, 0, 0, 0, -1, -1, -1, -1, -1)}  # one ray finds nothing, LoS is always tested
+    # dense launch: four paths; a path-list capacity of 2 reports truncation
+    tr2 = Tracer(sc1, 1, 1, freq_hz=[28e9], max_reflections=2, rays_per_tx=40000, path_capacity=64)
+    tr2.set_frame(fr)
+    tr2.step(True)
+    full = tr2.paths(cap=8)
+    assert int(full["count"][0]) == 4 and not full["truncated"]
+    cut = tr2.paths(cap=2)
+    assert int(cut["count"][0]) == 2 and cut["truncated"]
+    ch = tr2.channels()
+    assert int(ch["n_paths"][0]) == 4  # sums always use every path
+    tr.close()
+    tr2.close()
+
+
+def test_error_paths_on_device():
+    from paper_2303_10521_amd import Tracer
+    from paper_2303_10521_amd.tracer import EmrtError
+
+    w = city.workload("district")
+    sc = w.scene
+    tr = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=[28e9], max_reflections=2, rays_per_tx=20000, diffraction=0,
+                path_capacity=1 << 16, table_capacity=1024)
+    fr = sc.frame(0.0)
+    tr.set_frame(fr)
+    tr.step(True)
+    assert tr.sync() == 2  # tiny path table: EMRT_W_CACHE_FULL (a warning, returned not raised)
+    bad = sc.frame(0.0)
+    bad.obj_xform = bad.obj_xform.copy()
+    bad.obj_xform[0, 0, 3] = np.nan
+    tr2 = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=[28e9], max_reflections=1, rays_per_tx=1000, path_capacity=1 << 16)
+    tr2.set_frame(bad)
+    tr2.step(True)
+    with pytest.raises(EmrtError) as e:
+        tr2.sync()
+    assert e.value.status == -6
+    sc_bad = city.workload("toy").scene
+    sc_bad.tris = sc_bad.tris.copy()
+    sc_bad.tris[3, 1] = len(sc_bad.verts) + 5
+    with pytest.raises(EmrtError) as e:
+        Tracer(sc_bad, 1, sc_bad.n_rx, rays_per_tx=100)
+    assert e.value.status == -1
+    tr.close()
+    tr2.close()

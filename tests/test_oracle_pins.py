@@ -166,10 +166,10 @@ def test_ground_and_wall_corner_paths(K, z_rx):
         assert abs(tau * C0 - L) < 1e-9 * L
 
 
-def test_street_canyon_one_plus_2k():
+@pytest.mark.parametrize("K", [3, 5])
+def test_street_canyon_one_plus_2k(K):
     """Two parallel walls, no ground: 1 + 2K paths for K reflections, lengths
-    from the unfolded images."""
-    K = 3
+    from the unfolded images (K = 5 is the deepest order the method runs)."""
     gap = 20.0
     sc = city.tiny_canyon(gap=gap)
     tx = np.array([[0.0, 2.0, 0.0]])
