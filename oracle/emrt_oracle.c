@@ -755,6 +755,55 @@ int32_t orc_validate(int32_t T, const float* tv, const int32_t* tri_face, const 
     return 0;
 }
 
+/* Interaction points of fixed keys (the gradient reading: the topology is
+ * held fixed, so containment, parameter ranges and occlusion are not
+ * re-evaluated).  Specular: images s_k = mirror(s_{k-1}, plane f_k), then
+ * back from Rx, x_k = segment(x_{k+1} -> s_k) meets plane f_k.  Diffraction:
+ * the Keller point on the edge line, z_Q = z_s + (z_r - z_s) rho_s /
+ * (rho_s + rho_r).  Line of sight has no points.  points [n][5][3]. */
+int32_t orc_image_points(int32_t n_keys, const int32_t* keys, const double* plane, const float* verts,
+                         const int32_t* edges, const double* edge_n, const double* txp, const double* rxp,
+                         double* points) {
+#pragma omp parallel for schedule(static)
+    for (int32_t q = 0; q < n_keys; q++) {
+        const int32_t* key = keys + 9 * q;
+        v3 s = ld3d(txp + 3 * key[0]);
+        v3 r = ld3d(rxp + 3 * key[1]);
+        int type = key[2], order = key[3];
+        for (int i = 0; i < 15; i++) points[15 * q + i] = 0.0;
+        if (type == 1) {
+            v3 img[6];
+            img[0] = s;
+            for (int i = 1; i <= order; i++) {
+                int32_t f = key[3 + i];
+                img[i] = mirror(img[i - 1], ld3d(plane + 4 * f), plane[4 * f + 3]);
+            }
+            v3 cur = r;
+            for (int i = order; i >= 1; i--) {
+                int32_t f = key[3 + i];
+                v3 n = ld3d(plane + 4 * f);
+                v3 dv = vsub(img[i], cur);
+                double tt = (plane[4 * f + 3] - vdot(n, cur)) / vdot(n, dv);
+                cur = vadd(cur, vmul(dv, tt));
+                points[15 * q + 3 * (i - 1) + 0] = cur.x;
+                points[15 * q + 3 * (i - 1) + 1] = cur.y;
+                points[15 * q + 3 * (i - 1) + 2] = cur.z;
+            }
+        } else if (type == 2) {
+            orc_wedge w = wedge_at(verts, edges + 6 * key[4], edge_n[key[4]]);
+            double zs = vdot(vsub(s, w.P0), w.e), zr = vdot(vsub(r, w.P0), w.e);
+            double rs = vlen(vsub(vsub(s, w.P0), vmul(w.e, zs)));
+            double rr = vlen(vsub(vsub(r, w.P0), vmul(w.e, zr)));
+            double zq = zs + (zr - zs) * rs / (rs + rr);
+            v3 Q = vadd(w.P0, vmul(w.e, zq));
+            points[15 * q + 0] = Q.x;
+            points[15 * q + 1] = Q.y;
+            points[15 * q + 2] = Q.z;
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* fields                                                                    */
 /* ------------------------------------------------------------------------ */

@@ -11,7 +11,11 @@ precision) and does the bookkeeping that the paper describes in words:
   invalid paths deleted (Section III-B, the "visibility hash table"),
 * per-receiver channel sums: complex gain, received power, delay and Doppler
   with its power-weighted mean and RMS spread (Section III-C Eq (3) and
-  Section V-D).
+  Section V-D),
+* gradients of a loss of those channels with respect to the permittivities,
+  the transmitter positions and the dipole orientation, by central
+  differences with the path topology held fixed (a reading: the paper has no
+  gradients; ``grad_fd``).
 
 It shares no code with the GPU library (``paper_2303_10521_amd``) and never
 imports it.  The only common dependency is the seeded input generator
@@ -54,7 +58,7 @@ def lib():
     if _lib is None:
         _lib = ctypes.CDLL(build())
         _lib.orc_num_threads.restype = ctypes.c_int32
-        for name in ("orc_face_planes", "orc_edges", "orc_trace", "orc_validate", "orc_eval"):
+        for name in ("orc_face_planes", "orc_edges", "orc_trace", "orc_validate", "orc_eval", "orc_image_points"):
             getattr(_lib, name).restype = ctypes.c_int32
     return _lib
 
@@ -267,7 +271,9 @@ def validate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, tx_pos: np.ndarra
 
 
 def evaluate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, pts: np.ndarray, frame, freqs: Sequence[float],
-             ant_mode: int = 0, obj_vel: Optional[np.ndarray] = None):
+             ant_mode: int = 0, obj_vel: Optional[np.ndarray] = None, materials: Optional[np.ndarray] = None):
+    """Fields of validated keys at the given interaction points.  ``materials``
+    (complex [M]) overrides the scene permittivities."""
     keys = _c(keys.reshape(-1, KEY_W), np.int32)
     n = len(keys)
     nf = len(freqs)
@@ -280,13 +286,112 @@ def evaluate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, pts: np.ndarray, 
     ov = _c(ov if ov.size else np.zeros((1, 3)), np.float64)
     edges = os_.edges if os_.E else np.zeros((1, 6), np.int32)
     en = os_.edge_n if os_.E else np.zeros(1)
+    if materials is None:
+        mats = os_.materials
+    else:
+        m = np.asarray(materials, np.complex128)
+        mats = _c(np.stack([m.real, m.imag], 1), np.float64)
     lib().orc_eval(ctypes.c_int32(n), _p(keys), _p(_c(pts, np.float64)), _p(g.plane), _p(os_.face_material),
-                   _p(os_.face_dyn), _p(ov), _p(os_.materials), _p(g.verts), _p(_c(edges, np.int32)),
+                   _p(os_.face_dyn), _p(ov), _p(mats), _p(g.verts), _p(_c(edges, np.int32)),
                    _p(_c(en, np.float64)), _p(_c(frame.tx_pos, np.float64)), _p(_c(frame.tx_vel, np.float64)),
                    _p(_c(frame.tx_orient, np.float64)), _p(_c(frame.rx_pos, np.float64)),
                    _p(_c(frame.rx_vel, np.float64)), ctypes.c_int32(ant_mode), ctypes.c_int32(nf),
                    _p(_c(np.asarray(freqs, np.float64), np.float64)), _p(a), _p(tau), _p(fd), _p(aod), _p(aoa))
     return a[..., 0] + 1j * a[..., 1], tau, fd, aod, aoa
+
+
+def image_points(os_: OracleScene, g: FrameGeom, keys: np.ndarray, tx_pos: np.ndarray,
+                 rx_pos: np.ndarray) -> np.ndarray:
+    """Interaction points of fixed keys: image method / Keller point with no
+    containment, range or occlusion test (the topology is held fixed)."""
+    keys = _c(keys.reshape(-1, KEY_W), np.int32)
+    n = len(keys)
+    pts = np.zeros((n, 5, 3))
+    edges = os_.edges if os_.E else np.zeros((1, 6), np.int32)
+    en = os_.edge_n if os_.E else np.zeros(1)
+    lib().orc_image_points(ctypes.c_int32(n), _p(keys), _p(g.plane), _p(g.verts), _p(_c(edges, np.int32)),
+                           _p(_c(en, np.float64)), _p(_c(tx_pos, np.float64)), _p(_c(rx_pos, np.float64)), _p(pts))
+    return pts
+
+
+class _FrameView:
+    """A frame with some fields replaced (for finite differences)."""
+
+    def __init__(self, fr, **kw) -> None:
+        for name in ("t", "obj_xform", "obj_vel", "tx_pos", "tx_vel", "rx_pos", "rx_vel", "tx_orient"):
+            setattr(self, name, kw.get(name, getattr(fr, name)))
+
+
+def channel_loss(os_: OracleScene, g: FrameGeom, frame, keys: np.ndarray, freqs: Sequence[float], G_H: np.ndarray,
+                 G_P: Optional[np.ndarray], n_rx: int, p_tx: float = P_TX_W, ant_mode: int = 0,
+                 materials: Optional[np.ndarray] = None) -> float:
+    """L = sum_{f, link} Re(conj(G_H) H) + G_P P_tx |H|^2, with H the coherent
+    sum of the fields of the fixed keys (points rebuilt from the frame).
+    G_H complex [nf, n_links], G_P real [nf, n_links] or None."""
+    keys = np.asarray(keys).reshape(-1, KEY_W)
+    if len(keys) == 0:
+        return 0.0
+    pts = image_points(os_, g, keys, frame.tx_pos, frame.rx_pos)
+    a, _, _, _, _ = evaluate(os_, g, keys, pts, frame, freqs, ant_mode, materials=materials)
+    link = keys[:, 0].astype(np.int64) * n_rx + keys[:, 1]
+    total = 0.0
+    for fi in range(len(freqs)):
+        H = np.zeros(G_H.shape[1], np.complex128)
+        np.add.at(H, link, a[:, fi])
+        total += float(np.sum((np.conj(G_H[fi]) * H).real))
+        if G_P is not None:
+            total += float(np.sum(G_P[fi] * p_tx * np.abs(H) ** 2))
+    return total
+
+
+def grad_fd(os_: OracleScene, g: FrameGeom, frame, keys: np.ndarray, freqs: Sequence[float], G_H: np.ndarray,
+            G_P: Optional[np.ndarray], n_rx: int, p_tx: float = P_TX_W, ant_mode: int = 0, h_pos: float = 1e-6,
+            h_ang: float = 1e-6, h_eps_rel: float = 1e-6) -> Dict[str, np.ndarray]:
+    """Gradients of ``channel_loss`` by central differences with the topology
+    fixed (the keys are not revalidated):
+      grad_tx_pos [n_tx, 3]   dL/d(transmitter position), step h_pos metres;
+      grad_tx_orient [n_tx, 2] dL/d(theta, phi) of the dipole, step h_ang rad
+                               (zero for the vertical isotropic antenna);
+      grad_eps [M] complex     dL/d Re(eps) + j dL/d Im(eps), steps
+                               h_eps_rel |eps| on each part separately.
+    Only the keys of transmitter t change with its position or orientation,
+    and the loss is separable per link, so those differences use its keys."""
+    keys = np.asarray(keys).reshape(-1, KEY_W)
+    n_tx = len(frame.tx_pos)
+    mats = os_.materials[:, 0] + 1j * os_.materials[:, 1]
+    out = {"grad_tx_pos": np.zeros((n_tx, 3)), "grad_tx_orient": np.zeros((n_tx, 2)),
+           "grad_eps": np.zeros(len(mats), np.complex128)}
+
+    def L(fr, ks, m=None):
+        return channel_loss(os_, g, fr, ks, freqs, G_H, G_P, n_rx, p_tx, ant_mode, m)
+
+    for t in range(n_tx):
+        kt = keys[keys[:, 0] == t]
+        if len(kt) == 0:
+            continue
+        for c in range(3):
+            tp, tm = frame.tx_pos.copy(), frame.tx_pos.copy()
+            tp[t, c] += h_pos
+            tm[t, c] -= h_pos
+            out["grad_tx_pos"][t, c] = (L(_FrameView(frame, tx_pos=tp), kt) - L(_FrameView(frame, tx_pos=tm), kt)) / (
+                2 * h_pos)
+        if ant_mode == 1:
+            for c in range(2):
+                op, om = frame.tx_orient.copy(), frame.tx_orient.copy()
+                op[t, c] += h_ang
+                om[t, c] -= h_ang
+                out["grad_tx_orient"][t, c] = (L(_FrameView(frame, tx_orient=op), kt)
+                                               - L(_FrameView(frame, tx_orient=om), kt)) / (2 * h_ang)
+    for m in range(len(mats)):
+        h = h_eps_rel * abs(mats[m])
+        parts = []
+        for d in (h, 1j * h):
+            mp, mm = mats.copy(), mats.copy()
+            mp[m] += d
+            mm[m] -= d
+            parts.append((L(frame, keys, mp) - L(frame, keys, mm)) / (2 * h))
+        out["grad_eps"][m] = parts[0] + 1j * parts[1]
+    return out
 
 
 def reduce_links(keys: np.ndarray, a: np.ndarray, tau: np.ndarray, fd: np.ndarray, n_tx: int, n_rx: int,
