@@ -29,6 +29,102 @@ FLOP_PER_NODE = 24  # two child-box slab tests: 6 sub + 6 mul each
 FLOP_PER_TRI = 36  # watertight test: 9 sub, 6 shear, 9 edge-function, 2 det, 3 scale, 6 T, 1 div
 
 
+def _ev_ms(torch, fn, reps, stream=None):
+    """Mean device time of fn() over reps calls (events on the stream)."""
+    stream = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_adjoint(torch, np, reps: int = 3) -> dict:
+    """Adjoint vs plain forward on the 8-material district: one discovery
+    step forward, then emrt_backward of a loss of every link's H and P_coh."""
+    from paper_2303_10521_amd import Tracer
+    from synth import workload
+
+    w = workload("adjoint")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    kw = dict(freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections, rays_per_tx=w.rays_per_tx,
+              diffraction=int(w.diffraction), diff_max_leg_m=w.diff_max_leg, path_capacity=1 << 22)
+    plain = Tracer(sc, sc.n_tx, sc.n_rx, **kw)
+    plain_bytes = plain.workspace.numel()
+    plain.close()
+    tr = Tracer(sc, sc.n_tx, sc.n_rx, adjoint_materials=len(sc.materials), **kw)
+    tr.set_frame(fr)
+    nf, nl = len(w.freqs_hz), sc.n_tx * sc.n_rx
+    rng = np.random.default_rng(0)
+    GH = torch.as_tensor(rng.normal(size=(nf, nl)) + 1j * rng.normal(size=(nf, nl))).cuda()
+    GP = torch.as_tensor(rng.normal(size=(nf, nl))).cuda()
+    tr.step(True)
+    tr.backward(GH, GP)
+    fwd = _ev_ms(torch, lambda: tr.step(True), reps)
+    bwd = _ev_ms(torch, lambda: tr.backward(GH, GP), reps)
+    st = tr.stats()
+    out = {
+        "workload": f"district with 8 materials: {len(sc.tris)} triangles, {sc.n_tx} Tx x {w.rays_per_tx} rays, "
+                    f"{sc.n_rx} Rx, K={w.max_reflections}, diffraction",
+        "forward_ms": round(fwd, 3),
+        "backward_ms": round(bwd, 3),
+        "backward_over_forward": round(bwd / fwd, 4),
+        "valid_paths": int(st["n_valid"]),
+        "workspace_bytes": int(tr.workspace.numel()),
+        "plain_workspace_bytes": int(plain_bytes),
+    }
+    tr.close()
+    return out
+
+
+def bench_batched(torch, reps: int = 3) -> dict:
+    """64 uneven cities: one batched discovery step (multi-scene bounce
+    launches, graph replay, autotuned launch shape) vs the 64 cities stepped
+    one after the other."""
+    from paper_2303_10521_amd import Batch, Tracer
+    from synth.city import batch_city
+
+    ws = [batch_city(i) for i in range(64)]
+    trs = []
+    for w in ws:
+        sc = w.scene
+        trs.append(Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections,
+                          rays_per_tx=w.rays_per_tx, diffraction=int(w.diffraction), path_capacity=1 << 20))
+        trs[-1].set_frame(sc.frame(0.0))
+    rays = sum(w.rays_per_tx * w.scene.n_tx for w in ws)
+
+    def plain_step():
+        for t in trs:
+            t.step(True)
+
+    plain_step()
+    plain_ms = _ev_ms(torch, plain_step, reps)
+    b = Batch(trs)
+    grid, streams = b.autotune()
+    b.step(True)
+    batched_ms = _ev_ms(torch, lambda: b.step(True), reps, b.stream)
+    rc = b.sync()
+    b.close()
+    for t in trs:
+        t.close()
+    return {
+        "cities": len(ws),
+        "rays_per_step": int(rays),
+        "plain_ms_per_step": round(plain_ms, 3),
+        "batched_ms_per_step": round(batched_ms, 3),
+        "plain_mrays_s": round(rays / (plain_ms * 1e-3) / 1e6, 3),
+        "batched_mrays_s": round(rays / (batched_ms * 1e-3) / 1e6, 3),
+        "speedup": round(plain_ms / batched_ms, 3),
+        "grid": grid,
+        "streams": streams,
+        "status": rc,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,8 +132,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="city")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=512, help="oracle traces every n-th launch direction")
+    ap.add_argument("--cpu-stride", type=int, default=200, help="oracle traces every n-th launch direction")
     ap.add_argument("--timed-only", action="store_true", help="skip extra measurements (for profiler runs)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy 1 GiB device-to-device before the warm-up (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
@@ -59,6 +158,13 @@ def main() -> int:
                 path_capacity=1 << 23)
     stream = torch.cuda.current_stream()
     rays = sc.n_tx * w.rays_per_tx
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # warmup
     for i in range(args.warmup):
@@ -181,6 +287,9 @@ def main() -> int:
                       f"{dt:.1f} s)",
         }
     tr.close()
+    if not args.timed_only and not args.no_extras:
+        out["adjoint"] = bench_adjoint(torch, np)
+        out["batched"] = bench_batched(torch)
     print(json.dumps(out))
     return 0
 

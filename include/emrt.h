@@ -73,6 +73,8 @@ typedef struct emrt_config {
     int32_t path_cap_per_link;  /* default path-list capacity per link (emrt_read_paths) */
     int64_t path_capacity;      /* max candidate keys per frame and cached paths (default 4 Mi) */
     int64_t table_capacity;     /* path-table slots, rounded up to a power of two (default 4 x path_capacity) */
+    int32_t adjoint_materials;  /* 0: no adjoint; else the most materials emrt_backward supports (<= 256);
+                                   adds 8 (5 + 2 adjoint_materials) bytes per link to the workspace */
 } emrt_config;
 
 /* Fill *cfg with the defaults above (one 28 GHz carrier, K = 3, no
@@ -180,6 +182,59 @@ typedef struct emrt_path_view {
     int32_t* count;   /* [n_links] paths written */
 } emrt_path_view;
 int32_t emrt_read_paths(emrt_ctx* ctx, const emrt_path_view* view);
+
+/* Adjoint of the last step: gradients of a real loss L of the channels with
+ * the path topology of that step held fixed (its valid paths are kept; their
+ * interaction points and fields are rebuilt as functions of the parameters).
+ * The paper computes channels only (received power, delay, Doppler:
+ * Section III-C, Section V-D); gradients are an extension of it.
+ *   dL_dH   device [n_freq][n_links][2]  dL/dRe H + j dL/dIm H, or NULL;
+ *   dL_dP   device [n_freq][n_links]     dL/dP_coh, or NULL;
+ * outputs (device, any may be NULL, overwritten):
+ *   grad_eps        [n_materials][2]  dL/dRe eps + j dL/dIm eps;
+ *   grad_tx_pos     [n_tx][3]         dL/d(transmitter position);
+ *   grad_tx_orient  [n_tx][2]         dL/d(theta, phi) of the dipole (0 for EMRT_ANT_ISO_V).
+ * Evaluated at the frame of the last step and the current materials.
+ * Deterministic (fixed-order sums).  Errors: EMRT_E_STATE (no step, or
+ * set_frame since the last step), EMRT_E_UNSUPPORTED (adjoint_materials is 0
+ * or smaller than the scene's material count). */
+int32_t emrt_backward(emrt_ctx* ctx, const double* dL_dH, const double* dL_dP, double* grad_eps, double* grad_tx_pos,
+                      double* grad_tx_orient);
+
+/* Batched stepping of several independent scenes (extension of the frame
+ * step above to many cities at once).  A batch groups contexts that are
+ * bound and have their scene set; it takes over their streams (all work goes
+ * to the batch stream and up to n_streams - 1 helper streams of default
+ * priority).  Per scene the step is the same as emrt_step; the bounces of
+ * all scenes run as one persistent launch per bounce level, and the step is
+ * captured once per (discover, cache parity) as a HIP graph and replayed.
+ * Frames are set and results read through the member contexts
+ * (emrt_set_frame, emrt_read_channels, ...); while batched, emrt_step on a
+ * member returns EMRT_E_STATE.  The batch workspace (device, caller-owned,
+ * from emrt_batch_workspace_size) holds the per-level bounce arguments and
+ * the chunk tables. */
+typedef struct emrt_batch emrt_batch;
+/* Errors: EMRT_E_STATE (a context unbound, without scene or already batched),
+ * EMRT_E_INVALID (repeated context). */
+int32_t emrt_batch_create(emrt_ctx* const* ctxs, int32_t n, emrt_batch** out);
+int32_t emrt_batch_destroy(emrt_batch* batch);
+int32_t emrt_batch_workspace_size(emrt_batch* batch, size_t* bytes);
+int32_t emrt_batch_bind_workspace(emrt_batch* batch, void* device_ptr, size_t bytes);
+/* hipStream_t of the batch (and of every member from now on). */
+int32_t emrt_batch_set_stream(emrt_batch* batch, void* stream);
+/* use_graph 0/1 (default 1), n_streams 1..16 (default 4), grid = workgroups
+ * of the persistent multi-scene bounce launch (default 2048). */
+int32_t emrt_batch_set_options(emrt_batch* batch, int32_t use_graph, int32_t n_streams, int32_t grid);
+/* Step every member (discover as in emrt_step).  Errors: EMRT_E_STATE (a
+ * member without frame, or members at different cache parities),
+ * EMRT_E_WORKSPACE, EMRT_E_HIP (graph capture or launch). */
+int32_t emrt_batch_step(emrt_batch* batch, int32_t discover);
+/* Choose grid and n_streams by timing real discovery steps of the members'
+ * current frames (about nine steps; synchronises). */
+int32_t emrt_batch_autotune(emrt_batch* batch, int32_t* best_grid, int32_t* best_streams);
+/* emrt_sync of every member; returns the most severe status. */
+int32_t emrt_batch_sync(emrt_batch* batch);
+int32_t emrt_batch_last_error(emrt_batch* batch, char* buf, size_t len);
 
 /* Triangle hit per bounce of the last discovery step for launch directions
  * ray_ids (device [n]) of transmitter tx: out device [n][K+1], -1 miss,

@@ -8,7 +8,7 @@ from ._abi import LIB_PATH, load  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Tracer", "EmrtError"):
+    if name in ("Tracer", "Batch", "EmrtError"):
         from . import tracer
 
         return getattr(tracer, name)

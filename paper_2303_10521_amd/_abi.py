@@ -25,6 +25,7 @@ class Config(ctypes.Structure):
         ("n_freq", c_i32), ("freq_hz", c_f64 * 4), ("max_reflections", c_i32), ("diffraction", c_i32),
         ("rays_per_tx", c_i32), ("rx_sphere_k", c_f64), ("diff_max_leg_m", c_f64), ("tx_power_w", c_f64),
         ("antenna_mode", c_i32), ("path_cap_per_link", c_i32), ("path_capacity", c_i64), ("table_capacity", c_i64),
+        ("adjoint_materials", c_i32),
     ]
 
 
@@ -77,6 +78,17 @@ SIGNATURES = {
     "emrt_step": (c_i32, [c_vp, c_i32]),
     "emrt_read_channels": (c_i32, [c_vp, ctypes.POINTER(ChannelView)]),
     "emrt_read_paths": (c_i32, [c_vp, ctypes.POINTER(PathView)]),
+    "emrt_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "emrt_batch_create": (c_i32, [ctypes.POINTER(c_vp), c_i32, ctypes.POINTER(c_vp)]),
+    "emrt_batch_destroy": (c_i32, [c_vp]),
+    "emrt_batch_workspace_size": (c_i32, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "emrt_batch_bind_workspace": (c_i32, [c_vp, c_vp, ctypes.c_size_t]),
+    "emrt_batch_set_stream": (c_i32, [c_vp, c_vp]),
+    "emrt_batch_set_options": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
+    "emrt_batch_step": (c_i32, [c_vp, c_i32]),
+    "emrt_batch_autotune": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "emrt_batch_sync": (c_i32, [c_vp]),
+    "emrt_batch_last_error": (c_i32, [c_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "emrt_debug_ray_records": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_vp]),
     "emrt_cache_size": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "emrt_cache_export": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),

@@ -62,6 +62,10 @@ struct emrt_ctx {
     emrt_config cfg{};
     emrt_sizes sz{};
     bool sized = false, bound = false, scene_set = false, frame_set = false, stepped = false, discovered = false;
+    bool frame_since_step = false;  // set_frame after the last step (the adjoint needs the step's frame)
+    bool batched = false;           // member of an emrt_batch
+    double* adj_rows = nullptr;     // [5 + 2 adjoint_materials][n_links]
+    CompactTemp ctmp{};             // table compaction scratch
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -204,6 +208,9 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->ctr = cv.take<unsigned long long>(kNumCounters);
     c->table = cv.take<unsigned long long>(c->table_slots);
+    c->ctmp.flags = cv.take<uint32_t>(c->table_slots);
+    c->ctmp.off = cv.take<uint32_t>(c->table_slots);
+    c->ctmp.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(c->table_slots) / 4 + 16);
     c->cand = cv.take<KeyRec>(c->P);
     c->cache[0] = cv.take<KeyRec>(c->P);
     c->cache[1] = cv.take<KeyRec>(c->P);
@@ -245,6 +252,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->f_ov = cv.take<double>(3 * O);
     c->mat = cv.take<double>(2 * kMaxMaterials);
     c->flags = cv.take<uint32_t>(16);
+    if (c->cfg.adjoint_materials > 0) c->adj_rows = cv.take<double>((5LL + 2LL * c->cfg.adjoint_materials) * c->n_links);
     if (!cv.measure) c->vp.count = c->ctr + C_NVALID;
 }
 
@@ -290,7 +298,8 @@ int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
     if (cfg->n_freq < 1 || cfg->n_freq > 4 || cfg->max_reflections < 0 || cfg->max_reflections > 5)
         return EMRT_E_UNSUPPORTED;
     if (cfg->rays_per_tx < 1 || !(cfg->rx_sphere_k > 0) || !(cfg->diff_max_leg_m >= 0) || cfg->path_capacity < 1 ||
-        cfg->path_capacity > (1LL << 31) || cfg->antenna_mode < 0 || cfg->antenna_mode > 1)
+        cfg->path_capacity > (1LL << 31) || cfg->antenna_mode < 0 || cfg->antenna_mode > 1 ||
+        cfg->adjoint_materials < 0 || cfg->adjoint_materials > kMaxMaterials)
         return EMRT_E_INVALID;
     for (int i = 0; i < cfg->n_freq; i++)
         if (!(cfg->freq_hz[i] > 0)) return EMRT_E_INVALID;
@@ -444,6 +453,7 @@ int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
         HC(hipMemcpyAsync(c->f_ov, f->obj_vel, sizeof(double) * 3 * c->S.O_d, hipMemcpyDeviceToDevice, st));
     }
     c->frame_set = true;
+    c->frame_since_step = true;
     c->frame_idx = f->frame;
     return hip_check(c, hipGetLastError(), "set_frame");
 }
@@ -499,10 +509,10 @@ static PathArgs path_args(emrt_ctx* c) {
     a.f.rx_pos = c->f_rx; a.f.rx_vel = c->f_rxv; a.f.obj_vel = c->f_ov;
     a.st = c->st.view(); a.dy = c->dy.view();
     a.st_prims = c->st_prims; a.dy_prims = c->dy_prims;
-    a.mat_eps = c->mat;
-    a.nf = c->nf;
-    for (int i = 0; i < EMRT_NF; i++) a.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
-    a.ant_mode = c->cfg.antenna_mode;
+    a.fc.mat_eps = c->mat;
+    a.fc.nf = c->nf;
+    for (int i = 0; i < EMRT_NF; i++) a.fc.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
+    a.fc.ant_mode = c->cfg.antenna_mode;
     a.diff_max_leg = c->cfg.diff_max_leg_m;
     a.out = c->vp;
     a.legs = c->legs;
@@ -513,9 +523,50 @@ static PathArgs path_args(emrt_ctx* c) {
     return a;
 }
 
-int32_t emrt_step(emrt_ctx* c, int32_t discover) {
-    if (!c) return EMRT_E_INVALID;
-    if (!c->scene_set || !c->frame_set) return fail(c, EMRT_E_STATE, "set_scene and set_frame first");
+// ---------------------------------------------------- step, in phases ----
+// A step is enqueued in three phases so that batched stepping can run the
+// bounces of several scenes in one launch: step_pre (frame geometry, trees,
+// on discovery frames the table and the primary rays), the K + 1 bounces,
+// and step_post (candidates, validation, fields, per-link sums, next cache).
+
+// Bounce arguments of level k; tree sizes are those the step's trees have
+// once step_pre has run (so the arguments can be prepared in advance).
+static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
+    SceneDev& S = c->S;
+    bool diff = c->cfg.diffraction && S.E > 0;
+    BounceArgs b{};
+    b.K = c->K;
+    b.n_total = c->n_total;
+    b.rays_per_tx = c->cfg.rays_per_tx;
+    b.st = Bvh{c->st.nodes, S.T_s};
+    b.dy = Bvh{c->dy.nodes, S.T_d};
+    b.st_prims = c->st_prims;
+    b.dy_prims = c->dy_prims;
+    b.plane = S.plane;
+    b.rxt = Bvh{c->rxt.nodes, c->sz.n_rx};
+    b.rx_prims = c->rx_prims;
+    b.alpha_k = (float)(c->cfg.rx_sphere_k * sqrt(4.0 * kPi / (double)c->cfg.rays_per_tx));
+    b.diffraction = diff ? 1 : 0;
+    b.edt = Bvh{c->edt.nodes, diff ? S.E : 0};
+    b.edge_prims = c->edge_prims;
+    b.illum = c->illum;
+    b.e_words = c->e_words;
+    b.table = c->table;
+    b.mask = (unsigned long long)c->table_slots - 1ULL;
+    b.src = KeySrc{c->hitlog, S.tri_face, c->cache[parity], c->n_total, c->cfg.rays_per_tx};
+    b.hitlog = c->hitlog;
+    b.flags = c->flags;
+    b.stats = c->ctr + C_STATS;
+    b.b = k;
+    b.in = c->rays[k & 1];
+    b.out = c->rays[(k + 1) & 1];
+    b.n_in = c->ctr + C_RAYS + k;
+    b.n_out = c->ctr + C_RAYS + k + 1;
+    b.work = (unsigned int*)(c->ctr + C_WORK + k);
+    return b;
+}
+
+static void step_pre(emrt_ctx* c, int discover) {
     hipStream_t st = c->stream;
     SceneDev& S = c->S;
     const int K = c->K;
@@ -546,52 +597,40 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
         bvh_build(c->box_ed, S.E, c->edt, c->tmp, st);
         edge_prims(S, c->edt, c->edge_prims, st);
     }
-    KeySrc src{c->hitlog, S.tri_face, c->cache[c->cur], c->n_total, c->cfg.rays_per_tx};
-    PathArgs pa = path_args(c);
-    const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
     if (discover) {
+        KeySrc src{c->hitlog, S.tri_face, c->cache[c->cur], c->n_total, c->cfg.rays_per_tx};
+        const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
         fill_u64(c->table, 0ULL, c->table_slots, st);
         fill_u32((uint32_t*)c->hitlog, 0xFFFFFFFEu, (long long)(K + 1) * c->n_total, st);
         if (diff) fill_u32(c->illum, 0u, (long long)c->sz.n_tx * c->e_words, st);
         cache_insert(c->table, mask, c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, src, c->flags, st);
         raygen(c->f_tx, c->sz.n_tx, c->cfg.rays_per_tx, c->dir_perm, c->rays[0], c->ctr + C_RAYS, st);
-        BounceArgs b{};
-        b.K = K;
-        b.n_total = c->n_total;
-        b.rays_per_tx = c->cfg.rays_per_tx;
-        b.st = c->st.view(); b.dy = c->dy.view();
-        b.st_prims = c->st_prims; b.dy_prims = c->dy_prims;
-        b.plane = S.plane;
-        b.rxt = c->rxt.view();
-        b.rx_prims = c->rx_prims;
-        b.alpha_k = (float)(c->cfg.rx_sphere_k * sqrt(4.0 * kPi / (double)c->cfg.rays_per_tx));
-        b.diffraction = diff ? 1 : 0;
-        b.edt = c->edt.view();
-        b.edge_prims = c->edge_prims;
-        b.illum = c->illum;
-        b.e_words = c->e_words;
-        b.table = c->table;
-        b.mask = mask;
-        b.src = src;
-        b.hitlog = c->hitlog;
-        b.flags = c->flags;
-        b.stats = c->ctr + C_STATS;
-        long long g = (c->n_total + 255) / 256;
-        int grid = (int)std::min<long long>(std::max<long long>(g, 1), 2048);
-        for (int k = 0; k <= K; k++) {
-            b.b = k;
-            b.in = c->rays[k & 1];
-            b.out = c->rays[(k + 1) & 1];
-            b.n_in = c->ctr + C_RAYS + k;
-            b.n_out = c->ctr + C_RAYS + k + 1;
-            b.work = (unsigned int*)(c->ctr + C_WORK + k);
-            ev_record(c);
-            bounce(b, c->stats_on != 0, grid, st);
-            ev_record(c);
-        }
-        c->evs[c->ev_parity].bounce_end = c->evs[c->ev_parity].used;
+    }
+}
+
+static void step_bounces(emrt_ctx* c) {
+    long long g = (c->n_total + 255) / 256;
+    int grid = (int)std::min<long long>(std::max<long long>(g, 1), 2048);
+    for (int k = 0; k <= c->K; k++) {
+        BounceArgs b = bounce_args(c, k, c->cur);
+        ev_record(c);
+        bounce(b, c->stats_on != 0, grid, c->stream);
+        ev_record(c);
+    }
+    c->evs[c->ev_parity].bounce_end = c->evs[c->ev_parity].used;
+}
+
+static void step_post(emrt_ctx* c, int discover) {
+    hipStream_t st = c->stream;
+    SceneDev& S = c->S;
+    bool diff = c->cfg.diffraction && S.E > 0;
+    KeySrc src{c->hitlog, S.tri_face, c->cache[c->cur], c->n_total, c->cfg.rays_per_tx};
+    PathArgs pa = path_args(c);
+    const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
+    if (discover) {
         if (diff) diff_candidates(pa, c->illum, c->e_words, c->rxt.view(), c->rx_prims, c->table, mask, src, st);
-        table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags, st);
+        table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags,
+                      c->ctmp, st);
         pa.cand = c->cand;
         pa.n_cand = c->ctr + C_NCAND;
         c->discovered = true;
@@ -619,11 +658,54 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
     cache_write(c->vp, c->order, c->link_start, c->link_end, c->link_off, c->n_links, c->cache[nxt], st);
     c->cur = nxt;
     c->stepped = true;
+    c->frame_since_step = false;
     if (c->timing_on) {
         c->evs[c->ev_parity].pending = true;
         c->ev_parity ^= 1;
     }
+}
+
+int32_t emrt_step(emrt_ctx* c, int32_t discover) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->scene_set || !c->frame_set) return fail(c, EMRT_E_STATE, "set_scene and set_frame first");
+    if (c->batched) return fail(c, EMRT_E_STATE, "context belongs to a batch: use emrt_batch_step");
+    step_pre(c, discover);
+    if (discover) step_bounces(c);
+    step_post(c, discover);
     return hip_check(c, hipGetLastError(), "step");
+}
+
+int32_t emrt_backward(emrt_ctx* c, const double* dL_dH, const double* dL_dP, double* grad_eps, double* grad_tx_pos,
+                      double* grad_tx_orient) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->stepped || c->frame_since_step)
+        return fail(c, EMRT_E_STATE, "backward needs a step after the last set_frame");
+    if (c->cfg.adjoint_materials <= 0 || !c->adj_rows)
+        return fail(c, EMRT_E_UNSUPPORTED, "adjoint_materials is 0 in the configuration");
+    if (c->S.M > c->cfg.adjoint_materials)
+        return fail(c, EMRT_E_UNSUPPORTED, "more materials than adjoint_materials");
+    AdjArgs a{};
+    a.s = c->S;
+    a.fc.mat_eps = c->mat;
+    a.fc.nf = c->nf;
+    for (int i = 0; i < EMRT_NF; i++) a.fc.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
+    a.fc.ant_mode = c->cfg.antenna_mode;
+    a.tx_pos = c->f_tx;
+    a.tx_orient = c->f_txo;
+    a.rx_pos = c->f_rx;
+    a.vp = c->vp;
+    a.order = c->order;
+    a.start = c->link_start;
+    a.end = c->link_end;
+    a.chan = c->chan;
+    a.dL_dH = dL_dH;
+    a.dL_dP = dL_dP;
+    a.p_tx = c->cfg.tx_power_w;
+    a.n_links = c->n_links;
+    a.M = c->S.M;
+    a.rows = c->adj_rows;
+    adjoint(a, c->sz.n_tx, c->sz.n_rx, grad_tx_pos, grad_tx_orient, grad_eps, c->stream);
+    return hip_check(c, hipGetLastError(), "backward");
 }
 
 int32_t emrt_sync(emrt_ctx* c) {
@@ -788,6 +870,352 @@ int32_t emrt_last_error(emrt_ctx* c, char* buf, size_t len) {
     size_t n = std::min(len - 1, c->err.size());
     memcpy(buf, c->err.data(), n);
     buf[n] = 0;
+    return EMRT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch ----
+// Batched stepping of several independent scenes (each a context with its
+// own workspace): the per-scene phases run on n_streams streams (scenes
+// round-robin), the bounces of all scenes run as one persistent launch per
+// bounce level (k_bounce_multi over a device table of chunk offsets), and
+// the whole step is captured once per (discover, cache parity) as a HIP graph
+// and replayed.  Results are those of stepping each context alone.
+struct emrt_batch {
+    std::vector<emrt_ctx*> ctx;
+    int kmax = 0;
+    hipStream_t stream = nullptr;
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    int n_streams = 4, grid = 2048;
+    bool use_graph = true;
+    // workspace
+    char* ws = nullptr;
+    BounceArgs* args = nullptr;  // [2 parities][kmax + 1][n]
+    uint32_t* chunk_off = nullptr;  // [kmax + 1][n + 1]
+    uint32_t* work = nullptr;       // [kmax + 1]
+    unsigned long long* zero = nullptr;
+    bool args_ready[2] = {false, false};
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [discover][parity]
+    std::string err;
+};
+
+static size_t batch_layout(emrt_batch* b, Carver& cv) {
+    long long n = (long long)b->ctx.size();
+    b->args = cv.take<BounceArgs>(2LL * (b->kmax + 1) * n);
+    b->chunk_off = cv.take<uint32_t>((long long)(b->kmax + 1) * (n + 1));
+    b->work = cv.take<uint32_t>(b->kmax + 1);
+    b->zero = cv.take<unsigned long long>(1);
+    return cv.off;
+}
+
+static void batch_drop_graphs(emrt_batch* b) {
+    for (auto& row : b->exec)
+        for (auto& e : row)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+}
+
+static void batch_streams(emrt_batch* b) {
+    for (auto s : b->side) (void)hipStreamDestroy(s);
+    b->side.clear();
+    for (auto e : b->join) (void)hipEventDestroy(e);
+    b->join.clear();
+    for (int i = 0; i + 1 < b->n_streams; i++) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
+        b->side.push_back(s);
+        hipEvent_t e;
+        (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        b->join.push_back(e);
+    }
+}
+
+// run f(ctx) for every scene, scene i on stream i mod (1 + side streams)
+template <class F>
+static void batch_fan(emrt_batch* b, F f) {
+    int ns = 1 + (int)b->side.size();
+    if (ns > 1) {
+        (void)hipEventRecord(b->fork, b->stream);
+        for (auto s : b->side) (void)hipStreamWaitEvent(s, b->fork, 0);
+    }
+    for (size_t i = 0; i < b->ctx.size(); i++) {
+        int k = (int)(i % ns);
+        b->ctx[i]->stream = k == 0 ? b->stream : b->side[k - 1];
+        f(b->ctx[i]);
+    }
+    for (size_t j = 0; j < b->side.size(); j++) {
+        (void)hipEventRecord(b->join[j], b->side[j]);
+        (void)hipStreamWaitEvent(b->stream, b->join[j], 0);
+    }
+    for (auto c : b->ctx) c->stream = b->stream;
+}
+
+static void batch_enqueue(emrt_batch* b, int discover, int parity) {
+    batch_fan(b, [&](emrt_ctx* c) { step_pre(c, discover); });
+    if (discover) {
+        long long n = (long long)b->ctx.size();
+        for (int k = 0; k <= b->kmax; k++)
+            bounce_multi(b->args + ((long long)parity * (b->kmax + 1) + k) * n, (int)n,
+                         b->chunk_off + (long long)k * (n + 1), b->work + k, b->grid, b->stream);
+    }
+    batch_fan(b, [&](emrt_ctx* c) { step_post(c, discover); });
+}
+
+static int32_t batch_fail(emrt_batch* b, int32_t st, const std::string& m) {
+    if (b) b->err = m;
+    return st;
+}
+
+extern "C" {
+
+int32_t emrt_batch_create(emrt_ctx* const* ctxs, int32_t n, emrt_batch** out) {
+    if (!ctxs || n < 1 || !out) return EMRT_E_INVALID;
+    *out = nullptr;
+    emrt_batch* b = new emrt_batch();
+    for (int i = 0; i < n; i++) {
+        emrt_ctx* c = ctxs[i];
+        if (!c || !c->bound || !c->scene_set || c->batched) {
+            delete b;
+            return EMRT_E_STATE;
+        }
+        for (int j = 0; j < i; j++)
+            if (ctxs[j] == c) {
+                delete b;
+                return EMRT_E_INVALID;
+            }
+        b->ctx.push_back(c);
+        b->kmax = std::max(b->kmax, c->K);
+    }
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return EMRT_E_HIP;
+    }
+    b->stream = ctxs[0]->stream;
+    batch_streams(b);
+    for (auto c : b->ctx) {
+        c->batched = true;
+        c->stream = b->stream;
+    }
+    *out = b;
+    return EMRT_OK;
+}
+
+int32_t emrt_batch_destroy(emrt_batch* b) {
+    if (!b) return EMRT_E_INVALID;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    for (auto s : b->side) (void)hipStreamSynchronize(s);
+    for (auto s : b->side) (void)hipStreamDestroy(s);
+    for (auto e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (auto c : b->ctx) c->batched = false;
+    delete b;
+    return EMRT_OK;
+}
+
+int32_t emrt_batch_workspace_size(emrt_batch* b, size_t* bytes) {
+    if (!b || !bytes) return EMRT_E_INVALID;
+    Carver m(nullptr);
+    *bytes = batch_layout(b, m) + 256;
+    return EMRT_OK;
+}
+
+int32_t emrt_batch_bind_workspace(emrt_batch* b, void* ptr, size_t bytes) {
+    if (!b || !ptr) return batch_fail(b, EMRT_E_WORKSPACE, "null workspace");
+    Carver m(nullptr);
+    char* base = (char*)(((uintptr_t)ptr + 255) & ~(uintptr_t)255);
+    if (bytes < batch_layout(b, m) + (size_t)(base - (char*)ptr)) return batch_fail(b, EMRT_E_WORKSPACE, "too small");
+    Carver cv(base);
+    batch_layout(b, cv);
+    b->ws = (char*)ptr;
+    b->args_ready[0] = b->args_ready[1] = false;
+    batch_drop_graphs(b);
+    fill_u64(b->zero, 0ULL, 1, b->stream);
+    return EMRT_OK;
+}
+
+int32_t emrt_batch_set_stream(emrt_batch* b, void* s) {
+    if (!b) return EMRT_E_INVALID;
+    b->stream = (hipStream_t)s;
+    for (auto c : b->ctx) c->stream = b->stream;
+    batch_drop_graphs(b);
+    return EMRT_OK;
+}
+
+int32_t emrt_batch_set_options(emrt_batch* b, int32_t use_graph, int32_t n_streams, int32_t grid) {
+    if (!b || n_streams < 1 || n_streams > 16 || grid < 1 || grid > (1 << 20)) return EMRT_E_INVALID;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    b->use_graph = use_graph != 0;
+    b->grid = grid;
+    if (n_streams != b->n_streams) {
+        b->n_streams = n_streams;
+        batch_streams(b);
+    }
+    return EMRT_OK;
+}
+
+int32_t emrt_batch_step(emrt_batch* b, int32_t discover) {
+    if (!b) return EMRT_E_INVALID;
+    if (!b->ws) return batch_fail(b, EMRT_E_WORKSPACE, "bind a batch workspace first");
+    const int parity = b->ctx[0]->cur;
+    for (auto c : b->ctx) {
+        if (!c->scene_set || !c->frame_set) return batch_fail(b, EMRT_E_STATE, "set_scene and set_frame on every member");
+        if (c->cur != parity) return batch_fail(b, EMRT_E_STATE, "members stepped separately");
+    }
+    discover = discover ? 1 : 0;
+    const long long n = (long long)b->ctx.size();
+    if (discover && !b->args_ready[parity]) {
+        std::vector<BounceArgs> h((size_t)(b->kmax + 1) * n);
+        for (int k = 0; k <= b->kmax; k++)
+            for (long long i = 0; i < n; i++) {
+                emrt_ctx* c = b->ctx[i];
+                BounceArgs a = bounce_args(c, std::min(k, c->K), parity);
+                if (k > c->K) a.n_in = b->zero;  // scene with fewer bounces: nothing to trace
+                h[(size_t)k * n + i] = a;
+            }
+        BounceArgs* dst = b->args + (long long)parity * (b->kmax + 1) * n;
+        hipError_t e = hipMemcpyAsync(dst, h.data(), sizeof(BounceArgs) * h.size(), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return batch_fail(b, EMRT_E_HIP, hipGetErrorString(e));
+        b->args_ready[parity] = true;
+    }
+    // timing and statistics instrumentation is not used in batched steps
+    std::vector<int> timing(n), stats(n);
+    for (long long i = 0; i < n; i++) {
+        timing[i] = b->ctx[i]->timing_on;
+        stats[i] = b->ctx[i]->stats_on;
+        b->ctx[i]->timing_on = 0;
+        b->ctx[i]->stats_on = 0;
+    }
+    int32_t rc = EMRT_OK;
+    if (!b->use_graph) {
+        batch_enqueue(b, discover, parity);
+    } else {
+        hipGraphExec_t& ex = b->exec[discover][parity];
+        if (!ex) {
+            // capture: enqueueing advances host state, which the graph has not
+            // executed yet; keep it and restore after the capture
+            std::vector<int> cur(n);
+            std::vector<char> disc(n);
+            std::vector<int> dyn(n);
+            for (long long i = 0; i < n; i++) {
+                cur[i] = b->ctx[i]->cur;
+                disc[i] = b->ctx[i]->discovered;
+                dyn[i] = b->ctx[i]->dy.n;
+            }
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                batch_enqueue(b, discover, parity);
+                e = hipStreamEndCapture(b->stream, &g);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            for (long long i = 0; i < n; i++) {
+                b->ctx[i]->cur = cur[i];
+                b->ctx[i]->discovered = disc[i];
+                b->ctx[i]->dy.n = dyn[i];
+            }
+            if (e != hipSuccess) {
+                ex = nullptr;
+                rc = batch_fail(b, EMRT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            }
+        }
+        if (rc == EMRT_OK) {
+            hipError_t e = hipGraphLaunch(ex, b->stream);
+            if (e != hipSuccess) rc = batch_fail(b, EMRT_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+            for (auto c : b->ctx) {
+                c->cur = 1 - parity;
+                if (discover) c->discovered = true;
+                if (c->S.T_d > 0) c->dy.n = c->S.T_d;
+            }
+        }
+    }
+    for (long long i = 0; i < n; i++) {
+        b->ctx[i]->timing_on = timing[i];
+        b->ctx[i]->stats_on = stats[i];
+        if (rc == EMRT_OK) {
+            b->ctx[i]->stepped = true;
+            b->ctx[i]->frame_since_step = false;
+        }
+    }
+    if (rc != EMRT_OK) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? EMRT_OK : batch_fail(b, EMRT_E_HIP, hipGetErrorString(e));
+}
+
+// Autotune the launch shape on real discovery steps (the member frames as
+// set): the persistent grid of the multi-scene bounce, then the number of
+// streams the per-scene phases are spread over.  Each trial is one eager
+// discovery step timed with HIP events on the batch stream.
+int32_t emrt_batch_autotune(emrt_batch* b, int32_t* best_grid, int32_t* best_streams) {
+    if (!b) return EMRT_E_INVALID;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return batch_fail(b, EMRT_E_HIP, "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return batch_fail(b, EMRT_E_HIP, "event");
+    }
+    bool graph = b->use_graph;
+    auto trial = [&](int grid, int ns, float& ms) -> int32_t {
+        int32_t rc = emrt_batch_set_options(b, 0, ns, grid);
+        if (rc) return rc;
+        (void)hipEventRecord(e0, b->stream);
+        rc = emrt_batch_step(b, 1);
+        (void)hipEventRecord(e1, b->stream);
+        if (rc) return rc;
+        if (hipEventSynchronize(e1) != hipSuccess) return batch_fail(b, EMRT_E_HIP, "autotune sync");
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return EMRT_OK;
+    };
+    int32_t rc = EMRT_OK;
+    float warm = 0;
+    rc = trial(b->grid, b->n_streams, warm);  // warm-up (first-touch, code loading)
+    int g_best = b->grid, s_best = b->n_streams;
+    float t_best = 1e30f;
+    const int grids[] = {1024, 2048, 4096, 8192};
+    for (int g : grids) {
+        float ms = 0;
+        if (rc == EMRT_OK) rc = trial(g, s_best, ms);
+        if (rc == EMRT_OK && ms < t_best) { t_best = ms; g_best = g; }
+    }
+    const int streams[] = {1, 2, 4, 8};
+    for (int ns : streams) {
+        float ms = 0;
+        if (rc == EMRT_OK) rc = trial(g_best, ns, ms);
+        if (rc == EMRT_OK && ms < t_best) { t_best = ms; s_best = ns; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != EMRT_OK) return rc;
+    rc = emrt_batch_set_options(b, graph ? 1 : 0, s_best, g_best);
+    if (best_grid) *best_grid = g_best;
+    if (best_streams) *best_streams = s_best;
+    return rc;
+}
+
+int32_t emrt_batch_sync(emrt_batch* b) {
+    if (!b) return EMRT_E_INVALID;
+    int32_t worst = EMRT_OK;
+    for (auto c : b->ctx) {
+        int32_t r = emrt_sync(c);
+        if (r < 0 && (worst >= 0 || r < worst)) worst = r;
+        else if (r > 0 && worst == EMRT_OK) worst = r;
+    }
+    return worst;
+}
+
+int32_t emrt_batch_last_error(emrt_batch* b, char* buf, size_t len) {
+    if (!b || !buf || len == 0) return EMRT_E_INVALID;
+    size_t k = std::min(len - 1, b->err.size());
+    memcpy(buf, b->err.data(), k);
+    buf[k] = 0;
     return EMRT_OK;
 }
 

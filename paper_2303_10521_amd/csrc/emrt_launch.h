@@ -129,6 +129,9 @@ void ray_order(int N, uint32_t* perm, const BuildTemp& tmp, hipStream_t st);
 void raygen(const double* tx_pos, int n_tx, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
             hipStream_t st);
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
+// one launch over several scenes' live rays (args device [n_scenes]; chunk_off [n_scenes + 1], work: scratch)
+void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid,
+                  hipStream_t st);
 void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ray_ids, int n, int* out,
                 hipStream_t st);
 
@@ -163,6 +166,14 @@ struct LegBuf {
     long long cap;
 };
 
+// inputs of the field evaluation shared by the forward and the adjoint
+struct FieldCtx {
+    const double* mat_eps;  // [M][2] relative permittivities
+    double freq[EMRT_NF];   // carriers, Hz
+    int nf;
+    int ant_mode;           // transmit antenna
+};
+
 struct PathArgs {
     SceneDev s;
     LegBuf legs;
@@ -172,10 +183,7 @@ struct PathArgs {
     Bvh st, dy;
     const TriP* st_prims;
     const TriP* dy_prims;
-    const double* mat_eps;  // [M][2]
-    int nf;
-    double freq[EMRT_NF];
-    int ant_mode;
+    FieldCtx fc;
     double diff_max_leg;
     // inputs
     const KeyRec* cand;
@@ -188,8 +196,14 @@ void cache_insert(unsigned long long* table, unsigned long long mask, const KeyR
                   const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags, hipStream_t st);
 void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, Bvh rxt, const float4* rx_prims,
                      unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
+// scratch of the table compaction: [n_slots] flags and offsets + scan temp
+struct CompactTemp {
+    uint32_t* flags;
+    uint32_t* off;
+    uint32_t* scan_tmp;
+};
 void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
-                   unsigned long long* n_cand, long long cap, uint32_t* flags, hipStream_t st);
+                   unsigned long long* n_cand, long long cap, uint32_t* flags, const CompactTemp& t, hipStream_t st);
 void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, hipStream_t st);
 void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st);
 void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
@@ -205,5 +219,26 @@ void path_gather(const ValidPaths& vp, const uint32_t* order, const int* start, 
                  int32_t* count, hipStream_t st);
 void keys_export(const KeyRec* cache, long long n, int32_t* out, hipStream_t st);
 void keys_import(const int32_t* in, long long n, KeyRec* cache, hipStream_t st);
+
+// ---------------------------------------------------------- adjoint.hip ----
+struct AdjArgs {
+    SceneDev s;
+    FieldCtx fc;
+    const double* tx_pos;     // [N_tx][3] frame of the last step
+    const double* tx_orient;  // [N_tx][2]
+    const double* rx_pos;     // [N_rx][3]
+    ValidPaths vp;            // valid paths of the last step
+    const uint32_t* order;    // path indices sorted by (link, key)
+    const int* start;         // [n_links] first sorted index of a link, -1 if none
+    const int* end;           // [n_links]
+    const double* chan;       // channel sums of the last step (H at [(f n_links + l) 8 + 0, 1])
+    const double* dL_dH;      // [nf][n_links][2] or null
+    const double* dL_dP;      // [nf][n_links] or null
+    double p_tx;
+    long long n_links;
+    int M;                    // materials
+    double* rows;             // [5 + 2 M][n_links] per-link partial gradients
+};
+void adjoint(const AdjArgs& a, int n_tx, int n_rx, double* g_pos, double* g_ori, double* g_eps, hipStream_t st);
 
 }  // namespace emrt

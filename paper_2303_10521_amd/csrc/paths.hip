@@ -13,6 +13,7 @@
 // power-weighted mean Doppler shift / RMS Doppler spread of Section V-D.
 #include "emrt_dev.h"
 #include "emrt_launch.h"
+#include "fields.h"
 
 namespace emrt {
 
@@ -43,37 +44,41 @@ void cache_insert(unsigned long long* table, unsigned long long mask, const KeyR
                        flags);
 }
 
-__global__ void __launch_bounds__(256) k_table_compact(const unsigned long long* table, unsigned long long n_slots,
-                                                       KeySrc src, KeyRec* cand, unsigned long long* n_cand,
-                                                       long long cap, uint32_t* flags) {
-    // every lane of a wave runs the same number of iterations (ballot below)
-    unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    unsigned long long start = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long iters = (n_slots + stride - 1) / stride;
-    for (unsigned long long it = 0; it < iters; it++) {
-        unsigned long long i = start + it * stride;
-        unsigned long long ref = i < n_slots ? table[i] : 0ULL;
-        long long pos = wave_append(n_cand, ref != 0ULL);
-        if (pos >= 0) {
-            if (pos < cap) {
-                KeyRec k;
-                expand_ref(ref, src, k);
-                cand[pos] = k;
-            } else {
-                atomicOr(flags, FLAG_CAND_CAP);
-            }
+// Table compaction without a shared counter: occupied-slot flags, an
+// exclusive scan (the candidate index of every occupied slot, in slot
+// order), then each occupied slot expands its reference into the full key.
+__global__ void __launch_bounds__(256) k_slot_flags(const unsigned long long* table, unsigned long long n_slots,
+                                                    uint32_t* flags_out) {
+    GRID_STRIDE(i, (long long)n_slots) flags_out[i] = table[i] != 0ULL ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_table_emit(const unsigned long long* table, unsigned long long n_slots,
+                                                    const uint32_t* off, KeySrc src, KeyRec* cand, long long cap,
+                                                    uint32_t* flags) {
+    GRID_STRIDE(i, (long long)n_slots) {
+        unsigned long long ref = table[i];
+        if (ref == 0ULL) continue;
+        long long pos = (long long)off[i];
+        if (pos < cap) {
+            KeyRec k;
+            expand_ref(ref, src, k);
+            cand[pos] = k;
+        } else {
+            atomicOr(flags, FLAG_CAND_CAP);
         }
     }
 }
 
 void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
-                   unsigned long long* n_cand, long long cap, uint32_t* flags, hipStream_t st) {
-    hipLaunchKernelGGL(k_table_compact, dim3(grid_for((long long)n_slots)), dim3(256), 0, st, table, n_slots, src,
-                       cand, n_cand, cap, flags);
+                   unsigned long long* n_cand, long long cap, uint32_t* flags, const CompactTemp& t, hipStream_t st) {
+    int g = grid_for((long long)n_slots, 256, 16384);
+    hipLaunchKernelGGL(k_slot_flags, dim3(g), dim3(256), 0, st, table, n_slots, t.flags);
+    // n_cand: low word = scan total (its high word is cleared with the step's counters)
+    exclusive_scan(t.flags, t.off, (long long)n_slots, t.scan_tmp, (uint32_t*)n_cand, st);
+    hipLaunchKernelGGL(k_table_emit, dim3(g), dim3(256), 0, st, table, n_slots, t.off, src, cand, cap, flags);
 }
 
 // ------------------------------------------------------------ geometry ----
-__device__ __forceinline__ dv3 vert(const SceneDev& s, int v) { return ldf3(s.verts + 3 * (long long)v); }
 
 __device__ __forceinline__ dv3 mirror(dv3 p, const double* pl) {
     dv3 n = d3(pl[0], pl[1], pl[2]);
@@ -111,38 +116,6 @@ __device__ __forceinline__ bool occluded(const PathArgs& a, dv3 p0, dv3 p1, int 
     RayPre r = ray_pre((float)p0.x, (float)p0.y, (float)p0.z, (float)d.x, (float)d.y, (float)d.z);
     if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb)) return true;
     return any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb);
-}
-
-struct Wedge {
-    dv3 P0, e, t0, n0;
-    double len, n;
-    int f0, fn;
-};
-
-__device__ __forceinline__ Wedge wedge_of(const SceneDev& s, int e) {
-    const int* row = s.edge_i + 6 * (long long)e;
-    Wedge w;
-    w.P0 = vert(s, row[0]);
-    dv3 ev = vert(s, row[1]) - w.P0;
-    w.len = len(ev);
-    w.e = ev * (1.0 / w.len);
-    dv3 r0 = vert(s, row[4]) - w.P0, rn = vert(s, row[5]) - w.P0;
-    w.t0 = unit(r0 - w.e * dot(r0, w.e));
-    dv3 tn = unit(rn - w.e * dot(rn, w.e));
-    dv3 n0 = cross(w.e, w.t0);
-    if (dot(n0, tn) > 0) n0 = n0 * -1.0;
-    w.n0 = n0;
-    w.n = s.edge_n[e];
-    w.f0 = row[2];
-    w.fn = row[3];
-    return w;
-}
-
-__device__ __forceinline__ double wedge_angle(const Wedge& w, dv3 p) {
-    dv3 v = p - w.P0;
-    double ph = atan2(dot(v, w.n0), dot(v, w.t0));
-    if (ph < 0) ph += 2.0 * kPi;
-    return ph;
 }
 
 // Keller point (equal angles with the edge) strictly inside the edge, both
@@ -195,117 +168,6 @@ void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, Bvh 
     hipLaunchKernelGGL(k_diff_cand, dim3(grid_for(n, 128)), dim3(128), 0, st, a, illum, e_words, rxt, rx_prims, table,
                        mask, src);
 }
-
-// -------------------------------------------------------------- fields ----
-// Fresnel reflection coefficients for relative permittivity eps (eps' - j eps'',
-// time factor exp(+j w t)) at incidence cosine c, principal square root.
-__device__ __forceinline__ void fresnel(cd eps, double c, cd& te, cd& tm) {
-    cd rt = csqrtd(eps - C(1.0 - c * c));
-    te = cdiv(C(c) - rt, C(c) + rt);
-    cd ec = eps * c;
-    tm = cdiv(ec - rt, ec + rt);
-}
-
-// erfcx(w) = exp(w^2) erfc(w) on w = exp(j pi/4) v, v >= 0: power series of
-// erf for v < 2.5 (Abramowitz & Stegun 7.1.5), Laplace continued fraction
-// (A&S 7.1.14) by the modified Lentz method otherwise.
-__device__ cd erfcx_diag(double v) {
-    const double h = 0.70710678118654752440;
-    cd w = C(v * h, v * h);
-    if (v < 2.5) {
-        cd w2 = w * w;
-        cd term = w, sum = w;
-        for (int n = 1; n < 400; n++) {
-            term = term * (w2 * (-1.0 / (double)n));
-            cd add = term * (1.0 / (double)(2 * n + 1));
-            sum = sum + add;
-            if (cabsd(add) < 1e-18 * (cabsd(sum) + 1e-300)) break;
-        }
-        cd erfc_w = C(1.0) - sum * (2.0 / sqrt(kPi));
-        return cexpi(v * v) * erfc_w;  // exp(w^2), w^2 = j v^2
-    }
-    const double tiny = 1e-300;
-    cd f = w, Cc = w, D = C(0.0);
-    for (int n = 1; n < 5000; n++) {
-        double an = 0.5 * n;
-        D = w + D * an;
-        if (cabsd(D) < tiny) D = C(tiny);
-        Cc = w + cdiv(C(an), Cc);
-        if (cabsd(Cc) < tiny) Cc = C(tiny);
-        D = cdiv(C(1.0), D);
-        cd delta = Cc * D;
-        f = f * delta;
-        if (cabsd(delta - C(1.0)) < 1e-16) break;
-    }
-    return cdiv(C(1.0), f * sqrt(kPi));
-}
-
-// UTD transition function F(X) = e^{j pi/4} sqrt(pi X) erfcx(e^{j pi/4} sqrt X)
-// (Kouyoumjian & Pathak 1974), X >= 0.
-__device__ cd utd_F(double X) {
-    if (X <= 0) return C(0.0);
-    const double h = 0.70710678118654752440;
-    return C(h, h) * erfcx_diag(sqrt(X)) * sqrt(kPi * X);
-}
-
-// cot((pi + sg beta)/(2n)) F(kL a^{sg}(beta)), with the boundary limit
-// n e^{j pi/4} [sqrt(2 pi kL) sgn(eps) - 2 kL eps e^{j pi/4}] for |eps| < 1e-4.
-__device__ cd utd_term(double sg, double beta, double n, double kL) {
-    double N = rint((beta + sg * kPi) / (2.0 * kPi * n));
-    double eps = kPi + sg * (beta - 2.0 * kPi * n * N);
-    const double h = 0.70710678118654752440;
-    if (fabs(eps) < 1e-4) {
-        double sgn = eps > 0 ? 1.0 : (eps < 0 ? -1.0 : 0.0);
-        cd e4 = C(h, h);
-        return e4 * (C(sqrt(2.0 * kPi * kL) * sgn) - e4 * (2.0 * kL * eps)) * n;
-    }
-    double c = cos((2.0 * kPi * n * N - beta) * 0.5);
-    double x = (kPi + sg * beta) / (2.0 * n);
-    return utd_F(kL * 2.0 * c * c) * (cos(x) / sin(x));
-}
-
-// Kouyoumjian-Pathak coefficient with the Luebbers lossy-face factors
-// (R_0 of the 0-face at incidence cosine sin(beta0)|sin phi'|, R_n of the
-// n-face at sin(beta0)|sin(n pi - phi)|; TE for soft, TM for hard).
-__device__ void utd_D(double n, double k, double L, double beta0, double php, double ph, cd eps0, cd epsn, cd& Ds,
-                      cd& Dh) {
-    double sb = sin(beta0);
-    const double h = 0.70710678118654752440;
-    cd Cc = C(-h, h) * (1.0 / (2.0 * n * sqrt(2.0 * kPi * k) * sb));  // -e^{-j pi/4} / (...)
-    double kL = k * L;
-    cd t1 = utd_term(+1, ph - php, n, kL);
-    cd t2 = utd_term(-1, ph - php, n, kL);
-    cd t3 = utd_term(+1, ph + php, n, kL);
-    cd t4 = utd_term(-1, ph + php, n, kL);
-    cd r0te, r0tm, rnte, rntm;
-    fresnel(eps0, sb * fabs(sin(php)), r0te, r0tm);
-    fresnel(epsn, sb * fabs(sin(n * kPi - ph)), rnte, rntm);
-    Ds = Cc * (t1 + t2 + rnte * t3 + r0te * t4);
-    Dh = Cc * (t1 + t2 + rntm * t3 + r0tm * t4);
-}
-
-// transmit / receive polarisation: vertical iso (mode 0) or short dipole along
-// (theta, phi) (mode 1)
-__device__ __forceinline__ dv3 antenna(int mode, dv3 k, double th, double ph) {
-    if (mode == 1) {
-        double st, ct, sp, cp;
-        sincos(th, &st, &ct);
-        sincos(ph, &sp, &cp);
-        dv3 u = d3(st * cp, st * sp, ct);
-        return (u - k * dot(u, k)) * sqrt(1.5);
-    }
-    dv3 e = d3(0, 0, 1) - k * k.z;
-    if (len(e) < 1e-12) e = d3(1, 0, 0) - k * k.x;
-    return unit(e);
-}
-
-__device__ __forceinline__ cd phase(double L, double lam) {
-    double x = L / lam;
-    return cexpi(-2.0 * kPi * (x - rint(x)));
-}
-
-struct CV { cd x, y, z; };
-__device__ __forceinline__ cd cdot(dv3 a, const CV& b) { return b.x * a.x + b.y * a.y + b.z * a.z; }
 
 // Geometry of one path key.  Points: P[0] = Tx, P[1..order] reflection
 // points (or P[1] = Keller point), R = Rx; leg i runs from P[i] to P[i+1]
@@ -479,15 +341,10 @@ __global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
     }
 }
 
-// Phase 3: fields of the unoccluded keys (double precision).
-//   Specular: E = e_tx(k_0); at each bounce, with the face normal n turned
-//   against the incident k_{i-1}: s = normalize(k_{i-1} x n) (normal
-//   incidence: normalize(n x z), else normalize(n x x)), p_in = s x k_{i-1},
-//   p_out = s x k_i, E <- Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out;
-//   a = lambda / (4 pi L) (e_rx(k_K).E) exp(-j 2 pi frac(L / lambda)).
-//   Diffraction: a = lambda/(4 pi) (1/s') sqrt(s'/(s (s + s'))) e_rx.(D e_tx)
-//   exp(-j 2 pi frac((s + s')/lambda)), D = -b0 b0' D_s - ph ph' D_h.
-//   Delay L / c; Doppler -(1/lambda)[k_K.v_rx - k_0.v_tx + sum (k_{i-1} - k_i).v_obj].
+// Phase 3: fields of the unoccluded keys (double precision; the field model
+// is in fields.h).  Delay L / c; Doppler (Section III-C, Eq (3) generalised
+// to moving interaction points) -(1/lambda)[k_K.v_rx - k_0.v_tx +
+// sum (k_{i-1} - k_i).v_obj]; AoD / AoA the directions of k_0 and -k_K.
 __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, long long cap_cand) {
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
@@ -510,100 +367,44 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, l
         if (pos >= a.out.cap) { atomicOr(a.flags, FLAG_PATH_CAP); continue; }
         dv3 vt = ldd3(a.f.tx_vel + 3 * key.tx), vr = ldd3(a.f.rx_vel + 3 * key.rx);
         double th = a.f.tx_orient[2 * key.tx], phi = a.f.tx_orient[2 * key.tx + 1];
-        // unit directions of the legs and the unfolded length
-        dv3 kk[EMRT_KMAX + 1];
-        double L = 0.0;
+        PathGeo<double> pg;
 #pragma unroll
-        for (int i = 0; i <= EMRT_KMAX; i++) {
-            if (i + 1 >= g.np) break;
-            dv3 p1 = (i + 2 == g.np) ? g.R : g.P[i + 1 <= EMRT_KMAX + 1 ? i + 1 : EMRT_KMAX + 1];
-            dv3 dv = p1 - g.P[i];
-            double l = len(dv);
-            L += l;
-            kk[i] = dv * (1.0 / l);
-        }
+        for (int i = 0; i < EMRT_KMAX + 2; i++) pg.P[i] = v3c<double>(g.P[i]);
+        pg.Rx = v3c<double>(g.R);
+        pg.np = g.np;
+        pg.order = g.order;
+        pg.type = g.type;
+        V3<double> kk[EMRT_KMAX + 1];
+        double L;
+        Cx<double> amp[EMRT_NF];
+        path_field<double>(S, a.fc, key, pg, th, phi, 0, kk, L, amp);
         const int nlegs = g.np - 1;
-        dv3 k0 = kk[0];
-        dv3 kK = kk[0];
+        dv3 k0 = val3(kk[0]);
+        dv3 kK = k0;
 #pragma unroll
         for (int i = 1; i <= EMRT_KMAX; i++)
-            if (i == nlegs - 1) kK = kk[i];
+            if (i == nlegs - 1) kK = val3(kk[i]);
         double dop = dot(kK, vr) - dot(k0, vt);
-        cd amp[EMRT_NF];
-        if (g.type != KT_DIFF) {
-            dv3 e0 = antenna(a.ant_mode, k0, th, phi);
-            dv3 er = antenna(0, kK, 0, 0);
+        if (g.type == KT_SPEC) {
 #pragma unroll
             for (int i = 1; i <= EMRT_KMAX; i++) {
-                if (i > g.order || g.type == KT_LOS) break;
+                if (i > g.order) break;
                 int od = S.face_dyn[key.ids[i - 1]];
-                if (od >= 0) dop += dot(kk[i - 1] - kk[i], ldd3(a.f.obj_vel + 3 * (long long)od));
+                if (od >= 0) dop += dot(val3(kk[i - 1]) - val3(kk[i]), ldd3(a.f.obj_vel + 3 * (long long)od));
             }
-            for (int fi = 0; fi < a.nf; fi++) {
-                double lam = kC0 / a.freq[fi];
-                CV E = {C(e0.x), C(e0.y), C(e0.z)};
-#pragma unroll
-                for (int i = 1; i <= EMRT_KMAX; i++) {
-                    if (i > g.order || g.type == KT_LOS) break;
-                    int f = key.ids[i - 1];
-                    const double* pl = S.plane + 4 * (long long)f;
-                    dv3 nrm = d3(pl[0], pl[1], pl[2]);
-                    dv3 ki = kk[i - 1], ko = kk[i];
-                    if (dot(nrm, ki) > 0) nrm = nrm * -1.0;
-                    double c = -dot(ki, nrm);
-                    dv3 sv = cross(ki, nrm);
-                    if (len(sv) < 1e-12) {
-                        sv = cross(nrm, d3(0, 0, 1));
-                        if (len(sv) < 1e-12) sv = cross(nrm, d3(1, 0, 0));
-                    }
-                    sv = unit(sv);
-                    dv3 pin = cross(sv, ki), pout = cross(sv, ko);
-                    int m = S.face_material[f];
-                    cd te, tm;
-                    fresnel(C(a.mat_eps[2 * m], a.mat_eps[2 * m + 1]), c, te, tm);
-                    cd es = cdot(sv, E) * te, ep = cdot(pin, E) * tm;
-                    E.x = es * sv.x + ep * pout.x;
-                    E.y = es * sv.y + ep * pout.y;
-                    E.z = es * sv.z + ep * pout.z;
-                }
-                amp[fi] = cdot(er, E) * phase(L, lam) * (lam / (4.0 * kPi * L));
-            }
-        } else {
-            const Wedge& w = g.w;
-            int od = S.face_dyn[w.f0];
-            if (od >= 0) dop += dot(kk[0] - kk[1], ldd3(a.f.obj_vel + 3 * (long long)od));
-            double sp = len(g.P[1] - g.P[0]), sd = len(g.R - g.P[1]);
-            dv3 si = kk[0], so = kk[1];
-            double cb = fmin(1.0, fmax(-1.0, dot(si, w.e)));
-            double beta0 = acos(cb);
-            double php = wedge_angle(w, g.P[0]), ph = wedge_angle(w, g.R);
-            double sb = sin(beta0);
-            double Lp = sd * sp * sb * sb / (sd + sp);
-            dv3 fp = unit(cross(w.e, si)) * -1.0, bp = cross(fp, si);
-            dv3 fo = unit(cross(w.e, so)), bo = cross(fo, so);
-            int m0 = S.face_material[w.f0], mn = S.face_material[w.fn];
-            dv3 et = antenna(a.ant_mode, si, th, phi);
-            dv3 er = antenna(0, so, 0, 0);
-            double spread = (1.0 / sp) * sqrt(sp / (sd * (sd + sp)));
-            for (int fi = 0; fi < a.nf; fi++) {
-                double lam = kC0 / a.freq[fi];
-                double k = 2.0 * kPi / lam;
-                cd Ds, Dh;
-                utd_D(w.n, k, Lp, beta0, php, ph, C(a.mat_eps[2 * m0], a.mat_eps[2 * m0 + 1]),
-                      C(a.mat_eps[2 * mn], a.mat_eps[2 * mn + 1]), Ds, Dh);
-                cd fld = Ds * (-dot(er, bo) * dot(bp, et)) - Dh * (dot(er, fo) * dot(fp, et));
-                amp[fi] = fld * phase(L, lam) * (lam / (4.0 * kPi) * spread);
-            }
+        } else if (g.type == KT_DIFF) {
+            int od = S.face_dyn[g.w.f0];
+            if (od >= 0) dop += dot(val3(kk[0]) - val3(kk[1]), ldd3(a.f.obj_vel + 3 * (long long)od));
         }
         ValidPaths& o = a.out;
         o.key[pos] = key;
 #pragma unroll
         for (int j = 0; j < 5; j++) o.tri[5 * pos + j] = g.tri[j];
-        for (int fi = 0; fi < a.nf; fi++) {
-            double lam = kC0 / a.freq[fi];
-            o.a[2 * (pos * a.nf + fi)] = amp[fi].re;
-            o.a[2 * (pos * a.nf + fi) + 1] = amp[fi].im;
-            o.fd[pos * a.nf + fi] = -dop / lam;
+        for (int fi = 0; fi < a.fc.nf; fi++) {
+            double lam = kC0 / a.fc.freq[fi];
+            o.a[2 * (pos * a.fc.nf + fi)] = amp[fi].re;
+            o.a[2 * (pos * a.fc.nf + fi) + 1] = amp[fi].im;
+            o.fd[pos * a.fc.nf + fi] = -dop / lam;
         }
         o.tau[pos] = L / kC0;
         float aod_az = (float)atan2(k0.y, k0.x), aod_el = (float)asin(fmin(1.0, fmax(-1.0, k0.z)));

@@ -106,11 +106,140 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
     return sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1.0f;
 }
 
+// One 64-ray chunk of a bounce: rays [base, base + 64) of the live buffer.
+template <bool STATS>
+__device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long long n_in, unsigned long long base,
+                                             int lane, unsigned& s_nodes, unsigned& s_tris, unsigned& s_seg,
+                                             unsigned& s_cap) {
+    const int b = a.b;
+    unsigned long long i = base + (unsigned long long)lane;
+    bool act = i < n_in;
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, L = 0;
+    uint32_t id = 0;
+    int prev = -1;
+    if (act) {
+        ox = a.in.ox[i]; oy = a.in.oy[i]; oz = a.in.oz[i];
+        dx = a.in.dx[i]; dy = a.in.dy[i]; dz = a.in.dz[i];
+        L = a.in.L[i];
+        id = a.in.id[i];
+        prev = a.in.prev[i];
+    }
+    RayPre r = ray_pre(ox, oy, oz, dx, dy, dz);
+    float best_t = INFINITY;
+    int best_tri = 0x7FFFFFFF, best_face = -1;
+    if (act) {
+        if (STATS) s_seg++;
+        closest_hit<STATS>(a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
+        closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
+    }
+    bool hit = act && best_tri != 0x7FFFFFFF;
+    if (act) a.hitlog[(long long)b * a.n_total + id] = hit ? best_tri : -1;
+    float t_end = hit ? best_t : INFINITY;
+
+    // receiver capture on segments after at least one reflection
+    if (act && b >= 1 && a.rxt.n_prims > 0) {
+        float tcap = fminf(t_end, root_far(a.rxt, ox, oy, oz));
+        float grow = a.alpha_k * (L + tcap);
+        KeyRec mine;
+        bool have = false;
+        uint64_t h = 0;
+        all_hits(a.rxt, r, tcap, grow, [&](int slot) {
+            float4 p = a.rx_prims[slot];
+            float wx = p.x - ox, wy = p.y - oy, wz = p.z - oz;
+            float s = wx * dx + wy * dy + wz * dz;
+            if (!(s > 0.0f && s < t_end)) return;
+            float rho2 = wx * wx + wy * wy + wz * wz - s * s;
+            float rs = a.alpha_k * (L + s);
+            if (!(rho2 < rs * rs)) return;
+            int rx = __float_as_int(p.w);
+            if (!have) {
+                mine.tx = (int)(id / (uint32_t)a.rays_per_tx);
+                mine.to = KT_SPEC | (b << 8);
+                for (int j = 0; j < 5; j++)
+                    mine.ids[j] = j < b ? a.src.tri_face[a.hitlog[(long long)j * a.n_total + id]] : -1;
+                have = true;
+            }
+            mine.rx = rx;
+            h = key_hash(mine.tx, mine.rx, mine.to, mine.ids);
+            int res = table_insert(a.table, a.mask, ref_ray(b, rx, id), mine, h, a.src);
+            if (res < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
+            if (STATS) s_cap++;
+        });
+    }
+
+    // edge capture on the first segment
+    if (act && b == 0 && a.diffraction && a.edt.n_prims > 0) {
+        float tcap = fminf(t_end, root_far(a.edt, ox, oy, oz));
+        float grow = a.alpha_k * tcap;
+        int tx = (int)(id / (uint32_t)a.rays_per_tx);
+        all_hits(a.edt, r, tcap, grow, [&](int slot) {
+            float4 P0 = a.edge_prims[2 * slot], P1 = a.edge_prims[2 * slot + 1];
+            float ex = P1.x - P0.x, ey = P1.y - P0.y, ez = P1.z - P0.z;
+            float wx = ox - P0.x, wy = oy - P0.y, wz = oz - P0.z;
+            float aa = dx * dx + dy * dy + dz * dz;
+            float bb = dx * ex + dy * ey + dz * ez;
+            float cc = ex * ex + ey * ey + ez * ez;
+            float dd = dx * wx + dy * wy + dz * wz;
+            float ee = ex * wx + ey * wy + ez * wz;
+            float den = aa * cc - bb * bb;
+            if (!(den > 1e-12f * aa * cc)) return;
+            float s = (bb * ee - cc * dd) / den;
+            float u = (aa * ee - bb * dd) / den;
+            if (!(s > 0.0f && s < t_end && u > 0.0f && u < 1.0f)) return;
+            float qx = ox + s * dx - (P0.x + u * ex);
+            float qy = oy + s * dy - (P0.y + u * ey);
+            float qz = oz + s * dz - (P0.z + u * ez);
+            float re = a.alpha_k * s;
+            if (!(qx * qx + qy * qy + qz * qz < re * re)) return;
+            int e = __float_as_int(P0.w);
+            uint32_t* w = a.illum + (long long)tx * a.e_words + (e >> 5);
+            uint32_t bit = 1u << (e & 31);
+            if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(w, bit);
+        });
+    }
+
+    // specular reflection about the face plane
+    bool alive = hit && b < a.K;
+    float nox = 0, noy = 0, noz = 0, ndx = 0, ndy = 0, ndz = 0;
+    if (alive) {
+        const double* pl = a.plane + 4 * (long long)best_face;
+        float nx = (float)pl[0], ny = (float)pl[1], nzv = (float)pl[2];
+        nox = ox + best_t * dx;
+        noy = oy + best_t * dy;
+        noz = oz + best_t * dz;
+        float dn = 2.0f * (dx * nx + dy * ny + dz * nzv);
+        ndx = dx - dn * nx;
+        ndy = dy - dn * ny;
+        ndz = dz - dn * nzv;
+    }
+    long long o = wave_append(a.n_out, alive);
+    if (alive) {
+        a.out.ox[o] = nox; a.out.oy[o] = noy; a.out.oz[o] = noz;
+        a.out.dx[o] = ndx; a.out.dy[o] = ndy; a.out.dz[o] = ndz;
+        a.out.L[o] = L + best_t;
+        a.out.id[o] = id;
+        a.out.prev[o] = best_face;
+    }
+}
+
+template <bool STATS>
+__device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane, unsigned s_nodes, unsigned s_tris,
+                                            unsigned s_seg, unsigned s_cap) {
+    if (STATS) {
+        unsigned long long v[4] = {s_nodes, s_tris, s_seg, s_cap};
+        for (int k = 0; k < 4; k++) {
+            unsigned long long x = v[k];
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+            if (lane == 0 && x) atomicAdd(&stats[k], x);
+        }
+    }
+}
+
+// Persistent: waves pull 64-ray chunks from a device counter.
 template <bool STATS>
 __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
-    const int b = a.b;
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
     while (true) {
         unsigned int chunk = 0;
@@ -118,128 +247,75 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
         chunk = __shfl(chunk, 0);
         unsigned long long base = (unsigned long long)chunk * 64ULL;
         if (base >= n_in) break;
-        unsigned long long i = base + (unsigned long long)lane;
-        bool act = i < n_in;
-        float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, L = 0;
-        uint32_t id = 0;
-        int prev = -1;
-        if (act) {
-            ox = a.in.ox[i]; oy = a.in.oy[i]; oz = a.in.oz[i];
-            dx = a.in.dx[i]; dy = a.in.dy[i]; dz = a.in.dz[i];
-            L = a.in.L[i];
-            id = a.in.id[i];
-            prev = a.in.prev[i];
-        }
-        RayPre r = ray_pre(ox, oy, oz, dx, dy, dz);
-        float best_t = INFINITY;
-        int best_tri = 0x7FFFFFFF, best_face = -1;
-        if (act) {
-            if (STATS) s_seg++;
-            closest_hit<STATS>(a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
-            closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
-        }
-        bool hit = act && best_tri != 0x7FFFFFFF;
-        if (act) a.hitlog[(long long)b * a.n_total + id] = hit ? best_tri : -1;
-        float t_end = hit ? best_t : INFINITY;
-
-        // receiver capture on segments after at least one reflection
-        if (act && b >= 1 && a.rxt.n_prims > 0) {
-            float tcap = fminf(t_end, root_far(a.rxt, ox, oy, oz));
-            float grow = a.alpha_k * (L + tcap);
-            KeyRec mine;
-            bool have = false;
-            uint64_t h = 0;
-            all_hits(a.rxt, r, tcap, grow, [&](int slot) {
-                float4 p = a.rx_prims[slot];
-                float wx = p.x - ox, wy = p.y - oy, wz = p.z - oz;
-                float s = wx * dx + wy * dy + wz * dz;
-                if (!(s > 0.0f && s < t_end)) return;
-                float rho2 = wx * wx + wy * wy + wz * wz - s * s;
-                float rs = a.alpha_k * (L + s);
-                if (!(rho2 < rs * rs)) return;
-                int rx = __float_as_int(p.w);
-                if (!have) {
-                    mine.tx = (int)(id / (uint32_t)a.rays_per_tx);
-                    mine.to = KT_SPEC | (b << 8);
-                    for (int j = 0; j < 5; j++)
-                        mine.ids[j] = j < b ? a.src.tri_face[a.hitlog[(long long)j * a.n_total + id]] : -1;
-                    have = true;
-                }
-                mine.rx = rx;
-                h = key_hash(mine.tx, mine.rx, mine.to, mine.ids);
-                int res = table_insert(a.table, a.mask, ref_ray(b, rx, id), mine, h, a.src);
-                if (res < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
-                if (STATS) s_cap++;
-            });
-        }
-
-        // edge capture on the first segment
-        if (act && b == 0 && a.diffraction && a.edt.n_prims > 0) {
-            float tcap = fminf(t_end, root_far(a.edt, ox, oy, oz));
-            float grow = a.alpha_k * tcap;
-            int tx = (int)(id / (uint32_t)a.rays_per_tx);
-            all_hits(a.edt, r, tcap, grow, [&](int slot) {
-                float4 P0 = a.edge_prims[2 * slot], P1 = a.edge_prims[2 * slot + 1];
-                float ex = P1.x - P0.x, ey = P1.y - P0.y, ez = P1.z - P0.z;
-                float wx = ox - P0.x, wy = oy - P0.y, wz = oz - P0.z;
-                float aa = dx * dx + dy * dy + dz * dz;
-                float bb = dx * ex + dy * ey + dz * ez;
-                float cc = ex * ex + ey * ey + ez * ez;
-                float dd = dx * wx + dy * wy + dz * wz;
-                float ee = ex * wx + ey * wy + ez * wz;
-                float den = aa * cc - bb * bb;
-                if (!(den > 1e-12f * aa * cc)) return;
-                float s = (bb * ee - cc * dd) / den;
-                float u = (aa * ee - bb * dd) / den;
-                if (!(s > 0.0f && s < t_end && u > 0.0f && u < 1.0f)) return;
-                float qx = ox + s * dx - (P0.x + u * ex);
-                float qy = oy + s * dy - (P0.y + u * ey);
-                float qz = oz + s * dz - (P0.z + u * ez);
-                float re = a.alpha_k * s;
-                if (!(qx * qx + qy * qy + qz * qz < re * re)) return;
-                int e = __float_as_int(P0.w);
-                uint32_t* w = a.illum + (long long)tx * a.e_words + (e >> 5);
-                uint32_t bit = 1u << (e & 31);
-                if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(w, bit);
-            });
-        }
-
-        // specular reflection about the face plane
-        bool alive = hit && b < a.K;
-        float nox = 0, noy = 0, noz = 0, ndx = 0, ndy = 0, ndz = 0;
-        if (alive) {
-            const double* pl = a.plane + 4 * (long long)best_face;
-            float nx = (float)pl[0], ny = (float)pl[1], nzv = (float)pl[2];
-            nox = ox + best_t * dx;
-            noy = oy + best_t * dy;
-            noz = oz + best_t * dz;
-            float dn = 2.0f * (dx * nx + dy * ny + dz * nzv);
-            ndx = dx - dn * nx;
-            ndy = dy - dn * ny;
-            ndz = dz - dn * nzv;
-        }
-        long long o = wave_append(a.n_out, alive);
-        if (alive) {
-            a.out.ox[o] = nox; a.out.oy[o] = noy; a.out.oz[o] = noz;
-            a.out.dx[o] = ndx; a.out.dy[o] = ndy; a.out.dz[o] = ndz;
-            a.out.L[o] = L + best_t;
-            a.out.id[o] = id;
-            a.out.prev[o] = best_face;
-        }
+        bounce_chunk<STATS>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap);
     }
-    if (STATS) {
-        unsigned long long v[4] = {s_nodes, s_tris, s_seg, s_cap};
-        for (int k = 0; k < 4; k++) {
-            unsigned long long x = v[k];
-            for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
-            if (lane == 0 && x) atomicAdd(&a.stats[k], x);
-        }
-    }
+    flush_stats<STATS>(a.stats, lane, s_nodes, s_tris, s_seg, s_cap);
 }
 
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {
     if (stats) hipLaunchKernelGGL(k_bounce<true>, dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_bounce<false>, dim3(grid), dim3(256), 0, st, a);
+}
+
+// Several scenes in one launch (batched stepping): chunk_off[c] is the first
+// global chunk of scene c (an exclusive scan of its live-ray chunks, built on
+// the device by k_chunk_table); a wave takes the next global chunk, finds its
+// scene by binary search and runs that scene's bounce on it.
+__global__ void __launch_bounds__(256) k_chunk_table(const BounceArgs* __restrict__ args, int n_scenes,
+                                                     uint32_t* chunk_off, uint32_t* work) {
+    __shared__ uint32_t sh[256];
+    uint32_t carry = 0;
+    for (int base = 0; base < n_scenes; base += 256) {
+        int c = base + (int)threadIdx.x;
+        uint32_t v = c < n_scenes ? (uint32_t)((*args[c].n_in + 63ULL) / 64ULL) : 0u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        // inclusive Hillis-Steele scan of 256 values
+        for (int o = 1; o < 256; o <<= 1) {
+            uint32_t y = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (c < n_scenes) chunk_off[c] = carry + sh[threadIdx.x] - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        chunk_off[n_scenes] = carry;
+        *work = 0u;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restrict__ args,
+                                                      const uint32_t* __restrict__ chunk_off, uint32_t* work,
+                                                      int n_scenes) {
+    const int lane = lane_id();
+    const uint32_t total = chunk_off[n_scenes];
+    unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
+    while (true) {
+        uint32_t g = 0;
+        if (lane == 0) g = atomicAdd(work, 1u);
+        g = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(g, 0));
+        if (g >= total) break;
+        int lo = 0, hi = n_scenes - 1;  // last scene with chunk_off[c] <= g
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (chunk_off[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const int c = __builtin_amdgcn_readfirstlane(lo);
+        const BounceArgs& a = args[c];
+        const unsigned long long n_in = *a.n_in;
+        bounce_chunk<false>(a, n_in, (unsigned long long)(g - chunk_off[c]) * 64ULL, lane, s_nodes, s_tris, s_seg,
+                            s_cap);
+    }
+}
+
+void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(256), 0, st, args, n_scenes, chunk_off, work);
+    hipLaunchKernelGGL(k_bounce_multi, dim3(grid), dim3(256), 0, st, args, chunk_off, work, n_scenes);
 }
 
 __global__ void k_debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ids, int n,

@@ -35,7 +35,7 @@ class Tracer:
     object_dynamic, materials`` (numpy or torch); ``config`` keys mirror
     ``emrt_config`` (freq_hz list, max_reflections, diffraction, rays_per_tx,
     rx_sphere_k, diff_max_leg_m, tx_power_w, antenna_mode, path_cap_per_link,
-    path_capacity, table_capacity).
+    path_capacity, table_capacity, adjoint_materials).
     """
 
     def __init__(self, scene, n_tx: int, n_rx: int, device: str = "cuda", **config):
@@ -186,6 +186,30 @@ class Tracer:
         res["truncated"] = p["truncated"]
         return res
 
+    def backward(self, dL_dH: Optional[torch.Tensor] = None,
+                 dL_dP: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+        """Adjoint of the last step (emrt_backward).  dL_dH complex [n_freq,
+        n_links] (dL/dRe H + j dL/dIm H), dL_dP real [n_freq, n_links]
+        (dL/dP_coh); returns grad_eps complex [n_materials], grad_tx_pos
+        [n_tx, 3] and grad_tx_orient [n_tx, 2]."""
+        nf, nl, d = len(self.freqs), self.n_links, self.device
+        gh = None
+        if dL_dH is not None:
+            gh = torch.view_as_real(dL_dH.to(device=d, dtype=torch.complex128).reshape(nf, nl).contiguous()).contiguous()
+        gp = None if dL_dP is None else dL_dP.to(device=d, dtype=torch.float64).reshape(nf, nl).contiguous()
+        m = len(self._mat_host)
+        out = {
+            "grad_eps": torch.empty((m, 2), dtype=torch.float64, device=d),
+            "grad_tx_pos": torch.empty((self.n_tx, 3), dtype=torch.float64, device=d),
+            "grad_tx_orient": torch.empty((self.n_tx, 2), dtype=torch.float64, device=d),
+        }
+        self._check(self.lib.emrt_backward(self.ctx, _ptr(gh), _ptr(gp), _ptr(out["grad_eps"]),
+                                           _ptr(out["grad_tx_pos"]), _ptr(out["grad_tx_orient"])))
+        self._check(self.lib.emrt_sync(self.ctx))
+        self._bw_refs = (gh, gp)
+        out["grad_eps"] = torch.view_as_complex(out["grad_eps"])
+        return out
+
     def debug_rays(self, tx: int, ray_ids) -> np.ndarray:
         ids = _dev(ray_ids, torch.int32, self.device)
         out = torch.empty((len(ids), int(self.cfg.max_reflections) + 1), dtype=torch.int32, device=self.device)
@@ -210,3 +234,64 @@ class Tracer:
         s = A.Stats()
         self._check(self.lib.emrt_read_stats(self.ctx, ctypes.byref(s)))
         return {f: (list(getattr(s, f)) if f == "rays_per_bounce" else getattr(s, f)) for f, _ in A.Stats._fields_}
+
+
+class Batch:
+    """Batched stepping of several Tracers (emrt_batch): the members' bounces
+    run as one persistent launch per bounce level and the step is replayed
+    from a HIP graph.  Frames are set and results read on the member
+    Tracers; ``step`` replaces their individual ``step``."""
+
+    def __init__(self, tracers: Sequence[Tracer], use_graph: bool = True, n_streams: int = 4, grid: int = 2048):
+        self.lib = A.load()
+        self.tracers = list(tracers)
+        n = len(self.tracers)
+        arr = (ctypes.c_void_p * n)(*[t.ctx.value for t in self.tracers])
+        b = ctypes.c_void_p()
+        st = self.lib.emrt_batch_create(arr, n, ctypes.byref(b))
+        if st < 0:
+            raise EmrtError(st, A.load().emrt_status_string(st).decode())
+        self.b = b
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.emrt_batch_workspace_size(self.b, ctypes.byref(nbytes)))
+        dev = self.tracers[0].device
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        # graph capture needs a stream other than the device's default stream
+        self.stream = torch.cuda.Stream(device=dev)
+        torch.cuda.current_stream(dev).synchronize()
+        self._check(self.lib.emrt_batch_set_stream(self.b, ctypes.c_void_p(self.stream.cuda_stream)))
+        self._check(self.lib.emrt_batch_bind_workspace(self.b, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
+        self.set_options(use_graph, n_streams, grid)
+
+    def _check(self, st: int) -> int:
+        if st < 0:
+            buf = ctypes.create_string_buffer(512)
+            self.lib.emrt_batch_last_error(self.b, buf, 512)
+            raise EmrtError(st, buf.value.decode() or A.load().emrt_status_string(st).decode())
+        return st
+
+    def set_options(self, use_graph: bool = True, n_streams: int = 4, grid: int = 2048) -> None:
+        self._check(self.lib.emrt_batch_set_options(self.b, int(use_graph), int(n_streams), int(grid)))
+
+    def step(self, discover: bool = True) -> int:
+        return self._check(self.lib.emrt_batch_step(self.b, 1 if discover else 0))
+
+    def autotune(self):
+        g, s = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.emrt_batch_autotune(self.b, ctypes.byref(g), ctypes.byref(s)))
+        return g.value, s.value
+
+    def sync(self) -> int:
+        return self._check(self.lib.emrt_batch_sync(self.b))
+
+    def close(self) -> None:
+        if getattr(self, "b", None):
+            torch.cuda.synchronize(self.tracers[0].device)
+            self.lib.emrt_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

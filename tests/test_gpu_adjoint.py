@@ -1,0 +1,179 @@
+"""Adjoint (emrt_backward) vs the oracle's central-difference gradients.
+
+The loss is L = sum_{f, link} Re(conj(G_H) H) + G_P P_coh with seeded random
+cotangents.  The oracle differentiates its own channel sums over its own
+valid keys (topology fixed) by central differences; the GPU differentiates
+the paths of its last step with forward-mode dual numbers.  Links whose path
+sets differ between the two (keys the oracle marks ambiguous) get zero
+cotangents, so both sides differentiate the same function.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from synth import city  # noqa: E402
+from synth.city import Frame  # noqa: E402
+from tests import parity as P  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5  # of the largest component of each gradient (finite-difference error ~1e-7)
+
+
+def _cotangents(nf, nl, seed, p_scale):
+    r = np.random.default_rng(seed)
+    GH = r.normal(size=(nf, nl)) + 1j * r.normal(size=(nf, nl))
+    GP = r.normal(size=(nf, nl)) * p_scale
+    return GH, GP
+
+
+def _link_mask(gpu_keys, ref_keys, n_rx, nl):
+    """Links whose GPU and oracle key sets are equal."""
+    ok = np.ones(nl, bool)
+    g = {}
+    for k in np.asarray(gpu_keys).reshape(-1, 9):
+        g.setdefault(int(k[0]) * n_rx + int(k[1]), set()).add(tuple(int(x) for x in k))
+    r = {}
+    for k in np.asarray(ref_keys).reshape(-1, 9):
+        r.setdefault(int(k[0]) * n_rx + int(k[1]), set()).add(tuple(int(x) for x in k))
+    for l in set(g) | set(r):
+        if g.get(l, set()) != r.get(l, set()):
+            ok[l] = False
+    return ok
+
+
+def _close(got, want, rtol=RTOL):
+    """Each row (a transmitter's components; the permittivities as one row)
+    within rtol of that row's largest magnitude."""
+    got, want = np.atleast_2d(np.asarray(got)), np.atleast_2d(np.asarray(want))
+    scale = np.maximum(np.abs(want).max(axis=1, keepdims=True), 1e-300)
+    err = (np.abs(got - want) / scale).max()
+    return err <= rtol, err
+
+
+def _run(sc, fr, n_tx, n_rx, K, N, freqs, diffraction, ant_mode, seed, p_scale=1e6):
+    from paper_2303_10521_amd import Tracer
+
+    M = len(sc.materials)
+    tr = Tracer(sc, n_tx, n_rx, freq_hz=list(freqs), max_reflections=K, rays_per_tx=N, diffraction=int(diffraction),
+                antenna_mode=ant_mode, adjoint_materials=M, path_capacity=1 << 20)
+    tr.set_frame(fr)
+    tr.step(True)
+    assert tr.sync() == 0
+    gk = tr.flat_paths(cap=256)["key"]
+    os_ = O.OracleScene(sc)
+    ref = O.run_frame(os_, fr, N, K, list(freqs), diffraction=diffraction, ant_mode=ant_mode)
+    nl = n_tx * n_rx
+    mask = _link_mask(gk, ref.keys, n_rx, nl)
+    assert mask.mean() >= 0.9
+    GH, GP = _cotangents(len(freqs), nl, seed, p_scale)
+    GH[:, ~mask] = 0
+    GP[:, ~mask] = 0
+    g = tr.backward(torch.as_tensor(GH), torch.as_tensor(GP))
+    geo = os_.geometry(fr.obj_xform)
+    want = O.grad_fd(os_, geo, fr, ref.keys, list(freqs), GH, GP, n_rx, ant_mode=ant_mode)
+    got = {k: v.cpu().numpy() for k, v in g.items()}
+    return tr, got, want, (GH, GP)
+
+
+def test_adjoint_toy_iso():
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    tr, got, want, _ = _run(sc, fr, sc.n_tx, sc.n_rx, w.max_reflections, w.rays_per_tx, w.freqs_hz, False, 0, 1)
+    for name in ("grad_tx_pos", "grad_eps"):
+        ok, err = _close(got[name], want[name])
+        assert ok, (name, err, got[name], want[name])
+    assert np.all(got["grad_tx_orient"] == 0)
+    tr.close()
+
+
+def test_adjoint_toy_dipole_two_carriers():
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    fr.tx_orient = np.array([[0.6, 0.4]])
+    freqs = (3.5e9, 28e9)
+    tr, got, want, _ = _run(sc, fr, sc.n_tx, sc.n_rx, w.max_reflections, w.rays_per_tx, freqs, False, 1, 2)
+    for name in ("grad_tx_pos", "grad_tx_orient", "grad_eps"):
+        ok, err = _close(got[name], want[name])
+        assert ok, (name, err, got[name], want[name])
+    tr.close()
+
+
+def _subset_frame(fr, tx_idx, rx_idx):
+    return Frame(t=fr.t, obj_xform=fr.obj_xform, obj_vel=fr.obj_vel, tx_pos=fr.tx_pos[tx_idx],
+                 tx_vel=fr.tx_vel[tx_idx], rx_pos=fr.rx_pos[rx_idx], rx_vel=fr.rx_vel[rx_idx],
+                 tx_orient=fr.tx_orient[tx_idx])
+
+
+def test_adjoint_eight_materials_with_diffraction():
+    """The 8-material district (facades by building id), first-order
+    diffraction, two transmitters and 40 receivers, K = 4."""
+    w = city.workload("adjoint")
+    sc = w.scene
+    fr0 = sc.frame(0.0)
+    rx_idx = np.arange(0, len(fr0.rx_pos), 25)[:40]
+    fr = _subset_frame(fr0, np.array([0, 3]), rx_idx)
+    tr, got, want, _ = _run(sc, fr, 2, len(rx_idx), w.max_reflections, 20000, w.freqs_hz, True, 0, 3)
+    for name in ("grad_tx_pos", "grad_eps"):
+        ok, err = _close(got[name], want[name])
+        assert ok, (name, err, got[name], want[name])
+    tr.close()
+
+
+def test_adjoint_deterministic_and_state_errors():
+    from paper_2303_10521_amd import Tracer
+    from paper_2303_10521_amd.tracer import EmrtError
+
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    tr = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections,
+                rays_per_tx=w.rays_per_tx, adjoint_materials=len(sc.materials), path_capacity=1 << 16)
+    GH = torch.ones((1, sc.n_tx * sc.n_rx), dtype=torch.complex128)
+    with pytest.raises(EmrtError):
+        tr.backward(GH)  # no step yet
+    tr.set_frame(fr)
+    tr.step(True)
+    a = tr.backward(GH)
+    b = tr.backward(GH)
+    for k in a:
+        assert torch.equal(a[k], b[k])
+    tr.set_frame(fr)
+    with pytest.raises(EmrtError):
+        tr.backward(GH)  # frame changed since the step
+    tr.close()
+    tr0 = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections,
+                 rays_per_tx=w.rays_per_tx, path_capacity=1 << 16)
+    tr0.set_frame(fr)
+    tr0.step(True)
+    with pytest.raises(EmrtError):
+        tr0.backward(GH)  # adjoint_materials = 0
+    tr0.close()
+
+
+def test_autograd_function_matches_backward():
+    from paper_2303_10521_amd import Tracer
+    from paper_2303_10521_amd.autograd import channels
+
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    tr = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections,
+                rays_per_tx=w.rays_per_tx, adjoint_materials=len(sc.materials), path_capacity=1 << 16)
+    eps = torch.tensor(np.asarray(sc.materials), dtype=torch.complex128, requires_grad=True)
+    txp = torch.tensor(fr.tx_pos, dtype=torch.float64, requires_grad=True)
+    txo = torch.tensor(fr.tx_orient, dtype=torch.float64, requires_grad=True)
+    H, Pc = channels(tr, fr, eps, txp, txo, True)
+    loss = (H.abs() ** 2).sum() * 1e6 + Pc.sum() * 3.0
+    loss.backward()
+    ch = tr.channels()
+    gH = 2e6 * ch["H"]
+    gP = torch.full_like(ch["P_coh"], 3.0)
+    ref = tr.backward(gH, gP)
+    assert torch.allclose(eps.grad, ref["grad_eps"].cpu(), rtol=1e-12, atol=0)
+    assert torch.allclose(txp.grad, ref["grad_tx_pos"].cpu(), rtol=1e-12, atol=0)
+    tr.close()

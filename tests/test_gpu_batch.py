@@ -1,0 +1,108 @@
+"""Batched stepping (emrt_batch) vs stepping each scene alone.
+
+Several uneven cities of the 64-city batched workload (moving vehicles, 1-3
+transmitters, K = 4) are stepped through a schedule of discovery and cached
+frames twice: once with one context per city stepped alone, and once as a
+batch (multi-scene persistent bounce launches, HIP-graph replay).  Every
+replay is checked against the separate steps, with eager host work and
+synchronisations in between.  The per-city results are deterministic, so
+channels and path lists must be identical.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from synth import city  # noqa: E402
+from tests import parity as P  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CITIES = (44, 9, 29, 34, 20, 4)  # the smallest of the 64 (75k-117k rays each)
+SCHEDULE = (True, False, False, True, False, True)
+
+
+def _tracer(w, **kw):
+    from paper_2303_10521_amd import Tracer
+
+    sc = w.scene
+    args = dict(freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections, rays_per_tx=w.rays_per_tx,
+                diffraction=int(w.diffraction), path_capacity=1 << 20)
+    args.update(kw)
+    return Tracer(sc, sc.n_tx, sc.n_rx, **args)
+
+
+def _snapshot(tr):
+    ch = tr.channels()
+    out = {k: ch[k].cpu().numpy().copy() for k in ("H", "P_coh", "P_inc", "tau_mean", "fd_mean", "fd_rms", "n_paths")}
+    p = tr.flat_paths(cap=64)
+    out["keys"] = p["key"].copy()
+    return out
+
+
+def _equal(a, b):
+    for k in a:
+        assert a[k].shape == b[k].shape, k
+        assert np.array_equal(a[k], b[k]), k
+
+
+def _run_schedule(use_graph, n_streams, grid, ks=None):
+    from paper_2303_10521_amd import Batch
+
+    ws = [city.batch_city(i) for i in CITIES]
+    if ks is not None:
+        for w, k in zip(ws, ks):
+            w.max_reflections = k
+    solo = [_tracer(w) for w in ws]
+    members = [_tracer(w) for w in ws]
+    batch = Batch(members, use_graph=use_graph, n_streams=n_streams, grid=grid)
+    for f, disc in enumerate(SCHEDULE):
+        for w, a, b in zip(ws, solo, members):
+            fr = w.scene.frame(f * w.frame_dt)
+            a.set_frame(fr, f)
+            b.set_frame(fr, f)
+            a.step(disc)
+        batch.step(disc)
+        assert batch.sync() == 0
+        for a, b in zip(solo, members):
+            assert a.sync() == 0
+            _equal(_snapshot(a), _snapshot(b))
+    batch.close()
+    for t in solo + members:
+        t.close()
+
+
+def test_batch_graph_replays_match_separate_steps():
+    _run_schedule(True, 4, 2048)
+
+
+def test_batch_eager_single_stream_matches_separate_steps():
+    _run_schedule(False, 1, 512)
+
+
+def test_batch_mixed_bounce_depths():
+    _run_schedule(True, 2, 1024, ks=(4, 2, 4, 3, 0, 4))
+
+
+def test_batch_rules_and_autotune():
+    from paper_2303_10521_amd import Batch
+    from paper_2303_10521_amd.tracer import EmrtError
+
+    ws = [city.batch_city(i) for i in CITIES[:3]]
+    members = [_tracer(w) for w in ws]
+    batch = Batch(members)
+    with pytest.raises(EmrtError):
+        batch.step(True)  # no frames yet
+    for w, t in zip(ws, members):
+        t.set_frame(w.scene.frame(0.0))
+    with pytest.raises(EmrtError):
+        members[0].step(True)  # members step through the batch only
+    with pytest.raises(EmrtError):
+        Batch([members[0]])  # already batched
+    grid, ns = batch.autotune()
+    assert grid in (1024, 2048, 4096, 8192) and ns in (1, 2, 4, 8)
+    batch.step(True)
+    assert batch.sync() == 0
+    batch.close()
+    for t in members:
+        t.close()
