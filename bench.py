@@ -11,7 +11,11 @@ GPU before the timed region starts.
 
 Prints one JSON line.  Extra keys: cached-frame and 10-frame-schedule
 ms/frame (the paper's Table II analogue), the roofline of the dominant kernel
-(the bounce kernel) and the oracle timed on the host cores.
+(the bounce kernel; its HBM traffic comes from the committed counter summary
+profiles/k_bounce_city_traffic.txt while the kernel sources are unchanged),
+the oracle timed on the host cores, the adjoint against the plain forward
+step (8-material district) and 64 uneven cities stepped as one batch against
+the same cities stepped one after the other.
 """
 from __future__ import annotations
 
@@ -27,6 +31,24 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (packed; 78.6 non-packed)
 FLOP_PER_NODE = 24  # two child-box slab tests: 6 sub + 6 mul each
 FLOP_PER_TRI = 36  # watertight test: 9 sub, 6 shear, 9 edge-function, 2 det, 3 scale, 6 T, 1 div
+
+
+def committed_traffic():
+    """HBM bytes per bounce launch from the committed counter summary, or
+    None when the bounce kernel's sources changed since it was measured."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_bounce_city_traffic.txt")
+    try:
+        kv = dict(ln.split(": ", 1) for ln in open(path).read().splitlines() if ": " in ln and ln[0].isalpha())
+        m = hashlib.sha256()
+        for f in ("trace.hip", "emrt_dev.h"):
+            m.update(open(os.path.join(ROOT, "paper_2303_10521_amd", "csrc", f), "rb").read())
+        if m.hexdigest() != kv.get("kernel_source_sha256", "").strip():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _ev_ms(torch, fn, reps, stream=None):
@@ -237,7 +259,7 @@ def main() -> int:
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
-            "traffic": None,
+            "traffic": committed_traffic(),
             "avg_launch_ms": round(bounce_ms / max(bounce_launches, 1), 4),
             "flops_per_launch": int(flops / max(bounce_launches, 1)),
             "segments_per_step": int(segs / args.steps),
