@@ -66,6 +66,8 @@ struct emrt_ctx {
     bool batched = false;           // member of an emrt_batch
     double* adj_rows = nullptr;     // [5 + 2 adjoint_materials][n_links]
     CompactTemp ctmp{};             // table compaction scratch
+    RxBins bins{};                  // receivers binned for the diffraction candidates
+    ValidTemp vtmp{};               // validation survivors
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -215,6 +217,15 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->cache[0] = cv.take<KeyRec>(c->P);
     c->cache[1] = cv.take<KeyRec>(c->P);
     c->illum = cv.take<uint32_t>((long long)z.n_tx * c->e_words);
+    {
+        const long long nc = (long long)kGridN * kGridN;
+        c->bins.grid = cv.take<RxGrid>(1);
+        c->bins.cnt = cv.take<uint32_t>(nc);
+        c->bins.cursor = cv.take<uint32_t>(nc);
+        c->bins.start = cv.take<uint32_t>(nc + 1);
+        c->bins.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(nc) / 4 + 16);
+        c->bins.sorted = cv.take<float4>(z.n_rx);
+    }
     ValidPaths& vp = c->vp;
     vp.cap = c->vcap;
     vp.key = cv.take<KeyRec>(c->vcap);
@@ -237,6 +248,10 @@ static void layout(emrt_ctx* c, Carver& cv) {
     lg.key = cv.take<uint32_t>(lg.cap);
     c->kstate = cv.take<uint8_t>(c->vcap);
     c->occl = cv.take<uint32_t>(c->vcap);
+    c->vtmp.flag = cv.take<uint32_t>(c->vcap);
+    c->vtmp.off = cv.take<uint32_t>(c->vcap);
+    c->vtmp.surv = cv.take<uint32_t>(c->vcap);
+    c->vtmp.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(c->vcap) / 4 + 16);
     c->link_start = cv.take<int>(c->n_links);
     c->link_end = cv.take<int>(c->n_links);
     c->link_cnt = cv.take<uint32_t>(c->n_links);
@@ -628,7 +643,10 @@ static void step_post(emrt_ctx* c, int discover) {
     PathArgs pa = path_args(c);
     const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
     if (discover) {
-        if (diff) diff_candidates(pa, c->illum, c->e_words, c->rxt.view(), c->rx_prims, c->table, mask, src, st);
+        if (diff) {
+            rx_grid_build(c->f_rx, c->sz.n_rx, c->bins, st);
+            diff_candidates(pa, c->illum, c->e_words, c->bins, c->table, mask, src, st);
+        }
         table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags,
                       c->ctmp, st);
         pa.cand = c->cand;
@@ -640,7 +658,7 @@ static void step_post(emrt_ctx* c, int discover) {
     }
     // ---- exact validation + fields (Sections II-A, III-B, III-C)
     ev_record(c);
-    validate_eval(pa, c->n_links, c->P, st);
+    validate_eval(pa, c->n_links, c->P, c->vtmp, st);
     ev_record(c);
     // ---- per-link reduction (Section V-D statistics)
     link_keys(c->vp, c->sz.n_rx, c->sk0, c->sv0, st);

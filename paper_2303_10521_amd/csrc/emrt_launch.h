@@ -194,7 +194,21 @@ struct PathArgs {
 
 void cache_insert(unsigned long long* table, unsigned long long mask, const KeyRec* cache,
                   const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags, hipStream_t st);
-void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, Bvh rxt, const float4* rx_prims,
+// receivers binned on a kGridN x kGridN grid over their x-y bounding box
+constexpr int kGridN = 128;
+struct RxGrid {
+    float x0, y0, inv_h;  // cell (cx, cy) = floor((x - x0) inv_h), floor((y - y0) inv_h), clamped
+};
+struct RxBins {
+    RxGrid* grid;
+    uint32_t* cnt;       // [kGridN^2]
+    uint32_t* cursor;    // [kGridN^2]
+    uint32_t* start;     // [kGridN^2 + 1] first sorted receiver of each cell
+    uint32_t* scan_tmp;
+    float4* sorted;      // [n_rx] (x, y, z, receiver index) by cell
+};
+void rx_grid_build(const double* rx_pos, int n_rx, const RxBins& b, hipStream_t st);
+void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
                      unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
 // scratch of the table compaction: [n_slots] flags and offsets + scan temp
 struct CompactTemp {
@@ -204,7 +218,14 @@ struct CompactTemp {
 };
 void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
                    unsigned long long* n_cand, long long cap, uint32_t* flags, const CompactTemp& t, hipStream_t st);
-void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, hipStream_t st);
+// scratch of the validation: [n_links + cap_cand] survivor flags, offsets, list + scan temp
+struct ValidTemp {
+    uint32_t* flag;
+    uint32_t* off;
+    uint32_t* surv;
+    uint32_t* scan_tmp;
+};
+void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, const ValidTemp& t, hipStream_t st);
 void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st);
 void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
                  int* cnt, long long n_links, hipStream_t st);

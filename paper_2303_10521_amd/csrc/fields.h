@@ -411,6 +411,7 @@ struct Wedge {
 __device__ __forceinline__ dv3 vert(const SceneDev& s, int v) { return ldf3(s.verts + 3 * (long long)v); }
 
 __device__ __forceinline__ Wedge wedge_of(const SceneDev& s, int e) {
+#pragma clang fp contract(off)
     const int* row = s.edge_i + 6 * (long long)e;
     Wedge w;
     w.P0 = vert(s, row[0]);
@@ -431,6 +432,7 @@ __device__ __forceinline__ Wedge wedge_of(const SceneDev& s, int e) {
 
 // angle of p about the edge, measured from the 0-face into the exterior, [0, 2 pi)
 __device__ __forceinline__ double wedge_angle(const Wedge& w, dv3 p) {
+#pragma clang fp contract(off)
     dv3 v = p - w.P0;
     double ph = atan2(dot(v, w.n0), dot(v, w.t0));
     if (ph < 0) ph += 2.0 * kPi;

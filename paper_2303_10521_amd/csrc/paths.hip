@@ -81,12 +81,14 @@ void table_compact(const unsigned long long* table, unsigned long long n_slots, 
 // ------------------------------------------------------------ geometry ----
 
 __device__ __forceinline__ dv3 mirror(dv3 p, const double* pl) {
+#pragma clang fp contract(off)
     dv3 n = d3(pl[0], pl[1], pl[2]);
     return p - n * (2.0 * (dot(n, p) - pl[3]));
 }
 
 // point-in-triangle after dropping the dominant normal axis (edges inside)
 __device__ __forceinline__ bool in_tri(dv3 p, dv3 a, dv3 b, dv3 c) {
+#pragma clang fp contract(off)
     dv3 n = cross(b - a, c - a);
     double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
     double P0, P1, A0, A1, B0, B1, C0, C1;
@@ -121,6 +123,7 @@ __device__ __forceinline__ bool occluded(const PathArgs& a, dv3 p0, dv3 p1, int 
 // Keller point (equal angles with the edge) strictly inside the edge, both
 // ends in the exterior wedge, receiver leg within diff_max_leg.
 __device__ __forceinline__ bool keller(const Wedge& w, dv3 s, dv3 r, double max_leg, dv3& Q) {
+#pragma clang fp contract(off)
     double zs = dot(s - w.P0, w.e), zr = dot(r - w.P0, w.e);
     double rs = len(s - w.P0 - w.e * zs), rr = len(r - w.P0 - w.e * zr);
     if (!(rs + rr > 0)) return false;
@@ -134,11 +137,87 @@ __device__ __forceinline__ bool keller(const Wedge& w, dv3 s, dv3 r, double max_
 }
 
 // -------------------------------------------------------- diffraction ----
-__global__ void __launch_bounds__(128) k_diff_cand(PathArgs a, const uint32_t* illum, int e_words, Bvh rxt,
-                                                   const float4* rx_prims, unsigned long long* table,
-                                                   unsigned long long mask, KeySrc src) {
-    long long n = (long long)a.f.n_tx * a.s.E;
-    GRID_STRIDE(k, n) {
+// Diffraction candidates: for every lit (tx, edge) pair, the receivers in the
+// edge's box grown by diff_max_leg + 1 m, each tested exactly (Keller point
+// strictly inside the edge, both ends in the exterior wedge, receiver leg
+// within diff_max_leg) and inserted into the path table.
+//
+// The receivers are binned per frame on a kGridN x kGridN grid over their
+// x-y bounding box (counting sort by cell), so the receivers of one row of
+// cells are contiguous; one wave takes one lit pair and its lanes test the
+// receivers of each overlapped row in parallel.  Cell indices are monotone
+// in the float32 coordinates, so the rows cover every receiver in the box.
+__device__ __forceinline__ int grid_cell(float v, float v0, float inv_h) {
+    float f = floorf((v - v0) * inv_h);
+    if (!(f >= 0.0f)) return 0;  // also NaN
+    return f > (float)(kGridN - 1) ? kGridN - 1 : (int)f;
+}
+
+__global__ void __launch_bounds__(256) k_rx_grid(const double* rx, int n, RxGrid* g) {
+    __shared__ float sh[4][256];
+    float lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        float x = (float)rx[3 * (long long)i], y = (float)rx[3 * (long long)i + 1];
+        lx = fminf(lx, x); ly = fminf(ly, y); hx = fmaxf(hx, x); hy = fmaxf(hy, y);
+    }
+    sh[0][threadIdx.x] = lx; sh[1][threadIdx.x] = ly; sh[2][threadIdx.x] = hx; sh[3][threadIdx.x] = hy;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] = fminf(sh[0][threadIdx.x], sh[0][threadIdx.x + w]);
+            sh[1][threadIdx.x] = fminf(sh[1][threadIdx.x], sh[1][threadIdx.x + w]);
+            sh[2][threadIdx.x] = fmaxf(sh[2][threadIdx.x], sh[2][threadIdx.x + w]);
+            sh[3][threadIdx.x] = fmaxf(sh[3][threadIdx.x], sh[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float ext = fmaxf(fmaxf(sh[2][0] - sh[0][0], sh[3][0] - sh[1][0]), 1.0f);
+        if (!(ext < INFINITY)) ext = 1.0f;  // no receivers, or non-finite input (flagged elsewhere)
+        g->x0 = sh[0][0] < INFINITY ? sh[0][0] : 0.0f;
+        g->y0 = sh[1][0] < INFINITY ? sh[1][0] : 0.0f;
+        g->inv_h = (float)kGridN / ext;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rx_count(const double* rx, int n, const RxGrid* g, uint32_t* cnt) {
+    const RxGrid gr = *g;
+    GRID_STRIDE(i, (long long)n) {
+        int cx = grid_cell((float)rx[3 * i], gr.x0, gr.inv_h), cy = grid_cell((float)rx[3 * i + 1], gr.y0, gr.inv_h);
+        atomicAdd(&cnt[cy * kGridN + cx], 1u);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rx_scatter(const double* rx, int n, const RxGrid* g, const uint32_t* start,
+                                                    uint32_t* cursor, float4* sorted) {
+    const RxGrid gr = *g;
+    GRID_STRIDE(i, (long long)n) {
+        float x = (float)rx[3 * i], y = (float)rx[3 * i + 1], z = (float)rx[3 * i + 2];
+        int c = grid_cell(y, gr.y0, gr.inv_h) * kGridN + grid_cell(x, gr.x0, gr.inv_h);
+        uint32_t pos = start[c] + atomicAdd(&cursor[c], 1u);
+        sorted[pos] = make_float4(x, y, z, __int_as_float((int)i));
+    }
+}
+
+void rx_grid_build(const double* rx_pos, int n_rx, const RxBins& b, hipStream_t st) {
+    const long long nc = (long long)kGridN * kGridN;
+    hipLaunchKernelGGL(k_rx_grid, dim3(1), dim3(256), 0, st, rx_pos, n_rx, b.grid);
+    fill_u32(b.cnt, 0u, nc, st);
+    fill_u32(b.cursor, 0u, nc, st);
+    int g = grid_for(n_rx);
+    hipLaunchKernelGGL(k_rx_count, dim3(g), dim3(256), 0, st, rx_pos, n_rx, b.grid, b.cnt);
+    exclusive_scan(b.cnt, b.start, nc, b.scan_tmp, b.start + nc, st);
+    hipLaunchKernelGGL(k_rx_scatter, dim3(g), dim3(256), 0, st, rx_pos, n_rx, b.grid, b.start, b.cursor, b.sorted);
+}
+
+__global__ void __launch_bounds__(256) k_diff_cand(PathArgs a, const uint32_t* illum, int e_words, RxBins bins,
+                                                   unsigned long long* table, unsigned long long mask, KeySrc src) {
+    const long long n = (long long)a.f.n_tx * a.s.E;
+    const int lane = lane_id();
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long n_waves = ((long long)gridDim.x * blockDim.x) >> 6;
+    const RxGrid gr = *bins.grid;
+    for (long long k = wave; k < n; k += n_waves) {
         int tx = (int)(k / a.s.E), e = (int)(k - (long long)tx * a.s.E);
         if (!(illum[(long long)tx * e_words + (e >> 5)] & (1u << (e & 31)))) continue;
         Wedge w = wedge_of(a.s, e);
@@ -147,25 +226,31 @@ __global__ void __launch_bounds__(128) k_diff_cand(PathArgs a, const uint32_t* i
         float g = (float)a.diff_max_leg + 1.0f;
         float qlx = (float)fmin(w.P0.x, P1.x) - g, qly = (float)fmin(w.P0.y, P1.y) - g, qlz = (float)fmin(w.P0.z, P1.z) - g;
         float qhx = (float)fmax(w.P0.x, P1.x) + g, qhy = (float)fmax(w.P0.y, P1.y) + g, qhz = (float)fmax(w.P0.z, P1.z) + g;
-        box_query(rxt, qlx, qly, qlz, qhx, qhy, qhz, [&](int slot) {
-            int rx = __float_as_int(rx_prims[slot].w);
-            dv3 r = ldd3(a.f.rx_pos + 3 * rx);
-            dv3 Q;
-            if (!keller(w, s, r, a.diff_max_leg, Q)) return;
-            KeyRec key;
-            key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
-            key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
-            uint64_t h = key_hash(key.tx, key.rx, key.to, key.ids);
-            if (table_insert(table, mask, ref_diff(tx, e, rx), key, h, src) < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
-        });
+        int cx0 = grid_cell(qlx, gr.x0, gr.inv_h), cx1 = grid_cell(qhx, gr.x0, gr.inv_h);
+        int cy0 = grid_cell(qly, gr.y0, gr.inv_h), cy1 = grid_cell(qhy, gr.y0, gr.inv_h);
+        for (int cy = cy0; cy <= cy1; cy++) {
+            uint32_t j0 = bins.start[cy * kGridN + cx0], j1 = bins.start[cy * kGridN + cx1 + 1];
+            for (uint32_t j = j0 + (uint32_t)lane; j < j1; j += 64u) {
+                float4 p = bins.sorted[j];
+                if (!(p.x >= qlx && p.x <= qhx && p.y >= qly && p.y <= qhy && p.z >= qlz && p.z <= qhz)) continue;
+                int rx = __float_as_int(p.w);
+                dv3 Q;
+                if (!keller(w, s, ldd3(a.f.rx_pos + 3 * rx), a.diff_max_leg, Q)) continue;
+                KeyRec key;
+                key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
+                key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
+                uint64_t h = key_hash(key.tx, key.rx, key.to, key.ids);
+                if (table_insert(table, mask, ref_diff(tx, e, rx), key, h, src) < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
+            }
+        }
     }
 }
 
-void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, Bvh rxt, const float4* rx_prims,
+void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
                      unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st) {
     long long n = (long long)a.f.n_tx * a.s.E;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_diff_cand, dim3(grid_for(n, 128)), dim3(128), 0, st, a, illum, e_words, rxt, rx_prims, table,
+    hipLaunchKernelGGL(k_diff_cand, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, a, illum, e_words, bins, table,
                        mask, src);
 }
 
@@ -205,6 +290,7 @@ __device__ __forceinline__ bool key_in_range(const PathArgs& a, const KeyRec& ke
 //   diffraction: Keller point strictly inside the edge, both ends in the
 //   exterior wedge, receiver leg within diff_max_leg.
 __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, Built& g) {
+#pragma clang fp contract(off)
     const SceneDev& S = a.s;
     g.type = key.to & 0xff;
     g.order = key.to >> 8;
@@ -345,26 +431,46 @@ __global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
 // is in fields.h).  Delay L / c; Doppler (Section III-C, Eq (3) generalised
 // to moving interaction points) -(1/lambda)[k_K.v_rx - k_0.v_tx +
 // sum (k_{i-1} - k_i).v_obj]; AoD / AoA the directions of k_0 and -k_K.
-__global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, long long cap_cand) {
+// Survivors of the validation (constructed, no leg blocked) get their path
+// slot from an exclusive scan of 0/1 flags in key order, so the field kernel
+// runs on dense waves and the valid paths keep the keys' order.
+__global__ void __launch_bounds__(256) k_valid_flags(PathArgs a, long long n_links, long long cap_cand,
+                                                     uint32_t* flag) {
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     long long n = n_links + nc;
-    long long stride = (long long)gridDim.x * blockDim.x;
-    long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long iters = (n + stride - 1) / stride;
+    GRID_STRIDE(q, n_links + cap_cand) flag[q] = (q < n && a.state[q] && !a.occl[q]) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_valid_list(const uint32_t* flag, const uint32_t* off, long long n,
+                                                    uint32_t* surv) {
+    GRID_STRIDE(q, n) if (flag[q]) surv[off[q]] = (uint32_t)q;
+}
+
+__global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, const uint32_t* surv) {
+    long long n = (long long)*a.out.count;
+    if (n > a.out.cap) n = a.out.cap;
     const SceneDev& S = a.s;
-    for (long long it = 0; it < iters; it++) {
-        long long q = start + it * stride;
-        bool ok = q < n && a.state[q] && !a.occl[q];
-        KeyRec key;
+    GRID_STRIDE(pos, n) {
+        long long q = surv[pos];
+        KeyRec key = key_at(a, q, n_links);
         Built g;
-        if (ok) {
-            key = key_at(a, q, n_links);
-            ok = construct(a, key, g);
+        if (!construct(a, key, g)) {
+            // k_construct accepted this key with the same code (contraction
+            // off) and inputs, so this does not happen; keep the slot defined
+            a.out.key[pos] = key;
+#pragma unroll
+            for (int j = 0; j < 5; j++) a.out.tri[5 * pos + j] = -1;
+            for (int fi = 0; fi < a.fc.nf; fi++) {
+                a.out.a[2 * (pos * a.fc.nf + fi)] = 0.0;
+                a.out.a[2 * (pos * a.fc.nf + fi) + 1] = 0.0;
+                a.out.fd[pos * a.fc.nf + fi] = 0.0;
+            }
+            a.out.tau[pos] = 0.0;
+            a.out.ang[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
+            atomicOr(a.flags, FLAG_PATH_CAP);
+            continue;
         }
-        long long pos = wave_append(a.out.count, ok);
-        if (!ok) continue;
-        if (pos >= a.out.cap) { atomicOr(a.flags, FLAG_PATH_CAP); continue; }
         dv3 vt = ldd3(a.f.tx_vel + 3 * key.tx), vr = ldd3(a.f.rx_vel + 3 * key.rx);
         double th = a.f.tx_orient[2 * key.tx], phi = a.f.tx_orient[2 * key.tx + 1];
         PathGeo<double> pg;
@@ -413,11 +519,16 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, l
     }
 }
 
-void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, hipStream_t st) {
+void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, const ValidTemp& t, hipStream_t st) {
     long long n = n_links + cap_cand;
     hipLaunchKernelGGL(k_construct, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
     hipLaunchKernelGGL(k_shadow, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_fields, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
+    int g = grid_for(n, 256, 16384);
+    hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t.flag);
+    // valid-path count: low word = scan total (the high word is cleared with the step's counters)
+    exclusive_scan(t.flag, t.off, n, t.scan_tmp, (uint32_t*)a.out.count, st);
+    hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t.flag, t.off, n, t.surv);
+    hipLaunchKernelGGL(k_fields, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t.surv);
 }
 
 // ----------------------------------------------------------- per link ----
