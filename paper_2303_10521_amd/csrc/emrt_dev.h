@@ -303,16 +303,29 @@ __device__ __forceinline__ bool tri_hit(const TriP& p, const RayPre& r, float& t
 }
 
 // --------------------------------------------------------------------------
-// stackless traversal over parent links
+// BVH traversal
 //
-// State per ray: the current internal node and what is left to do there:
-//   0 test the first child, 1 test the second child, 2 climb to the parent,
-//   3 just climbed back from child `came` (decides between 1 and 2).
-// A node is loaded once when entered and once more when climbed back to.
-// Closest-hit and shadow traversal visit the near child first (the child on
-// the ray's side of the Morton split axis); the all-leaves queries go left
-// first.
+// Main loop: a short per-ray stack.  At an internal node both child boxes
+// are tested; the near child (the child on the ray's side of the Morton
+// split axis, or the left child for the unordered queries) is entered and the
+// other pushed with its entry distance, which is checked again against the
+// current bound when it is popped.  Each internal node is loaded once.
+//
+// The stack holds kStackDepth entries; it only holds the pending far
+// children along the current path, and the LBVHs of a city are about 25
+// levels deep.  The compiler keeps the stack in registers, so a deeper stack
+// costs occupancy: 16 entries traced the city's bounces fastest of 16, 24
+// and 32.  If a deeper tree overflows it, the traversal starts over
+// with the stackless walk over parent links below, which needs no stack; all
+// queries are idempotent (closest hit with a fixed tie rule, any hit, leaf
+// visits whose effects are set inserts), so work done before the restart
+// does not change the result.
 // --------------------------------------------------------------------------
+#ifndef EMRT_STACK_DEPTH
+#define EMRT_STACK_DEPTH 16
+#endif
+constexpr int kStackDepth = EMRT_STACK_DEPTH;
+
 __device__ __forceinline__ BNode ld_node(const BNode* n, int i) { return n[i]; }
 
 __device__ __forceinline__ void child_box(const BNode& nd, int side, float& lx, float& ly, float& lz, float& hx,
@@ -326,22 +339,24 @@ __device__ __forceinline__ int near_side(const BNode& nd, const RayPre& r) {
     return (r.negmask >> axis) & 1;
 }
 
-// Generic driver.  test(nd, side, child) returns true to descend into `child`
-// (an internal node); it handles leaves itself and returns false for them.
-// ordered: visit the near child first.  Returns early when stop() is true.
+// Stackless walk over parent links.  State per ray: the current internal
+// node and what is left to do there: 0 test the first child, 1 test the
+// second child, 2 climb to the parent, 3 just climbed back from child `came`
+// (decides between 1 and 2).
 template <bool ORDERED, class Test, class Stop>
-__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Stop stop) {
+__device__ __forceinline__ void traverse_stackless(const BNode* nodes, const RayPre& r, Test test, Stop stop) {
     int cur = 0, state = 0, came = 0;
     while (true) {
         BNode nd = ld_node(nodes, cur);
         int first = ORDERED ? near_side(nd, r) : 0;
         if (state == 3) state = (came == first) ? 1 : 2;
         bool descended = false;
+        float tn;
         if (state == 0) {
             int child;
             float lx, ly, lz, hx, hy, hz;
             child_box(nd, first, lx, ly, lz, hx, hy, hz, child);
-            if (test(lx, ly, lz, hx, hy, hz, child)) { cur = child; descended = true; }
+            if (test(lx, ly, lz, hx, hy, hz, child, tn)) { cur = child; descended = true; }
             else state = 1;
             if (stop()) return;
         }
@@ -349,7 +364,7 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
             int child;
             float lx, ly, lz, hx, hy, hz;
             child_box(nd, 1 - first, lx, ly, lz, hx, hy, hz, child);
-            if (test(lx, ly, lz, hx, hy, hz, child)) { cur = child; state = 0; descended = true; }
+            if (test(lx, ly, lz, hx, hy, hz, child, tn)) { cur = child; state = 0; descended = true; }
             else state = 2;
             if (stop()) return;
         }
@@ -362,7 +377,58 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
     }
 }
 
+// Generic driver.  test(box, child, tn) returns true to descend into `child`
+// (an internal node; tn = the box's entry distance); it handles leaves itself
+// and returns false for them.  keep(tn) re-checks a pushed child when it is
+// popped.  Returns early when stop() is true.
+template <bool ORDERED, class Test, class Keep, class Stop>
+__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Keep keep, Stop stop) {
+    int stk_node[kStackDepth];
+    float stk_t[kStackDepth];
+    int sp = 0, cur = 0;
+    bool overflow = false;
+    while (true) {
+        BNode nd = ld_node(nodes, cur);
+        int first = ORDERED ? near_side(nd, r) : 0;
+        int ca, cb;
+        float la, lb;
+        float lx, ly, lz, hx, hy, hz;
+        child_box(nd, first, lx, ly, lz, hx, hy, hz, ca);
+        bool da = test(lx, ly, lz, hx, hy, hz, ca, la);
+        if (stop()) return;
+        child_box(nd, 1 - first, lx, ly, lz, hx, hy, hz, cb);
+        bool db = test(lx, ly, lz, hx, hy, hz, cb, lb);
+        if (stop()) return;
+        if (da) {
+            if (db) {
+                if (sp == kStackDepth) { overflow = true; break; }
+                stk_node[sp] = cb;
+                stk_t[sp] = lb;
+                sp++;
+            }
+            cur = ca;
+            continue;
+        }
+        if (db) {
+            cur = cb;
+            continue;
+        }
+        bool found = false;
+        while (sp > 0) {
+            sp--;
+            if (keep(stk_t[sp])) {
+                cur = stk_node[sp];
+                found = true;
+                break;
+            }
+        }
+        if (!found) return;
+    }
+    if (overflow) traverse_stackless<ORDERED>(nodes, r, test, stop);
+}
+
 struct NoStop { __device__ bool operator()() const { return false; } };
+struct KeepAll { __device__ bool operator()(float) const { return true; } };
 
 // Closest hit among triangles not on face `skip_face`.  best_t / best_tri /
 // best_face carry the current best (ties broken by the lowest triangle id),
@@ -374,8 +440,7 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
     if (bvh.n_prims <= 0) return;
     if (STATS) n_nodes++;
     traverse<true>(bvh.nodes, r,
-        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
-            float tn;
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
             if (!slab(lx, ly, lz, hx, hy, hz, r, 0.0f, best_t, tn)) return false;
             if (!((uint32_t)child & EMRT_LEAF)) { if (STATS) n_nodes++; return true; }
             TriP p = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
@@ -388,6 +453,7 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
             }
             return false;
         },
+        [&](float tn) -> bool { return tn <= best_t; },
         NoStop());
 }
 
@@ -397,8 +463,7 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
     if (bvh.n_prims <= 0) return false;
     bool found = false;
     traverse<true>(bvh.nodes, r,
-        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
-            float tn;
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
             if (!slab(lx, ly, lz, hx, hy, hz, r, 0.0f, tmax, tn)) return false;
             if (!((uint32_t)child & EMRT_LEAF)) return true;
             TriP p = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
@@ -407,6 +472,7 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
             if (face != xa && face != xb && tri_hit(p, r, t) && t < tmax) found = true;
             return false;
         },
+        KeepAll(),
         [&]() { return found; });
     return found;
 }
@@ -416,13 +482,13 @@ template <class Leaf>
 __device__ __forceinline__ void all_hits(const Bvh& bvh, const RayPre& r, float tmax, float grow, Leaf leaf) {
     if (bvh.n_prims <= 0) return;
     traverse<false>(bvh.nodes, r,
-        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
-            float tn;
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
             if (!slab(lx - grow, ly - grow, lz - grow, hx + grow, hy + grow, hz + grow, r, 0.0f, tmax, tn)) return false;
             if (!((uint32_t)child & EMRT_LEAF)) return true;
             leaf((int)((uint32_t)child & ~EMRT_LEAF));
             return false;
         },
+        KeepAll(),
         NoStop());
 }
 
@@ -433,13 +499,15 @@ __device__ __forceinline__ void box_query(const Bvh& bvh, float qlx, float qly, 
     if (bvh.n_prims <= 0) return;
     RayPre dummy{};
     traverse<false>(bvh.nodes, dummy,
-        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child) -> bool {
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
+            tn = 0.0f;
             bool ov = lx <= qhx && hx >= qlx && ly <= qhy && hy >= qly && lz <= qhz && hz >= qlz;
             if (!ov) return false;
             if (!((uint32_t)child & EMRT_LEAF)) return true;
             leaf((int)((uint32_t)child & ~EMRT_LEAF));
             return false;
         },
+        KeepAll(),
         NoStop());
 }
 
