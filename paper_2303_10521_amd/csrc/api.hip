@@ -68,6 +68,7 @@ struct emrt_ctx {
     CompactTemp ctmp{};             // table compaction scratch
     RxBins bins{};                  // receivers binned for the diffraction candidates
     ValidTemp vtmp{};               // validation survivors
+    int* ktri = nullptr;            // [vcap][5] reflection triangles of constructed keys
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -166,6 +167,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     S.face_first = cv.take<int>(F);
     S.face_off = cv.take<int>(F + 1);
     S.face_tris = cv.take<int>(T);
+    S.face_tv = cv.take<float>(9 * T);
     S.tris_static = cv.take<int>(T);
     S.tris_dynamic = cv.take<int>(T);
     S.edge_i = cv.take<int>(2 * 6 * (long long)c->E_cap);
@@ -250,7 +252,11 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->occl = cv.take<uint32_t>(c->vcap);
     c->vtmp.flag = cv.take<uint32_t>(c->vcap);
     c->vtmp.off = cv.take<uint32_t>(c->vcap);
+    c->vtmp.flag_d = cv.take<uint32_t>(c->vcap);
+    c->vtmp.off_d = cv.take<uint32_t>(c->vcap);
+    c->vtmp.cnt = cv.take<uint32_t>(2);
     c->vtmp.surv = cv.take<uint32_t>(c->vcap);
+    c->ktri = cv.take<int>(5 * c->vcap);
     c->vtmp.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(c->vcap) / 4 + 16);
     c->link_start = cv.take<int>(c->n_links);
     c->link_end = cv.take<int>(c->n_links);
@@ -534,6 +540,7 @@ static PathArgs path_args(emrt_ctx* c) {
     a.legs.count = c->ctr + C_NLEGS;
     a.state = c->kstate;
     a.occl = c->occl;
+    a.ktri = c->ktri;
     a.flags = c->flags;
     return a;
 }
@@ -597,6 +604,7 @@ static void step_pre(emrt_ctx* c, int discover) {
     // ---- frame geometry (Section II-A: BVH updated between frames)
     scene_world(S, c->f_xf, c->flags, st);
     scene_planes(S, st);
+    scene_face_tv(S, st);
     if (S.T_d > 0) {
         tri_boxes(S, S.tris_dynamic, S.T_d, c->box_dy, st);
         if (discover || c->dy.n != S.T_d) bvh_build(c->box_dy, S.T_d, c->dy, c->tmp, st);

@@ -528,4 +528,22 @@ __device__ __forceinline__ long long wave_append(unsigned long long* counter, bo
     return keep ? (long long)(base + (unsigned long long)prefix_below(m)) : -1;
 }
 
+// One atomic per wave for a variable number of items per lane: every lane of
+// the wave calls this at the same point (uniform control flow); returns the
+// lane's first slot.  Inclusive scan over the wave with shuffles.
+__device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* counter, uint32_t n) {
+    const int lane = lane_id();
+    uint32_t x = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    uint32_t total = __shfl(x, 63);
+    unsigned long long base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned long long)total);
+    base = __shfl(base, 63);
+    return base + (unsigned long long)(x - n);
+}
+
 }  // namespace emrt

@@ -62,6 +62,7 @@ struct SceneDev {
     int* face_first;            // [F] lowest triangle id
     int* face_off;              // [F+1]
     int* face_tris;             // [T] sorted by (face, tri)
+    float* face_tv;             // [T][9] world vertices of face_tris[q] (refreshed every frame)
     int* tris_static;           // [T_s]
     int* tris_dynamic;          // [T_d]
     int T_s, T_d, O_d;
@@ -79,6 +80,8 @@ void scene_prepare(SceneDev& s, const uint8_t* object_dynamic, uint32_t* scratch
 int scene_edges(SceneDev& s, int* obj_off, int* obj_faces, int* counter, const BuildTemp& tmp, hipStream_t st);
 void scene_world(const SceneDev& s, const double* xform, uint32_t* flags, hipStream_t st);
 void scene_planes(const SceneDev& s, hipStream_t st);
+// face-ordered triangle vertices (face_tv) of the current world vertices
+void scene_face_tv(const SceneDev& s, hipStream_t st);
 void tri_boxes(const SceneDev& s, const int* list, int n, float* box6, hipStream_t st);
 void tri_prims(const SceneDev& s, const int* list, const Tree& tree, TriP* prims, hipStream_t st);
 void edge_boxes(const SceneDev& s, float* box6, hipStream_t st);
@@ -179,6 +182,7 @@ struct PathArgs {
     LegBuf legs;
     uint8_t* state;   // [n_links + cap_cand] 1 = constructed
     uint32_t* occl;   // [n_links + cap_cand] 1 = a leg is blocked
+    int* ktri;        // [n_links + cap_cand][5] triangle of each reflection point of a constructed key
     FrameDev f;
     Bvh st, dy;
     const TriP* st_prims;
@@ -220,9 +224,12 @@ void table_compact(const unsigned long long* table, unsigned long long n_slots, 
                    unsigned long long* n_cand, long long cap, uint32_t* flags, const CompactTemp& t, hipStream_t st);
 // scratch of the validation: [n_links + cap_cand] survivor flags, offsets, list + scan temp
 struct ValidTemp {
-    uint32_t* flag;
+    uint32_t* flag;     // line of sight and specular survivors
     uint32_t* off;
-    uint32_t* surv;
+    uint32_t* flag_d;   // diffraction survivors
+    uint32_t* off_d;
+    uint32_t* cnt;      // [2] survivor counts of the two kinds
+    uint32_t* surv;     // survivors, the first kind first
     uint32_t* scan_tmp;
 };
 void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, const ValidTemp& t, hipStream_t st);

@@ -462,6 +462,7 @@ struct PathGeo {
 // of the points with respect to the transmitter flow through R.
 template <class R>
 __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key, V3<R> s, dv3 rx, PathGeo<R>& g) {
+#pragma clang fp contract(off)
     g.type = key.to & 0xff;
     g.order = key.to >> 8;
     g.P[0] = s;
@@ -511,7 +512,9 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
 // every carrier.  dmode = 0: the field; dmode = i >= 1 (specular): the
 // derivative with respect to the permittivity of bounce i's material;
 // dmode = 1 / 2 (diffraction): with respect to the 0-face / n-face material.
-template <class R>
+// KIND = 1 / 2 compiles only the line-of-sight-and-specular / diffraction
+// branch (the caller guarantees the path type); 0 keeps both.
+template <class R, int KIND = 0>
 __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc, const KeyRec& key, const PathGeo<R>& g,
                                            R th, R phi, int dmode, V3<R>* kk, R& L, Cx<R>* amp) {
     L = rl<R>(0.0);
@@ -530,7 +533,8 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
 #pragma unroll
     for (int i = 1; i <= EMRT_KMAX; i++)
         if (i == nlegs - 1) kK = kk[i];
-    if (g.type != KT_DIFF) {
+    const bool diffracted = KIND == 2 ? true : (KIND == 1 ? false : g.type == KT_DIFF);
+    if (!diffracted) {
         V3<R> e0 = antenna_x<R>(fc.ant_mode, k0, th, phi);
         V3<R> er = antenna_x<R>(0, kK, rl<R>(0.0), rl<R>(0.0));
         for (int fi = 0; fi < fc.nf; fi++) {

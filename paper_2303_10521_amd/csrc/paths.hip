@@ -101,15 +101,15 @@ __device__ __forceinline__ bool in_tri(dv3 p, dv3 a, dv3 b, dv3 c) {
     return (w0 >= 0 && w1 >= 0 && w2 >= 0) || (w0 <= 0 && w1 <= 0 && w2 <= 0);
 }
 
-// lowest triangle id of face f containing p, or -1
+// lowest triangle id of face f containing p, or -1 (face_tris is sorted by
+// id within a face, so the first hit is the lowest; face_tv holds the world
+// vertices of face_tris[q] at 9 q)
 __device__ __forceinline__ int face_contains(const SceneDev& s, int f, dv3 p) {
-    int found = -1;
     for (int q = s.face_off[f]; q < s.face_off[f + 1]; q++) {
-        int t = s.face_tris[q];
-        if (found >= 0 && t > found) break;  // face_tris is sorted by id
-        if (in_tri(p, vert(s, s.tris[3 * t]), vert(s, s.tris[3 * t + 1]), vert(s, s.tris[3 * t + 2]))) found = t;
+        const float* v = s.face_tv + 9 * (long long)q;
+        if (in_tri(p, ldf3(v), ldf3(v + 3), ldf3(v + 6))) return s.face_tris[q];
     }
-    return found;
+    return -1;
 }
 
 // float32 shadow ray over the open segment p0 -> p1
@@ -365,12 +365,10 @@ __device__ __forceinline__ KeyRec key_at(const PathArgs& a, long long q, long lo
     return key;
 }
 
+// shadow-ray record of leg I (compile-time) of a constructed key at slot pos
 template <int I>
-__device__ __forceinline__ void emit_leg(const PathArgs& a, const Built& g, const KeyRec& key, bool ok, uint32_t q) {
-    bool has = ok && I + 1 < g.np;
-    long long pos = wave_append(a.legs.count, has);
-    if (!has) return;
-    if (pos >= a.legs.cap) { atomicOr(a.flags, FLAG_PATH_CAP); a.state[q] = 0; return; }
+__device__ __forceinline__ void write_leg(const PathArgs& a, const Built& g, const KeyRec& key, unsigned long long pos,
+                                          uint32_t q) {
     dv3 p0, p1;
     int xa, xb;
     leg_of<I>(g, key, p0, p1, xa, xb);
@@ -402,13 +400,29 @@ __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links
             ok = key_in_range(a, key) && construct(a, key, g);
             a.state[q] = ok ? (uint8_t)1 : (uint8_t)0;
             a.occl[q] = 0u;
+            if (ok) {
+#pragma unroll
+                for (int j = 0; j < EMRT_KMAX; j++) a.ktri[5 * q + j] = g.tri[j];
+            }
         }
-        emit_leg<0>(a, g, key, ok, (uint32_t)q);
-        emit_leg<1>(a, g, key, ok, (uint32_t)q);
-        emit_leg<2>(a, g, key, ok, (uint32_t)q);
-        emit_leg<3>(a, g, key, ok, (uint32_t)q);
-        emit_leg<4>(a, g, key, ok, (uint32_t)q);
-        emit_leg<5>(a, g, key, ok, (uint32_t)q);
+        // one reservation per wave for all legs; a key whose legs do not all
+        // fit is invalid, but every slot below the capacity is still written
+        const uint32_t nleg = ok ? (uint32_t)(g.np - 1) : 0u;
+        const unsigned long long pos = wave_reserve(a.legs.count, nleg);
+        const unsigned long long cap = (unsigned long long)a.legs.cap;
+        if (ok && pos + nleg > cap) {
+            atomicOr(a.flags, FLAG_PATH_CAP);
+            a.state[q] = 0;
+        }
+        if (ok) {
+            const uint32_t qq = (uint32_t)q;
+            if (pos + 0 < cap) write_leg<0>(a, g, key, pos + 0, qq);
+            if (nleg > 1 && pos + 1 < cap) write_leg<1>(a, g, key, pos + 1, qq);
+            if (nleg > 2 && pos + 2 < cap) write_leg<2>(a, g, key, pos + 2, qq);
+            if (nleg > 3 && pos + 3 < cap) write_leg<3>(a, g, key, pos + 3, qq);
+            if (nleg > 4 && pos + 4 < cap) write_leg<4>(a, g, key, pos + 4, qq);
+            if (nleg > 5 && pos + 5 < cap) write_leg<5>(a, g, key, pos + 5, qq);
+        }
     }
 }
 
@@ -432,80 +446,79 @@ __global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
 // to moving interaction points) -(1/lambda)[k_K.v_rx - k_0.v_tx +
 // sum (k_{i-1} - k_i).v_obj]; AoD / AoA the directions of k_0 and -k_K.
 // Survivors of the validation (constructed, no leg blocked) get their path
-// slot from an exclusive scan of 0/1 flags in key order, so the field kernel
-// runs on dense waves and the valid paths keep the keys' order.
+// slot from exclusive scans of 0/1 flags in key order, line of sight and
+// specular paths first, then diffraction paths, so each field kernel runs on
+// dense waves of one path type.
 __global__ void __launch_bounds__(256) k_valid_flags(PathArgs a, long long n_links, long long cap_cand,
-                                                     uint32_t* flag) {
+                                                     uint32_t* flag, uint32_t* flag_d) {
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     long long n = n_links + nc;
-    GRID_STRIDE(q, n_links + cap_cand) flag[q] = (q < n && a.state[q] && !a.occl[q]) ? 1u : 0u;
+    GRID_STRIDE(q, n_links + cap_cand) {
+        bool keep = q < n && a.state[q] && !a.occl[q];
+        bool d = keep && q >= n_links && (a.cand[q - n_links].to & 0xff) == KT_DIFF;
+        flag[q] = (keep && !d) ? 1u : 0u;
+        flag_d[q] = d ? 1u : 0u;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_valid_list(const uint32_t* flag, const uint32_t* off, long long n,
-                                                    uint32_t* surv) {
-    GRID_STRIDE(q, n) if (flag[q]) surv[off[q]] = (uint32_t)q;
+__global__ void __launch_bounds__(256) k_valid_list(ValidTemp t, long long n, unsigned long long* count) {
+    const uint32_t n0 = t.cnt[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = (unsigned long long)n0 + t.cnt[1];
+    GRID_STRIDE(q, n) {
+        if (t.flag[q]) t.surv[t.off[q]] = (uint32_t)q;
+        else if (t.flag_d[q]) t.surv[n0 + t.off_d[q]] = (uint32_t)q;
+    }
 }
 
-__global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, const uint32_t* surv) {
-    long long n = (long long)*a.out.count;
-    if (n > a.out.cap) n = a.out.cap;
+// Fields of the survivors of one kind (KIND 1: line of sight and specular,
+// 2: diffraction); the interaction points are rebuilt with the same formulas
+// as the construction (image method / Keller point), the reflection
+// triangles come from the construction.  Delay L / c; Doppler (Section
+// III-C, Eq (3) generalised to moving interaction points) -(1/lambda)
+// [k_K.v_rx - k_0.v_tx + sum (k_{i-1} - k_i).v_obj]; AoD / AoA the
+// directions of k_0 and -k_K.
+template <int KIND>
+__global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, ValidTemp t) {
+    const long long lo = KIND == 1 ? 0 : (long long)t.cnt[0];
+    const long long hi = KIND == 1 ? (long long)t.cnt[0] : (long long)t.cnt[0] + t.cnt[1];
     const SceneDev& S = a.s;
-    GRID_STRIDE(pos, n) {
-        long long q = surv[pos];
+    for (long long pos = lo + (long long)blockIdx.x * blockDim.x + threadIdx.x; pos < hi;
+         pos += (long long)gridDim.x * blockDim.x) {
+        long long q = t.surv[pos];
         KeyRec key = key_at(a, q, n_links);
-        Built g;
-        if (!construct(a, key, g)) {
-            // k_construct accepted this key with the same code (contraction
-            // off) and inputs, so this does not happen; keep the slot defined
-            a.out.key[pos] = key;
-#pragma unroll
-            for (int j = 0; j < 5; j++) a.out.tri[5 * pos + j] = -1;
-            for (int fi = 0; fi < a.fc.nf; fi++) {
-                a.out.a[2 * (pos * a.fc.nf + fi)] = 0.0;
-                a.out.a[2 * (pos * a.fc.nf + fi) + 1] = 0.0;
-                a.out.fd[pos * a.fc.nf + fi] = 0.0;
-            }
-            a.out.tau[pos] = 0.0;
-            a.out.ang[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
-            atomicOr(a.flags, FLAG_PATH_CAP);
-            continue;
-        }
+        dv3 sx = ldd3(a.f.tx_pos + 3 * key.tx), rx = ldd3(a.f.rx_pos + 3 * key.rx);
+        PathGeo<double> pg;
+        path_points<double>(S, key, v3c<double>(sx), rx, pg);
         dv3 vt = ldd3(a.f.tx_vel + 3 * key.tx), vr = ldd3(a.f.rx_vel + 3 * key.rx);
         double th = a.f.tx_orient[2 * key.tx], phi = a.f.tx_orient[2 * key.tx + 1];
-        PathGeo<double> pg;
-#pragma unroll
-        for (int i = 0; i < EMRT_KMAX + 2; i++) pg.P[i] = v3c<double>(g.P[i]);
-        pg.Rx = v3c<double>(g.R);
-        pg.np = g.np;
-        pg.order = g.order;
-        pg.type = g.type;
         V3<double> kk[EMRT_KMAX + 1];
         double L;
         Cx<double> amp[EMRT_NF];
-        path_field<double>(S, a.fc, key, pg, th, phi, 0, kk, L, amp);
-        const int nlegs = g.np - 1;
+        path_field<double, KIND>(S, a.fc, key, pg, th, phi, 0, kk, L, amp);
+        const int nlegs = pg.np - 1;
         dv3 k0 = val3(kk[0]);
         dv3 kK = k0;
 #pragma unroll
         for (int i = 1; i <= EMRT_KMAX; i++)
             if (i == nlegs - 1) kK = val3(kk[i]);
         double dop = dot(kK, vr) - dot(k0, vt);
-        if (g.type == KT_SPEC) {
+        if (KIND == 1) {
 #pragma unroll
             for (int i = 1; i <= EMRT_KMAX; i++) {
-                if (i > g.order) break;
+                if (i > pg.order || pg.type != KT_SPEC) break;
                 int od = S.face_dyn[key.ids[i - 1]];
                 if (od >= 0) dop += dot(val3(kk[i - 1]) - val3(kk[i]), ldd3(a.f.obj_vel + 3 * (long long)od));
             }
-        } else if (g.type == KT_DIFF) {
-            int od = S.face_dyn[g.w.f0];
+        } else {
+            int od = S.face_dyn[S.edge_i[6 * (long long)key.ids[0] + 2]];
             if (od >= 0) dop += dot(val3(kk[0]) - val3(kk[1]), ldd3(a.f.obj_vel + 3 * (long long)od));
         }
         ValidPaths& o = a.out;
         o.key[pos] = key;
 #pragma unroll
-        for (int j = 0; j < 5; j++) o.tri[5 * pos + j] = g.tri[j];
+        for (int j = 0; j < 5; j++)
+            o.tri[5 * pos + j] = (KIND == 1 && pg.type == KT_SPEC) ? a.ktri[5 * q + j] : -1;
         for (int fi = 0; fi < a.fc.nf; fi++) {
             double lam = kC0 / a.fc.freq[fi];
             o.a[2 * (pos * a.fc.nf + fi)] = amp[fi].re;
@@ -524,11 +537,12 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
     hipLaunchKernelGGL(k_construct, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
     hipLaunchKernelGGL(k_shadow, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
     int g = grid_for(n, 256, 16384);
-    hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t.flag);
-    // valid-path count: low word = scan total (the high word is cleared with the step's counters)
-    exclusive_scan(t.flag, t.off, n, t.scan_tmp, (uint32_t*)a.out.count, st);
-    hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t.flag, t.off, n, t.surv);
-    hipLaunchKernelGGL(k_fields, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t.surv);
+    hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t.flag, t.flag_d);
+    exclusive_scan(t.flag, t.off, n, t.scan_tmp, t.cnt, st);
+    exclusive_scan(t.flag_d, t.off_d, n, t.scan_tmp, t.cnt + 1, st);
+    hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t, n, a.out.count);
+    hipLaunchKernelGGL(k_fields<1>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
+    hipLaunchKernelGGL(k_fields<2>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
 }
 
 // ----------------------------------------------------------- per link ----

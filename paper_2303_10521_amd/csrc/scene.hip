@@ -333,6 +333,23 @@ void scene_planes(const SceneDev& s, hipStream_t st) {
     hipLaunchKernelGGL(k_planes, dim3(grid_for(s.F)), dim3(256), 0, st, s.F, s.face_first, s.tris, s.verts, s.plane);
 }
 
+__global__ void k_face_tv(int T, const int* face_tris, const int* tris, const float* verts, float* tv) {
+    GRID_STRIDE(q, (long long)T) {
+        int t = face_tris[q];
+        for (int k = 0; k < 3; k++) {
+            const float* v = verts + 3 * (long long)tris[3 * t + k];
+            tv[9 * q + 3 * k] = v[0];
+            tv[9 * q + 3 * k + 1] = v[1];
+            tv[9 * q + 3 * k + 2] = v[2];
+        }
+    }
+}
+
+void scene_face_tv(const SceneDev& s, hipStream_t st) {
+    hipLaunchKernelGGL(k_face_tv, dim3(grid_for(s.T)), dim3(256), 0, st, s.T, s.face_tris, s.tris, s.verts,
+                       s.face_tv);
+}
+
 __global__ void k_tri_boxes(const int* list, int n, const int* tris, const float* verts, float* box) {
     GRID_STRIDE(k, (long long)n) {
         int t = list[k];
