@@ -168,6 +168,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     S.face_off = cv.take<int>(F + 1);
     S.face_tris = cv.take<int>(T);
     S.face_tv = cv.take<float>(9 * T);
+    S.face_box = cv.take<float>(6 * F);
     S.tris_static = cv.take<int>(T);
     S.tris_dynamic = cv.take<int>(T);
     S.edge_i = cv.take<int>(2 * 6 * (long long)c->E_cap);

@@ -63,6 +63,7 @@ struct SceneDev {
     int* face_off;              // [F+1]
     int* face_tris;             // [T] sorted by (face, tri)
     float* face_tv;             // [T][9] world vertices of face_tris[q] (refreshed every frame)
+    float* face_box;            // [F][6] bounding box (lo, hi) of each face (refreshed every frame)
     int* tris_static;           // [T_s]
     int* tris_dynamic;          // [T_d]
     int T_s, T_d, O_d;

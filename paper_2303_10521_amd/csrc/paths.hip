@@ -104,7 +104,19 @@ __device__ __forceinline__ bool in_tri(dv3 p, dv3 a, dv3 b, dv3 c) {
 // lowest triangle id of face f containing p, or -1 (face_tris is sorted by
 // id within a face, so the first hit is the lowest; face_tv holds the world
 // vertices of face_tris[q] at 9 q)
+//
+// A point farther than 1e-6 m (+ 1e-9 of the coordinate) outside the face's
+// bounding box is rejected at once: the points tested lie on the face plane
+// up to double rounding, and a triangle test can only accept points of the
+// triangle up to that rounding, which the margin covers.
 __device__ __forceinline__ int face_contains(const SceneDev& s, int f, dv3 p) {
+    const float* bx = s.face_box + 6 * (long long)f;
+    const double pc[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        double m = 1e-6 + 1e-9 * fabs(pc[c]);
+        if (pc[c] < (double)bx[c] - m || pc[c] > (double)bx[3 + c] + m) return -1;
+    }
     for (int q = s.face_off[f]; q < s.face_off[f + 1]; q++) {
         const float* v = s.face_tv + 9 * (long long)q;
         if (in_tri(p, ldf3(v), ldf3(v + 3), ldf3(v + 6))) return s.face_tris[q];

@@ -345,9 +345,27 @@ __global__ void k_face_tv(int T, const int* face_tris, const int* tris, const fl
     }
 }
 
+// bounding box of each face's triangles (after k_face_tv)
+__global__ void k_face_box(int F, const int* face_off, const float* tv, float* box) {
+    GRID_STRIDE(f, (long long)F) {
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int q = face_off[f]; q < face_off[f + 1]; q++)
+            for (int k = 0; k < 9; k++) {
+                float v = tv[9 * (long long)q + k];
+                lo[k % 3] = fminf(lo[k % 3], v);
+                hi[k % 3] = fmaxf(hi[k % 3], v);
+            }
+        for (int c = 0; c < 3; c++) {
+            box[6 * f + c] = lo[c];
+            box[6 * f + 3 + c] = hi[c];
+        }
+    }
+}
+
 void scene_face_tv(const SceneDev& s, hipStream_t st) {
     hipLaunchKernelGGL(k_face_tv, dim3(grid_for(s.T)), dim3(256), 0, st, s.T, s.face_tris, s.tris, s.verts,
                        s.face_tv);
+    hipLaunchKernelGGL(k_face_box, dim3(grid_for(s.F)), dim3(256), 0, st, s.F, s.face_off, s.face_tv, s.face_box);
 }
 
 __global__ void k_tri_boxes(const int* list, int n, const int* tris, const float* verts, float* box) {
