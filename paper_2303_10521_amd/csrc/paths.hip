@@ -101,27 +101,62 @@ __device__ __forceinline__ bool in_tri(dv3 p, dv3 a, dv3 b, dv3 c) {
     return (w0 >= 0 && w1 >= 0 && w2 >= 0) || (w0 <= 0 && w1 <= 0 && w2 <= 0);
 }
 
-// lowest triangle id of face f containing p, or -1 (face_tris is sorted by
-// id within a face, so the first hit is the lowest; face_tv holds the world
-// vertices of face_tris[q] at 9 q)
+// Lowest triangle id of face f containing p, or -1.
 //
-// A point farther than 1e-6 m (+ 1e-9 of the coordinate) outside the face's
-// bounding box is rejected at once: the points tested lie on the face plane
-// up to double rounding, and a triangle test can only accept points of the
-// triangle up to that rounding, which the margin covers.
-__device__ __forceinline__ int face_contains(const SceneDev& s, int f, dv3 p) {
-    const float* bx = s.face_box + 6 * (long long)f;
-    const double pc[3] = {p.x, p.y, p.z};
+// Faces of at most kFaceLinearMax triangles are scanned in id order
+// (face_tris is sorted by id within a face, so the first hit is the lowest;
+// face_tv holds the world vertices of face_tris[q] at 9 q), after a reject
+// against the face's bounding box: a point farther than 1e-6 m (+ 1e-9 of
+// the coordinate) outside it cannot be accepted, since the points tested lie
+// on the face plane up to double rounding and the triangle test accepts
+// points of the triangle only up to that rounding.
+//
+// Larger faces (a tiled ground) are searched through the triangle LBVH of
+// their kind (static or dynamic): every triangle of the face whose box
+// overlaps p +- 1 mm is tested and the lowest accepted id kept, which is the
+// same triangle the scan in id order would find.
+constexpr int kFaceLinearMax = 32;
+
+__device__ __forceinline__ int face_contains(const PathArgs& a, int f, dv3 p) {
+    const SceneDev& s = a.s;
+    const int q0 = s.face_off[f], q1 = s.face_off[f + 1];
+    if (q1 - q0 <= kFaceLinearMax) {
+        const float* bx = s.face_box + 6 * (long long)f;
+        const double pc[3] = {p.x, p.y, p.z};
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        double m = 1e-6 + 1e-9 * fabs(pc[c]);
-        if (pc[c] < (double)bx[c] - m || pc[c] > (double)bx[3 + c] + m) return -1;
+        for (int c = 0; c < 3; c++) {
+            double m = 1e-6 + 1e-9 * fabs(pc[c]);
+            if (pc[c] < (double)bx[c] - m || pc[c] > (double)bx[3 + c] + m) return -1;
+        }
+        for (int q = q0; q < q1; q++) {
+            const float* v = s.face_tv + 9 * (long long)q;
+            if (in_tri(p, ldf3(v), ldf3(v + 3), ldf3(v + 6))) return s.face_tris[q];
+        }
+        return -1;
     }
-    for (int q = s.face_off[f]; q < s.face_off[f + 1]; q++) {
-        const float* v = s.face_tv + 9 * (long long)q;
-        if (in_tri(p, ldf3(v), ldf3(v + 3), ldf3(v + 6))) return s.face_tris[q];
-    }
-    return -1;
+    const bool dyn = s.face_dyn[f] >= 0;
+    const Bvh t = dyn ? a.dy : a.st;
+    const TriP* prims = dyn ? a.dy_prims : a.st_prims;
+    if (t.n_prims <= 0) return -1;
+    const float qlx = (float)(p.x - 1e-3), qly = (float)(p.y - 1e-3), qlz = (float)(p.z - 1e-3);
+    const float qhx = (float)(p.x + 1e-3), qhy = (float)(p.y + 1e-3), qhz = (float)(p.z + 1e-3);
+    int found = -1;
+    RayPre dummy{};
+    traverse_stackless<false>(t.nodes, dummy,
+        [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
+            tn = 0.0f;
+            if (!(lx <= qhx && hx >= qlx && ly <= qhy && hy >= qly && lz <= qhz && hz >= qlz)) return false;
+            if (!((uint32_t)child & EMRT_LEAF)) return true;
+            TriP tp = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
+            if (__float_as_int(tp.v1.w) != f) return false;
+            int id = __float_as_int(tp.v0.w);
+            if (found >= 0 && id > found) return false;
+            dv3 v0 = d3(tp.v0.x, tp.v0.y, tp.v0.z), v1 = d3(tp.v1.x, tp.v1.y, tp.v1.z), v2 = d3(tp.v2.x, tp.v2.y, tp.v2.z);
+            if (in_tri(p, v0, v1, v2)) found = id;
+            return false;
+        },
+        NoStop());
+    return found;
 }
 
 // float32 shadow ray over the open segment p0 -> p1
@@ -340,7 +375,7 @@ __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, 
         if (!(tt > 0.0 && tt < 1.0)) return false;
         cur = cur + dv * tt;
         g.P[i] = cur;
-        int t = face_contains(S, key.ids[i - 1], cur);
+        int t = face_contains(a, key.ids[i - 1], cur);
         if (t < 0) return false;
         g.tri[i - 1] = t;
     }

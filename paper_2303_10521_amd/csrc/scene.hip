@@ -345,11 +345,14 @@ __global__ void k_face_tv(int T, const int* face_tris, const int* tris, const fl
     }
 }
 
-// bounding box of each face's triangles (after k_face_tv)
+// bounding box of each face's triangles (after k_face_tv); only faces of at
+// most 32 triangles use it (larger faces are searched through the LBVH)
 __global__ void k_face_box(int F, const int* face_off, const float* tv, float* box) {
     GRID_STRIDE(f, (long long)F) {
         float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int q = face_off[f]; q < face_off[f + 1]; q++)
+        int q0 = face_off[f], q1 = face_off[f + 1];
+        if (q1 - q0 > 32) q1 = q0;  // box unused
+        for (int q = q0; q < q1; q++)
             for (int k = 0; k < 9; k++) {
                 float v = tv[9 * (long long)q + k];
                 lo[k % 3] = fminf(lo[k % 3], v);
