@@ -201,6 +201,35 @@ int32_t emrt_read_paths(emrt_ctx* ctx, const emrt_path_view* view);
 int32_t emrt_backward(emrt_ctx* ctx, const double* dL_dH, const double* dL_dP, double* grad_eps, double* grad_tx_pos,
                       double* grad_tx_orient);
 
+/* Coherence statistics over frames (Section III-B): every step updates, per
+ * link and carrier, running sums of g = |H| and of its lagged products, and
+ * per link the spatial-consistency triggers.  They tell the caller when to
+ * rediscover (emrt_step with discover = 1) instead of revalidating the cache.
+ * Readings (the paper prints the formulas, not their estimators):
+ *   corr: Eq (1) as the normalised autocovariance of g at lags of 1..4
+ *     frames, (mean_{t>=k} g_t g_{t-k} - m^2) / (mean g^2 - m^2), m = mean g,
+ *     over the steps since the last reset (NaN while undefined);
+ *   tc: Eq (2), sqrt(1/R^4 - 1) / (2 pi f_D theta^2), f_D = f_c |v_rx - v_tx| / c,
+ *     theta the acute angle between the line of motion and the Tx -> Rx
+ *     direction of the last step's frame (+inf when f_D theta^2 = 0);
+ *   trigger: bit 0 the line of sight changed at the last step, bit 1 the set
+ *     of first-order paths (one reflection or one diffraction) changed.
+ * Device buffers, any may be NULL. */
+#define EMRT_CORR_LAGS 4
+typedef struct emrt_coherence_view {
+    double* tc;        /* [n_freq][n_links] s */
+    double* corr;      /* [n_freq][n_links][EMRT_CORR_LAGS] lags 1..4 frames */
+    uint32_t* trigger; /* [n_links] */
+} emrt_coherence_view;
+/* R in (0, 1) (0.5 is a common choice); min_tc (host, may be NULL) gets the
+ * smallest finite T_c over links and carriers (+inf if none), n_triggered
+ * (host, may be NULL) the number of triggered links.  Synchronises.
+ * Errors: EMRT_E_INVALID (R), EMRT_E_STATE (no step yet). */
+int32_t emrt_read_coherence(emrt_ctx* ctx, double R, const emrt_coherence_view* view, double* min_tc,
+                            int64_t* n_triggered);
+/* Start the statistics afresh (a new trajectory segment). */
+int32_t emrt_coherence_reset(emrt_ctx* ctx);
+
 /* Batched stepping of several independent scenes (extension of the frame
  * step above to many cities at once).  A batch groups contexts that are
  * bound and have their scene set; it takes over their streams (all work goes

@@ -56,6 +56,13 @@ class PathView(ctypes.Structure):
                 ("angles", c_vp), ("count", c_vp)]
 
 
+CORR_LAGS = 4
+
+
+class CoherenceView(ctypes.Structure):
+    _fields_ = [("tc", c_vp), ("corr", c_vp), ("trigger", c_vp)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("rays_per_bounce", c_i64 * 7), ("n_candidates", c_i64), ("n_valid", c_i64), ("n_cache", c_i64),
                 ("node_visits", c_i64), ("tri_tests", c_i64), ("segments", c_i64), ("captures", c_i64),
@@ -79,6 +86,9 @@ SIGNATURES = {
     "emrt_read_channels": (c_i32, [c_vp, ctypes.POINTER(ChannelView)]),
     "emrt_read_paths": (c_i32, [c_vp, ctypes.POINTER(PathView)]),
     "emrt_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "emrt_read_coherence": (c_i32, [c_vp, c_f64, ctypes.POINTER(CoherenceView), ctypes.POINTER(c_f64),
+                                    ctypes.POINTER(c_i64)]),
+    "emrt_coherence_reset": (c_i32, [c_vp]),
     "emrt_batch_create": (c_i32, [ctypes.POINTER(c_vp), c_i32, ctypes.POINTER(c_vp)]),
     "emrt_batch_destroy": (c_i32, [c_vp]),
     "emrt_batch_workspace_size": (c_i32, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),

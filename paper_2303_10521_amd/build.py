@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libemrt.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "scene.hip", "sort.hip", "bvh.hip", "trace.hip", "paths.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "scene.hip", "sort.hip", "bvh.hip", "trace.hip", "paths.hip", "adjoint.hip", "coherence.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -28,6 +28,7 @@ constexpr int C_NCACHE = 18;   // [18, 19] cache sizes (double buffer)
 constexpr int C_STATS = 20;    // [20..23]
 constexpr int C_TRUNC = 24;    // path-list truncation flag
 constexpr int C_NLEGS = 25;    // shadow legs of the step
+constexpr int C_COH = 26;      // [26, 27] coherence read-back (min T_c bits, triggered links)
 constexpr int C_SCRATCH = 32;  // ints for set_scene
 
 struct Carver {
@@ -69,6 +70,7 @@ struct emrt_ctx {
     RxBins bins{};                  // receivers binned for the diffraction candidates
     ValidTemp vtmp{};               // validation survivors
     int* ktri = nullptr;            // [vcap][5] reflection triangles of constructed keys
+    CohState coh{};                 // coherence statistics over frames
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -274,6 +276,17 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->f_ov = cv.take<double>(3 * O);
     c->mat = cv.take<double>(2 * kMaxMaterials);
     c->flags = cv.take<uint32_t>(16);
+    {
+        long long nl = c->n_links, nfl = (long long)c->nf * nl;
+        c->coh.frames = cv.take<unsigned long long>(1);
+        c->coh.ring = cv.take<double>(nfl * EMRT_CORR_LAGS);
+        c->coh.prod = cv.take<double>(nfl * EMRT_CORR_LAGS);
+        c->coh.s1 = cv.take<double>(nfl);
+        c->coh.s2 = cv.take<double>(nfl);
+        c->coh.prev_los = cv.take<uint32_t>(nl);
+        c->coh.prev_hash = cv.take<unsigned long long>(nl);
+        c->coh.trigger = cv.take<uint32_t>(nl);
+    }
     if (c->cfg.adjoint_materials > 0) c->adj_rows = cv.take<double>((5LL + 2LL * c->cfg.adjoint_materials) * c->n_links);
     if (!cv.measure) c->vp.count = c->ctr + C_NVALID;
 }
@@ -293,6 +306,8 @@ static void derive(emrt_ctx* c) {
                                        z.n_faces, z.n_objects, 16LL});
     c->bcap = b;
 }
+
+static void coherence_clear(emrt_ctx* c);
 
 // ---------------------------------------------------------------- ABI ----
 extern "C" {
@@ -376,6 +391,7 @@ int32_t emrt_bind_workspace(emrt_ctx* c, void* ptr, size_t bytes) {
     c->scene_set = c->frame_set = c->stepped = false;
     fill_u64(c->ctr, 0ULL, kNumCounters, c->stream);
     fill_u32(c->flags, 0u, 16, c->stream);
+    coherence_clear(c);
     return EMRT_OK;
 }
 
@@ -394,6 +410,19 @@ int32_t emrt_set_materials(emrt_ctx* c, const double* eps, int32_t M) {
     c->S.M = M;
     return hip_check(c, hipMemcpyAsync(c->mat, c->mat_host.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice,
                                        c->stream), "material upload");
+}
+
+static void coherence_clear(emrt_ctx* c) {
+    long long nl = c->n_links, nfl = (long long)c->nf * nl;
+    hipStream_t st = c->stream;
+    fill_u64(c->coh.frames, 0ULL, 1, st);
+    fill_u64((unsigned long long*)c->coh.ring, 0ULL, nfl * EMRT_CORR_LAGS, st);
+    fill_u64((unsigned long long*)c->coh.prod, 0ULL, nfl * EMRT_CORR_LAGS, st);
+    fill_u64((unsigned long long*)c->coh.s1, 0ULL, nfl, st);
+    fill_u64((unsigned long long*)c->coh.s2, 0ULL, nfl, st);
+    fill_u32(c->coh.prev_los, 0u, nl, st);
+    fill_u64(c->coh.prev_hash, 0ULL, nl, st);
+    fill_u32(c->coh.trigger, 0u, nl, st);
 }
 
 static int32_t sync_read(emrt_ctx* c, void* dst, const void* src, size_t n) {
@@ -677,6 +706,8 @@ static void step_post(emrt_ctx* c, int discover) {
     c->order = which ? c->sv1 : c->sv0;
     link_ranges(skeys, c->vp.count, c->vcap, c->link_start, c->link_end, c->n_links, st);
     link_reduce(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->nf, c->cfg.tx_power_w, c->chan, st);
+    // ---- coherence statistics over frames (Section III-B)
+    coherence_update(c->coh, c->vp, c->order, c->link_start, c->link_end, c->chan, c->n_links, c->nf, st);
     // ---- next cache: valid non-LoS keys in link/key order
     int nxt = 1 - c->cur;
     cache_counts(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->link_cnt, st);
@@ -733,6 +764,34 @@ int32_t emrt_backward(emrt_ctx* c, const double* dL_dH, const double* dL_dP, dou
     a.rows = c->adj_rows;
     adjoint(a, c->sz.n_tx, c->sz.n_rx, grad_tx_pos, grad_tx_orient, grad_eps, c->stream);
     return hip_check(c, hipGetLastError(), "backward");
+}
+
+int32_t emrt_read_coherence(emrt_ctx* c, double R, const emrt_coherence_view* v, double* min_tc,
+                            int64_t* n_triggered) {
+    if (!c || !v) return EMRT_E_INVALID;
+    if (!(R > 0.0 && R < 1.0)) return fail(c, EMRT_E_INVALID, "correlation threshold R must be in (0, 1)");
+    if (!c->stepped) return fail(c, EMRT_E_STATE, "no step yet");
+    unsigned long long* tmp = c->ctr + C_COH;  // [2] min_tc bits, triggered count
+    unsigned long long init[2] = {0x7FF0000000000000ULL, 0ULL};  // +inf, 0
+    HC(hipMemcpyAsync(tmp, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    CohRead r{R, v->tc, v->corr, v->trigger, tmp, tmp + 1};
+    FieldCtx fc{};
+    fc.nf = c->nf;
+    for (int i = 0; i < EMRT_NF; i++) fc.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
+    coherence_read(c->coh, r, c->n_links, c->sz.n_rx, c->nf, c->f_tx, c->f_txv, c->f_rx, c->f_rxv, fc, c->stream);
+    unsigned long long h[2];
+    int32_t rc = sync_read(c, h, tmp, sizeof(h));
+    if (rc) return rc;
+    if (min_tc) memcpy(min_tc, &h[0], sizeof(double));
+    if (n_triggered) *n_triggered = (int64_t)h[1];
+    return emrt_sync(c);
+}
+
+int32_t emrt_coherence_reset(emrt_ctx* c) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace");
+    coherence_clear(c);
+    return hip_check(c, hipGetLastError(), "coherence_reset");
 }
 
 int32_t emrt_sync(emrt_ctx* c) {

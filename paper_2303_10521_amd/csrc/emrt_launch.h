@@ -249,6 +249,32 @@ void path_gather(const ValidPaths& vp, const uint32_t* order, const int* start, 
 void keys_export(const KeyRec* cache, long long n, int32_t* out, hipStream_t st);
 void keys_import(const int32_t* in, long long n, KeyRec* cache, hipStream_t st);
 
+// -------------------------------------------------------- coherence.hip ----
+#define EMRT_CORR_LAGS 4
+struct CohState {
+    unsigned long long* frames;  // steps since the last reset
+    double* ring;                // [nf][n_links][EMRT_CORR_LAGS] last |H| values
+    double* prod;                // [nf][n_links][EMRT_CORR_LAGS] sums of g_t g_{t-k}
+    double* s1;                  // [nf][n_links] sum of g
+    double* s2;                  // [nf][n_links] sum of g^2
+    uint32_t* prev_los;          // [n_links]
+    unsigned long long* prev_hash;  // [n_links] first-order key-set hash
+    uint32_t* trigger;           // [n_links] bits of the last step
+};
+struct CohRead {
+    double R;                    // correlation threshold of Eq (2)
+    double* tc;                  // [nf][n_links] or null
+    double* corr;                // [nf][n_links][EMRT_CORR_LAGS] or null
+    uint32_t* trigger;           // [n_links] or null
+    unsigned long long* min_tc;  // bit pattern of the smallest finite T_c (device), or null
+    unsigned long long* n_triggered;
+};
+void coherence_update(const CohState& c, const ValidPaths& vp, const uint32_t* order, const int* start,
+                      const int* end, const double* chan, long long n_links, int nf, hipStream_t st);
+void coherence_read(const CohState& c, const CohRead& r, long long n_links, int n_rx, int nf, const double* tx_pos,
+                    const double* tx_vel, const double* rx_pos, const double* rx_vel, const FieldCtx& fc,
+                    hipStream_t st);
+
 // ---------------------------------------------------------- adjoint.hip ----
 struct AdjArgs {
     SceneDev s;

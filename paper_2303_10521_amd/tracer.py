@@ -210,6 +210,27 @@ class Tracer:
         out["grad_eps"] = torch.view_as_complex(out["grad_eps"])
         return out
 
+    def coherence(self, R: float = 0.5) -> Dict[str, object]:
+        """Coherence statistics after the last step (emrt_read_coherence):
+        tc [n_freq, n_links] (Eq (2)), corr [n_freq, n_links, 4] (Eq (1) at
+        lags 1..4 frames), trigger [n_links], min_tc, n_triggered."""
+        nf, nl, d = len(self.freqs), self.n_links, self.device
+        out = {
+            "tc": torch.empty((nf, nl), dtype=torch.float64, device=d),
+            "corr": torch.empty((nf, nl, A.CORR_LAGS), dtype=torch.float64, device=d),
+            "trigger": torch.empty((nl,), dtype=torch.int32, device=d),
+        }
+        v = A.CoherenceView(_ptr(out["tc"]), _ptr(out["corr"]), _ptr(out["trigger"]))
+        mt, nt = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.emrt_read_coherence(self.ctx, float(R), ctypes.byref(v), ctypes.byref(mt),
+                                                 ctypes.byref(nt)))
+        out["min_tc"] = mt.value
+        out["n_triggered"] = nt.value
+        return out
+
+    def coherence_reset(self) -> None:
+        self._check(self.lib.emrt_coherence_reset(self.ctx))
+
     def debug_rays(self, tx: int, ray_ids) -> np.ndarray:
         ids = _dev(ray_ids, torch.int32, self.device)
         out = torch.empty((len(ids), int(self.cfg.max_reflections) + 1), dtype=torch.int32, device=self.device)
