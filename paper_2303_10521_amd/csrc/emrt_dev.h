@@ -308,21 +308,22 @@ __device__ __forceinline__ bool tri_hit(const TriP& p, const RayPre& r, float& t
 // Main loop: a short per-ray stack.  At an internal node both child boxes
 // are tested; the near child (the child on the ray's side of the Morton
 // split axis, or the left child for the unordered queries) is entered and the
-// other pushed with its entry distance, which is checked again against the
-// current bound when it is popped.  Each internal node is loaded once.
+// other pushed.  Each internal node is loaded once.
 //
-// The stack holds kStackDepth entries; it only holds the pending far
+// The stack holds kStackDepth node ids; it only holds the pending far
 // children along the current path, and the LBVHs of a city are about 25
 // levels deep.  The compiler keeps the stack in registers, so a deeper stack
-// costs occupancy: 16 entries traced the city's bounces fastest of 16, 24
-// and 32.  If a deeper tree overflows it, the traversal starts over
+// costs occupancy.  On the city's bounces 10, 12 and 14 entries ran alike and
+// about 7% faster than 16 (storing entry distances to re-check at the pop
+// cost another 6%); at 12 a restart is rare (0.0001% more node visits than
+// with no overflow).  If a deeper tree overflows it, the traversal starts over
 // with the stackless walk over parent links below, which needs no stack; all
 // queries are idempotent (closest hit with a fixed tie rule, any hit, leaf
 // visits whose effects are set inserts), so work done before the restart
 // does not change the result.
 // --------------------------------------------------------------------------
 #ifndef EMRT_STACK_DEPTH
-#define EMRT_STACK_DEPTH 16
+#define EMRT_STACK_DEPTH 12
 #endif
 constexpr int kStackDepth = EMRT_STACK_DEPTH;
 
@@ -379,12 +380,10 @@ __device__ __forceinline__ void traverse_stackless(const BNode* nodes, const Ray
 
 // Generic driver.  test(box, child, tn) returns true to descend into `child`
 // (an internal node; tn = the box's entry distance); it handles leaves itself
-// and returns false for them.  keep(tn) re-checks a pushed child when it is
-// popped.  Returns early when stop() is true.
-template <bool ORDERED, class Test, class Keep, class Stop>
-__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Keep keep, Stop stop) {
+// and returns false for them.  Returns early when stop() is true.
+template <bool ORDERED, class Test, class Stop>
+__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Stop stop) {
     int stk_node[kStackDepth];
-    float stk_t[kStackDepth];
     int sp = 0, cur = 0;
     bool overflow = false;
     while (true) {
@@ -403,7 +402,6 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
             if (db) {
                 if (sp == kStackDepth) { overflow = true; break; }
                 stk_node[sp] = cb;
-                stk_t[sp] = lb;
                 sp++;
             }
             cur = ca;
@@ -413,22 +411,13 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
             cur = cb;
             continue;
         }
-        bool found = false;
-        while (sp > 0) {
-            sp--;
-            if (keep(stk_t[sp])) {
-                cur = stk_node[sp];
-                found = true;
-                break;
-            }
-        }
-        if (!found) return;
+        if (sp == 0) return;
+        cur = stk_node[--sp];
     }
     if (overflow) traverse_stackless<ORDERED>(nodes, r, test, stop);
 }
 
 struct NoStop { __device__ bool operator()() const { return false; } };
-struct KeepAll { __device__ bool operator()(float) const { return true; } };
 
 // Closest hit among triangles not on face `skip_face`.  best_t / best_tri /
 // best_face carry the current best (ties broken by the lowest triangle id),
@@ -453,7 +442,6 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
             }
             return false;
         },
-        [&](float tn) -> bool { return tn <= best_t; },
         NoStop());
 }
 
@@ -472,7 +460,6 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
             if (face != xa && face != xb && tri_hit(p, r, t) && t < tmax) found = true;
             return false;
         },
-        KeepAll(),
         [&]() { return found; });
     return found;
 }
@@ -488,7 +475,6 @@ __device__ __forceinline__ void all_hits(const Bvh& bvh, const RayPre& r, float 
             leaf((int)((uint32_t)child & ~EMRT_LEAF));
             return false;
         },
-        KeepAll(),
         NoStop());
 }
 
@@ -507,7 +493,6 @@ __device__ __forceinline__ void box_query(const Bvh& bvh, float qlx, float qly, 
             leaf((int)((uint32_t)child & ~EMRT_LEAF));
             return false;
         },
-        KeepAll(),
         NoStop());
 }
 
