@@ -831,6 +831,23 @@ static void gammas(double complex eps, double c, double complex* te, double comp
     *tm = (eps * c - rt) / (eps * c + rt);
 }
 
+/* Reflection coefficients of material m.  Table I lists surfaces by a
+ * reflection coefficient alone (0.8 wall, 0.9 metal).  Reading: where
+ * refl[m] = g > 0 the coefficient has magnitude g at every angle and for both
+ * polarisations, with the signs a perfect conductor has in the basis above
+ * (the eps -> infinity limit of the Fresnel forms: Gamma_TE = -g,
+ * Gamma_TM = +g); refl[m] = 0 selects the Fresnel coefficients of the
+ * material's permittivity. */
+static void material_gammas(const double* mat_eps, const double* refl, int32_t m, double c, double complex* te,
+                            double complex* tm) {
+    if (refl[m] > 0.0) {
+        *te = -refl[m];
+        *tm = refl[m];
+        return;
+    }
+    gammas(mat_eps[2 * m] + I * mat_eps[2 * m + 1], c, te, tm);
+}
+
 /* Scaled complementary error function erfcx(w) = exp(w^2) erfc(w) on the
  * ray w = exp(j pi/4) v, v >= 0.  Method: power series of erf
  * (Abramowitz & Stegun 7.1.5) for v < 2.5 and the Laplace continued
@@ -911,12 +928,13 @@ static double complex utd_term(double sg, double beta, double n, double kL) {
  * angle n pi: Kouyoumjian-Pathak (1974) with the Luebbers (1984) lossy-face
  * form, D = C [T(+,phi-phi') + T(-,phi-phi') + R_n T(+,phi+phi') +
  * R_0 T(-,phi+phi')], C = -e^{-j pi/4} / (2 n sqrt(2 pi k) sin beta0).
- * R_0 / R_n are the Fresnel coefficients of the 0-face / n-face (TE for
- * soft, TM for hard) at incidence cosines sin(beta0) |sin phi'| and
+ * R_0 / R_n are the reflection coefficients (material_gammas) of the 0-face /
+ * n-face materials m0 / mn (TE for soft, TM for hard) at incidence cosines
+ * sin(beta0) |sin phi'| and
  * sin(beta0) |sin(n pi - phi)| (reading: Luebbers' grazing angles, taken on
  * the actual incidence angle for an oblique edge). */
-static void utd_D(double n, double k, double L, double beta0, double php, double ph,
-                  double complex eps0, double complex epsn, double complex* Ds, double complex* Dh) {
+static void utd_D(double n, double k, double L, double beta0, double php, double ph, const double* mat_eps,
+                  const double* refl, int32_t m0, int32_t mn, double complex* Ds, double complex* Dh) {
     double sb = sin(beta0);
     double complex C = -cexp(-I * M_PI / 4.0) / (2.0 * n * sqrt(2.0 * M_PI * k) * sb);
     double kL = k * L;
@@ -927,8 +945,8 @@ static void utd_D(double n, double k, double L, double beta0, double php, double
     double c0 = sb * fabs(sin(php));
     double cn = sb * fabs(sin(n * M_PI - ph));
     double complex r0te, r0tm, rnte, rntm;
-    gammas(eps0, c0, &r0te, &r0tm);
-    gammas(epsn, cn, &rnte, &rntm);
+    material_gammas(mat_eps, refl, m0, c0, &r0te, &r0tm);
+    material_gammas(mat_eps, refl, mn, cn, &rnte, &rntm);
     *Ds = C * (t1 + t2 + rnte * t3 + r0te * t4);
     *Dh = C * (t1 + t2 + rntm * t3 + r0tm * t4);
 }
@@ -936,7 +954,8 @@ static void utd_D(double n, double k, double L, double beta0, double php, double
 void orc_utd_D(double n, double k, double L, double beta0, double php, double ph, const double* eps0,
                const double* epsn, double* out) {
     double complex ds, dh;
-    utd_D(n, k, L, beta0, php, ph, eps0[0] + I * eps0[1], epsn[0] + I * epsn[1], &ds, &dh);
+    const double mats[4] = {eps0[0], eps0[1], epsn[0], epsn[1]}, refl[2] = {0.0, 0.0};
+    utd_D(n, k, L, beta0, php, ph, mats, refl, 0, 1, &ds, &dh);
     out[0] = creal(ds); out[1] = cimag(ds); out[2] = creal(dh); out[3] = cimag(dh);
 }
 
@@ -972,7 +991,9 @@ static double complex phase(double L, double lam) {
  *   incident k_{i-1}, outgoing k_i and face normal n oriented against k_{i-1}:
  *   s = normalize(k_{i-1} x n) (normal incidence: normalize(n x z), else
  *   normalize(n x x)), p_in = s x k_{i-1}, p_out = s x k_i,
- *   E <- Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out;
+ *   E <- Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out, with the coefficients of
+ *   the face's material (material_gammas: Fresnel from mat_eps [M][2], or the
+ *   constant magnitude mat_refl [M] where that is > 0);
  *   a = lambda/(4 pi L) (e_rx(k_K).E) exp(-j 2 pi frac(L/lambda)), L the
  *   unfolded length (line of sight: Friis amplitude).
  *   Diffraction: a = lambda/(4 pi) (1/s') sqrt(s'/(s (s+s'))) e_rx.(D.e_tx)
@@ -988,7 +1009,8 @@ static double complex phase(double L, double lam) {
  * Outputs: a [n][nf][2], tau [n], fd [n][nf], aod [n][2], aoa [n][2]. */
 int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, const double* plane,
                  const int32_t* face_material, const int32_t* face_dyn, const double* obj_vel,
-                 const double* mat_eps, const float* verts, const int32_t* edges, const double* edge_n,
+                 const double* mat_eps, const double* mat_refl, const float* verts, const int32_t* edges,
+                 const double* edge_n,
                  const double* txp, const double* txv, const double* txo, const double* rxp, const double* rxv,
                  int32_t ant_mode, int32_t nf, const double* freqs,
                  double* a_out, double* tau_out, double* fd_out, double* aod, double* aoa) {
@@ -1043,7 +1065,7 @@ int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, con
                     v3 pin = vcross(sv, ki), pout = vcross(sv, ko);
                     int32_t m = face_material[f];
                     double complex te, tm;
-                    gammas(mat_eps[2 * m] + I * mat_eps[2 * m + 1], c, &te, &tm);
+                    material_gammas(mat_eps, mat_refl, m, c, &te, &tm);
                     double complex es = cdotr(sv, E), ep = cdotr(pin, E);
                     E = cadd(cmk(sv, te * es), cmk(pout, tm * ep));
                 }
@@ -1076,8 +1098,7 @@ int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, con
                 double lam = ORC_C0 / freqs[fi];
                 double k = 2.0 * M_PI / lam;
                 double complex Ds, Dh;
-                utd_D(w.n, k, Lp, beta0, php, ph, mat_eps[2 * m0] + I * mat_eps[2 * m0 + 1],
-                      mat_eps[2 * mn] + I * mat_eps[2 * mn + 1], &Ds, &Dh);
+                utd_D(w.n, k, Lp, beta0, php, ph, mat_eps, mat_refl, m0, mn, &Ds, &Dh);
                 v3 et = antenna(ant_mode, si, th, phi);
                 v3 er = antenna(0, so, 0, 0);
                 double complex fld = -vdot(er, bo) * vdot(bp, et) * Ds - vdot(er, fo) * vdot(fp, et) * Dh;

@@ -160,6 +160,8 @@ class OracleScene:
         self.edges = out[:ne].copy()
         self.edge_n = wn[:ne].copy()
         self.materials = _c(np.stack([sc.materials.real, sc.materials.imag], 1), np.float64)
+        refl = getattr(sc, "material_refl", None)
+        self.material_refl = _c(np.zeros(len(sc.materials)) if refl is None else refl, np.float64)
 
     @property
     def E(self) -> int:
@@ -292,7 +294,7 @@ def evaluate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, pts: np.ndarray, 
         m = np.asarray(materials, np.complex128)
         mats = _c(np.stack([m.real, m.imag], 1), np.float64)
     lib().orc_eval(ctypes.c_int32(n), _p(keys), _p(_c(pts, np.float64)), _p(g.plane), _p(os_.face_material),
-                   _p(os_.face_dyn), _p(ov), _p(mats), _p(g.verts), _p(_c(edges, np.int32)),
+                   _p(os_.face_dyn), _p(ov), _p(mats), _p(os_.material_refl), _p(g.verts), _p(_c(edges, np.int32)),
                    _p(_c(en, np.float64)), _p(_c(frame.tx_pos, np.float64)), _p(_c(frame.tx_vel, np.float64)),
                    _p(_c(frame.tx_orient, np.float64)), _p(_c(frame.rx_pos, np.float64)),
                    _p(_c(frame.rx_vel, np.float64)), ctypes.c_int32(ant_mode), ctypes.c_int32(nf),

@@ -46,6 +46,9 @@ RX_VEH_DZ = 0.2
 EPS_GROUND = 15.0 - 1.5j
 EPS_CONCRETE = 5.3 - 0.2j
 EPS_METAL = 1.0 - 1.0e6j
+# Table I's reflection coefficients (magnitudes) of walls and of metal
+REFL_WALL = 0.8
+REFL_METAL = 0.9
 
 
 @dataclasses.dataclass
@@ -81,6 +84,8 @@ class Scene:
     rx_ped: Dict[str, np.ndarray]  # per receiver (kind 0): axis, coord, s0, vel, z
     building_heights: Optional[np.ndarray] = None
     name: str = ""
+    # per material: 0 = Fresnel from the permittivity, g > 0 = constant reflection coefficient magnitude
+    material_refl: Optional[np.ndarray] = None
 
     @property
     def n_tx(self) -> int:
@@ -468,6 +473,59 @@ def batch_city(i: int) -> WorkloadConfig:
     p = CityParams(n, "uniform", 3, 1, 1, nveh, ntx, sites, None, nrv, nrx - nrv, False, 0, 0, i)
     sc = make_city(p, f"batch{i}")
     return WorkloadConfig(f"batch{i}", sc, max(1024, rays // ntx), 4, False, (28e9,), 20)
+
+
+def table3_street(distance: float, speed: float, rays_per_tx: int = 1_000_000, n_blocks: int = 16,
+                  seed: int = 7) -> WorkloadConfig:
+    """Table III's scenario: one vehicle carrying a receiver drives along a
+    street at ``speed`` m/s past a roadside transmitter that is ``distance``
+    metres away at t = 0; 30 GHz; Table I's constant reflection coefficients
+    (0.8 for the buildings and the ground, 0.9 for the metal vehicle).
+
+    The paper gives only the speeds, the distances and the carrier; the
+    street is this generator's: an east-west street 20 m wide between two
+    rows of ``n_blocks`` box buildings (30 m footprints, 20 m cross streets,
+    heights uniform in 15..35 m), the transmitter at (20, 8, 2) on the north
+    kerb, the vehicle in the south lane (y = -2) heading east with its
+    receiver 2 m above the road.  At distance 10 the vehicle is abeam the
+    transmitter (line of sight perpendicular to the motion); otherwise it
+    starts sqrt(distance^2 - 100) m west of it, approaching.
+    """
+    rng = np.random.default_rng(seed)
+    w = n_blocks * PITCH / 2.0
+    hts = rng.uniform(15.0, 35.0, 2 * n_blocks).astype(np.float32).astype(np.float64)
+    mb = _MeshBuilder()
+    m_wall, m_metal = 0, 1
+    _ground(mb, n_blocks, w, m_wall)
+    tv, tt, tf = box_template(1, 1, 1)
+    for side in range(2):
+        y0 = 10.0 if side == 0 else -10.0 - FOOT
+        for i in range(n_blocks):
+            x0 = -w + i * PITCH + (PITCH - FOOT) / 2
+            v = np.empty_like(tv)
+            v[:, 0] = x0 + tv[:, 0] * FOOT
+            v[:, 1] = y0 + tv[:, 1] * FOOT
+            v[:, 2] = tv[:, 2] * hts[side * n_blocks + i]
+            mb.add(v, tt, tf, mb.new_object(False), [m_wall] * 5)
+    vv, vt, vf = vehicle_template()
+    obj = mb.new_object(True)
+    mb.add(vv, vt, vf, obj, [m_metal] * 6)
+    verts, tris, tri_face, face_object, face_material, object_dynamic = mb.finish()
+    lane = -2.0
+    tx = np.array([[20.0, 8.0, VEH_Z1 + RX_VEH_DZ]])
+    lateral = tx[0, 1] - lane
+    s0 = tx[0, 0] - math.sqrt(max(distance * distance - lateral * lateral, 0.0))
+    veh = {"axis": np.zeros(1), "coord": np.array([lane]), "sign": np.ones(1), "s0": np.array([s0]),
+           "speed": np.array([float(speed)]), "obj": np.array([float(obj)])}
+    sc = Scene(
+        verts=verts, tris=tris, tri_face=tri_face, face_object=face_object, face_material=face_material,
+        object_dynamic=object_dynamic, materials=np.asarray([EPS_CONCRETE, EPS_METAL], np.complex128),
+        extent=w, tx_pos=tx, veh=veh, rx_kind=np.ones(1, np.int32), rx_veh=np.zeros(1, np.int32),
+        rx_off=np.zeros(1), rx_ped={k: np.zeros(1) for k in ("axis", "coord", "s0", "vel", "z")},
+        building_heights=hts, name=f"table3_v{speed:g}_d{distance:g}",
+        material_refl=np.array([REFL_WALL, REFL_METAL]),
+    )
+    return WorkloadConfig(sc.name, sc, rays_per_tx, 4, True, (30e9,), 1)
 
 
 # ---------------------------------------------------------------------------
