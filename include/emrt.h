@@ -125,6 +125,18 @@ typedef struct emrt_scene_desc {
 int32_t emrt_set_scene(emrt_ctx* ctx, const emrt_scene_desc* scene);
 /* Replace the permittivity table without touching geometry (host array). */
 int32_t emrt_set_materials(emrt_ctx* ctx, const double* material_eps, int32_t n_materials);
+/* Constant reflection coefficients (Section IV, Table I, which describes its
+ * wall and metal surfaces by a reflection coefficient alone: 0.8 and 0.9).
+ * refl: host [n_materials], copied before the call returns.  0 keeps the
+ * material's Fresnel coefficients from its permittivity (the state after
+ * emrt_set_scene); g in (0, 1] gives it a coefficient of magnitude g at every
+ * incidence angle for both polarisations, with a perfect conductor's signs
+ * (TE -g, TM +g: the large-permittivity limit of the Fresnel forms), in
+ * reflections and in the face terms of the diffraction coefficient.  Such a
+ * material's permittivity gradient from emrt_backward is zero.
+ * Errors: EMRT_E_INVALID (NULL, n_materials differs from the scene's, a value
+ * outside [0, 1] or NaN), EMRT_E_STATE (no scene). */
+int32_t emrt_set_reflection_coefficients(emrt_ctx* ctx, const double* refl, int32_t n_materials);
 
 /* Per-frame state (Section III-A/C: moving objects and receivers; the base
  * station is static by default, but transmitter velocities are honoured).

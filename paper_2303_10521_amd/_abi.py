@@ -81,6 +81,7 @@ SIGNATURES = {
     "emrt_set_stream": (c_i32, [c_vp, c_vp]),
     "emrt_set_scene": (c_i32, [c_vp, ctypes.POINTER(SceneDesc)]),
     "emrt_set_materials": (c_i32, [c_vp, c_vp, c_i32]),
+    "emrt_set_reflection_coefficients": (c_i32, [c_vp, c_vp, c_i32]),
     "emrt_set_frame": (c_i32, [c_vp, ctypes.POINTER(FrameDesc)]),
     "emrt_step": (c_i32, [c_vp, c_i32]),
     "emrt_read_channels": (c_i32, [c_vp, ctypes.POINTER(ChannelView)]),

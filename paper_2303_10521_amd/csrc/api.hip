@@ -122,6 +122,8 @@ struct emrt_ctx {
            *f_ov = nullptr;
     double* mat = nullptr;
     std::vector<double> mat_host;
+    double* refl = nullptr;          // [kMaxMaterials] constant reflection magnitudes (0: Fresnel)
+    std::vector<double> refl_host;
     uint32_t* flags = nullptr;
     uint32_t* scene_scratch = nullptr;
     int *obj_off = nullptr, *obj_faces = nullptr;
@@ -275,6 +277,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->f_xf = cv.take<double>(12 * O);
     c->f_ov = cv.take<double>(3 * O);
     c->mat = cv.take<double>(2 * kMaxMaterials);
+    c->refl = cv.take<double>(kMaxMaterials);
     c->flags = cv.take<uint32_t>(16);
     {
         long long nl = c->n_links, nfl = (long long)c->nf * nl;
@@ -412,6 +415,19 @@ int32_t emrt_set_materials(emrt_ctx* c, const double* eps, int32_t M) {
                                        c->stream), "material upload");
 }
 
+int32_t emrt_set_reflection_coefficients(emrt_ctx* c, const double* refl, int32_t M) {
+    if (!c || !refl) return fail(c, EMRT_E_INVALID, "null reflection table");
+    if (!c->bound || c->S.M < 1) return fail(c, EMRT_E_STATE, "no scene");
+    if (M != c->S.M) return fail(c, EMRT_E_INVALID, "reflection table size differs from the material count");
+    for (int i = 0; i < M; i++)
+        if (!(refl[i] >= 0.0 && refl[i] <= 1.0)) return fail(c, EMRT_E_INVALID, "reflection coefficient outside [0, 1]");
+    c->refl_host.assign(kMaxMaterials, 0.0);
+    std::copy(refl, refl + M, c->refl_host.begin());
+    return hip_check(c, hipMemcpyAsync(c->refl, c->refl_host.data(), sizeof(double) * kMaxMaterials,
+                                       hipMemcpyHostToDevice, c->stream),
+                     "reflection table upload");
+}
+
 static void coherence_clear(emrt_ctx* c) {
     long long nl = c->n_links, nfl = (long long)c->nf * nl;
     hipStream_t st = c->stream;
@@ -441,6 +457,9 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
         return fail(c, EMRT_E_INVALID, "null scene array");
     int32_t rc = emrt_set_materials(c, d->material_eps, d->n_materials);
     if (rc) return rc;
+    c->refl_host.assign(kMaxMaterials, 0.0);
+    HC(hipMemcpyAsync(c->refl, c->refl_host.data(), sizeof(double) * kMaxMaterials, hipMemcpyHostToDevice,
+                      c->stream));
     hipStream_t st = c->stream;
     SceneDev& S = c->S;
     S.V = (int)z.n_verts; S.T = (int)z.n_tris; S.F = (int)z.n_faces; S.O = (int)z.n_objects;
@@ -561,6 +580,7 @@ static PathArgs path_args(emrt_ctx* c) {
     a.st = c->st.view(); a.dy = c->dy.view();
     a.st_prims = c->st_prims; a.dy_prims = c->dy_prims;
     a.fc.mat_eps = c->mat;
+    a.fc.mat_refl = c->refl;
     a.fc.nf = c->nf;
     for (int i = 0; i < EMRT_NF; i++) a.fc.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
     a.fc.ant_mode = c->cfg.antenna_mode;
@@ -745,6 +765,7 @@ int32_t emrt_backward(emrt_ctx* c, const double* dL_dH, const double* dL_dP, dou
     AdjArgs a{};
     a.s = c->S;
     a.fc.mat_eps = c->mat;
+    a.fc.mat_refl = c->refl;
     a.fc.nf = c->nf;
     for (int i = 0; i < EMRT_NF; i++) a.fc.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
     a.fc.ant_mode = c->cfg.antenna_mode;

@@ -173,6 +173,7 @@ struct LegBuf {
 // inputs of the field evaluation shared by the forward and the adjoint
 struct FieldCtx {
     const double* mat_eps;  // [M][2] relative permittivities
+    const double* mat_refl; // [M] 0: Fresnel from mat_eps; g > 0: constant reflection coefficient magnitude
     double freq[EMRT_NF];   // carriers, Hz
     int nf;
     int ant_mode;           // transmit antenna

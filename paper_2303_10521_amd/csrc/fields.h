@@ -248,6 +248,24 @@ __device__ __forceinline__ void fresnel_x(cd eps, R c, bool deriv, Cx<R>& te, Cx
     tm = cdivx(num, r * er * er);
 }
 
+// Reflection coefficients of material m.  Table I (Section IV) gives its
+// surfaces a reflection coefficient alone; where fc.mat_refl[m] = g > 0 the
+// coefficient is that magnitude at every angle and for both polarisations,
+// with a perfect conductor's signs in this basis (the eps -> infinity limit of
+// fresnel_x: TE -g, TM +g), and has no permittivity derivative.  Otherwise
+// the Fresnel coefficients of the material's permittivity.
+template <class R>
+__device__ __forceinline__ void material_x(const FieldCtx& fc, int m, R c, bool deriv, Cx<R>& te, Cx<R>& tm) {
+    const double g = fc.mat_refl[m];
+    if (g > 0.0) {
+        const double s = deriv ? 0.0 : g;
+        te = cx<R>(rl<R>(-s), rl<R>(0.0));
+        tm = cx<R>(rl<R>(s), rl<R>(0.0));
+        return;
+    }
+    fresnel_x<R>(C(fc.mat_eps[2 * m], fc.mat_eps[2 * m + 1]), c, deriv, te, tm);
+}
+
 // erfcx(w) = exp(w^2) erfc(w) on w = exp(j pi/4) v, v >= 0: power series of
 // erf for v < 2.5 (Abramowitz & Stegun 7.1.5), Laplace continued fraction
 // (A&S 7.1.14) by the modified Lentz method otherwise.
@@ -336,10 +354,12 @@ __device__ __forceinline__ Cx<R> utd_term_x(double sg, R beta, double n, R kL) {
 // sin(beta0)|sin(n pi - phi)|, TE for soft and TM for hard:
 //   D = Cc [T(+, phi - phi') + T(-, phi - phi') + R_n T(+, phi + phi') + R_0 T(-, phi + phi')],
 //   Cc = -e^{-j pi/4} / (2 n sqrt(2 pi k) sin beta0).
-// dmode 1 / 2: the derivative with respect to the 0-face / n-face permittivity.
+// R_0 and R_n are the coefficients of the faces' materials m0 and mn
+// (material_x).  dmode 1 / 2: the derivative with respect to the 0-face /
+// n-face permittivity.
 template <class R>
-__device__ __forceinline__ void utd_D_x(double n, double k, R L, R beta0, R php, R ph, cd eps0, cd epsn, int dmode,
-                                        Cx<R>& Ds, Cx<R>& Dh) {
+__device__ __forceinline__ void utd_D_x(double n, double k, R L, R beta0, R php, R ph, const FieldCtx& fc, int m0,
+                                        int mn, int dmode, Cx<R>& Ds, Cx<R>& Dh) {
     R sb = sin_(beta0);
     const double h = 0.70710678118654752440;
     R cmag = 1.0 / ((2.0 * n * sqrt(2.0 * kPi * k)) * sb);
@@ -348,8 +368,8 @@ __device__ __forceinline__ void utd_D_x(double n, double k, R L, R beta0, R php,
     Cx<R> t3 = utd_term_x<R>(+1, ph + php, n, kL);
     Cx<R> t4 = utd_term_x<R>(-1, ph + php, n, kL);
     Cx<R> r0te, r0tm, rnte, rntm;
-    fresnel_x<R>(eps0, sb * abs_(sin_(php)), dmode == 1, r0te, r0tm);
-    fresnel_x<R>(epsn, sb * abs_(sin_(n * kPi - ph)), dmode == 2, rnte, rntm);
+    material_x<R>(fc, m0, sb * abs_(sin_(php)), dmode == 1, r0te, r0tm);
+    material_x<R>(fc, mn, sb * abs_(sin_(n * kPi - ph)), dmode == 2, rnte, rntm);
     if (dmode == 0) {
         Cx<R> t12 = utd_term_x<R>(+1, ph - php, n, kL) + utd_term_x<R>(-1, ph - php, n, kL);
         Ds = Cc * (t12 + rnte * t3 + r0te * t4);
@@ -558,7 +578,7 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
                 V3<R> pin = cross3(sv, ki), pout = cross3(sv, ko);
                 int m = S.face_material[f];
                 Cx<R> te, tm;
-                fresnel_x<R>(C(fc.mat_eps[2 * m], fc.mat_eps[2 * m + 1]), c, dmode == i, te, tm);
+                material_x<R>(fc, m, c, dmode == i, te, tm);
                 Cx<R> es = cdotx(sv, E) * te, ep = cdotx(pin, E) * tm;
                 E[0] = es * sv.x + ep * pout.x;
                 E[1] = es * sv.y + ep * pout.y;
@@ -588,8 +608,7 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
             double lam = kC0 / fc.freq[fi];
             double k = 2.0 * kPi / lam;
             Cx<R> Ds, Dh;
-            utd_D_x<R>(w.n, k, Lp, beta0, php, ph, C(fc.mat_eps[2 * m0], fc.mat_eps[2 * m0 + 1]),
-                       C(fc.mat_eps[2 * mn], fc.mat_eps[2 * mn + 1]), dmode, Ds, Dh);
+            utd_D_x<R>(w.n, k, Lp, beta0, php, ph, fc, m0, mn, dmode, Ds, Dh);
             Cx<R> fld = Ds * cs - Dh * ch;
             amp[fi] = fld * phase_x<R>(L, lam) * (spread * (lam / (4.0 * kPi)));
         }

@@ -111,6 +111,16 @@ class Tracer:
                            self._mat_host.ctypes.data)
         self.n_dynamic = int(np.asarray(sc.object_dynamic).sum())
         self._check(self.lib.emrt_set_scene(self.ctx, ctypes.byref(desc)))
+        refl = getattr(sc, "material_refl", None)
+        if refl is not None:
+            self.set_reflection_coefficients(refl)
+
+    def set_reflection_coefficients(self, refl: Sequence[float]) -> None:
+        """Per material: 0 = Fresnel from the permittivity, g in (0, 1] = a
+        constant reflection coefficient of magnitude g (Table I)."""
+        self._refl_host = np.ascontiguousarray(np.asarray(refl, np.float64).reshape(-1))
+        self._check(self.lib.emrt_set_reflection_coefficients(self.ctx, self._refl_host.ctypes.data,
+                                                              len(self._refl_host)))
 
     def set_materials(self, eps: Sequence[complex]) -> None:
         e = np.asarray(eps, np.complex128)

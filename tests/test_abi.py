@@ -85,6 +85,9 @@ def test_workspace_and_state_checks(lib):
         assert lib.emrt_last_error(ctx, buf, 256) == A.EMRT_OK
         assert b"small" in buf.value
         assert lib.emrt_read_channels(ctx, None) == A.EMRT_E_INVALID
+        refl = (ctypes.c_double * 2)(0.8, 0.9)
+        assert lib.emrt_set_reflection_coefficients(ctx, None, 2) == A.EMRT_E_INVALID
+        assert lib.emrt_set_reflection_coefficients(ctx, refl, 2) == A.EMRT_E_STATE  # no scene yet
     finally:
         assert lib.emrt_ctx_destroy(ctx) == A.EMRT_OK
 
