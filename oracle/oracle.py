@@ -248,6 +248,20 @@ def spec_keys(os_: OracleScene, tr: TraceResult, tx: int) -> Dict[tuple, bool]:
     return out
 
 
+def spec_keys_from_receiver(os_: OracleScene, tr: TraceResult, rx: int) -> Dict[tuple, bool]:
+    """Keys from a launch at receiver ``rx`` whose spheres sit on the
+    transmitters: a capture at transmitter t after b reflections off faces
+    f_1..f_b (in launch order) is the path from t to rx over f_b..f_1."""
+    out: Dict[tuple, bool] = {}
+    faces = np.where(tr.hit_tri >= 0, os_.tri_face[np.maximum(tr.hit_tri, 0)], -1)
+    for ri, b, t in tr.captures:
+        seq = tuple(int(f) for f in faces[ri, :b][::-1])
+        ids = seq + (-1,) * (5 - len(seq))
+        key = (int(t), rx, SPEC, int(b)) + ids
+        out[key] = out.get(key, False) or bool(tr.robust[ri])
+    return out
+
+
 def illuminated_edges(tr: TraceResult) -> Dict[int, bool]:
     out: Dict[int, bool] = {}
     for ri, e in tr.edge_hits:
@@ -475,6 +489,22 @@ def diffraction_candidates(os_: OracleScene, g: FrameGeom, tx: int, illum: Dict[
     return out
 
 
+def diffraction_candidates_from_receiver(g: FrameGeom, rx: int, illum: Dict[int, bool], rx_pos: np.ndarray,
+                                         n_tx: int, diff_max_leg: float) -> Dict[tuple, bool]:
+    """(tx, edge, rx) candidates for edges lit from receiver ``rx``: every
+    transmitter, when rx lies within diff_max_leg of the edge segment."""
+    out: Dict[tuple, bool] = {}
+    r = np.asarray(rx_pos[rx], np.float64)
+    for e, rob in illum.items():
+        p0 = g.edge_p[e, :3]
+        d = g.edge_p[e, 3:] - p0
+        s = float(np.clip(((r - p0) @ d) / float(d @ d), 0.0, 1.0))
+        if np.linalg.norm(r - (p0 + s * d)) <= diff_max_leg:
+            for tx in range(n_tx):
+                out[(tx, rx, DIFF, 1, e, -1, -1, -1, -1)] = rob
+    return out
+
+
 def sort_keys(keys: np.ndarray) -> np.ndarray:
     """Row-lexicographic order of (tx, rx, type, order, id0..id4)."""
     if len(keys) == 0:
@@ -485,16 +515,33 @@ def sort_keys(keys: np.ndarray) -> np.ndarray:
 def run_frame(os_: OracleScene, frame, N: int, K: int, freqs: Sequence[float], ray_ids: Optional[np.ndarray] = None,
               diffraction: bool = False, discover: bool = True, cache: Optional[np.ndarray] = None,
               k_rx: float = 1.0, diff_max_leg: float = 250.0, want_robust: bool = True, ant_mode: int = 0,
-              p_tx: float = P_TX_W) -> OracleFrame:
+              p_tx: float = P_TX_W, rx_sources: Optional[Sequence[int]] = None) -> OracleFrame:
     """One frame of the method: discovery (optional) on the given launch
     directions of every transmitter, union with the cache, exact validation of
     every candidate plus line of sight for every link, field evaluation and
-    per-link reduction (Sections II-A, III-B, III-C)."""
+    per-link reduction (Sections II-A, III-B, III-C).
+
+    With ``rx_sources`` the discovery launches from those receivers instead
+    (the backward launch of Section II-A): the same lattice of N directions
+    from each listed receiver, spheres k_rx sqrt(4 pi / N) (L + s) around the
+    transmitters, keys reversed into transmitter-to-receiver order, and edges
+    lit by the first segments proposing every transmitter."""
     g = os_.geometry(frame.obj_xform)
     n_tx, n_rx = len(frame.tx_pos), len(frame.rx_pos)
     cand: Dict[tuple, bool] = {}
     traces: List[TraceResult] = []
-    if discover:
+    if discover and rx_sources is not None:
+        ids = np.arange(N, dtype=np.int32) if ray_ids is None else _c(ray_ids, np.int32)
+        for r in sorted({int(x) for x in rx_sources}):
+            tr = trace(os_, g, frame.rx_pos[r], N, ids, K, frame.tx_pos, k_rx, diffraction, want_robust)
+            traces.append(tr)
+            for k, v in spec_keys_from_receiver(os_, tr, r).items():
+                cand[k] = cand.get(k, False) or v
+            if diffraction:
+                for k, v in diffraction_candidates_from_receiver(g, r, illuminated_edges(tr), frame.rx_pos, n_tx,
+                                                                 diff_max_leg).items():
+                    cand[k] = cand.get(k, False) or v
+    elif discover:
         ids = np.arange(N, dtype=np.int32) if ray_ids is None else _c(ray_ids, np.int32)
         for tx in range(n_tx):
             tr = trace(os_, g, frame.tx_pos[tx], N, ids, K, frame.rx_pos, k_rx, diffraction, want_robust)
