@@ -163,6 +163,24 @@ int32_t emrt_set_frame(emrt_ctx* ctx, const emrt_frame_desc* frame);
  * dropped from the cache.  Errors: EMRT_E_STATE (no scene / frame). */
 int32_t emrt_step(emrt_ctx* ctx, int32_t discover);
 
+/* A discovery step whose rays start at receivers instead of transmitters
+ * (Section II-A: rays traced backward from the receivers), for rediscovering
+ * the links of a few receivers, e.g. those whose coherence statistics
+ * triggered.  From each receiver rx_ids[i] (host [n_rx_ids], copied before the
+ * call returns; 1..1024 entries, repeats allowed) rays_per_rx directions of
+ * the same Fibonacci lattice are launched and bounced through the same trees
+ * (K reflections); spheres of radius k_rx sqrt(4 pi / rays_per_rx) (L + s)
+ * around the transmitters capture them after at least one reflection, and a
+ * capture proposes the path from that transmitter to the receiver over the
+ * faces in reverse order.  With diffraction on, an edge that a first segment
+ * passes proposes the (tx, edge, rx) path for every transmitter.  The
+ * proposals join the cache, and validation, fields and per-link sums run as
+ * in emrt_step for every link, so other links are revalidated as on a cached
+ * frame.  rx_ids x rays_per_rx may not exceed n_tx x rays_per_tx (the ray
+ * buffers).  Errors: EMRT_E_STATE (no scene / frame, batched context),
+ * EMRT_E_INVALID (count, rays or a receiver index out of range). */
+int32_t emrt_step_rx(emrt_ctx* ctx, const int32_t* rx_ids, int32_t n_rx_ids, int32_t rays_per_rx);
+
 /* Channel outputs of the last step.  Device buffers, any may be NULL.  Links
  * are ordered tx-major: link = tx * n_rx + rx.  Frequency-dependent arrays
  * are [n_freq][n_links]. */
@@ -279,7 +297,8 @@ int32_t emrt_batch_last_error(emrt_batch* batch, char* buf, size_t len);
 
 /* Triangle hit per bounce of the last discovery step for launch directions
  * ray_ids (device [n]) of transmitter tx: out device [n][K+1], -1 miss,
- * -2 not traced (the ray ended earlier). */
+ * -2 not traced (the ray ended earlier).  EMRT_E_STATE when the last
+ * discovery step was a receiver-side one (emrt_step_rx). */
 int32_t emrt_debug_ray_records(emrt_ctx* ctx, int32_t tx, const int32_t* ray_ids, int32_t n, int32_t* out);
 
 /* Path cache (checkpoint / resume): the valid non-line-of-sight keys after

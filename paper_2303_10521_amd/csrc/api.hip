@@ -18,6 +18,7 @@ using namespace emrt;
 namespace {
 
 constexpr int kMaxMaterials = 256;
+constexpr int kMaxRxSources = 1024;  // receivers of one receiver-side launch
 constexpr int kNumCounters = 64;
 // counter slots (u64)
 constexpr int C_RAYS = 0;      // [0..7] live rays entering bounce b
@@ -131,6 +132,15 @@ struct emrt_ctx {
     uint32_t flag_accum = 0;
     int64_t frame_idx = -1;
     hipError_t pending = hipSuccess;  // first error of an unchecked async call
+    // receiver-side launch: transmitter spheres and the launch's receivers
+    Tree txt;
+    float4* tx_prims = nullptr;
+    float* box_tx = nullptr;
+    int* rev_rx = nullptr;           // [kMaxRxSources]
+    double* rev_pos = nullptr;       // [kMaxRxSources][3]
+    std::vector<int> rev_host;
+    int rev_n = 0, rev_rays = 0;     // nonzero only while a receiver-side step is enqueued
+    bool last_rev = false;           // the hit log holds a receiver-side launch
 };
 
 #define HC(expr)                                                         \
@@ -195,6 +205,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     tree(c->dy, T);
     tree(c->rxt, z.n_rx);
     tree(c->edt, c->E_cap);
+    tree(c->txt, z.n_tx);
     c->st_prims = cv.take<TriP>(T);
     c->dy_prims = cv.take<TriP>(T);
     c->rx_prims = cv.take<float4>(z.n_rx);
@@ -203,6 +214,10 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->box_dy = cv.take<float>(6 * T);
     c->box_rx = cv.take<float>(6LL * z.n_rx);
     c->box_ed = cv.take<float>(6LL * c->E_cap);
+    c->tx_prims = cv.take<float4>(z.n_tx);
+    c->box_tx = cv.take<float>(6LL * z.n_tx);
+    c->rev_rx = cv.take<int>(kMaxRxSources);
+    c->rev_pos = cv.take<double>(3LL * kMaxRxSources);
     char* bt = cv.take<char>((long long)build_temp_bytes(c->bcap));
     if (!cv.measure) carve_build_temp(bt, c->bcap, c->tmp);
     for (int k = 0; k < 2; k++) {
@@ -223,7 +238,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->cand = cv.take<KeyRec>(c->P);
     c->cache[0] = cv.take<KeyRec>(c->P);
     c->cache[1] = cv.take<KeyRec>(c->P);
-    c->illum = cv.take<uint32_t>((long long)z.n_tx * c->e_words);
+    c->illum = cv.take<uint32_t>((long long)std::max<long long>(z.n_tx, kMaxRxSources) * c->e_words);
     {
         const long long nc = (long long)kGridN * kGridN;
         c->bins.grid = cv.take<RxGrid>(1);
@@ -305,8 +320,8 @@ static void derive(emrt_ctx* c) {
     c->vcap = c->n_links + c->P;
     c->E_cap = (int)std::min<long long>(3LL * z.n_faces + 16, (1LL << 24) - 1);
     c->e_words = (c->E_cap + 31) / 32;
-    long long b = std::max<long long>({z.n_tris, (long long)c->E_cap, (long long)z.n_rx, (long long)c->cfg.rays_per_tx,
-                                       z.n_faces, z.n_objects, 16LL});
+    long long b = std::max<long long>({z.n_tris, (long long)c->E_cap, (long long)z.n_rx, (long long)z.n_tx,
+                                       (long long)c->cfg.rays_per_tx, z.n_faces, z.n_objects, 16LL});
     c->bcap = b;
 }
 
@@ -601,23 +616,36 @@ static PathArgs path_args(emrt_ctx* c) {
 // on discovery frames the table and the primary rays), the K + 1 bounces,
 // and step_post (candidates, validation, fields, per-link sums, next cache).
 
+// The discovery launch of the step being enqueued: from every transmitter,
+// or (rev_n > 0) from the rev_n receivers of a receiver-side step.
+static long long launch_total(const emrt_ctx* c) {
+    return c->rev_n > 0 ? (long long)c->rev_n * c->rev_rays : c->n_total;
+}
+static KeySrc key_src(const emrt_ctx* c, const KeyRec* cache) {
+    const bool rev = c->rev_n > 0;
+    return KeySrc{c->hitlog, c->S.tri_face, cache, launch_total(c), rev ? c->rev_rays : c->cfg.rays_per_tx,
+                  rev ? c->rev_rx : nullptr};
+}
+
 // Bounce arguments of level k; tree sizes are those the step's trees have
 // once step_pre has run (so the arguments can be prepared in advance).
 static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     SceneDev& S = c->S;
     bool diff = c->cfg.diffraction && S.E > 0;
+    const bool rev = c->rev_n > 0;
+    const int rays = rev ? c->rev_rays : c->cfg.rays_per_tx;
     BounceArgs b{};
     b.K = c->K;
-    b.n_total = c->n_total;
-    b.rays_per_tx = c->cfg.rays_per_tx;
+    b.n_total = launch_total(c);
+    b.rays_per_tx = rays;
     b.st = Bvh{c->st.nodes, S.T_s};
     b.dy = Bvh{c->dy.nodes, S.T_d};
     b.st_prims = c->st_prims;
     b.dy_prims = c->dy_prims;
     b.plane = S.plane;
-    b.rxt = Bvh{c->rxt.nodes, c->sz.n_rx};
-    b.rx_prims = c->rx_prims;
-    b.alpha_k = (float)(c->cfg.rx_sphere_k * sqrt(4.0 * kPi / (double)c->cfg.rays_per_tx));
+    b.rxt = rev ? Bvh{c->txt.nodes, c->sz.n_tx} : Bvh{c->rxt.nodes, c->sz.n_rx};
+    b.rx_prims = rev ? c->tx_prims : c->rx_prims;
+    b.alpha_k = (float)(c->cfg.rx_sphere_k * sqrt(4.0 * kPi / (double)rays));
     b.diffraction = diff ? 1 : 0;
     b.edt = Bvh{c->edt.nodes, diff ? S.E : 0};
     b.edge_prims = c->edge_prims;
@@ -625,7 +653,7 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.e_words = c->e_words;
     b.table = c->table;
     b.mask = (unsigned long long)c->table_slots - 1ULL;
-    b.src = KeySrc{c->hitlog, S.tri_face, c->cache[parity], c->n_total, c->cfg.rays_per_tx};
+    b.src = key_src(c, c->cache[parity]);
     b.hitlog = c->hitlog;
     b.flags = c->flags;
     b.stats = c->ctr + C_STATS;
@@ -664,6 +692,12 @@ static void step_pre(emrt_ctx* c, int discover) {
     rx_boxes(c->f_rx, c->sz.n_rx, c->box_rx, st);
     bvh_build(c->box_rx, c->sz.n_rx, c->rxt, c->tmp, st);
     rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
+    const bool rev = discover && c->rev_n > 0;
+    if (rev) {  // spheres on the transmitters
+        rx_boxes(c->f_tx, c->sz.n_tx, c->box_tx, st);
+        bvh_build(c->box_tx, c->sz.n_tx, c->txt, c->tmp, st);
+        rx_prims(c->f_tx, c->txt, c->tx_prims, st);
+    }
     bool diff = c->cfg.diffraction && S.E > 0;
     if (diff) {
         edge_boxes(S, c->box_ed, st);
@@ -671,18 +705,24 @@ static void step_pre(emrt_ctx* c, int discover) {
         edge_prims(S, c->edt, c->edge_prims, st);
     }
     if (discover) {
-        KeySrc src{c->hitlog, S.tri_face, c->cache[c->cur], c->n_total, c->cfg.rays_per_tx};
+        KeySrc src = key_src(c, c->cache[c->cur]);
         const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
+        const int n_src = rev ? c->rev_n : c->sz.n_tx;
         fill_u64(c->table, 0ULL, c->table_slots, st);
-        fill_u32((uint32_t*)c->hitlog, 0xFFFFFFFEu, (long long)(K + 1) * c->n_total, st);
-        if (diff) fill_u32(c->illum, 0u, (long long)c->sz.n_tx * c->e_words, st);
+        fill_u32((uint32_t*)c->hitlog, 0xFFFFFFFEu, (long long)(K + 1) * launch_total(c), st);
+        if (diff) fill_u32(c->illum, 0u, (long long)n_src * c->e_words, st);
         cache_insert(c->table, mask, c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, src, c->flags, st);
-        raygen(c->f_tx, c->sz.n_tx, c->cfg.rays_per_tx, c->dir_perm, c->rays[0], c->ctr + C_RAYS, st);
+        if (rev) {
+            gather_rx(c->f_rx, c->rev_rx, c->rev_n, c->rev_pos, st);
+            raygen(c->rev_pos, c->rev_n, c->rev_rays, nullptr, c->rays[0], c->ctr + C_RAYS, st);
+        } else {
+            raygen(c->f_tx, c->sz.n_tx, c->cfg.rays_per_tx, c->dir_perm, c->rays[0], c->ctr + C_RAYS, st);
+        }
     }
 }
 
 static void step_bounces(emrt_ctx* c) {
-    long long g = (c->n_total + 255) / 256;
+    long long g = (launch_total(c) + 255) / 256;
     int grid = (int)std::min<long long>(std::max<long long>(g, 1), 2048);
     for (int k = 0; k <= c->K; k++) {
         BounceArgs b = bounce_args(c, k, c->cur);
@@ -697,11 +737,13 @@ static void step_post(emrt_ctx* c, int discover) {
     hipStream_t st = c->stream;
     SceneDev& S = c->S;
     bool diff = c->cfg.diffraction && S.E > 0;
-    KeySrc src{c->hitlog, S.tri_face, c->cache[c->cur], c->n_total, c->cfg.rays_per_tx};
+    KeySrc src = key_src(c, c->cache[c->cur]);
     PathArgs pa = path_args(c);
     const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
     if (discover) {
-        if (diff) {
+        if (diff && c->rev_n > 0) {
+            diff_candidates_rx(pa, c->illum, c->e_words, c->rev_rx, c->rev_n, c->table, mask, src, st);
+        } else if (diff) {
             rx_grid_build(c->f_rx, c->sz.n_rx, c->bins, st);
             diff_candidates(pa, c->illum, c->e_words, c->bins, c->table, mask, src, st);
         }
@@ -710,6 +752,7 @@ static void step_post(emrt_ctx* c, int discover) {
         pa.cand = c->cand;
         pa.n_cand = c->ctr + C_NCAND;
         c->discovered = true;
+        c->last_rev = c->rev_n > 0;
     } else {
         pa.cand = c->cache[c->cur];
         pa.n_cand = c->ctr + C_NCACHE + c->cur;
@@ -751,6 +794,27 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
     if (discover) step_bounces(c);
     step_post(c, discover);
     return hip_check(c, hipGetLastError(), "step");
+}
+
+int32_t emrt_step_rx(emrt_ctx* c, const int32_t* rx_ids, int32_t n_src, int32_t rays_per_rx) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->scene_set || !c->frame_set) return fail(c, EMRT_E_STATE, "set_scene and set_frame first");
+    if (c->batched) return fail(c, EMRT_E_STATE, "context belongs to a batch: use emrt_batch_step");
+    if (!rx_ids || n_src < 1 || n_src > kMaxRxSources) return fail(c, EMRT_E_INVALID, "1..1024 receivers per launch");
+    if (rays_per_rx < 1 || (long long)n_src * rays_per_rx > c->n_total)
+        return fail(c, EMRT_E_INVALID, "receivers x rays_per_rx exceeds n_tx x rays_per_tx (the ray buffers)");
+    for (int i = 0; i < n_src; i++)
+        if (rx_ids[i] < 0 || rx_ids[i] >= c->sz.n_rx) return fail(c, EMRT_E_INVALID, "receiver index out of range");
+    c->rev_host.assign(rx_ids, rx_ids + n_src);
+    HC(hipMemcpyAsync(c->rev_rx, c->rev_host.data(), sizeof(int) * n_src, hipMemcpyHostToDevice, c->stream));
+    c->rev_n = n_src;
+    c->rev_rays = rays_per_rx;
+    step_pre(c, 1);
+    step_bounces(c);
+    step_post(c, 1);
+    c->rev_n = 0;
+    c->rev_rays = 0;
+    return hip_check(c, hipGetLastError(), "step_rx");
 }
 
 int32_t emrt_backward(emrt_ctx* c, const double* dL_dH, const double* dL_dP, double* grad_eps, double* grad_tx_pos,
@@ -893,6 +957,7 @@ int32_t emrt_read_paths(emrt_ctx* c, const emrt_path_view* v) {
 int32_t emrt_debug_ray_records(emrt_ctx* c, int32_t tx, const int32_t* ray_ids, int32_t n, int32_t* out) {
     if (!c || (n > 0 && (!ray_ids || !out)) || tx < 0 || tx >= c->sz.n_tx) return fail(c, EMRT_E_INVALID, "bad arguments");
     if (!c->discovered) return fail(c, EMRT_E_STATE, "no discovery step yet");
+    if (c->last_rev) return fail(c, EMRT_E_STATE, "the last discovery step launched from receivers");
     debug_rays(c->hitlog, c->n_total, c->K, tx, c->cfg.rays_per_tx, ray_ids, n, out, c->stream);
     return hip_check(c, hipGetLastError(), "debug_ray_records");
 }

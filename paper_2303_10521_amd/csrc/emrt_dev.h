@@ -139,25 +139,43 @@ __device__ __forceinline__ uint64_t ref_diff(int tx, int e, int rx) {
     return (3ULL << 62) | ((uint64_t)tx << 50) | ((uint64_t)e << 26) | (uint64_t)rx;
 }
 
-// Context needed to expand a table reference into its key.
+// Context needed to expand a table reference into its key.  A ray reference
+// holds (order, target, ray id); the launch's source is ray / rays_per_tx.
+// From the transmitters (src_rx null) the target is a receiver and the faces
+// are in launch order; from receivers (src_rx[source] = receiver index) the
+// target is a transmitter and the faces are taken in reverse, so the key is
+// the same transmitter-to-receiver path either way.
 struct KeySrc {
     const int* hitlog;     // [K+1][n_total] triangle id per bounce
     const int* tri_face;   // [T]
     const KeyRec* cache;   // previous cache
     long long n_total;     // rays in the launch
-    int rays_per_tx;
+    int rays_per_tx;       // rays per source
+    const int* src_rx;     // receiver-side launch: receiver of each source; null otherwise
 };
 
+// SIDE: 0 transmitter-side launch, 1 receiver-side, -1 read from s.src_rx
+// (the bounce kernel, which knows its side, keeps the other branch out).
+template <int SIDE = -1>
 __device__ __forceinline__ void expand_ref(uint64_t ref, const KeySrc& s, KeyRec& k) {
     uint32_t tag = (uint32_t)(ref >> 62);
     if (tag == 1) {
         uint32_t ray = (uint32_t)ref;
         int order = (int)((ref >> 59) & 7);
-        k.tx = (int)(ray / (uint32_t)s.rays_per_tx);
-        k.rx = (int)((ref >> 32) & 0x7FFFFFF);
+        int source = (int)(ray / (uint32_t)s.rays_per_tx);
+        int target = (int)((ref >> 32) & 0x7FFFFFF);
         k.to = KT_SPEC | (order << 8);
-        for (int j = 0; j < 5; j++)
-            k.ids[j] = j < order ? s.tri_face[s.hitlog[(long long)j * s.n_total + ray]] : -1;
+        if (SIDE == 1 || (SIDE < 0 && s.src_rx)) {
+            k.tx = target;
+            k.rx = s.src_rx[source];
+            for (int j = 0; j < 5; j++)
+                k.ids[j] = j < order ? s.tri_face[s.hitlog[(long long)(order - 1 - j) * s.n_total + ray]] : -1;
+        } else {
+            k.tx = source;
+            k.rx = target;
+            for (int j = 0; j < 5; j++)
+                k.ids[j] = j < order ? s.tri_face[s.hitlog[(long long)j * s.n_total + ray]] : -1;
+        }
     } else if (tag == 2) {
         k = s.cache[(uint32_t)(ref & 0x3FFFFFFFFFFFFFFFULL)];
     } else {
@@ -193,6 +211,7 @@ __device__ __forceinline__ bool key_less(const KeyRec& a, const KeyRec& b) {
 // inserted, 0 when an equal key is present, -1 when the table is full.
 // Lock-free: a slot is claimed by one 64-bit CAS holding the whole
 // reference, whose key data were written before this kernel started.
+template <int SIDE = -1>
 __device__ __forceinline__ int table_insert(unsigned long long* table, uint64_t mask, uint64_t ref, const KeyRec& mine,
                                             uint64_t h, const KeySrc& src) {
     uint64_t slot = h & mask;
@@ -205,7 +224,7 @@ __device__ __forceinline__ int table_insert(unsigned long long* table, uint64_t 
         }
         if (cur == ref) return 0;
         KeyRec other;
-        expand_ref(cur, src, other);
+        expand_ref<SIDE>(cur, src, other);
         if (key_eq(other, mine)) return 0;
         slot = (slot + 1) & mask;
     }

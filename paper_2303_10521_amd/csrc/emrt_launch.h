@@ -130,7 +130,8 @@ struct BounceArgs {
     unsigned long long* stats;  // [4] node visits, triangle tests, segments, captures (STATS only)
 };
 void ray_order(int N, uint32_t* perm, const BuildTemp& tmp, hipStream_t st);
-void raygen(const double* tx_pos, int n_tx, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
+// sources src_pos [n_src][3], N directions each; perm: launch order of the directions (null: index order)
+void raygen(const double* src_pos, int n_src, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
             hipStream_t st);
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
 // one launch over several scenes' live rays (args device [n_scenes]; chunk_off [n_scenes + 1], work: scratch)
@@ -216,6 +217,10 @@ struct RxBins {
 void rx_grid_build(const double* rx_pos, int n_rx, const RxBins& b, hipStream_t st);
 void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
                      unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
+// receiver-side launch: illum rows are the sources src_rx[0..n_src); every transmitter is tried
+void diff_candidates_rx(const PathArgs& a, const uint32_t* illum, int e_words, const int* src_rx, int n_src,
+                        unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
+void gather_rx(const double* rx_pos, const int* sel, int n, double* out, hipStream_t st);
 // scratch of the table compaction: [n_slots] flags and offsets + scan temp
 struct CompactTemp {
     uint32_t* flags;

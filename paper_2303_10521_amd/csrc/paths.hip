@@ -301,6 +301,57 @@ void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, cons
                        mask, src);
 }
 
+// Edges lit from receivers (a receiver-side launch): one wave per lit
+// (source, edge) pair, lanes over the transmitters; a transmitter whose Keller
+// point on the edge passes the construction test becomes the candidate
+// (tx, edge, receiver).
+__global__ void __launch_bounds__(256) k_diff_cand_rx(PathArgs a, const uint32_t* illum, int e_words,
+                                                      const int* src_rx, int n_src, unsigned long long* table,
+                                                      unsigned long long mask, KeySrc src) {
+    const long long n = (long long)n_src * a.s.E;
+    const int lane = lane_id();
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long n_waves = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long k = wave; k < n; k += n_waves) {
+        int q = (int)(k / a.s.E), e = (int)(k - (long long)q * a.s.E);
+        if (!(illum[(long long)q * e_words + (e >> 5)] & (1u << (e & 31)))) continue;
+        const int rx = src_rx[q];
+        const Wedge w = wedge_of(a.s, e);
+        const dv3 r = ldd3(a.f.rx_pos + 3 * rx);
+        for (int tx = lane; tx < a.f.n_tx; tx += 64) {
+            dv3 Q;
+            if (!keller(w, ldd3(a.f.tx_pos + 3 * tx), r, a.diff_max_leg, Q)) continue;
+            KeyRec key;
+            key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
+            key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
+            uint64_t h = key_hash(key.tx, key.rx, key.to, key.ids);
+            if (table_insert(table, mask, ref_diff(tx, e, rx), key, h, src) < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
+        }
+    }
+}
+
+void diff_candidates_rx(const PathArgs& a, const uint32_t* illum, int e_words, const int* src_rx, int n_src,
+                        unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st) {
+    long long n = (long long)n_src * a.s.E;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_diff_cand_rx, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, a, illum, e_words, src_rx,
+                       n_src, table, mask, src);
+}
+
+// Receiver positions of a receiver-side launch, gathered as its sources.
+__global__ void k_gather_rx(const double* rx_pos, const int* sel, int n, double* out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int r = sel[i];
+    out[3 * i] = rx_pos[3 * r];
+    out[3 * i + 1] = rx_pos[3 * r + 1];
+    out[3 * i + 2] = rx_pos[3 * r + 2];
+}
+
+void gather_rx(const double* rx_pos, const int* sel, int n, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_rx, dim3((n + 255) / 256), dim3(256), 0, st, rx_pos, sel, n, out);
+}
+
 // Geometry of one path key.  Points: P[0] = Tx, P[1..order] reflection
 // points (or P[1] = Keller point), R = Rx; leg i runs from P[i] to P[i+1]
 // (R for the last leg).  Loops run to the compile-time bound so every array

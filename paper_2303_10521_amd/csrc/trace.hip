@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_raygen(const double* tx_pos, int n_tx, 
     if (k >= total) return;
     int tx = (int)(k / N);
     int t = (int)(k - (long long)tx * N);
-    uint32_t i = perm[t];
+    uint32_t i = perm ? perm[t] : (uint32_t)t;
     float x, y, z;
     fib_dir(i, N, x, y, z);
     out.ox[k] = (float)tx_pos[3 * tx];
@@ -107,7 +107,10 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
 }
 
 // One 64-ray chunk of a bounce: rays [base, base + 64) of the live buffer.
-template <bool STATS>
+// REV: a launch from receivers (a.src.src_rx) whose spheres sit on the
+// transmitters; the captured key is reversed into transmitter-to-receiver
+// order (expand_ref rebuilds the same key from the reference).
+template <bool STATS, bool REV>
 __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long long n_in, unsigned long long base,
                                              int lane, unsigned& s_nodes, unsigned& s_tris, unsigned& s_seg,
                                              unsigned& s_cap) {
@@ -151,17 +154,25 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             float rho2 = wx * wx + wy * wy + wz * wz - s * s;
             float rs = a.alpha_k * (L + s);
             if (!(rho2 < rs * rs)) return;
-            int rx = __float_as_int(p.w);
+            int target = __float_as_int(p.w);
             if (!have) {
-                mine.tx = (int)(id / (uint32_t)a.rays_per_tx);
+                const int source = (int)(id / (uint32_t)a.rays_per_tx);
                 mine.to = KT_SPEC | (b << 8);
-                for (int j = 0; j < 5; j++)
-                    mine.ids[j] = j < b ? a.src.tri_face[a.hitlog[(long long)j * a.n_total + id]] : -1;
+                if (REV) {
+                    mine.rx = a.src.src_rx[source];
+                    for (int j = 0; j < 5; j++)
+                        mine.ids[j] = j < b ? a.src.tri_face[a.hitlog[(long long)(b - 1 - j) * a.n_total + id]] : -1;
+                } else {
+                    mine.tx = source;
+                    for (int j = 0; j < 5; j++)
+                        mine.ids[j] = j < b ? a.src.tri_face[a.hitlog[(long long)j * a.n_total + id]] : -1;
+                }
                 have = true;
             }
-            mine.rx = rx;
+            if (REV) mine.tx = target;
+            else mine.rx = target;
             h = key_hash(mine.tx, mine.rx, mine.to, mine.ids);
-            int res = table_insert(a.table, a.mask, ref_ray(b, rx, id), mine, h, a.src);
+            int res = table_insert<REV ? 1 : 0>(a.table, a.mask, ref_ray(b, target, id), mine, h, a.src);
             if (res < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
             if (STATS) s_cap++;
         });
@@ -171,7 +182,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
     if (act && b == 0 && a.diffraction && a.edt.n_prims > 0) {
         float tcap = fminf(t_end, root_far(a.edt, ox, oy, oz));
         float grow = a.alpha_k * tcap;
-        int tx = (int)(id / (uint32_t)a.rays_per_tx);
+        const int source = (int)(id / (uint32_t)a.rays_per_tx);  // row of the illumination bitmap
         all_hits(a.edt, r, tcap, grow, [&](int slot) {
             float4 P0 = a.edge_prims[2 * slot], P1 = a.edge_prims[2 * slot + 1];
             float ex = P1.x - P0.x, ey = P1.y - P0.y, ez = P1.z - P0.z;
@@ -192,7 +203,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             float re = a.alpha_k * s;
             if (!(qx * qx + qy * qy + qz * qz < re * re)) return;
             int e = __float_as_int(P0.w);
-            uint32_t* w = a.illum + (long long)tx * a.e_words + (e >> 5);
+            uint32_t* w = a.illum + (long long)source * a.e_words + (e >> 5);
             uint32_t bit = 1u << (e & 31);
             if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(w, bit);
         });
@@ -236,7 +247,7 @@ __device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane,
 }
 
 // Persistent: waves pull 64-ray chunks from a device counter.
-template <bool STATS>
+template <bool STATS, bool REV>
 __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
@@ -247,14 +258,20 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
         chunk = __shfl(chunk, 0);
         unsigned long long base = (unsigned long long)chunk * 64ULL;
         if (base >= n_in) break;
-        bounce_chunk<STATS>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap);
+        bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap);
     }
     flush_stats<STATS>(a.stats, lane, s_nodes, s_tris, s_seg, s_cap);
 }
 
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {
-    if (stats) hipLaunchKernelGGL(k_bounce<true>, dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_bounce<false>, dim3(grid), dim3(256), 0, st, a);
+    const bool rev = a.src.src_rx != nullptr;
+    if (rev) {
+        if (stats) hipLaunchKernelGGL((k_bounce<true, true>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_bounce<false, true>), dim3(grid), dim3(256), 0, st, a);
+    } else {
+        if (stats) hipLaunchKernelGGL((k_bounce<true, false>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_bounce<false, false>), dim3(grid), dim3(256), 0, st, a);
+    }
 }
 
 // Several scenes in one launch (batched stepping): chunk_off[c] is the first
@@ -307,8 +324,8 @@ __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restri
         const int c = __builtin_amdgcn_readfirstlane(lo);
         const BounceArgs& a = args[c];
         const unsigned long long n_in = *a.n_in;
-        bounce_chunk<false>(a, n_in, (unsigned long long)(g - chunk_off[c]) * 64ULL, lane, s_nodes, s_tris, s_seg,
-                            s_cap);
+        bounce_chunk<false, false>(a, n_in, (unsigned long long)(g - chunk_off[c]) * 64ULL, lane, s_nodes, s_tris,
+                                   s_seg, s_cap);
     }
 }
 

@@ -146,6 +146,12 @@ class Tracer:
     def step(self, discover: bool = True) -> int:
         return self._check(self.lib.emrt_step(self.ctx, 1 if discover else 0))
 
+    def step_rx(self, rx_ids: Sequence[int], rays_per_rx: int) -> int:
+        """Discovery step launched from the given receivers (emrt_step_rx)."""
+        self._rev_host = np.ascontiguousarray(np.asarray(rx_ids, np.int32).reshape(-1))
+        return self._check(self.lib.emrt_step_rx(self.ctx, self._rev_host.ctypes.data, len(self._rev_host),
+                                                 int(rays_per_rx)))
+
     def sync(self) -> int:
         return self._check(self.lib.emrt_sync(self.ctx))
 

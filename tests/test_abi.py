@@ -88,6 +88,8 @@ def test_workspace_and_state_checks(lib):
         refl = (ctypes.c_double * 2)(0.8, 0.9)
         assert lib.emrt_set_reflection_coefficients(ctx, None, 2) == A.EMRT_E_INVALID
         assert lib.emrt_set_reflection_coefficients(ctx, refl, 2) == A.EMRT_E_STATE  # no scene yet
+        ids = (ctypes.c_int32 * 2)(0, 1)
+        assert lib.emrt_step_rx(ctx, ids, 2, 100) == A.EMRT_E_STATE  # no scene yet
     finally:
         assert lib.emrt_ctx_destroy(ctx) == A.EMRT_OK
 
