@@ -35,14 +35,15 @@ FLOP_PER_TRI = 36  # watertight test: 9 sub, 6 shear, 9 edge-function, 2 det, 3 
 
 def committed_traffic():
     """HBM bytes per bounce launch from the committed counter summary, or
-    None when the bounce kernel's sources changed since it was measured."""
+    None when the bounce kernel's sources (or the builder of the trees it
+    reads) changed since it was measured."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "k_bounce_city_traffic.txt")
     try:
         kv = dict(ln.split(": ", 1) for ln in open(path).read().splitlines() if ": " in ln and ln[0].isalpha())
         m = hashlib.sha256()
-        for f in ("trace.hip", "emrt_dev.h"):
+        for f in ("trace.hip", "emrt_dev.h", "bvh.hip"):
             m.update(open(os.path.join(ROOT, "paper_2303_10521_amd", "csrc", f), "rb").read())
         if m.hexdigest() != kv.get("kernel_source_sha256", "").strip():
             return None
@@ -265,6 +266,7 @@ def main() -> int:
             "segments_per_step": int(segs / args.steps),
             "node_visits_per_segment": round(nodes / max(segs, 1), 2),
             "tri_tests_per_segment": round(tris / max(segs, 1), 2),
+            "static_tree_area": round(float(st["static_tree_area"]), 2),
         }
         out["validate_ms_per_step"] = round(validate_ms / args.steps, 3)
         out["bounce_ms_per_step"] = round(bounce_ms / args.steps, 3)

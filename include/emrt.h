@@ -324,6 +324,8 @@ typedef struct emrt_stats {
     int32_t bounce_launches;
     double validate_ms;         /* summed time of the validation stage (construct, shadow, fields) */
     int32_t validate_launches;
+    double static_tree_area;    /* static tree quality: summed surface area of every node below the
+                                   root over the root's (the expected box tests of a random ray) */
 } emrt_stats;
 int32_t emrt_read_stats(emrt_ctx* ctx, emrt_stats* out);
 /* Optional instrumentation: stats = count traversal work (slower), timing =

@@ -141,6 +141,7 @@ struct emrt_ctx {
     std::vector<int> rev_host;
     int rev_n = 0, rev_rays = 0;     // nonzero only while a receiver-side step is enqueued
     bool last_rev = false;           // the hit log holds a receiver-side launch
+    double st_area = 0.0;            // static tree quality (emrt_stats.static_tree_area)
 };
 
 #define HC(expr)                                                         \
@@ -506,8 +507,23 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     // static tree (world == local for static vertices)
     scene_planes(S, st);
     tri_boxes(S, S.tris_static, S.T_s, c->box_st, st);
-    bvh_build(c->box_st, S.T_s, c->st, c->tmp, st);
+    if (bvh_build_sah(c->box_st, S.T_s, c->st, c->tmp, st) < 0) return fail(c, EMRT_E_HIP, "static tree build");
     tri_prims(S, S.tris_static, c->st, c->st_prims, st);
+    c->st_area = 0.0;
+    if (S.T_s > 1) {  // tree quality: child box areas over the root box area
+        double* acc = (double*)c->tmp.bounds;
+        fill_u64((unsigned long long*)acc, 0ULL, 1, st);
+        bvh_sah(c->st, acc, st);
+        double sum = 0.0;
+        BNode root;
+        if ((rc = sync_read(c, &sum, acc, sizeof(sum)))) return rc;
+        if ((rc = sync_read(c, &root, c->st.nodes, sizeof(root)))) return rc;
+        double lo[3] = {std::min(root.a.x, root.b.z), std::min(root.a.y, root.b.w), std::min(root.a.z, root.c.x)};
+        double hi[3] = {std::max(root.a.w, root.c.y), std::max(root.b.x, root.c.z), std::max(root.b.y, root.c.w)};
+        double ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+        double ra = 2.0 * (ex * ey + ey * ez + ez * ex);
+        c->st_area = ra > 0.0 ? sum / ra : 0.0;
+    }
     c->dy.n = 0;
     ray_order(c->cfg.rays_per_tx, c->dir_perm, c->tmp, st);
     // empty cache
@@ -1019,6 +1035,7 @@ int32_t emrt_read_stats(emrt_ctx* c, emrt_stats* o) {
     o->bounce_launches = c->t_bounce_n;
     o->validate_ms = c->t_validate_ms;
     o->validate_launches = c->t_validate_n;
+    o->static_tree_area = c->st_area;
     return EMRT_OK;
 }
 

@@ -36,6 +36,8 @@ __device__ __forceinline__ unsigned long long split3(uint32_t a) {
     return x;
 }
 
+__global__ void k_fill_zero1(uint32_t* p) { *p = 0u; }
+
 __global__ void k_init_bounds(uint32_t* b) {
     int t = threadIdx.x;
     if (t < 3) b[t] = 0xFFFFFFFFu;
@@ -188,6 +190,213 @@ __global__ void __launch_bounds__(256) k_sah(const BNode* nodes, int n_int, doub
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicAdd(out, sh[0]);
+}
+
+// ---- top-down binned SAH build (the static scene, once per scene) ----
+// The same node format as the LBVH, so every query runs on either tree.  A
+// level of the build is one launch with one block per node: centroid bounds,
+// kSahBins bins per axis (counts and primitive boxes), the split of least
+// A_L N_L + A_R N_R, a stable partition of the node's primitive indices, and
+// the two children (a one-primitive child is a leaf).  Boxes come from a
+// refit at the end.  Where every centroid falls in one bin the range is cut
+// in half.
+constexpr int kSahBins = 32;
+struct SahItem { int node, start, count, pad; };
+
+__device__ __forceinline__ int sah_bin(float c, float lo, float scale) {
+    int b = (int)((c - lo) * scale);
+    return b < 0 ? 0 : (b >= kSahBins ? kSahBins - 1 : b);
+}
+
+__global__ void __launch_bounds__(256) k_sah_level(const float* box, const SahItem* items, const uint32_t* idx_in,
+                                                   uint32_t* idx_out, BNode* nodes, int* leaf_parent, uint32_t* perm,
+                                                   SahItem* next, uint32_t* ctr) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t s_cb[6];                      // centroid bounds (ordered floats)
+    __shared__ uint32_t s_cnt[3][kSahBins];
+    __shared__ uint32_t s_bb[3][kSahBins][6];         // bin boxes (ordered floats)
+    __shared__ float s_cost[3];
+    __shared__ int s_split[3];
+    __shared__ uint32_t s_scan[256];
+    const SahItem it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    auto cen = [&](uint32_t p, int ax) { return 0.5f * (box[6 * (long long)p + ax] + box[6 * (long long)p + 3 + ax]); };
+    if (tid < 3) { s_cb[tid] = 0xFFFFFFFFu; s_cb[3 + tid] = 0u; }
+    for (int k = tid; k < 3 * kSahBins; k += 256) {
+        (&s_cnt[0][0])[k] = 0u;
+        for (int j = 0; j < 3; j++) { (&s_bb[0][0][0])[6 * k + j] = 0xFFFFFFFFu; (&s_bb[0][0][0])[6 * k + 3 + j] = 0u; }
+    }
+    __syncthreads();
+    for (int i = tid; i < it.count; i += 256) {
+        uint32_t p = idx_in[it.start + i];
+        for (int ax = 0; ax < 3; ax++) {
+            uint32_t o = f2ord(cen(p, ax));
+            atomicMin(&s_cb[ax], o);
+            atomicMax(&s_cb[3 + ax], o);
+        }
+    }
+    __syncthreads();
+    float clo[3], scale[3];
+    for (int ax = 0; ax < 3; ax++) {
+        clo[ax] = ord2f(s_cb[ax]);
+        float ext = ord2f(s_cb[3 + ax]) - clo[ax];
+        scale[ax] = ext > 0.0f ? (float)kSahBins / ext : 0.0f;
+    }
+    for (int i = tid; i < it.count; i += 256) {
+        uint32_t p = idx_in[it.start + i];
+        const float* b = box + 6 * (long long)p;
+        for (int ax = 0; ax < 3; ax++) {
+            int k = sah_bin(cen(p, ax), clo[ax], scale[ax]);
+            atomicAdd(&s_cnt[ax][k], 1u);
+            for (int j = 0; j < 3; j++) {
+                atomicMin(&s_bb[ax][k][j], f2ord(b[j]));
+                atomicMax(&s_bb[ax][k][3 + j], f2ord(b[3 + j]));
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < 3) {  // sweep of axis tid: cost of cutting after bin s
+        const int ax = tid;
+        float rl[3] = {INFINITY, INFINITY, INFINITY}, rh[3] = {-INFINITY, -INFINITY, -INFINITY};
+        float right_area[kSahBins];
+        uint32_t right_n[kSahBins];
+        uint32_t n = 0;
+        for (int k = kSahBins - 1; k >= 1; k--) {
+            if (s_cnt[ax][k]) {
+                for (int j = 0; j < 3; j++) {
+                    rl[j] = fminf(rl[j], ord2f(s_bb[ax][k][j]));
+                    rh[j] = fmaxf(rh[j], ord2f(s_bb[ax][k][3 + j]));
+                }
+            }
+            n += s_cnt[ax][k];
+            float ex = rh[0] - rl[0], ey = rh[1] - rl[1], ez = rh[2] - rl[2];
+            right_area[k] = n ? 2.0f * (ex * ey + ey * ez + ez * ex) : 0.0f;
+            right_n[k] = n;
+        }
+        float ll[3] = {INFINITY, INFINITY, INFINITY}, lh[3] = {-INFINITY, -INFINITY, -INFINITY};
+        uint32_t nl = 0;
+        float best = INFINITY;
+        int bs = -1;
+        for (int k = 0; k < kSahBins - 1; k++) {
+            if (s_cnt[ax][k]) {
+                for (int j = 0; j < 3; j++) {
+                    ll[j] = fminf(ll[j], ord2f(s_bb[ax][k][j]));
+                    lh[j] = fmaxf(lh[j], ord2f(s_bb[ax][k][3 + j]));
+                }
+            }
+            nl += s_cnt[ax][k];
+            if (nl == 0 || right_n[k + 1] == 0) continue;
+            float ex = lh[0] - ll[0], ey = lh[1] - ll[1], ez = lh[2] - ll[2];
+            float cost = 2.0f * (ex * ey + ey * ez + ez * ex) * (float)nl + right_area[k + 1] * (float)right_n[k + 1];
+            if (cost < best) { best = cost; bs = k; }
+        }
+        s_cost[ax] = best;
+        s_split[ax] = bs;
+    }
+    __syncthreads();
+    int axis = 0;
+    for (int ax = 1; ax < 3; ax++)
+        if (s_cost[ax] < s_cost[axis]) axis = ax;
+    int split = s_split[axis];  // -1: cut the range in half
+    const int half = it.count / 2;
+    // count the left side with the same test the partition uses
+    if (tid == 0) s_cb[0] = 0u;
+    __syncthreads();
+    if (split >= 0) {
+        uint32_t mine = 0;
+        for (int i = tid; i < it.count; i += 256)
+            mine += sah_bin(cen(idx_in[it.start + i], axis), clo[axis], scale[axis]) <= split ? 1u : 0u;
+        atomicAdd(&s_cb[0], mine);
+    }
+    __syncthreads();
+    uint32_t n_left = split >= 0 ? s_cb[0] : (uint32_t)half;
+    if (n_left == 0u || n_left >= (uint32_t)it.count) {
+        split = -1;
+        n_left = (uint32_t)half;
+    }
+    // stable partition, 256 indices at a time
+    uint32_t base_l = 0, base_r = 0;
+    for (int c0 = 0; c0 < it.count; c0 += 256) {
+        const int i = c0 + tid;
+        const bool act = i < it.count;
+        uint32_t p = act ? idx_in[it.start + i] : 0u;
+        bool left = false;
+        if (act) left = split >= 0 ? sah_bin(cen(p, axis), clo[axis], scale[axis]) <= split : i < half;
+        s_scan[tid] = left ? 1u : 0u;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
+            uint32_t y = tid >= o ? s_scan[tid - o] : 0u;
+            __syncthreads();
+            s_scan[tid] += y;
+            __syncthreads();
+        }
+        const uint32_t incl = s_scan[tid];
+        const uint32_t tot_l = s_scan[255];
+        const int n_act = min(256, it.count - c0);
+        if (act) {
+            uint32_t dst = left ? base_l + incl - 1u : n_left + base_r + ((uint32_t)tid + 1u - incl) - 1u;
+            idx_out[it.start + dst] = p;
+        }
+        base_l += tot_l;
+        base_r += (uint32_t)n_act - tot_l;
+        __syncthreads();
+    }
+    if (tid < 2) {
+        const int side = tid;
+        const int cs = side ? it.start + (int)n_left : it.start;
+        const int cn = side ? it.count - (int)n_left : (int)n_left;
+        int child;
+        if (cn == 1) {
+            child = (int)(EMRT_LEAF | (uint32_t)cs);
+            perm[cs] = idx_out[cs];
+            leaf_parent[cs] = (int)((uint32_t)it.node | (side ? EMRT_SIDE : 0u));
+        } else {
+            child = (int)atomicAdd(&ctr[1], 1u);
+            ((int*)&nodes[child].m)[2] = (int)((uint32_t)it.node | (side ? EMRT_SIDE : 0u));
+            uint32_t q = atomicAdd(&ctr[0], 1u);
+            next[q] = SahItem{child, cs, cn, 0};
+        }
+        int* m = (int*)&nodes[it.node].m;
+        m[side] = child;
+        if (side == 0) m[3] = axis;
+    }
+}
+
+__global__ void k_sah_init(uint32_t* idx, int n, SahItem* items, BNode* nodes, uint32_t* ctr) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) idx[i] = (uint32_t)i;
+    if (i == 0) {
+        items[0] = SahItem{0, 0, n, 0};
+        ((int*)&nodes[0].m)[2] = -1;
+        ctr[0] = 0u;  // items of the next level
+        ctr[1] = 1u;  // nodes allocated (the root)
+    }
+}
+
+int bvh_build_sah(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st) {
+    if (n < 2) {
+        bvh_build(box6, n, tree, tmp, st);
+        return 0;
+    }
+    tree.n = n;
+    SahItem* items[2] = {(SahItem*)tmp.k0, (SahItem*)tmp.k1};  // each holds cap / 2 items >= n / 2
+    uint32_t* idx[2] = {tmp.v0, tmp.v1};
+    uint32_t* ctr = tmp.bounds;
+    hipLaunchKernelGGL(k_sah_init, dim3((n + 255) / 256), dim3(256), 0, st, idx[0], n, items[0], tree.nodes, ctr);
+    int n_items = 1, cur = 0, levels = 0;
+    while (n_items > 0) {
+        hipLaunchKernelGGL(k_fill_zero1, dim3(1), dim3(1), 0, st, ctr);
+        hipLaunchKernelGGL(k_sah_level, dim3(n_items), dim3(256), 0, st, box6, items[cur], idx[cur], idx[1 - cur],
+                           tree.nodes, tree.leaf_parent, tree.perm, items[1 - cur], ctr);
+        uint32_t h = 0;
+        if (hipMemcpyAsync(&h, ctr, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
+        if (hipStreamSynchronize(st) != hipSuccess) return -1;
+        n_items = (int)h;
+        cur = 1 - cur;
+        if (++levels > n) return -1;  // a level always splits every range: cannot happen
+    }
+    bvh_refit(box6, tree, st);
+    return levels;
 }
 
 size_t build_temp_bytes(long long cap) {

@@ -42,6 +42,9 @@ size_t build_temp_bytes(long long cap);
 void carve_build_temp(void* base, long long cap, BuildTemp& t);
 void bvh_build(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st);
 void bvh_refit(const float* box6, Tree& tree, hipStream_t st);
+// top-down binned SAH build into the same node format (static scene, once): one launch per level,
+// synchronises per level; returns the number of levels, -1 on a HIP error
+int bvh_build_sah(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st);
 // extra tree statistics: surface-area sum of internal nodes (device double)
 void bvh_sah(const Tree& tree, double* out, hipStream_t st);
 
