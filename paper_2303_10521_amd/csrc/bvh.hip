@@ -197,9 +197,11 @@ __global__ void __launch_bounds__(256) k_sah(const BNode* nodes, int n_int, doub
 // level of the build is one launch with one block per node: centroid bounds,
 // kSahBins bins per axis (counts and primitive boxes), the split of least
 // A_L N_L + A_R N_R, a stable partition of the node's primitive indices, and
-// the two children (a one-primitive child is a leaf).  Boxes come from a
-// refit at the end.  Where every centroid falls in one bin the range is cut
-// in half.
+// the two children (a one-primitive child is a leaf).  Internal nodes are
+// numbered in depth-first order (a node's left child follows it, its right
+// child follows the left subtree), so a walk down the near side reads nearby
+// nodes.  Boxes come from a refit at the end.  Where every centroid falls in
+// one bin the range is cut in half.
 constexpr int kSahBins = 32;
 struct SahItem { int node, start, count, pad; };
 
@@ -351,7 +353,8 @@ __global__ void __launch_bounds__(256) k_sah_level(const float* box, const SahIt
             perm[cs] = idx_out[cs];
             leaf_parent[cs] = (int)((uint32_t)it.node | (side ? EMRT_SIDE : 0u));
         } else {
-            child = (int)atomicAdd(&ctr[1], 1u);
+            // depth-first order: the left subtree's n_left - 1 internal nodes follow the node
+            child = side ? it.node + (int)n_left : it.node + 1;
             ((int*)&nodes[child].m)[2] = (int)((uint32_t)it.node | (side ? EMRT_SIDE : 0u));
             uint32_t q = atomicAdd(&ctr[0], 1u);
             next[q] = SahItem{child, cs, cn, 0};
@@ -369,7 +372,6 @@ __global__ void k_sah_init(uint32_t* idx, int n, SahItem* items, BNode* nodes, u
         items[0] = SahItem{0, 0, n, 0};
         ((int*)&nodes[0].m)[2] = -1;
         ctr[0] = 0u;  // items of the next level
-        ctr[1] = 1u;  // nodes allocated (the root)
     }
 }
 
