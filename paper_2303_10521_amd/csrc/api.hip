@@ -705,17 +705,20 @@ static void step_pre(emrt_ctx* c, int discover) {
         else bvh_refit(c->box_dy, c->dy, st);
         tri_prims(S, S.tris_dynamic, c->dy, c->dy_prims, st);
     }
-    rx_boxes(c->f_rx, c->sz.n_rx, c->box_rx, st);
-    bvh_build(c->box_rx, c->sz.n_rx, c->rxt, c->tmp, st);
-    rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
+    // capture trees: only the bounce kernel reads them, so cached frames skip them
     const bool rev = discover && c->rev_n > 0;
+    if (discover && !rev) {  // spheres on the receivers
+        rx_boxes(c->f_rx, c->sz.n_rx, c->box_rx, st);
+        bvh_build(c->box_rx, c->sz.n_rx, c->rxt, c->tmp, st);
+        rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
+    }
     if (rev) {  // spheres on the transmitters
         rx_boxes(c->f_tx, c->sz.n_tx, c->box_tx, st);
         bvh_build(c->box_tx, c->sz.n_tx, c->txt, c->tmp, st);
         rx_prims(c->f_tx, c->txt, c->tx_prims, st);
     }
     bool diff = c->cfg.diffraction && S.E > 0;
-    if (diff) {
+    if (diff && discover) {
         edge_boxes(S, c->box_ed, st);
         bvh_build(c->box_ed, S.E, c->edt, c->tmp, st);
         edge_prims(S, c->edt, c->edge_prims, st);
