@@ -368,8 +368,9 @@ static int seg_box(v3 o, v3 d, double t1, const double* lo, const double* hi) {
  *   receiver capture on segment b >= 1: receiver r is captured when
  *   s = (r-o).d lies in (0, t_end) and its distance to the ray is below
  *   k_rx * alpha * (L_acc + s), alpha = sqrt(4 pi / N) (reception sphere);
- *   edge capture on segment 0 (when diffraction is on): the ray passes within
- *   k_rx * alpha * s of an edge's interior before t_end;
+ *   edge capture on segment 0 (diffraction >= 1), and on segment 1 as well
+ *   (diffraction = 2: reflection then diffraction): the ray passes within
+ *   k_rx * alpha * (L_acc + s) of an edge's interior before t_end;
  *   reflect: d' = d - 2 (d.n) n about the face plane, L_acc += t;
  *   stop on a miss or after K reflections (no power threshold).
  * Direct-segment (b = 0) receiver captures are not emitted: line of sight is
@@ -378,7 +379,8 @@ static int seg_box(v3 o, v3 d, double t1, const double* lo, const double* hi) {
  * when want_robust, robust = 1 iff every segment keeps the distance margin
  * rob_m from every decision (grazing, triangle edges, near-coincident hits,
  * capture thresholds).  Capture rows (ray index, b, rx) and edge rows
- * (ray index, edge) are appended; counts beyond capacity are still counted. */
+ * (ray index, edge, b) are appended; counts beyond capacity are still
+ * counted. */
 int32_t orc_trace(int32_t T, const float* tv, const int32_t* tri_face, const double* plane,
                   const double* tx, int32_t N, int32_t n_rays, const int32_t* ray_ids, int32_t K,
                   int32_t n_rx, const double* rx, double k_rx, int32_t n_edges, const double* edge_p,
@@ -493,8 +495,9 @@ int32_t orc_trace(int32_t T, const float* tv, const int32_t* tri_face, const dou
                     }
                 }
             }
-            /* edge capture on the first segment */
-            if (b == 0 && diffraction) {
+            /* edge capture on the first segment, and with diffraction = 2 on
+             * the second (after one reflection) too; radius k_rx alpha (L + s) */
+            if ((b == 0 && diffraction) || (b == 1 && diffraction == 2)) {
                 for (int32_t e = 0; e < n_edges; e++) {
                     v3 q0 = ld3d(edge_p + 6 * e), q1 = ld3d(edge_p + 6 * e + 3);
                     v3 ev = vsub(q1, q0);
@@ -506,7 +509,7 @@ int32_t orc_trace(int32_t T, const float* tv, const int32_t* tri_face, const dou
                     double s = (bb * ee - c * dd) / den;
                     double u = (a * ee - bb * dd) / den;
                     double dist = vlen(vsub(vadd(o, vmul(d, s)), vadd(q0, vmul(ev, u))));
-                    double re = k_rx * alpha * s;
+                    double re = k_rx * alpha * (L + s);
                     double elen = sqrt(c);
                     if (want_robust && rob) {
                         double m = rob_m(s);
@@ -521,8 +524,9 @@ int32_t orc_trace(int32_t T, const float* tv, const int32_t* tri_face, const dou
 #pragma omp atomic capture
                         slot = nedge++;
                         if (slot < edge_cap) {
-                            edge_out[2 * slot + 0] = k;
-                            edge_out[2 * slot + 1] = e;
+                            edge_out[3 * slot + 0] = k;
+                            edge_out[3 * slot + 1] = e;
+                            edge_out[3 * slot + 2] = b;
                         }
                     }
                 }
@@ -577,14 +581,15 @@ static int in_tri(v3 p, v3 a, v3 b, v3 c, double* edist) {
  * penetration).  Sets *amb when a triangle's edge passes within
  * 1 mm + 1e-6 * |p1 - p0| of the segment (the decision could flip under
  * float32 geometry). */
-static int occluded(int32_t T, const float* tv, const int32_t* tri_face, v3 p0, v3 p1, int32_t xa, int32_t xb, int* amb) {
+static int occluded3(int32_t T, const float* tv, const int32_t* tri_face, v3 p0, v3 p1, int32_t xa, int32_t xb,
+                     int32_t xc, int* amb) {
     v3 d = vsub(p1, p0);
     double len = vlen(d);
     double m = 1.0e-3 + 1.0e-6 * len;
     int occ = 0;
     for (int32_t t = 0; t < T; t++) {
         int32_t f = tri_face[t];
-        if (f == xa || f == xb) continue;
+        if (f == xa || f == xb || f == xc) continue;
         v3 a = tvert(tv, t, 0), b = tvert(tv, t, 1), c = tvert(tv, t, 2);
         double th;
         if (tri_hit(p0, d, a, b, c, &th) && th < 1.0) occ = 1;
@@ -604,6 +609,10 @@ static int occluded(int32_t T, const float* tv, const int32_t* tri_face, v3 p0, 
         if (occ && !amb) return 1;
     }
     return occ;
+}
+
+static int occluded(int32_t T, const float* tv, const int32_t* tri_face, v3 p0, v3 p1, int32_t xa, int32_t xb, int* amb) {
+    return occluded3(T, tv, tri_face, p0, p1, xa, xb, -1, amb);
 }
 
 /* mirror point p about plane (n, dd) */
@@ -655,6 +664,13 @@ static double wedge_angle(const orc_wedge* w, v3 p) {
  *   edge: unfold Rx about the edge), strictly inside the edge; Tx and Rx in
  *   the exterior wedge (0 < phi', phi < n pi); |Q - Rx| <= diff_max_leg;
  *   both legs unoccluded outside the two wedge faces.
+ *   Reflection then diffraction (type 3, ids = face, edge) and diffraction
+ *   then reflection (type 4, ids = edge, face), order 2: the diffraction
+ *   rules applied to the image of Tx (type 3) or of Rx (type 4) in the face
+ *   plane; the reflection point where the segment from Q to that image
+ *   crosses the plane (parameter in (0, 1), inside the face, which is not a
+ *   wedge face); the receiver-side length |Q - image| or |Q - Rx| within
+ *   diff_max_leg; three legs unoccluded outside the faces of their ends.
  * ambiguous = 1 when a decision is within its margin (containment within
  * 1e-6 m of a triangle edge, an image parameter within 1e-9 of its ends, a
  * shadow leg within 1 mm + 1e-6 |leg| of a triangle edge, a Keller point
@@ -746,6 +762,77 @@ int32_t orc_validate(int32_t T, const float* tv, const int32_t* tri_face, const 
                 if (occluded(T, tv, tri_face, s, Q, w.f0, w.fn, &amb)) ok = 0;
                 else if (occluded(T, tv, tri_face, Q, r, w.f0, w.fn, &amb)) ok = 0;
             }
+        } else if (type == 3 || type == 4) {
+            /* one reflection and one diffraction: the reflection is unfolded by
+             * the image of the transmitter (3, reflection first) or of the
+             * receiver (4, diffraction first) in the face plane; the Keller
+             * point joins the real end to that image, and the reflection point
+             * is where the segment from the Keller point to the image crosses
+             * the plane. */
+            const int rd = type == 3;
+            int32_t f = rd ? key[4] : key[5], e = rd ? key[5] : key[4];
+            orc_wedge w = wedge_at(verts, edges + 6 * e, edge_n[e]);
+            v3 n = ld3d(plane + 4 * f);
+            double dpl = plane[4 * f + 3];
+            v3 a = rd ? mirror(s, n, dpl) : s;  /* source side of the edge (unfolded) */
+            v3 b = rd ? r : mirror(r, n, dpl);  /* receiver side (unfolded) */
+            if (f == w.f0 || f == w.fn || order != 2) ok = 0;
+            double za = vdot(vsub(a, w.P0), w.e), zb = vdot(vsub(b, w.P0), w.e);
+            double ra = vlen(vsub(vsub(a, w.P0), vmul(w.e, za)));
+            double rb = vlen(vsub(vsub(b, w.P0), vmul(w.e, zb)));
+            if (ok && !(ra + rb > 0)) ok = 0;
+            double zq = ok ? za + (zb - za) * ra / (ra + rb) : 0.0;
+            if (ok && !(zq > 0.0 && zq < w.len)) ok = 0;
+            v3 Q = vadd(w.P0, vmul(w.e, zq));
+            if (ok) {
+                double m = rob_m(vlen(vsub(Q, a)));
+                if (zq < m || w.len - zq < m) amb = 1;
+                double php = wedge_angle(&w, a), ph = wedge_angle(&w, b);
+                if (!(php > 0 && php < w.n * M_PI && ph > 0 && ph < w.n * M_PI)) ok = 0;
+                if (php < 1e-4 || fabs(php - w.n * M_PI) < 1e-4 || ph < 1e-4 || fabs(ph - w.n * M_PI) < 1e-4) amb = 1;
+            }
+            if (ok && !(vlen(vsub(Q, b)) <= diff_max_leg)) ok = 0;
+            v3 P = Q;
+            if (ok) {  /* reflection point on the segment Q -> image */
+                v3 img = rd ? a : b;
+                v3 dv = vsub(img, Q);
+                double den = vdot(n, dv);
+                if (den == 0.0) ok = 0;
+                double tt = ok ? (dpl - vdot(n, Q)) / den : 0.0;
+                if (ok && !(tt > 0.0 && tt < 1.0)) ok = 0;
+                if (ok && (tt < 1e-9 || tt > 1 - 1e-9)) amb = 1;
+                P = vadd(Q, vmul(dv, tt));
+            }
+            if (ok) {
+                int32_t found = -1;
+                double ed = 0;
+                for (int32_t j = face_off[f]; j < face_off[f + 1]; j++) {
+                    int32_t t = face_tris[j];
+                    double e1;
+                    if (in_tri(P, tvert(tv, t, 0), tvert(tv, t, 1), tvert(tv, t, 2), &e1)) {
+                        if (found < 0 || t < found) { found = t; ed = e1; }
+                    }
+                }
+                if (found < 0) ok = 0;
+                else {
+                    if (ed < 1e-6) amb = 1;
+                    tri_ids[5 * q + (rd ? 0 : 1)] = found;
+                }
+            }
+            if (ok) {
+                v3 x1 = rd ? P : Q, x2 = rd ? Q : P;
+                points[15 * q + 0] = x1.x; points[15 * q + 1] = x1.y; points[15 * q + 2] = x1.z;
+                points[15 * q + 3] = x2.x; points[15 * q + 4] = x2.y; points[15 * q + 5] = x2.z;
+                if (rd) {
+                    if (occluded(T, tv, tri_face, s, P, f, -1, &amb)) ok = 0;
+                    else if (occluded3(T, tv, tri_face, P, Q, f, w.f0, w.fn, &amb)) ok = 0;
+                    else if (occluded(T, tv, tri_face, Q, r, w.f0, w.fn, &amb)) ok = 0;
+                } else {
+                    if (occluded(T, tv, tri_face, s, Q, w.f0, w.fn, &amb)) ok = 0;
+                    else if (occluded3(T, tv, tri_face, Q, P, w.f0, w.fn, f, &amb)) ok = 0;
+                    else if (occluded(T, tv, tri_face, P, r, f, -1, &amb)) ok = 0;
+                }
+            }
         } else {
             ok = 0;
         }
@@ -799,6 +886,22 @@ int32_t orc_image_points(int32_t n_keys, const int32_t* keys, const double* plan
             points[15 * q + 0] = Q.x;
             points[15 * q + 1] = Q.y;
             points[15 * q + 2] = Q.z;
+        } else if (type == 3 || type == 4) {
+            const int rd = type == 3;
+            int32_t f = rd ? key[4] : key[5], e = rd ? key[5] : key[4];
+            orc_wedge w = wedge_at(verts, edges + 6 * e, edge_n[e]);
+            v3 n = ld3d(plane + 4 * f);
+            double dpl = plane[4 * f + 3];
+            v3 a = rd ? mirror(s, n, dpl) : s, b = rd ? r : mirror(r, n, dpl);
+            double za = vdot(vsub(a, w.P0), w.e), zb = vdot(vsub(b, w.P0), w.e);
+            double ra = vlen(vsub(vsub(a, w.P0), vmul(w.e, za)));
+            double rb = vlen(vsub(vsub(b, w.P0), vmul(w.e, zb)));
+            v3 Q = vadd(w.P0, vmul(w.e, za + (zb - za) * ra / (ra + rb)));
+            v3 dv = vsub(rd ? a : b, Q);
+            v3 P = vadd(Q, vmul(dv, (dpl - vdot(n, Q)) / vdot(n, dv)));
+            v3 x1 = rd ? P : Q, x2 = rd ? Q : P;
+            points[15 * q + 0] = x1.x; points[15 * q + 1] = x1.y; points[15 * q + 2] = x1.z;
+            points[15 * q + 3] = x2.x; points[15 * q + 4] = x2.y; points[15 * q + 5] = x2.z;
         }
     }
     return 0;
@@ -979,6 +1082,27 @@ static double complex cdotr(v3 a, c3 b) { return a.x * b.x + a.y * b.y + a.z * b
 static c3 cmk(v3 a, double complex s) { c3 r = {a.x * s, a.y * s, a.z * s}; return r; }
 static c3 cadd(c3 a, c3 b) { c3 r = {a.x + b.x, a.y + b.y, a.z + b.z}; return r; }
 
+/* Reflect the field vector E travelling along ki into ko at face f: the s/p
+ * basis of the bounce (s = normalize(ki x n), n against ki; normal incidence
+ * n x z, else n x x), E <- Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out. */
+static c3 reflect_at(c3 E, v3 ki, v3 ko, int32_t f, const double* plane, const int32_t* face_material,
+                     const double* mat_eps, const double* mat_refl) {
+    v3 n = ld3d(plane + 4 * f);
+    if (vdot(n, ki) > 0) n = vmul(n, -1.0);
+    double c = -vdot(ki, n);
+    v3 sv = vcross(ki, n);
+    if (vlen(sv) < 1e-12) {
+        sv = vcross(n, V(0, 0, 1));
+        if (vlen(sv) < 1e-12) sv = vcross(n, V(1, 0, 0));
+    }
+    sv = vnorm(sv);
+    v3 pin = vcross(sv, ki), pout = vcross(sv, ko);
+    double complex te, tm;
+    material_gammas(mat_eps, mat_refl, face_material[f], c, &te, &tm);
+    double complex es = cdotr(sv, E), ep = cdotr(pin, E);
+    return cadd(cmk(sv, te * es), cmk(pout, tm * ep));
+}
+
 /* phase factor exp(-j 2 pi frac(L / lambda)), frac(x) = x - round(x) */
 static double complex phase(double L, double lam) {
     double x = L / lam;
@@ -1050,46 +1174,56 @@ int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, con
                 double lam = ORC_C0 / freqs[fi];
                 v3 e0 = antenna(ant_mode, k0, th, phi);
                 c3 E = cmk(e0, 1.0);
-                for (int i = 1; i + 1 < np; i++) {
-                    int32_t f = key[3 + i];
-                    v3 n = ld3d(plane + 4 * f);
-                    v3 ki = kk[i - 1], ko = kk[i];
-                    if (vdot(n, ki) > 0) n = vmul(n, -1.0);
-                    double c = -vdot(ki, n);
-                    v3 sv = vcross(ki, n);
-                    if (vlen(sv) < 1e-12) {
-                        sv = vcross(n, V(0, 0, 1));
-                        if (vlen(sv) < 1e-12) sv = vcross(n, V(1, 0, 0));
-                    }
-                    sv = vnorm(sv);
-                    v3 pin = vcross(sv, ki), pout = vcross(sv, ko);
-                    int32_t m = face_material[f];
-                    double complex te, tm;
-                    material_gammas(mat_eps, mat_refl, m, c, &te, &tm);
-                    double complex es = cdotr(sv, E), ep = cdotr(pin, E);
-                    E = cadd(cmk(sv, te * es), cmk(pout, tm * ep));
-                }
+                for (int i = 1; i + 1 < np; i++)
+                    E = reflect_at(E, kk[i - 1], kk[i], key[3 + i], plane, face_material, mat_eps, mat_refl);
                 v3 er = antenna(0, kK, 0, 0);
                 amp[fi] = lam / (4.0 * M_PI * L) * cdotr(er, E) * phase(L, lam);
             }
         } else {
-            int32_t e = key[4];
+            /* diffraction alone (2), after a reflection (3) or before one (4):
+             * points s, [P], Q, [P], r; the reflection at P acts on the field
+             * vector arriving at Q (3) or leaving it (4); the spreading uses the
+             * unfolded source-side and receiver-side lengths. */
+            const int rd = type == 3, dr = type == 4;
+            int32_t e = rd ? key[5] : key[4];
+            int32_t fr = rd ? key[4] : (dr ? key[5] : -1);
             orc_wedge w = wedge_at(verts, edges + 6 * e, edge_n[e]);
-            v3 Q = ld3d(points + 15 * q);
-            v3 di = vsub(Q, s), dd = vsub(r, Q);
-            double sp = vlen(di), sd = vlen(dd);
-            v3 si = vmul(di, 1.0 / sp), so = vmul(dd, 1.0 / sd);
-            L = sp + sd;
-            k0 = si;
-            kK = so;
-            dop = vdot(so, vr) - vdot(si, vt);
+            v3 X1 = ld3d(points + 15 * q), X2 = ld3d(points + 15 * q + 3);
+            v3 Q = rd ? X2 : X1, Pr = rd ? X1 : X2;
+            v3 pt[4];
+            int np = 0;
+            pt[np++] = s;
+            if (rd) pt[np++] = Pr;
+            pt[np++] = Q;
+            if (dr) pt[np++] = Pr;
+            pt[np++] = r;
+            v3 kk[3];
+            double seg[3];
+            for (int i = 0; i + 1 < np; i++) {
+                v3 dv = vsub(pt[i + 1], pt[i]);
+                seg[i] = vlen(dv);
+                kk[i] = vmul(dv, 1.0 / seg[i]);
+                L += seg[i];
+            }
+            const int iq = rd ? 1 : 0; /* segment arriving at Q */
+            v3 si = kk[iq], so = kk[iq + 1];
+            double sp = rd ? seg[0] + seg[1] : seg[0];
+            double sd = dr ? seg[1] + seg[2] : seg[iq + 1];
+            k0 = kk[0];
+            kK = kk[np - 2];
+            dop = vdot(kK, vr) - vdot(k0, vt);
             int32_t od = face_dyn[w.f0];
             if (od >= 0) dop += vdot(vsub(si, so), ld3d(obj_vel + 3 * od));
+            if (fr >= 0) {
+                int32_t of = face_dyn[fr];
+                int ip = rd ? 1 : 2; /* point index of P: the segments ip - 1 and ip meet there */
+                if (of >= 0) dop += vdot(vsub(kk[ip - 1], kk[ip]), ld3d(obj_vel + 3 * of));
+            }
             double cb = vdot(si, w.e);
             if (cb > 1) cb = 1;
             if (cb < -1) cb = -1;
             double beta0 = acos(cb);
-            double php = wedge_angle(&w, s), ph = wedge_angle(&w, r);
+            double php = wedge_angle(&w, pt[iq]), ph = wedge_angle(&w, pt[iq + 2]);
             double Lp = sd * sp * sin(beta0) * sin(beta0) / (sd + sp);
             v3 fp = vmul(vnorm(vcross(w.e, si)), -1.0), bp = vcross(fp, si);
             v3 fo = vnorm(vcross(w.e, so)), bo = vcross(fo, so);
@@ -1099,10 +1233,12 @@ int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, con
                 double k = 2.0 * M_PI / lam;
                 double complex Ds, Dh;
                 utd_D(w.n, k, Lp, beta0, php, ph, mat_eps, mat_refl, m0, mn, &Ds, &Dh);
-                v3 et = antenna(ant_mode, si, th, phi);
-                v3 er = antenna(0, so, 0, 0);
-                double complex fld = -vdot(er, bo) * vdot(bp, et) * Ds - vdot(er, fo) * vdot(fp, et) * Dh;
-                amp[fi] = lam / (4.0 * M_PI) * (1.0 / sp) * sqrt(sp / (sd * (sd + sp))) * fld * phase(L, lam);
+                c3 E = cmk(antenna(ant_mode, k0, th, phi), 1.0);
+                if (rd) E = reflect_at(E, kk[0], kk[1], fr, plane, face_material, mat_eps, mat_refl);
+                c3 Ed = cadd(cmk(bo, -cdotr(bp, E) * Ds), cmk(fo, -cdotr(fp, E) * Dh));
+                if (dr) Ed = reflect_at(Ed, kk[1], kk[2], fr, plane, face_material, mat_eps, mat_refl);
+                v3 er = antenna(0, kK, 0, 0);
+                amp[fi] = lam / (4.0 * M_PI) * (1.0 / sp) * sqrt(sp / (sd * (sd + sp))) * cdotr(er, Ed) * phase(L, lam);
             }
         }
         for (int fi = 0; fi < nf; fi++) {

@@ -199,12 +199,13 @@ class TraceResult:
     hit_tri: np.ndarray  # [n, K+1]
     robust: np.ndarray  # [n] bool
     captures: np.ndarray  # [m, 3] (ray index into ray_ids, bounce, rx)
-    edge_hits: np.ndarray  # [q, 2] (ray index, edge)
+    edge_hits: np.ndarray  # [q, 3] (ray index, edge, segment: 0 direct, 1 after one reflection)
 
 
 def trace(os_: OracleScene, g: FrameGeom, tx_pos: np.ndarray, N: int, ray_ids: np.ndarray, K: int,
-          rx_pos: np.ndarray, k_rx: float = 1.0, diffraction: bool = False, want_robust: bool = True) -> TraceResult:
-    """Bounce loop for one transmitter over the launch directions ``ray_ids`` of N."""
+          rx_pos: np.ndarray, k_rx: float = 1.0, diffraction: int = 0, want_robust: bool = True) -> TraceResult:
+    """Bounce loop for one transmitter over the launch directions ``ray_ids`` of N
+    (diffraction: 0 off, 1 edge capture on the first segment, 2 on the first two)."""
     ray_ids = _c(ray_ids, np.int32)
     n = len(ray_ids)
     txf = _c(f32(tx_pos), np.float64)
@@ -215,14 +216,14 @@ def trace(os_: OracleScene, g: FrameGeom, tx_pos: np.ndarray, N: int, ray_ids: n
     ecap = max(1024, 4 * n) if diffraction else 1
     while True:
         caps = np.zeros((cap, 3), np.int32)
-        edges = np.zeros((ecap, 2), np.int32)
+        edges = np.zeros((ecap, 3), np.int32)
         ncap = ctypes.c_int64(0)
         nedge = ctypes.c_int64(0)
         lib().orc_trace(
             ctypes.c_int32(os_.T), _p(g.tv), _p(os_.tri_face), _p(g.plane), _p(txf), ctypes.c_int32(N),
             ctypes.c_int32(n), _p(ray_ids), ctypes.c_int32(K), ctypes.c_int32(len(rxf)), _p(rxf),
             ctypes.c_double(k_rx), ctypes.c_int32(os_.E if diffraction else 0), _p(g.edge_p),
-            ctypes.c_int32(1 if diffraction else 0), ctypes.c_int32(1 if want_robust else 0), _p(g.sphere),
+            ctypes.c_int32(int(diffraction)), ctypes.c_int32(1 if want_robust else 0), _p(g.sphere),
             _p(hit), _p(rob), ctypes.c_int64(cap), _p(caps), ctypes.byref(ncap), ctypes.c_int64(ecap), _p(edges),
             ctypes.byref(nedge))
         if ncap.value <= cap and nedge.value <= ecap:
@@ -233,7 +234,7 @@ def trace(os_: OracleScene, g: FrameGeom, tx_pos: np.ndarray, N: int, ray_ids: n
 
 
 KEY_W = 9  # tx, rx, type, order, id0..id4
-LOS, SPEC, DIFF = 0, 1, 2
+LOS, SPEC, DIFF, REFL_DIFF, DIFF_REFL = 0, 1, 2, 3, 4
 
 
 def spec_keys(os_: OracleScene, tr: TraceResult, tx: int) -> Dict[tuple, bool]:
@@ -262,9 +263,21 @@ def spec_keys_from_receiver(os_: OracleScene, tr: TraceResult, rx: int) -> Dict[
     return out
 
 
+def reflected_edges(os_: OracleScene, tr: TraceResult) -> Dict[Tuple[int, int], bool]:
+    """(face, edge) pairs lit by second segments: the ray reflected off the
+    face of its first hit and then passed the edge."""
+    out: Dict[Tuple[int, int], bool] = {}
+    for ri, e, b in tr.edge_hits:
+        if b != 1:
+            continue
+        f = int(os_.tri_face[tr.hit_tri[ri, 0]])
+        out[(f, int(e))] = out.get((f, int(e)), False) or bool(tr.robust[ri])
+    return out
+
+
 def illuminated_edges(tr: TraceResult) -> Dict[int, bool]:
     out: Dict[int, bool] = {}
-    for ri, e in tr.edge_hits:
+    for ri, e in tr.edge_hits[tr.edge_hits[:, 2] == 0, :2]:
         out[int(e)] = out.get(int(e), False) or bool(tr.robust[ri])
     return out
 
@@ -505,6 +518,22 @@ def diffraction_candidates_from_receiver(g: FrameGeom, rx: int, illum: Dict[int,
     return out
 
 
+def refl_diff_candidates(g: FrameGeom, tx: int, lit: Dict[Tuple[int, int], bool], rx_pos: np.ndarray,
+                         diff_max_leg: float) -> Dict[tuple, bool]:
+    """Reflection-then-diffraction candidates (tx, rx, face, edge) for (face,
+    edge) pairs lit from transmitter tx: every receiver within diff_max_leg of
+    the edge segment."""
+    out: Dict[tuple, bool] = {}
+    for (f, e), rob in lit.items():
+        p0 = g.edge_p[e, :3]
+        d = g.edge_p[e, 3:] - p0
+        s = np.clip(((rx_pos - p0) @ d) / float(d @ d), 0.0, 1.0)
+        dist = np.linalg.norm(rx_pos - (p0 + s[:, None] * d), axis=1)
+        for r in np.nonzero(dist <= diff_max_leg)[0]:
+            out[(tx, int(r), REFL_DIFF, 2, f, e, -1, -1, -1)] = rob
+    return out
+
+
 def sort_keys(keys: np.ndarray) -> np.ndarray:
     """Row-lexicographic order of (tx, rx, type, order, id0..id4)."""
     if len(keys) == 0:
@@ -513,7 +542,7 @@ def sort_keys(keys: np.ndarray) -> np.ndarray:
 
 
 def run_frame(os_: OracleScene, frame, N: int, K: int, freqs: Sequence[float], ray_ids: Optional[np.ndarray] = None,
-              diffraction: bool = False, discover: bool = True, cache: Optional[np.ndarray] = None,
+              diffraction: int = 0, discover: bool = True, cache: Optional[np.ndarray] = None,
               k_rx: float = 1.0, diff_max_leg: float = 250.0, want_robust: bool = True, ant_mode: int = 0,
               p_tx: float = P_TX_W, rx_sources: Optional[Sequence[int]] = None) -> OracleFrame:
     """One frame of the method: discovery (optional) on the given launch
@@ -525,7 +554,14 @@ def run_frame(os_: OracleScene, frame, N: int, K: int, freqs: Sequence[float], r
     (the backward launch of Section II-A): the same lattice of N directions
     from each listed receiver, spheres k_rx sqrt(4 pi / N) (L + s) around the
     transmitters, keys reversed into transmitter-to-receiver order, and edges
-    lit by the first segments proposing every transmitter."""
+    lit by the first segments proposing every transmitter.
+
+    diffraction: 0 off; 1 first-order edge diffraction; 2 also one reflection
+    combined with one diffraction -- from the transmitters, (face, edge) pairs
+    lit by second segments propose reflection-then-diffraction paths to every
+    receiver within diff_max_leg of the edge; from receivers, the same pairs
+    seen from the receiver propose the reverse, diffraction-then-reflection
+    paths, from every transmitter."""
     g = os_.geometry(frame.obj_xform)
     n_tx, n_rx = len(frame.tx_pos), len(frame.rx_pos)
     cand: Dict[tuple, bool] = {}
@@ -541,6 +577,11 @@ def run_frame(os_: OracleScene, frame, N: int, K: int, freqs: Sequence[float], r
                 for k, v in diffraction_candidates_from_receiver(g, r, illuminated_edges(tr), frame.rx_pos, n_tx,
                                                                  diff_max_leg).items():
                     cand[k] = cand.get(k, False) or v
+            if diffraction == 2:
+                for (f, e), v in reflected_edges(os_, tr).items():
+                    for t in range(n_tx):
+                        k = (t, r, DIFF_REFL, 2, e, f, -1, -1, -1)
+                        cand[k] = cand.get(k, False) or v
     elif discover:
         ids = np.arange(N, dtype=np.int32) if ray_ids is None else _c(ray_ids, np.int32)
         for tx in range(n_tx):
@@ -551,6 +592,10 @@ def run_frame(os_: OracleScene, frame, N: int, K: int, freqs: Sequence[float], r
             if diffraction:
                 for k, v in diffraction_candidates(os_, g, tx, illuminated_edges(tr), frame.rx_pos,
                                                    diff_max_leg).items():
+                    cand[k] = cand.get(k, False) or v
+            if diffraction == 2:
+                for k, v in refl_diff_candidates(g, tx, reflected_edges(os_, tr), frame.rx_pos,
+                                                 diff_max_leg).items():
                     cand[k] = cand.get(k, False) or v
     if cache is not None:
         for row in np.asarray(cache).reshape(-1, KEY_W):

@@ -581,6 +581,24 @@ def tiny_canyon(gap: float = 20.0, length: float = 4000.0, height: float = 4000.
     return _static_scene(v, tris, [0, 0, 1, 1], [0, 1], 2, [eps], [0, 0, 0], h)
 
 
+def tiny_box_ground(size: float = 40.0, height: float = 30.0, half: float = 500.0, refl=(1.0, 1.0)) -> Scene:
+    """One box building [0,size]^2 x [0,height] (walls + roof, object 1) on a
+    ground face at z = 0 (object 0); materials 0 ground, 1 building, with
+    constant reflection coefficients ``refl``."""
+    tv, tt, tf = box_template(1, 1, 1)
+    v = np.empty_like(tv)
+    v[:, 0] = tv[:, 0] * size
+    v[:, 1] = tv[:, 1] * size
+    v[:, 2] = tv[:, 2] * height
+    g = [(-half, -half, 0), (half, -half, 0), (half, half, 0), (-half, half, 0)]
+    verts = np.concatenate([np.asarray(g, np.float64), v])
+    tris = np.concatenate([np.array([(0, 1, 2), (0, 2, 3)]), np.asarray(tt) + 4])
+    faces = np.concatenate([[0, 0], np.asarray(tf) + 1])
+    sc = _static_scene(verts, tris, faces, [0] + [1] * 5, 2, [EPS_GROUND, EPS_CONCRETE], [-50, size / 2, 10], half,
+                       face_mat=[0] + [1] * 5)
+    return dataclasses.replace(sc, material_refl=np.asarray(refl, np.float64))
+
+
 def tiny_wedge(size: float = 40.0, height: float = 30.0, eps: complex = EPS_METAL,
                cols: int = 1, rows: int = 1) -> Scene:
     """One box building [0,size]^2 x [0,height] (walls + roof), no ground."""
