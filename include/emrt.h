@@ -64,7 +64,10 @@ typedef struct emrt_config {
     int32_t n_freq;             /* 1..4 */
     double freq_hz[4];          /* carrier frequencies evaluated on the same paths */
     int32_t max_reflections;    /* K, 0..5 */
-    int32_t diffraction;        /* 0/1: first-order edge diffraction */
+    int32_t diffraction;        /* 0: none; 1: first-order edge diffraction; 2 (one reflection with one
+                                   diffraction: transmitter-side steps propose reflection then
+                                   diffraction, receiver-side steps diffraction then reflection) is
+                                   refused with EMRT_E_UNSUPPORTED for now */
     int32_t rays_per_tx;        /* N launch directions per transmitter, >= 1 */
     double rx_sphere_k;         /* reception-sphere constant k_rx (default 1.0) */
     double diff_max_leg_m;      /* max edge-to-receiver distance (default 250) */
@@ -203,8 +206,10 @@ int32_t emrt_read_channels(emrt_ctx* ctx, const emrt_channel_view* view);
  * more than cap paths; the channel sums always use every path. */
 typedef struct emrt_path_view {
     int32_t cap;
-    int32_t* key;     /* [n_links][cap][9] tx, rx, type (0 LoS, 1 specular, 2 diffraction), order, id0..id4 */
-    int32_t* tri_ids; /* [n_links][cap][5] triangle of each reflection point */
+    int32_t* key;     /* [n_links][cap][9] tx, rx, type, order, id0..id4; type 0 line of sight, 1 specular
+                         (ids: faces), 2 diffraction (id0: edge), 3 reflection then diffraction (face,
+                         edge), 4 diffraction then reflection (edge, face) */
+    int32_t* tri_ids; /* [n_links][cap][5] triangle of each reflection point (-1 at a diffraction) */
     double* a;        /* [n_links][cap][n_freq][2] complex gain */
     double* tau;      /* [n_links][cap] delay */
     double* fd;       /* [n_links][cap][n_freq] Doppler shift */

@@ -17,7 +17,8 @@
 //     the field evaluated in the same numbers gives da/d(tx, theta, phi);
 //   * for every interaction, the field evaluated with that interaction's
 //     reflection coefficients replaced by their eps-derivatives gives
-//     da/deps of its material.
+//     da/deps of its material (a diffraction has two: its wedge faces; a
+//     path with one reflection and one diffraction has three).
 // The per-link partials go to rows [5 + 2 M][n_links]; a second kernel sums
 // them in a fixed order (per transmitter over its receivers, per material
 // over all links), so the result is deterministic.
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(128) k_adj_links(AdjArgs a) {
                     for (int k = 0; k < kTan; k++) acc[k] += g[f].re * amp[f].re.d[k] + g[f].im * amp[f].im.d[k];
                 }
                 // permittivity: one evaluation per interaction
-                int nmodes = gd.type == KT_SPEC ? gd.order : (gd.type == KT_DIFF ? 2 : 0);
+                int nmodes = gd.type == KT_SPEC ? gd.order : (gd.type == KT_DIFF ? 2 : (gd.type >= KT_RD ? 3 : 0));
                 if (nmodes == 0) continue;
                 PathGeo<double> gv;
 #pragma unroll
@@ -77,7 +78,9 @@ __global__ void __launch_bounds__(128) k_adj_links(AdjArgs a) {
                 for (int md = 1; md <= nmodes; md++) {
                     int m;
                     if (gd.type == KT_SPEC) m = S.face_material[key.ids[md - 1]];
-                    else m = S.face_material[S.edge_i[6 * (long long)key.ids[0] + (md == 1 ? 2 : 3)]];
+                    else if (md == 3) m = S.face_material[gd.type == KT_RD ? key.ids[0] : key.ids[1]];
+                    else m = S.face_material[S.edge_i[6 * (long long)(gd.type == KT_RD ? key.ids[1] : key.ids[0]) +
+                                                      (md == 1 ? 2 : 3)]];
                     if (m < 0 || m >= a.M) continue;
                     V3<double> kv[EMRT_KMAX + 1];
                     double Lv;

@@ -30,6 +30,8 @@ constexpr int C_STATS = 20;    // [20..23]
 constexpr int C_TRUNC = 24;    // path-list truncation flag
 constexpr int C_NLEGS = 25;    // shadow legs of the step
 constexpr int C_COH = 26;      // [26, 27] coherence read-back (min T_c bits, triggered links)
+constexpr int C_NPAIRS = 28;   // listed (source, face, edge) pairs
+constexpr int C_NEXTRA = 29;   // keys proposed into the extra-key array
 constexpr int C_SCRATCH = 32;  // ints for set_scene
 
 struct Carver {
@@ -141,6 +143,11 @@ struct emrt_ctx {
     std::vector<int> rev_host;
     int rev_n = 0, rev_rays = 0;     // nonzero only while a receiver-side step is enqueued
     bool last_rev = false;           // the hit log holds a receiver-side launch
+    // reflection-diffraction candidates (diffraction = 2)
+    unsigned long long* pairs = nullptr;  // [pair_slots] set of lit (source, face, edge)
+    unsigned long long* pair_list = nullptr;
+    long long pair_slots = 0;
+    KeyRec* extra = nullptr;              // [P] proposed keys, referenced from the path table
     double st_area = 0.0;            // static tree quality (emrt_stats.static_tree_area)
 };
 
@@ -240,6 +247,11 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->cache[0] = cv.take<KeyRec>(c->P);
     c->cache[1] = cv.take<KeyRec>(c->P);
     c->illum = cv.take<uint32_t>((long long)std::max<long long>(z.n_tx, kMaxRxSources) * c->e_words);
+    if (c->pair_slots > 0) {
+        c->pairs = cv.take<unsigned long long>(c->pair_slots);
+        c->pair_list = cv.take<unsigned long long>(c->pair_slots);
+        c->extra = cv.take<KeyRec>(c->P);
+    }
     {
         const long long nc = (long long)kGridN * kGridN;
         c->bins.grid = cv.take<RxGrid>(1);
@@ -268,6 +280,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     lg.dx = cv.take<float>(lg.cap); lg.dy = cv.take<float>(lg.cap); lg.dz = cv.take<float>(lg.cap);
     lg.xa = cv.take<int>(lg.cap);
     lg.xb = cv.take<int>(lg.cap);
+    lg.xc = cv.take<int>(lg.cap);
     lg.key = cv.take<uint32_t>(lg.cap);
     c->kstate = cv.take<uint8_t>(c->vcap);
     c->occl = cv.take<uint32_t>(c->vcap);
@@ -275,7 +288,9 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->vtmp.off = cv.take<uint32_t>(c->vcap);
     c->vtmp.flag_d = cv.take<uint32_t>(c->vcap);
     c->vtmp.off_d = cv.take<uint32_t>(c->vcap);
-    c->vtmp.cnt = cv.take<uint32_t>(2);
+    c->vtmp.flag_r = cv.take<uint32_t>(c->vcap);
+    c->vtmp.off_r = cv.take<uint32_t>(c->vcap);
+    c->vtmp.cnt = cv.take<uint32_t>(3);
     c->vtmp.surv = cv.take<uint32_t>(c->vcap);
     c->ktri = cv.take<int>(5 * c->vcap);
     c->vtmp.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(c->vcap) / 4 + 16);
@@ -324,6 +339,7 @@ static void derive(emrt_ctx* c) {
     long long b = std::max<long long>({z.n_tris, (long long)c->E_cap, (long long)z.n_rx, (long long)z.n_tx,
                                        (long long)c->cfg.rays_per_tx, z.n_faces, z.n_objects, 16LL});
     c->bcap = b;
+    c->pair_slots = c->cfg.diffraction == 2 ? pow2_at_least(std::max<int64_t>(c->cfg.table_capacity / 4, 1 << 16)) : 0;
 }
 
 static void coherence_clear(emrt_ctx* c);
@@ -355,8 +371,13 @@ int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
         return EMRT_E_UNSUPPORTED;
     if (cfg->rays_per_tx < 1 || !(cfg->rx_sphere_k > 0) || !(cfg->diff_max_leg_m >= 0) || cfg->path_capacity < 1 ||
         cfg->path_capacity > (1LL << 31) || cfg->antenna_mode < 0 || cfg->antenna_mode > 1 ||
-        cfg->adjoint_materials < 0 || cfg->adjoint_materials > kMaxMaterials)
+        cfg->adjoint_materials < 0 || cfg->adjoint_materials > kMaxMaterials || cfg->diffraction < 0 ||
+        cfg->diffraction > 2)
         return EMRT_E_INVALID;
+    // one reflection combined with one diffraction: the kernels below are
+    // complete (k_pair_list, k_pair_cand, the combined construction and
+    // fields) but the configuration stays refused until they have run clean
+    if (cfg->diffraction == 2) return EMRT_E_UNSUPPORTED;
     for (int i = 0; i < cfg->n_freq; i++)
         if (!(cfg->freq_hz[i] > 0)) return EMRT_E_INVALID;
     emrt_ctx* c = new emrt_ctx();
@@ -640,7 +661,7 @@ static long long launch_total(const emrt_ctx* c) {
 static KeySrc key_src(const emrt_ctx* c, const KeyRec* cache) {
     const bool rev = c->rev_n > 0;
     return KeySrc{c->hitlog, c->S.tri_face, cache, launch_total(c), rev ? c->rev_rays : c->cfg.rays_per_tx,
-                  rev ? c->rev_rx : nullptr};
+                  rev ? c->rev_rx : nullptr, c->extra};
 }
 
 // Bounce arguments of level k; tree sizes are those the step's trees have
@@ -662,7 +683,9 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.rxt = rev ? Bvh{c->txt.nodes, c->sz.n_tx} : Bvh{c->rxt.nodes, c->sz.n_rx};
     b.rx_prims = rev ? c->tx_prims : c->rx_prims;
     b.alpha_k = (float)(c->cfg.rx_sphere_k * sqrt(4.0 * kPi / (double)rays));
-    b.diffraction = diff ? 1 : 0;
+    b.diffraction = diff ? c->cfg.diffraction : 0;
+    b.pairs = c->pairs;
+    b.pair_mask = c->pair_slots ? (unsigned long long)c->pair_slots - 1ULL : 0ULL;
     b.edt = Bvh{c->edt.nodes, diff ? S.E : 0};
     b.edge_prims = c->edge_prims;
     b.illum = c->illum;
@@ -730,6 +753,7 @@ static void step_pre(emrt_ctx* c, int discover) {
         fill_u64(c->table, 0ULL, c->table_slots, st);
         fill_u32((uint32_t*)c->hitlog, 0xFFFFFFFEu, (long long)(K + 1) * launch_total(c), st);
         if (diff) fill_u32(c->illum, 0u, (long long)n_src * c->e_words, st);
+        if (diff && c->pairs) fill_u64(c->pairs, 0ULL, c->pair_slots, st);
         cache_insert(c->table, mask, c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, src, c->flags, st);
         if (rev) {
             gather_rx(c->f_rx, c->rev_rx, c->rev_n, c->rev_pos, st);
@@ -765,6 +789,11 @@ static void step_post(emrt_ctx* c, int discover) {
         } else if (diff) {
             rx_grid_build(c->f_rx, c->sz.n_rx, c->bins, st);
             diff_candidates(pa, c->illum, c->e_words, c->bins, c->table, mask, src, st);
+        }
+        if (diff && c->pairs) {  // one reflection and one diffraction
+            ExtraKeys xk{c->extra, c->ctr + C_NEXTRA, c->P};
+            pair_candidates(pa, c->pairs, c->pair_slots, c->pair_list, c->ctr + C_NPAIRS, c->bins,
+                            c->rev_n > 0 ? c->rev_rx : nullptr, xk, c->table, mask, src, st);
         }
         table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags,
                       c->ctmp, st);

@@ -41,7 +41,10 @@ struct KeyRec {
     int ids[5];
 };
 
-enum { KT_LOS = 0, KT_SPEC = 1, KT_DIFF = 2 };
+// path types: line of sight, specular (ids = faces), edge diffraction
+// (ids[0] = edge), reflection then diffraction (ids = face, edge) and
+// diffraction then reflection (ids = edge, face)
+enum { KT_LOS = 0, KT_SPEC = 1, KT_DIFF = 2, KT_RD = 3, KT_DR = 4 };
 
 // device status flags (read back on sync)
 enum : uint32_t {
@@ -127,7 +130,7 @@ __device__ __forceinline__ uint64_t key_hash(int tx, int rx, int to, const int* 
     uint64_t h = mix64(((uint64_t)(uint32_t)tx << 32) ^ (uint64_t)(uint32_t)rx ^ 0x9E3779B97F4A7C15ULL);
     h = mix64(h ^ (uint64_t)(uint32_t)to);
     int type = to & 0xff, order = to >> 8;
-    int n = type == KT_SPEC ? order : (type == KT_DIFF ? 1 : 0);
+    int n = type == KT_SPEC ? order : (type == KT_DIFF ? 1 : (type >= KT_RD ? 2 : 0));
     for (int j = 0; j < n; j++) h = mix64(h ^ ((uint64_t)(uint32_t)ids[j] + 0x632BE59BD9B4E019ULL * (uint64_t)(j + 1)));
     return h;
 }
@@ -135,6 +138,8 @@ __device__ __forceinline__ uint64_t ref_ray(int order, int rx, uint32_t ray) {
     return (1ULL << 62) | ((uint64_t)order << 59) | ((uint64_t)rx << 32) | (uint64_t)ray;
 }
 __device__ __forceinline__ uint64_t ref_cache(uint32_t idx) { return (2ULL << 62) | (uint64_t)idx; }
+// a key stored in the step's extra-key array (reflection-diffraction candidates)
+__device__ __forceinline__ uint64_t ref_extra(uint32_t idx) { return (2ULL << 62) | (1ULL << 61) | (uint64_t)idx; }
 __device__ __forceinline__ uint64_t ref_diff(int tx, int e, int rx) {
     return (3ULL << 62) | ((uint64_t)tx << 50) | ((uint64_t)e << 26) | (uint64_t)rx;
 }
@@ -152,6 +157,7 @@ struct KeySrc {
     long long n_total;     // rays in the launch
     int rays_per_tx;       // rays per source
     const int* src_rx;     // receiver-side launch: receiver of each source; null otherwise
+    const KeyRec* extra;   // keys proposed by the reflection-diffraction candidates
 };
 
 // SIDE: 0 transmitter-side launch, 1 receiver-side, -1 read from s.src_rx
@@ -177,7 +183,8 @@ __device__ __forceinline__ void expand_ref(uint64_t ref, const KeySrc& s, KeyRec
                 k.ids[j] = j < order ? s.tri_face[s.hitlog[(long long)j * s.n_total + ray]] : -1;
         }
     } else if (tag == 2) {
-        k = s.cache[(uint32_t)(ref & 0x3FFFFFFFFFFFFFFFULL)];
+        k = (ref >> 61) & 1 ? s.extra[(uint32_t)(ref & 0x1FFFFFFFFFFFFFFFULL)]
+                            : s.cache[(uint32_t)(ref & 0x1FFFFFFFFFFFFFFFULL)];
     } else {
         k.tx = (int)((ref >> 50) & 0xFFF);
         k.rx = (int)(ref & 0x3FFFFFF);
@@ -204,6 +211,26 @@ __device__ __forceinline__ bool key_less(const KeyRec& a, const KeyRec& b) {
     if (oa != ob) return oa < ob;
     for (int j = 0; j < 5; j++)
         if (a.ids[j] != b.ids[j]) return a.ids[j] < b.ids[j];
+    return false;
+}
+
+// Set of (source, face, edge) triples lit by second segments (a ray that
+// reflected off `face` passed the edge): 16 + 24 + 24 bits, bit 63 marks a
+// used slot.  Returns false when the set is full.
+__device__ __forceinline__ uint64_t pair_key(int source, int face, int edge) {
+    return (1ULL << 63) | ((uint64_t)(uint32_t)source << 48) | ((uint64_t)(uint32_t)face << 24) | (uint64_t)(uint32_t)edge;
+}
+__device__ __forceinline__ bool pair_insert(unsigned long long* set, uint64_t mask, uint64_t key) {
+    uint64_t slot = mix64(key) & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        unsigned long long cur = __hip_atomic_load(&set[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == key) return true;
+        if (cur == 0ULL) {
+            unsigned long long prev = atomicCAS(&set[slot], 0ULL, (unsigned long long)key);
+            if (prev == 0ULL || prev == key) return true;
+        }
+        slot = (slot + 1) & mask;
+    }
     return false;
 }
 
@@ -465,8 +492,9 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
 }
 
 // Any hit on the open segment t in (0, tmax) among triangles not on faces
-// xa / xb (shadow rays of path validation).
-__device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, float tmax, int xa, int xb) {
+// xa / xb / xc (shadow rays of path validation).
+__device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, float tmax, int xa, int xb,
+                                        int xc = -1) {
     if (bvh.n_prims <= 0) return false;
     bool found = false;
     traverse<true>(bvh.nodes, r,
@@ -476,7 +504,7 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
             TriP p = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
             int face = __float_as_int(p.v1.w);
             float t;
-            if (face != xa && face != xb && tri_hit(p, r, t) && t < tmax) found = true;
+            if (face != xa && face != xb && face != xc && tri_hit(p, r, t) && t < tmax) found = true;
             return false;
         },
         [&]() { return found; });

@@ -124,6 +124,8 @@ struct BounceArgs {
     const float4* edge_prims;  // [E][2]
     uint32_t* illum;           // [N_tx][E_words]
     int e_words;
+    unsigned long long* pairs; // (source, face, edge) lit by second segments (diffraction = 2)
+    unsigned long long pair_mask;
     // path table
     unsigned long long* table;
     unsigned long long mask;
@@ -168,7 +170,7 @@ struct ValidPaths {
 // shadow rays of the keys under validation (one per leg)
 struct LegBuf {
     float *ox, *oy, *oz, *dx, *dy, *dz;
-    int *xa, *xb;
+    int *xa, *xb, *xc;  // faces excluded from the leg's shadow ray
     uint32_t* key;
     unsigned long long* count;
     long long cap;
@@ -220,6 +222,18 @@ struct RxBins {
 void rx_grid_build(const double* rx_pos, int n_rx, const RxBins& b, hipStream_t st);
 void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
                      unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
+// keys proposed outside the path table's own references (reflection-diffraction candidates)
+struct ExtraKeys {
+    KeyRec* key;
+    unsigned long long* count;
+    long long cap;
+};
+// (source, face, edge) pairs lit by second segments -> reflection-then-diffraction keys to the
+// receivers near the edge (transmitter-side launch, src_rx null) or diffraction-then-reflection
+// keys from every transmitter (receiver-side launch)
+void pair_candidates(const PathArgs& a, const unsigned long long* set, long long n_slots, unsigned long long* list,
+                     unsigned long long* n_list, const RxBins& bins, const int* src_rx, const ExtraKeys& xk,
+                     unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
 // receiver-side launch: illum rows are the sources src_rx[0..n_src); every transmitter is tried
 void diff_candidates_rx(const PathArgs& a, const uint32_t* illum, int e_words, const int* src_rx, int n_src,
                         unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
@@ -238,8 +252,10 @@ struct ValidTemp {
     uint32_t* off;
     uint32_t* flag_d;   // diffraction survivors
     uint32_t* off_d;
-    uint32_t* cnt;      // [2] survivor counts of the two kinds
-    uint32_t* surv;     // survivors, the first kind first
+    uint32_t* flag_r;   // survivors with one reflection and one diffraction
+    uint32_t* off_r;
+    uint32_t* cnt;      // [3] survivor counts of the three kinds
+    uint32_t* surv;     // survivors, kind by kind
     uint32_t* scan_tmp;
 };
 void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, const ValidTemp& t, hipStream_t st);

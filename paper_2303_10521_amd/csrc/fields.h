@@ -480,7 +480,9 @@ struct PathGeo {
 // containment or occlusion test): image method for reflections, closed-form
 // Keller point for diffraction.  Used by the adjoint, where the derivatives
 // of the points with respect to the transmitter flow through R.
-template <class R>
+// KIND (as for path_field): 0 any type, 1 line of sight / specular only,
+// 2 diffraction alone only, 3 one reflection and one diffraction only.
+template <class R, int KIND = 0>
 __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key, V3<R> s, dv3 rx, PathGeo<R>& g) {
 #pragma clang fp contract(off)
     g.type = key.to & 0xff;
@@ -491,7 +493,7 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
         g.np = 2;
         return;
     }
-    if (g.type == KT_DIFF) {
+    if ((KIND == 0 || KIND == 2) && g.type == KT_DIFF) {
         g.np = 3;
         Wedge w = wedge_of(S, key.ids[0]);
         R zs = dot3(w.e, s - w.P0);
@@ -501,6 +503,29 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
         double rr = len(rr3);
         R zq = zs + (zr - zs) * rs / (rs + rr);
         g.P[1] = scale(w.e, zq) + w.P0;
+        return;
+    }
+    if ((KIND == 0 || KIND == 3) && (g.type == KT_RD || g.type == KT_DR)) {
+        // the Keller point between the unfolded ends (Tx's image and Rx, or Tx
+        // and Rx's image), then the reflection point on the segment from it to
+        // the image
+        const bool rd = g.type == KT_RD;
+        g.np = 4;
+        Wedge w = wedge_of(S, rd ? key.ids[1] : key.ids[0]);
+        const double* pl = S.plane + 4 * (long long)(rd ? key.ids[0] : key.ids[1]);
+        dv3 n = d3(pl[0], pl[1], pl[2]);
+        V3<R> a = s, b = g.Rx;
+        if (rd) a = s - scale(n, (dot3(n, s) - pl[3]) * 2.0);
+        else b = g.Rx - scale(n, (dot3(n, g.Rx) - pl[3]) * 2.0);
+        R za = dot3(w.e, a - w.P0), zb = dot3(w.e, b - w.P0);
+        R ra = len3((a - w.P0) - scale(w.e, za)), rb = len3((b - w.P0) - scale(w.e, zb));
+        R zq = za + (zb - za) * ra / (ra + rb);
+        V3<R> Q = scale(w.e, zq) + w.P0;
+        V3<R> dv = (rd ? a : b) - Q;
+        R tt = (pl[3] - dot3(n, Q)) / dot3(n, dv);
+        V3<R> P = Q + dv * tt;
+        g.P[1] = rd ? P : Q;
+        g.P[2] = rd ? Q : P;
         return;
     }
     const int order = g.order;
@@ -534,6 +559,33 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
 // dmode = 1 / 2 (diffraction): with respect to the 0-face / n-face material.
 // KIND = 1 / 2 compiles only the line-of-sight-and-specular / diffraction
 // branch (the caller guarantees the path type); 0 keeps both.
+// Reflection of the complex field vector E travelling along ki into ko at
+// face f, in the bounce's s/p basis (s = normalize(ki x n), n against ki;
+// normal incidence: n x z, else n x x): E <- Gamma_TE (E.s) s +
+// Gamma_TM (E.p_in) p_out, with p = s x k; deriv: the coefficients'
+// permittivity derivatives instead.
+template <class R>
+__device__ __forceinline__ void reflect_x(const SceneDev& S, const FieldCtx& fc, int f, V3<R> ki, V3<R> ko, bool deriv,
+                                          Cx<R>* E) {
+    const double* pl = S.plane + 4 * (long long)f;
+    dv3 nrm = d3(pl[0], pl[1], pl[2]);
+    if (vv(dot3(nrm, ki)) > 0) nrm = nrm * -1.0;
+    R c = rl<R>(0.0) - dot3(nrm, ki);
+    V3<R> sv = cross3(ki, nrm);
+    if (sqrt(vv(dot3(sv, sv))) < 1e-12) {
+        sv = v3c<R>(cross(nrm, d3(0, 0, 1)));
+        if (sqrt(vv(dot3(sv, sv))) < 1e-12) sv = v3c<R>(cross(nrm, d3(1, 0, 0)));
+    }
+    sv = unit3(sv);
+    V3<R> pin = cross3(sv, ki), pout = cross3(sv, ko);
+    Cx<R> te, tm;
+    material_x<R>(fc, S.face_material[f], c, deriv, te, tm);
+    Cx<R> es = cdotx(sv, E) * te, ep = cdotx(pin, E) * tm;
+    E[0] = es * sv.x + ep * pout.x;
+    E[1] = es * sv.y + ep * pout.y;
+    E[2] = es * sv.z + ep * pout.z;
+}
+
 template <class R, int KIND = 0>
 __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc, const KeyRec& key, const PathGeo<R>& g,
                                            R th, R phi, int dmode, V3<R>* kk, R& L, Cx<R>* amp) {
@@ -553,7 +605,7 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
 #pragma unroll
     for (int i = 1; i <= EMRT_KMAX; i++)
         if (i == nlegs - 1) kK = kk[i];
-    const bool diffracted = KIND == 2 ? true : (KIND == 1 ? false : g.type == KT_DIFF);
+    const bool diffracted = KIND >= 2 ? true : (KIND == 1 ? false : g.type >= KT_DIFF);
     if (!diffracted) {
         V3<R> e0 = antenna_x<R>(fc.ant_mode, k0, th, phi);
         V3<R> er = antenna_x<R>(0, kK, rl<R>(0.0), rl<R>(0.0));
@@ -563,54 +615,73 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
 #pragma unroll
             for (int i = 1; i <= EMRT_KMAX; i++) {
                 if (i > g.order || g.type == KT_LOS) break;
-                int f = key.ids[i - 1];
-                const double* pl = S.plane + 4 * (long long)f;
-                dv3 nrm = d3(pl[0], pl[1], pl[2]);
-                V3<R> ki = kk[i - 1], ko = kk[i];
-                if (vv(dot3(nrm, ki)) > 0) nrm = nrm * -1.0;
-                R c = rl<R>(0.0) - dot3(nrm, ki);
-                V3<R> sv = cross3(ki, nrm);
-                if (sqrt(vv(dot3(sv, sv))) < 1e-12) {
-                    sv = v3c<R>(cross(nrm, d3(0, 0, 1)));
-                    if (sqrt(vv(dot3(sv, sv))) < 1e-12) sv = v3c<R>(cross(nrm, d3(1, 0, 0)));
-                }
-                sv = unit3(sv);
-                V3<R> pin = cross3(sv, ki), pout = cross3(sv, ko);
-                int m = S.face_material[f];
-                Cx<R> te, tm;
-                material_x<R>(fc, m, c, dmode == i, te, tm);
-                Cx<R> es = cdotx(sv, E) * te, ep = cdotx(pin, E) * tm;
-                E[0] = es * sv.x + ep * pout.x;
-                E[1] = es * sv.y + ep * pout.y;
-                E[2] = es * sv.z + ep * pout.z;
+                reflect_x<R>(S, fc, key.ids[i - 1], kk[i - 1], kk[i], dmode == i, E);
             }
             R scl = lam / (4.0 * kPi * L);
             amp[fi] = cdotx(er, E) * phase_x<R>(L, lam) * scl;
         }
     } else {
-        Wedge w = wedge_of(S, key.ids[0]);
-        R sp = len3(g.P[1] - g.P[0]), sd = len3(g.Rx - g.P[1]);
-        V3<R> si = kk[0], so = kk[1];
+        // diffraction alone, or after (RD) / before (DR) one reflection: points
+        // Tx, [P], Q, [P], Rx; sp / sd are the unfolded lengths on the source /
+        // receiver side of the Keller point Q; the reflection acts on the field
+        // vector arriving at Q (RD) or leaving it (DR).  dmode 1 / 2: the wedge
+        // faces' permittivity derivative, 3: the reflection face's.
+        // KIND 2 / 3 compile only the diffraction-alone / the combined paths
+        const bool rd = KIND != 2 && g.type == KT_RD, dr = KIND != 2 && g.type == KT_DR;
+        Wedge w = wedge_of(S, rd ? key.ids[1] : key.ids[0]);
+        const int iq = rd ? 1 : 0;  // leg arriving at Q
+        V3<R> si = kk[iq], so = kk[iq + 1];
+        R sp, sd;
+        if (rd) {
+            sp = len3(g.P[1] - g.P[0]) + len3(g.P[2] - g.P[1]);
+            sd = len3(g.Rx - g.P[2]);
+        } else if (dr) {
+            sp = len3(g.P[1] - g.P[0]);
+            sd = len3(g.P[2] - g.P[1]) + len3(g.Rx - g.P[2]);
+        } else {
+            sp = len3(g.P[1] - g.P[0]);
+            sd = len3(g.Rx - g.P[1]);
+        }
         R cb = clamp1<R>(dot3(si, v3c<R>(w.e)));
         R beta0 = acos_(cb);
-        R php = wedge_angle_x<R>(w, g.P[0]), ph = wedge_angle_x<R>(w, g.Rx);
+        R php = wedge_angle_x<R>(w, rd ? g.P[1] : g.P[0]), ph = wedge_angle_x<R>(w, dr ? g.P[2] : g.Rx);
         R sb = sin_(beta0);
         R Lp = sd * sp * sb * sb / (sd + sp);
         V3<R> fp = scale(unit3(cross3(w.e, si)), -1.0), bp = cross3(fp, si);
         V3<R> fo = unit3(cross3(w.e, so)), bo = cross3(fo, so);
         int m0 = S.face_material[w.f0], mn = S.face_material[w.fn];
-        V3<R> et = antenna_x<R>(fc.ant_mode, si, th, phi);
-        V3<R> er = antenna_x<R>(0, so, rl<R>(0.0), rl<R>(0.0));
+        V3<R> et = antenna_x<R>(fc.ant_mode, k0, th, phi);
+        V3<R> er = antenna_x<R>(0, kK, rl<R>(0.0), rl<R>(0.0));
         R spread = (1.0 / sp) * sqrt_(sp / (sd * (sd + sp)));
-        R cs = rl<R>(0.0) - dot3(er, bo) * dot3(bp, et);
-        R ch = dot3(er, fo) * dot3(fp, et);
-        for (int fi = 0; fi < fc.nf; fi++) {
-            double lam = kC0 / fc.freq[fi];
-            double k = 2.0 * kPi / lam;
-            Cx<R> Ds, Dh;
-            utd_D_x<R>(w.n, k, Lp, beta0, php, ph, fc, m0, mn, dmode, Ds, Dh);
-            Cx<R> fld = Ds * cs - Dh * ch;
-            amp[fi] = fld * phase_x<R>(L, lam) * (spread * (lam / (4.0 * kPi)));
+        const int wmode = dmode == 3 ? 0 : dmode;
+        if (KIND != 3 && !rd && !dr) {
+            R cs = rl<R>(0.0) - dot3(er, bo) * dot3(bp, et);
+            R ch = dot3(er, fo) * dot3(fp, et);
+            for (int fi = 0; fi < fc.nf; fi++) {
+                double lam = kC0 / fc.freq[fi];
+                double k = 2.0 * kPi / lam;
+                Cx<R> Ds, Dh;
+                utd_D_x<R>(w.n, k, Lp, beta0, php, ph, fc, m0, mn, wmode, Ds, Dh);
+                Cx<R> fld = Ds * cs - Dh * ch;
+                amp[fi] = fld * phase_x<R>(L, lam) * (spread * (lam / (4.0 * kPi)));
+            }
+        } else {
+            const int fr = rd ? key.ids[0] : key.ids[1];
+            for (int fi = 0; fi < fc.nf; fi++) {
+                double lam = kC0 / fc.freq[fi];
+                double k = 2.0 * kPi / lam;
+                Cx<R> Ds, Dh;
+                utd_D_x<R>(w.n, k, Lp, beta0, php, ph, fc, m0, mn, wmode, Ds, Dh);
+                Cx<R> E[3] = {cx<R>(et.x, rl<R>(0.0)), cx<R>(et.y, rl<R>(0.0)), cx<R>(et.z, rl<R>(0.0))};
+                if (rd) reflect_x<R>(S, fc, fr, kk[0], kk[1], dmode == 3, E);
+                // diffracted field vector: -b0 (b0'.E) D_s - phi (phi'.E) D_h
+                Cx<R> cbs = cdotx(bp, E) * Ds, cfh = cdotx(fp, E) * Dh;
+                Cx<R> Ed[3] = {cx<R>(rl<R>(0.0), rl<R>(0.0)) - cbs * bo.x - cfh * fo.x,
+                               cx<R>(rl<R>(0.0), rl<R>(0.0)) - cbs * bo.y - cfh * fo.y,
+                               cx<R>(rl<R>(0.0), rl<R>(0.0)) - cbs * bo.z - cfh * fo.z};
+                if (dr) reflect_x<R>(S, fc, fr, kk[1], kk[2], dmode == 3, Ed);
+                amp[fi] = cdotx(er, Ed) * phase_x<R>(L, lam) * (spread * (lam / (4.0 * kPi)));
+            }
         }
     }
 }

@@ -338,6 +338,104 @@ void diff_candidates_rx(const PathArgs& a, const uint32_t* illum, int e_words, c
                        n_src, table, mask, src);
 }
 
+// ---- one reflection and one diffraction --------------------------------
+// The used slots of the pair set, listed (one atomic per wave).
+__global__ void __launch_bounds__(256) k_pair_list(const unsigned long long* set, long long n,
+                                                   unsigned long long* list, unsigned long long* count) {
+    const long long lanes = (long long)gridDim.x * blockDim.x;
+    const long long n_up = (n + 63) / 64 * 64;  // every lane of a wave takes the same trips
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_up; i += lanes) {
+        const unsigned long long v = i < n ? set[i] : 0ULL;
+        const long long pos = wave_append(count, v != 0ULL);
+        if (v != 0ULL) list[pos] = v;
+    }
+}
+
+// A proposed key goes into the extra-key array, then into the path table by
+// reference (duplicates of cached keys leave their extra slot unused).
+__device__ __forceinline__ void extra_insert(const ExtraKeys& xk, const KeyRec& key, unsigned long long* table,
+                                             unsigned long long mask, const KeySrc& src, uint32_t* flags) {
+    const unsigned long long i = atomicAdd(xk.count, 1ULL);
+    if (i >= (unsigned long long)xk.cap) {
+        atomicOr(flags, FLAG_CAND_CAP);
+        return;
+    }
+    xk.key[i] = key;
+    __threadfence();
+    const uint64_t h = key_hash(key.tx, key.rx, key.to, key.ids);
+    if (table_insert(table, mask, ref_extra((uint32_t)i), key, h, src) < 0) atomicOr(flags, FLAG_TABLE_FULL);
+}
+
+// One wave per listed (source, face, edge).  Transmitter-side launch (src_rx
+// null): the transmitter's image in the face plane diffracts at the edge
+// toward every receiver of the grid cells near the edge (reflection then
+// diffraction).  Receiver-side launch: the receiver's image in the face plane
+// receives the diffraction of every transmitter (diffraction then
+// reflection).  The Keller test is the construction's own, so no valid path
+// is lost.
+__global__ void __launch_bounds__(256) k_pair_cand(PathArgs a, const unsigned long long* list,
+                                                   const unsigned long long* n_list, RxBins bins, const int* src_rx,
+                                                   ExtraKeys xk, unsigned long long* table, unsigned long long mask,
+                                                   KeySrc src) {
+    const long long n = (long long)*n_list;
+    const int lane = lane_id();
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long n_waves = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long k = wave; k < n; k += n_waves) {
+        const uint64_t v = list[k];
+        const int source = (int)((v >> 48) & 0x7FFFULL), f = (int)((v >> 24) & 0xFFFFFFULL), e = (int)(v & 0xFFFFFFULL);
+        if (f >= a.s.F || e >= a.s.E) continue;
+        const Wedge w = wedge_of(a.s, e);
+        if (f == w.f0 || f == w.fn) continue;
+        const double* pl = a.s.plane + 4 * (long long)f;
+        if (!src_rx) {
+            if (source >= a.f.n_tx) continue;
+            const RxGrid gr = *bins.grid;
+            const dv3 img = mirror(ldd3(a.f.tx_pos + 3 * source), pl);
+            dv3 P1 = w.P0 + w.e * w.len;
+            float g = (float)a.diff_max_leg + 1.0f;
+            float qlx = (float)fmin(w.P0.x, P1.x) - g, qly = (float)fmin(w.P0.y, P1.y) - g, qlz = (float)fmin(w.P0.z, P1.z) - g;
+            float qhx = (float)fmax(w.P0.x, P1.x) + g, qhy = (float)fmax(w.P0.y, P1.y) + g, qhz = (float)fmax(w.P0.z, P1.z) + g;
+            int cx0 = grid_cell(qlx, gr.x0, gr.inv_h), cx1 = grid_cell(qhx, gr.x0, gr.inv_h);
+            int cy0 = grid_cell(qly, gr.y0, gr.inv_h), cy1 = grid_cell(qhy, gr.y0, gr.inv_h);
+            for (int cy = cy0; cy <= cy1; cy++) {
+                uint32_t j0 = bins.start[cy * kGridN + cx0], j1 = bins.start[cy * kGridN + cx1 + 1];
+                for (uint32_t j = j0 + (uint32_t)lane; j < j1; j += 64u) {
+                    float4 p = bins.sorted[j];
+                    if (!(p.x >= qlx && p.x <= qhx && p.y >= qly && p.y <= qhy && p.z >= qlz && p.z <= qhz)) continue;
+                    int rx = __float_as_int(p.w);
+                    dv3 Q;
+                    if (!keller(w, img, ldd3(a.f.rx_pos + 3 * rx), a.diff_max_leg, Q)) continue;
+                    KeyRec key;
+                    key.tx = source; key.rx = rx; key.to = KT_RD | (2 << 8);
+                    key.ids[0] = f; key.ids[1] = e; key.ids[2] = key.ids[3] = key.ids[4] = -1;
+                    extra_insert(xk, key, table, mask, src, a.flags);
+                }
+            }
+        } else {
+            const int rx = src_rx[source];
+            const dv3 img = mirror(ldd3(a.f.rx_pos + 3 * rx), pl);
+            for (int tx = lane; tx < a.f.n_tx; tx += 64) {
+                dv3 Q;
+                if (!keller(w, ldd3(a.f.tx_pos + 3 * tx), img, a.diff_max_leg, Q)) continue;
+                KeyRec key;
+                key.tx = tx; key.rx = rx; key.to = KT_DR | (2 << 8);
+                key.ids[0] = e; key.ids[1] = f; key.ids[2] = key.ids[3] = key.ids[4] = -1;
+                extra_insert(xk, key, table, mask, src, a.flags);
+            }
+        }
+    }
+}
+
+void pair_candidates(const PathArgs& a, const unsigned long long* set, long long n_slots, unsigned long long* list,
+                     unsigned long long* n_list, const RxBins& bins, const int* src_rx, const ExtraKeys& xk,
+                     unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st) {
+    if (n_slots <= 0) return;
+    hipLaunchKernelGGL(k_pair_list, dim3(grid_for(n_slots, 256, 4096)), dim3(256), 0, st, set, n_slots, list, n_list);
+    hipLaunchKernelGGL(k_pair_cand, dim3(4096), dim3(256), 0, st, a, list, n_list, bins, src_rx, xk, table, mask,
+                       src);
+}
+
 // Receiver positions of a receiver-side launch, gathered as its sources.
 __global__ void k_gather_rx(const double* rx_pos, const int* sel, int n, double* out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -374,6 +472,9 @@ __device__ __forceinline__ bool key_in_range(const PathArgs& a, const KeyRec& ke
             if (j < order && !(key.ids[j] >= 0 && key.ids[j] < a.s.F)) good = false;
     } else if (type == KT_DIFF) {
         good = good && order == 1 && key.ids[0] >= 0 && key.ids[0] < a.s.E;
+    } else if (type == KT_RD || type == KT_DR) {
+        const int f = type == KT_RD ? key.ids[0] : key.ids[1], e = type == KT_RD ? key.ids[1] : key.ids[0];
+        good = good && order == 2 && f >= 0 && f < a.s.F && e >= 0 && e < a.s.E;
     } else if (type != KT_LOS) {
         good = false;
     }
@@ -386,7 +487,10 @@ __device__ __forceinline__ bool key_in_range(const PathArgs& a, const KeyRec& ke
 //   back from Rx, x_k = segment(x_{k+1} -> s_k) meets plane f_k at a
 //   parameter in (0, 1) and lies in a triangle of f_k (lowest id reported);
 //   diffraction: Keller point strictly inside the edge, both ends in the
-//   exterior wedge, receiver leg within diff_max_leg.
+//   exterior wedge, receiver leg within diff_max_leg;
+//   reflection then diffraction / diffraction then reflection: the same with
+//   the image of Tx / of Rx in the face plane, plus the reflection point's
+//   parameter in (0, 1) and its face (not a face of the wedge).
 __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, Built& g) {
 #pragma clang fp contract(off)
     const SceneDev& S = a.s;
@@ -405,6 +509,34 @@ __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, 
         g.np = 3;
         g.w = wedge_of(S, key.ids[0]);
         return keller(g.w, s, g.R, a.diff_max_leg, g.P[1]);
+    }
+    if (g.type == KT_RD || g.type == KT_DR) {
+        // one reflection unfolded by the image of Tx (reflection first) or of
+        // Rx (diffraction first); the Keller point joins the real end to the
+        // image, the reflection point is where the segment from the Keller
+        // point to the image crosses the face plane
+        const bool rd = g.type == KT_RD;
+        const int f = rd ? key.ids[0] : key.ids[1];
+        g.np = 4;
+        g.w = wedge_of(S, rd ? key.ids[1] : key.ids[0]);
+        if (f == g.w.f0 || f == g.w.fn) return false;
+        const double* pl = S.plane + 4 * (long long)f;
+        const dv3 img = rd ? mirror(s, pl) : mirror(g.R, pl);
+        dv3 Q;
+        if (!keller(g.w, rd ? img : s, rd ? g.R : img, a.diff_max_leg, Q)) return false;
+        dv3 nrm = d3(pl[0], pl[1], pl[2]);
+        dv3 dv = img - Q;
+        double den = dot(nrm, dv);
+        if (den == 0.0) return false;
+        double tt = (pl[3] - dot(nrm, Q)) / den;
+        if (!(tt > 0.0 && tt < 1.0)) return false;
+        dv3 P = Q + dv * tt;
+        int t = face_contains(a, f, P);
+        if (t < 0) return false;
+        g.P[1] = rd ? P : Q;
+        g.P[2] = rd ? Q : P;
+        g.tri[rd ? 0 : 1] = t;
+        return true;
     }
     const int order = g.order;
     g.np = order + 2;
@@ -435,12 +567,25 @@ __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, 
 
 // endpoints and excluded faces of leg i (compile-time i)
 template <int I>
-__device__ __forceinline__ void leg_of(const Built& g, const KeyRec& key, dv3& p0, dv3& p1, int& xa, int& xb) {
+__device__ __forceinline__ void leg_of(const Built& g, const KeyRec& key, dv3& p0, dv3& p1, int& xa, int& xb,
+                                       int& xc) {
     p0 = g.P[I];
     p1 = (I + 2 == g.np) ? g.R : g.P[I + 1 <= EMRT_KMAX + 1 ? I + 1 : EMRT_KMAX + 1];
+    xc = -1;
     if (g.type == KT_DIFF) {
         xa = g.w.f0;
         xb = g.w.fn;
+    } else if (g.type == KT_RD || g.type == KT_DR) {
+        // legs: Tx -> P -> Q -> Rx (RD) or Tx -> Q -> P -> Rx (DR); the faces
+        // at a leg's ends are excluded: the reflection face at P, the two
+        // wedge faces at Q
+        const bool rd = g.type == KT_RD;
+        const int f = rd ? key.ids[0] : key.ids[1];
+        const bool p_at_start = rd ? I == 1 : I == 2, p_at_end = rd ? I == 0 : I == 1;
+        const bool q_at_start = rd ? I == 2 : I == 1, q_at_end = rd ? I == 1 : I == 0;
+        xa = (p_at_start || p_at_end) ? f : -1;
+        xb = (q_at_start || q_at_end) ? g.w.f0 : -1;
+        xc = (q_at_start || q_at_end) ? g.w.fn : -1;
     } else if (g.type == KT_SPEC) {
         xa = I >= 1 ? key.ids[I >= 1 ? I - 1 : 0] : -1;
         xb = I + 1 <= g.order ? key.ids[I < EMRT_KMAX ? I : EMRT_KMAX - 1] : -1;
@@ -468,13 +613,14 @@ template <int I>
 __device__ __forceinline__ void write_leg(const PathArgs& a, const Built& g, const KeyRec& key, unsigned long long pos,
                                           uint32_t q) {
     dv3 p0, p1;
-    int xa, xb;
-    leg_of<I>(g, key, p0, p1, xa, xb);
+    int xa, xb, xc;
+    leg_of<I>(g, key, p0, p1, xa, xb, xc);
     dv3 d = p1 - p0;
     a.legs.ox[pos] = (float)p0.x; a.legs.oy[pos] = (float)p0.y; a.legs.oz[pos] = (float)p0.z;
     a.legs.dx[pos] = (float)d.x; a.legs.dy[pos] = (float)d.y; a.legs.dz[pos] = (float)d.z;
     a.legs.xa[pos] = xa;
     a.legs.xb[pos] = xb;
+    a.legs.xc[pos] = xc;
     a.legs.key[pos] = q;
 }
 
@@ -533,8 +679,8 @@ __global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
         uint32_t q = a.legs.key[i];
         if (a.occl[q]) continue;
         RayPre r = ray_pre(a.legs.ox[i], a.legs.oy[i], a.legs.oz[i], a.legs.dx[i], a.legs.dy[i], a.legs.dz[i]);
-        int xa = a.legs.xa[i], xb = a.legs.xb[i];
-        if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb) || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb))
+        int xa = a.legs.xa[i], xb = a.legs.xb[i], xc = a.legs.xc[i];
+        if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc) || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc))
             a.occl[q] = 1u;
     }
 }
@@ -547,30 +693,32 @@ __global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
 // slot from exclusive scans of 0/1 flags in key order, line of sight and
 // specular paths first, then diffraction paths, so each field kernel runs on
 // dense waves of one path type.
-__global__ void __launch_bounds__(256) k_valid_flags(PathArgs a, long long n_links, long long cap_cand,
-                                                     uint32_t* flag, uint32_t* flag_d) {
+__global__ void __launch_bounds__(256) k_valid_flags(PathArgs a, long long n_links, long long cap_cand, ValidTemp t) {
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     long long n = n_links + nc;
     GRID_STRIDE(q, n_links + cap_cand) {
         bool keep = q < n && a.state[q] && !a.occl[q];
-        bool d = keep && q >= n_links && (a.cand[q - n_links].to & 0xff) == KT_DIFF;
-        flag[q] = (keep && !d) ? 1u : 0u;
-        flag_d[q] = d ? 1u : 0u;
+        int type = keep && q >= n_links ? (a.cand[q - n_links].to & 0xff) : KT_LOS;
+        bool r = keep && type >= KT_RD, d = keep && type == KT_DIFF;
+        t.flag[q] = (keep && !d && !r) ? 1u : 0u;
+        t.flag_d[q] = d ? 1u : 0u;
+        t.flag_r[q] = r ? 1u : 0u;
     }
 }
 
 __global__ void __launch_bounds__(256) k_valid_list(ValidTemp t, long long n, unsigned long long* count) {
-    const uint32_t n0 = t.cnt[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count = (unsigned long long)n0 + t.cnt[1];
+    const uint32_t n0 = t.cnt[0], n1 = t.cnt[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = (unsigned long long)n0 + n1 + t.cnt[2];
     GRID_STRIDE(q, n) {
         if (t.flag[q]) t.surv[t.off[q]] = (uint32_t)q;
         else if (t.flag_d[q]) t.surv[n0 + t.off_d[q]] = (uint32_t)q;
+        else if (t.flag_r[q]) t.surv[n0 + n1 + t.off_r[q]] = (uint32_t)q;
     }
 }
 
 // Fields of the survivors of one kind (KIND 1: line of sight and specular,
-// 2: diffraction); the interaction points are rebuilt with the same formulas
+// 2: diffraction, 3: one reflection and one diffraction); the interaction points are rebuilt with the same formulas
 // as the construction (image method / Keller point), the reflection
 // triangles come from the construction.  Delay L / c; Doppler (Section
 // III-C, Eq (3) generalised to moving interaction points) -(1/lambda)
@@ -578,8 +726,9 @@ __global__ void __launch_bounds__(256) k_valid_list(ValidTemp t, long long n, un
 // directions of k_0 and -k_K.
 template <int KIND>
 __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, ValidTemp t) {
-    const long long lo = KIND == 1 ? 0 : (long long)t.cnt[0];
-    const long long hi = KIND == 1 ? (long long)t.cnt[0] : (long long)t.cnt[0] + t.cnt[1];
+    const long long c0 = t.cnt[0], c1 = c0 + t.cnt[1], c2 = c1 + t.cnt[2];
+    const long long lo = KIND == 1 ? 0 : (KIND == 2 ? c0 : c1);
+    const long long hi = KIND == 1 ? c0 : (KIND == 2 ? c1 : c2);
     const SceneDev& S = a.s;
     for (long long pos = lo + (long long)blockIdx.x * blockDim.x + threadIdx.x; pos < hi;
          pos += (long long)gridDim.x * blockDim.x) {
@@ -587,7 +736,7 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
         KeyRec key = key_at(a, q, n_links);
         dv3 sx = ldd3(a.f.tx_pos + 3 * key.tx), rx = ldd3(a.f.rx_pos + 3 * key.rx);
         PathGeo<double> pg;
-        path_points<double>(S, key, v3c<double>(sx), rx, pg);
+        path_points<double, KIND>(S, key, v3c<double>(sx), rx, pg);
         dv3 vt = ldd3(a.f.tx_vel + 3 * key.tx), vr = ldd3(a.f.rx_vel + 3 * key.rx);
         double th = a.f.tx_orient[2 * key.tx], phi = a.f.tx_orient[2 * key.tx + 1];
         V3<double> kk[EMRT_KMAX + 1];
@@ -609,14 +758,22 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
                 if (od >= 0) dop += dot(val3(kk[i - 1]) - val3(kk[i]), ldd3(a.f.obj_vel + 3 * (long long)od));
             }
         } else {
-            int od = S.face_dyn[S.edge_i[6 * (long long)key.ids[0] + 2]];
-            if (od >= 0) dop += dot(val3(kk[0]) - val3(kk[1]), ldd3(a.f.obj_vel + 3 * (long long)od));
+            // the edge at Q and, for one reflection with the diffraction, the face at P
+            const bool rd = pg.type == KT_RD, dr = pg.type == KT_DR;
+            const int iq = rd ? 1 : 0;
+            int od = S.face_dyn[S.edge_i[6 * (long long)(rd ? key.ids[1] : key.ids[0]) + 2]];
+            if (od >= 0) dop += dot(val3(kk[iq]) - val3(kk[iq + 1]), ldd3(a.f.obj_vel + 3 * (long long)od));
+            if (rd || dr) {
+                const int ip = rd ? 1 : 2;  // legs ip - 1 and ip meet at P
+                int of = S.face_dyn[rd ? key.ids[0] : key.ids[1]];
+                if (of >= 0) dop += dot(val3(kk[ip - 1]) - val3(kk[ip]), ldd3(a.f.obj_vel + 3 * (long long)of));
+            }
         }
         ValidPaths& o = a.out;
         o.key[pos] = key;
 #pragma unroll
         for (int j = 0; j < 5; j++)
-            o.tri[5 * pos + j] = (KIND == 1 && pg.type == KT_SPEC) ? a.ktri[5 * q + j] : -1;
+            o.tri[5 * pos + j] = (pg.type == KT_SPEC || pg.type >= KT_RD) ? a.ktri[5 * q + j] : -1;
         for (int fi = 0; fi < a.fc.nf; fi++) {
             double lam = kC0 / a.fc.freq[fi];
             o.a[2 * (pos * a.fc.nf + fi)] = amp[fi].re;
@@ -635,12 +792,14 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
     hipLaunchKernelGGL(k_construct, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
     hipLaunchKernelGGL(k_shadow, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
     int g = grid_for(n, 256, 16384);
-    hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t.flag, t.flag_d);
+    hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t);
     exclusive_scan(t.flag, t.off, n, t.scan_tmp, t.cnt, st);
     exclusive_scan(t.flag_d, t.off_d, n, t.scan_tmp, t.cnt + 1, st);
+    exclusive_scan(t.flag_r, t.off_r, n, t.scan_tmp, t.cnt + 2, st);
     hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t, n, a.out.count);
     hipLaunchKernelGGL(k_fields<1>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
     hipLaunchKernelGGL(k_fields<2>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
+    hipLaunchKernelGGL(k_fields<3>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
 }
 
 // ----------------------------------------------------------- per link ----

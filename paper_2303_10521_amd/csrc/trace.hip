@@ -178,11 +178,13 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
         });
     }
 
-    // edge capture on the first segment
-    if (act && b == 0 && a.diffraction && a.edt.n_prims > 0) {
+    // edge capture on the first segment (and, for reflection-diffraction
+    // paths, on the second): radius k_rx alpha (L + s) as for receivers
+    if (act && (b == 0 || (b == 1 && a.diffraction == 2)) && a.diffraction && a.edt.n_prims > 0) {
         float tcap = fminf(t_end, root_far(a.edt, ox, oy, oz));
-        float grow = a.alpha_k * tcap;
+        float grow = a.alpha_k * (L + tcap);
         const int source = (int)(id / (uint32_t)a.rays_per_tx);  // row of the illumination bitmap
+        const int face1 = b == 1 ? a.src.tri_face[a.hitlog[id]] : -1;  // face of the first reflection
         all_hits(a.edt, r, tcap, grow, [&](int slot) {
             float4 P0 = a.edge_prims[2 * slot], P1 = a.edge_prims[2 * slot + 1];
             float ex = P1.x - P0.x, ey = P1.y - P0.y, ez = P1.z - P0.z;
@@ -200,12 +202,16 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             float qx = ox + s * dx - (P0.x + u * ex);
             float qy = oy + s * dy - (P0.y + u * ey);
             float qz = oz + s * dz - (P0.z + u * ez);
-            float re = a.alpha_k * s;
+            float re = a.alpha_k * (L + s);
             if (!(qx * qx + qy * qy + qz * qz < re * re)) return;
             int e = __float_as_int(P0.w);
-            uint32_t* w = a.illum + (long long)source * a.e_words + (e >> 5);
-            uint32_t bit = 1u << (e & 31);
-            if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(w, bit);
+            if (b == 0) {
+                uint32_t* w = a.illum + (long long)source * a.e_words + (e >> 5);
+                uint32_t bit = 1u << (e & 31);
+                if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(w, bit);
+            } else if (!pair_insert(a.pairs, a.pair_mask, pair_key(source, face1, e))) {
+                atomicOr(a.flags, FLAG_CAND_CAP);
+            }
         });
     }
 

@@ -55,6 +55,8 @@ def test_config_defaults(lib):
     (dict(rx_sphere_k=0.0), A.EMRT_E_INVALID),
     (dict(path_capacity=0), A.EMRT_E_INVALID),
     (dict(antenna_mode=7), A.EMRT_E_INVALID),
+    (dict(diffraction=3), A.EMRT_E_INVALID),
+    (dict(diffraction=2), A.EMRT_E_UNSUPPORTED),
 ])
 def test_ctx_create_rejects_bad_config(lib, kw, status):
     c = _cfg(lib, **kw)
