@@ -28,6 +28,9 @@
 
 namespace emrt {
 
+// KIND 0: every path type; 4: all but one reflection with one diffraction
+// (the configurations that cannot produce them compile without that code).
+template <int KIND>
 __global__ void __launch_bounds__(128) k_adj_links(AdjArgs a) {
     const SceneDev& S = a.s;
     const long long nl = a.n_links;
@@ -56,11 +59,11 @@ __global__ void __launch_bounds__(128) k_adj_links(AdjArgs a) {
                 DN th = dn_seed(a.tx_orient[2 * key.tx], 3), ph = dn_seed(a.tx_orient[2 * key.tx + 1], 4);
                 dv3 rx = ldd3(a.rx_pos + 3 * key.rx);
                 PathGeo<DN> gd;
-                path_points<DN>(S, key, s, rx, gd);
+                path_points<DN, KIND>(S, key, s, rx, gd);
                 V3<DN> kk[EMRT_KMAX + 1];
                 DN L;
                 Cx<DN> amp[EMRT_NF];
-                path_field<DN>(S, a.fc, key, gd, th, ph, 0, kk, L, amp);
+                path_field<DN, KIND>(S, a.fc, key, gd, th, ph, 0, kk, L, amp);
                 for (int f = 0; f < a.fc.nf; f++) {
 #pragma unroll
                     for (int k = 0; k < kTan; k++) acc[k] += g[f].re * amp[f].re.d[k] + g[f].im * amp[f].im.d[k];
@@ -85,7 +88,7 @@ __global__ void __launch_bounds__(128) k_adj_links(AdjArgs a) {
                     V3<double> kv[EMRT_KMAX + 1];
                     double Lv;
                     Cx<double> da[EMRT_NF];
-                    path_field<double>(S, a.fc, key, gv, th.v, ph.v, md, kv, Lv, da);
+                    path_field<double, KIND>(S, a.fc, key, gv, th.v, ph.v, md, kv, Lv, da);
                     double re = 0.0, im = 0.0;
                     for (int f = 0; f < a.fc.nf; f++) {
                         re += g[f].re * da[f].re + g[f].im * da[f].im;
@@ -139,7 +142,8 @@ void adjoint(const AdjArgs& a, int n_tx, int n_rx, double* g_pos, double* g_ori,
     long long g = (a.n_links + 127) / 128;
     if (g < 1) g = 1;
     if (g > 16384) g = 16384;
-    hipLaunchKernelGGL(k_adj_links, dim3((unsigned)g), dim3(128), 0, st, a);
+    if (a.combined) hipLaunchKernelGGL(k_adj_links<0>, dim3((unsigned)g), dim3(128), 0, st, a);
+    else hipLaunchKernelGGL(k_adj_links<4>, dim3((unsigned)g), dim3(128), 0, st, a);
     hipLaunchKernelGGL(k_adj_reduce, dim3(5 * n_tx + 2 * a.M), dim3(256), 0, st, a.rows, a.n_links, n_rx, n_tx, g_pos,
                        g_ori, g_eps);
 }

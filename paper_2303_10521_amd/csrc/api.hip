@@ -637,6 +637,7 @@ static PathArgs path_args(emrt_ctx* c) {
     for (int i = 0; i < EMRT_NF; i++) a.fc.freq[i] = i < c->nf ? c->cfg.freq_hz[i] : 1.0;
     a.fc.ant_mode = c->cfg.antenna_mode;
     a.diff_max_leg = c->cfg.diff_max_leg_m;
+    a.combined = c->cfg.diffraction == 2 ? 1 : 0;
     a.out = c->vp;
     a.legs = c->legs;
     a.legs.count = c->ctr + C_NLEGS;
@@ -894,6 +895,7 @@ int32_t emrt_backward(emrt_ctx* c, const double* dL_dH, const double* dL_dP, dou
     a.p_tx = c->cfg.tx_power_w;
     a.n_links = c->n_links;
     a.M = c->S.M;
+    a.combined = c->cfg.diffraction == 2 ? 1 : 0;
     a.rows = c->adj_rows;
     adjoint(a, c->sz.n_tx, c->sz.n_rx, grad_tx_pos, grad_tx_orient, grad_eps, c->stream);
     return hip_check(c, hipGetLastError(), "backward");

@@ -197,6 +197,7 @@ struct PathArgs {
     const TriP* dy_prims;
     FieldCtx fc;
     double diff_max_leg;
+    int combined;     // one reflection with one diffraction in use (types 3 and 4 valid)
     // inputs
     const KeyRec* cand;
     const unsigned long long* n_cand;
@@ -317,6 +318,7 @@ struct AdjArgs {
     double p_tx;
     long long n_links;
     int M;                    // materials
+    int combined;             // paths with one reflection and one diffraction can occur
     double* rows;             // [5 + 2 M][n_links] per-link partial gradients
 };
 void adjoint(const AdjArgs& a, int n_tx, int n_rx, double* g_pos, double* g_ori, double* g_eps, hipStream_t st);

@@ -481,7 +481,8 @@ struct PathGeo {
 // Keller point for diffraction.  Used by the adjoint, where the derivatives
 // of the points with respect to the transmitter flow through R.
 // KIND (as for path_field): 0 any type, 1 line of sight / specular only,
-// 2 diffraction alone only, 3 one reflection and one diffraction only.
+// 2 diffraction alone only, 3 one reflection and one diffraction only,
+// 4 any type but the last.
 template <class R, int KIND = 0>
 __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key, V3<R> s, dv3 rx, PathGeo<R>& g) {
 #pragma clang fp contract(off)
@@ -493,7 +494,7 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
         g.np = 2;
         return;
     }
-    if ((KIND == 0 || KIND == 2) && g.type == KT_DIFF) {
+    if ((KIND == 0 || KIND == 2 || KIND == 4) && g.type == KT_DIFF) {
         g.np = 3;
         Wedge w = wedge_of(S, key.ids[0]);
         R zs = dot3(w.e, s - w.P0);
@@ -556,9 +557,11 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
 // Leg directions k_i, the unfolded length L and the complex amplitude of
 // every carrier.  dmode = 0: the field; dmode = i >= 1 (specular): the
 // derivative with respect to the permittivity of bounce i's material;
-// dmode = 1 / 2 (diffraction): with respect to the 0-face / n-face material.
-// KIND = 1 / 2 compiles only the line-of-sight-and-specular / diffraction
-// branch (the caller guarantees the path type); 0 keeps both.
+// dmode = 1 / 2 (diffraction): with respect to the 0-face / n-face material,
+// 3 (one reflection with one diffraction): the reflection face's.
+// KIND = 1 / 2 / 3 compiles only the line-of-sight-and-specular / the
+// diffraction-alone / the combined paths (the caller guarantees the path
+// type); 4 all but the combined paths; 0 everything.
 // Reflection of the complex field vector E travelling along ki into ko at
 // face f, in the bounce's s/p basis (s = normalize(ki x n), n against ki;
 // normal incidence: n x z, else n x x): E <- Gamma_TE (E.s) s +
@@ -605,7 +608,7 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
 #pragma unroll
     for (int i = 1; i <= EMRT_KMAX; i++)
         if (i == nlegs - 1) kK = kk[i];
-    const bool diffracted = KIND >= 2 ? true : (KIND == 1 ? false : g.type >= KT_DIFF);
+    const bool diffracted = (KIND == 2 || KIND == 3) ? true : (KIND == 1 ? false : g.type >= KT_DIFF);
     if (!diffracted) {
         V3<R> e0 = antenna_x<R>(fc.ant_mode, k0, th, phi);
         V3<R> er = antenna_x<R>(0, kK, rl<R>(0.0), rl<R>(0.0));
@@ -626,8 +629,9 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
         // receiver side of the Keller point Q; the reflection acts on the field
         // vector arriving at Q (RD) or leaving it (DR).  dmode 1 / 2: the wedge
         // faces' permittivity derivative, 3: the reflection face's.
-        // KIND 2 / 3 compile only the diffraction-alone / the combined paths
-        const bool rd = KIND != 2 && g.type == KT_RD, dr = KIND != 2 && g.type == KT_DR;
+        // KIND 2 and 4 leave the combined paths out, KIND 3 the diffraction alone
+        const bool comb = KIND == 0 || KIND == 3;
+        const bool rd = comb && g.type == KT_RD, dr = comb && g.type == KT_DR;
         Wedge w = wedge_of(S, rd ? key.ids[1] : key.ids[0]);
         const int iq = rd ? 1 : 0;  // leg arriving at Q
         V3<R> si = kk[iq], so = kk[iq + 1];

@@ -474,7 +474,7 @@ __device__ __forceinline__ bool key_in_range(const PathArgs& a, const KeyRec& ke
         good = good && order == 1 && key.ids[0] >= 0 && key.ids[0] < a.s.E;
     } else if (type == KT_RD || type == KT_DR) {
         const int f = type == KT_RD ? key.ids[0] : key.ids[1], e = type == KT_RD ? key.ids[1] : key.ids[0];
-        good = good && order == 2 && f >= 0 && f < a.s.F && e >= 0 && e < a.s.E;
+        good = good && a.combined && order == 2 && f >= 0 && f < a.s.F && e >= 0 && e < a.s.E;
     } else if (type != KT_LOS) {
         good = false;
     }
@@ -795,11 +795,13 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
     hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t);
     exclusive_scan(t.flag, t.off, n, t.scan_tmp, t.cnt, st);
     exclusive_scan(t.flag_d, t.off_d, n, t.scan_tmp, t.cnt + 1, st);
-    exclusive_scan(t.flag_r, t.off_r, n, t.scan_tmp, t.cnt + 2, st);
+    if (a.combined) exclusive_scan(t.flag_r, t.off_r, n, t.scan_tmp, t.cnt + 2, st);
+    else fill_u32(t.cnt + 2, 0u, 1, st);  // no combined keys pass key_in_range
     hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t, n, a.out.count);
     hipLaunchKernelGGL(k_fields<1>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
     hipLaunchKernelGGL(k_fields<2>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
-    hipLaunchKernelGGL(k_fields<3>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
+    if (a.combined)
+        hipLaunchKernelGGL(k_fields<3>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
 }
 
 // ----------------------------------------------------------- per link ----
