@@ -8,8 +8,8 @@
 // its parent link and the split axis (the Morton bit at which its range
 // splits), which the traversal uses to visit the near child first.
 // Refit: one thread per leaf climbs towards the root; the second thread to
-// arrive at a node (device-scope atomic counter) merges the two child boxes
-// and continues, so every node is written exactly once per refit.
+// arrive at a node (device-scope acquire-release counter) merges the two
+// child boxes and continues, so every node is written exactly once per refit.
 // Paper: Section II-A (a BVH updated between frames), Section III-A (only
 // subtrees change within a trajectory segment).
 #include "emrt_dev.h"
@@ -159,10 +159,9 @@ __global__ void __launch_bounds__(256) k_refit(const float* box, const uint32_t*
             __hip_atomic_store(dst + c, lo[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(dst + 3 + c, hi[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __threadfence();
-        uint32_t old = atomicAdd(&counters[idx], 1u);
+        // release our box, acquire the sibling's: the second arrival sees both
+        uint32_t old = __hip_atomic_fetch_add(&counters[idx], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0u) return;
-        __threadfence();
         const float* o = nb + (side ? 0 : 6);
         for (int c = 0; c < 3; c++) {
             lo[c] = fminf(lo[c], aload(o + c));

@@ -91,6 +91,33 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(const uint32_t* in,
     }
 }
 
+// single block over a short array: tile by tile with a running carry, so a
+// scan of up to kScanSmall values is one launch instead of three
+constexpr long long kScanSmall = 16LL * SCAN_TILE;
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_small(const uint32_t* in, uint32_t* out, long long n,
+                                                            uint32_t* grand) {
+    __shared__ uint32_t sh[4];
+    uint32_t carry = 0;
+    for (long long base = 0; base < n; base += SCAN_TILE) {
+        uint32_t v[SCAN_ITEMS];
+        uint32_t s = 0;
+        for (int i = 0; i < SCAN_ITEMS; i++) {
+            long long k = base + (long long)threadIdx.x * SCAN_ITEMS + i;
+            v[i] = k < n ? in[k] : 0;
+            s += v[i];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_scan(s, sh, total) + carry;
+        for (int i = 0; i < SCAN_ITEMS; i++) {
+            long long k = base + (long long)threadIdx.x * SCAN_ITEMS + i;
+            if (k < n) out[k] = ex;
+            ex += v[i];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0 && grand) *grand = carry;
+}
+
 size_t scan_temp_bytes(long long n) { return sizeof(uint32_t) * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 1); }
 
 void exclusive_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* temp, uint32_t* grand,
@@ -98,6 +125,10 @@ void exclusive_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* te
     int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
     if (nb == 0) {
         if (grand) hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, st, temp, 0, grand);
+        return;
+    }
+    if (n <= kScanSmall) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SCAN_THREADS), 0, st, in, out, n, grand);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, st, in, n, temp);
