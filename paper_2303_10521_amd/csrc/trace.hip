@@ -252,11 +252,11 @@ __device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane,
     }
 }
 
-// Persistent: waves pull 64-ray chunks from a device counter.  Held to 80
-// VGPRs (six waves per SIMD instead of five at 93): 2% faster on the city's
-// bounces at the cost of a 36-byte spill; seven waves (72 VGPRs) gained nothing.
+// Persistent: waves pull 64-ray chunks from a device counter.  (Holding it to
+// six waves per SIMD with an 80-VGPR cap ran 1-2% faster but spilled 36 bytes
+// per lane, which raised its HBM traffic by 22%; it stays at the compiler's 93.)
 template <bool STATS, bool REV>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_bounce(BounceArgs a) {
+__global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
