@@ -207,6 +207,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
         t.leaf_parent = cv.take<int>(n);
         t.counters = cv.take<uint32_t>(ni);
         t.perm = cv.take<uint32_t>(n);
+        t.span = cv.take<int>(ni);
         t.cap = (int)n;
     };
     tree(c->st, T);
@@ -338,6 +339,7 @@ static void derive(emrt_ctx* c) {
     c->e_words = (c->E_cap + 31) / 32;
     long long b = std::max<long long>({z.n_tris, (long long)c->E_cap, (long long)z.n_rx, (long long)z.n_tx,
                                        (long long)c->cfg.rays_per_tx, z.n_faces, z.n_objects, 16LL});
+    b = std::max<long long>(b, z.n_tris + c->E_cap + std::max<long long>(z.n_rx, z.n_tx));  // one batched build
     c->bcap = b;
     c->pair_slots = c->cfg.diffraction == 2 ? pow2_at_least(std::max<int64_t>(c->cfg.table_capacity / 4, 1 << 16)) : 0;
 }
@@ -723,30 +725,32 @@ static void step_pre(emrt_ctx* c, int discover) {
     scene_world(S, c->f_xf, c->flags, st);
     scene_planes(S, st);
     scene_face_tv(S, st);
-    if (S.T_d > 0) {
-        tri_boxes(S, S.tris_dynamic, S.T_d, c->box_dy, st);
-        if (discover || c->dy.n != S.T_d) bvh_build(c->box_dy, S.T_d, c->dy, c->tmp, st);
-        else bvh_refit(c->box_dy, c->dy, st);
-        tri_prims(S, S.tris_dynamic, c->dy, c->dy_prims, st);
-    }
     // capture trees: only the bounce kernel reads them, so cached frames skip them
     const bool rev = discover && c->rev_n > 0;
+    bool diff = c->cfg.diffraction && S.E > 0;
+    const bool build_dy = S.T_d > 0 && (discover || c->dy.n != S.T_d);
+    BuildJob jobs[3];
+    int nj = 0;
+    if (S.T_d > 0) tri_boxes(S, S.tris_dynamic, S.T_d, c->box_dy, st);
+    if (build_dy) jobs[nj++] = BuildJob{c->box_dy, S.T_d, &c->dy};
     if (discover && !rev) {  // spheres on the receivers
         rx_boxes(c->f_rx, c->sz.n_rx, c->box_rx, st);
-        bvh_build(c->box_rx, c->sz.n_rx, c->rxt, c->tmp, st);
-        rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
+        jobs[nj++] = BuildJob{c->box_rx, c->sz.n_rx, &c->rxt};
     }
     if (rev) {  // spheres on the transmitters
         rx_boxes(c->f_tx, c->sz.n_tx, c->box_tx, st);
-        bvh_build(c->box_tx, c->sz.n_tx, c->txt, c->tmp, st);
-        rx_prims(c->f_tx, c->txt, c->tx_prims, st);
+        jobs[nj++] = BuildJob{c->box_tx, c->sz.n_tx, &c->txt};
     }
-    bool diff = c->cfg.diffraction && S.E > 0;
     if (diff && discover) {
         edge_boxes(S, c->box_ed, st);
-        bvh_build(c->box_ed, S.E, c->edt, c->tmp, st);
-        edge_prims(S, c->edt, c->edge_prims, st);
+        jobs[nj++] = BuildJob{c->box_ed, S.E, &c->edt};
     }
+    bvh_build_many(jobs, nj, c->tmp, st);  // the frame's rebuilt trees, in one batch
+    if (S.T_d > 0 && !build_dy) bvh_refit(c->box_dy, c->dy, st);
+    if (S.T_d > 0) tri_prims(S, S.tris_dynamic, c->dy, c->dy_prims, st);
+    if (discover && !rev) rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
+    if (rev) rx_prims(c->f_tx, c->txt, c->tx_prims, st);
+    if (diff && discover) edge_prims(S, c->edt, c->edge_prims, st);
     if (discover) {
         KeySrc src = key_src(c, c->cache[c->cur]);
         const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
@@ -815,8 +819,9 @@ static void step_post(emrt_ctx* c, int discover) {
     int which = radix_sort(c->sk0, c->sv0, c->sk1, c->sv1, (const long long*)c->vp.count, c->vcap, bits_for(c->n_links),
                            c->sort_tmp, st);
     unsigned long long* skeys = which ? c->sk1 : c->sk0;
-    c->order = which ? c->sv1 : c->sv0;
     link_ranges(skeys, c->vp.count, c->vcap, c->link_start, c->link_end, c->n_links, st);
+    link_rank(c->vp, skeys, which ? c->sv1 : c->sv0, c->link_start, c->link_end, which ? c->sv0 : c->sv1, st);
+    c->order = which ? c->sv0 : c->sv1;
     link_reduce(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->nf, c->cfg.tx_power_w, c->chan, st);
     // ---- coherence statistics over frames (Section III-B)
     coherence_update(c->coh, c->vp, c->order, c->link_start, c->link_end, c->chan, c->n_links, c->nf, st);

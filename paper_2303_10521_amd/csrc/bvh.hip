@@ -1,12 +1,16 @@
 // bvh.hip -- linear BVH over arbitrary primitive boxes.
 //
-// Build: 63-bit Morton codes of box centroids (21 bits per axis over the
-// centroid bounds), LSD radix sort, Karras-style hierarchy emission
+// Build: Morton codes of box centroids (b bits per axis over the centroid
+// bounds, b growing with the primitive count: 10 up to 2^18 primitives), LSD
+// radix sort, Karras-style hierarchy emission
 // (T. Karras, "Maximizing parallelism in the construction of BVHs, octrees
 // and k-d trees", HPG 2012) with ties between equal codes broken by the sorted
 // index, then a bottom-up refit.  Each internal node stores both child boxes,
 // its parent link and the split axis (the Morton bit at which its range
 // splits), which the traversal uses to visit the near child first.
+// Up to four trees build in one batch: the tree number sits above the Morton
+// bits, so one sort orders every tree's primitives into its own contiguous
+// segment, and each later launch (emission, refit) covers all the trees.
 // Refit: one thread per leaf climbs towards the root; the second thread to
 // arrive at a node (device-scope acquire-release counter) merges the two
 // child boxes and continues, so every node is written exactly once per refit.
@@ -38,47 +42,78 @@ __device__ __forceinline__ unsigned long long split3(uint32_t a) {
 
 __global__ void k_fill_zero1(uint32_t* p) { *p = 0u; }
 
-__global__ void k_init_bounds(uint32_t* b) {
-    int t = threadIdx.x;
-    if (t < 3) b[t] = 0xFFFFFFFFu;
-    else if (t < 6) b[t] = 0u;
+// The trees of one batched build: tree j owns the sorted positions
+// [off[j], off[j + 1]).
+struct BuildSet {
+    const float* box[kMaxBuildJobs];
+    BNode* nodes[kMaxBuildJobs];
+    int* leaf_parent[kMaxBuildJobs];
+    uint32_t* perm[kMaxBuildJobs];
+    uint32_t* counters[kMaxBuildJobs];
+    int* span[kMaxBuildJobs];
+    int off[kMaxBuildJobs + 1];
+    int nj;
+    int bits;  // Morton bits per axis
+};
+
+struct RefitBlocks {
+    int blk[kMaxBuildJobs + 1];  // first block of each tree
+};
+
+__device__ __forceinline__ int job_of(const BuildSet& S, int i) {
+    int j = 0;
+    while (j + 1 < S.nj && i >= S.off[j + 1]) j++;
+    return j;
 }
 
-__global__ void __launch_bounds__(256) k_bounds(const float* box, int n, uint32_t* b) {
-    __shared__ uint32_t sh[6];
-    if (threadIdx.x < 3) sh[threadIdx.x] = 0xFFFFFFFFu;
-    else if (threadIdx.x < 6) sh[threadIdx.x] = 0u;
+__global__ void k_init_bounds(uint32_t* b, int nj) {
+    int t = threadIdx.x;
+    if (t < 6 * nj) b[t] = (t % 6) < 3 ? 0xFFFFFFFFu : 0u;
+}
+
+// centroid bounds of every tree (ordered-integer min/max), [nj][6]
+__global__ void __launch_bounds__(256) k_bounds(BuildSet S, uint32_t* b) {
+    __shared__ uint32_t sh[6 * kMaxBuildJobs];
+    if (threadIdx.x < 6 * kMaxBuildJobs) sh[threadIdx.x] = (threadIdx.x % 6) < 3 ? 0xFFFFFFFFu : 0u;
     __syncthreads();
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const float* p = box + 6 * (long long)i;
+    if (i < S.off[S.nj]) {
+        int j = job_of(S, i);
+        const float* p = S.box[j] + 6 * (long long)(i - S.off[j]);
         for (int c = 0; c < 3; c++) {
             float m = 0.5f * (p[c] + p[3 + c]);
-            atomicMin(&sh[c], f2ord(m));
-            atomicMax(&sh[3 + c], f2ord(m));
+            atomicMin(&sh[6 * j + c], f2ord(m));
+            atomicMax(&sh[6 * j + 3 + c], f2ord(m));
         }
     }
     __syncthreads();
-    if (threadIdx.x < 3) atomicMin(&b[threadIdx.x], sh[threadIdx.x]);
-    else if (threadIdx.x < 6) atomicMax(&b[threadIdx.x], sh[threadIdx.x]);
+    int t = threadIdx.x;
+    if (t < 6 * S.nj) {
+        if ((t % 6) < 3) atomicMin(&b[t], sh[t]);
+        else atomicMax(&b[t], sh[t]);
+    }
 }
 
-__global__ void __launch_bounds__(256) k_morton(const float* box, int n, const uint32_t* b, unsigned long long* codes,
+// key = tree number above 3 * bits Morton bits; value = primitive index
+__global__ void __launch_bounds__(256) k_morton(BuildSet S, const uint32_t* b, unsigned long long* codes,
                                                 uint32_t* vals) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float* p = box + 6 * (long long)i;
+    if (i >= S.off[S.nj]) return;
+    int j = job_of(S, i);
+    int li = i - S.off[j];
+    const float* p = S.box[j] + 6 * (long long)li;
+    const float scale = (float)((1u << S.bits) - 1u);
     uint32_t q[3];
     for (int c = 0; c < 3; c++) {
-        float lo = ord2f(b[c]), hi = ord2f(b[3 + c]);
+        float lo = ord2f(b[6 * j + c]), hi = ord2f(b[6 * j + 3 + c]);
         float m = 0.5f * (p[c] + p[3 + c]);
         float e = hi - lo;
         float u = e > 0.0f ? (m - lo) / e : 0.5f;
         u = fminf(fmaxf(u, 0.0f), 1.0f);
-        q[c] = (uint32_t)(u * 2097151.0f);
+        q[c] = (uint32_t)(u * scale);
     }
-    codes[i] = (split3(q[0]) << 2) | (split3(q[1]) << 1) | split3(q[2]);
-    vals[i] = (uint32_t)i;
+    codes[i] = ((unsigned long long)j << (3 * S.bits)) | (split3(q[0]) << 2) | (split3(q[1]) << 1) | split3(q[2]);
+    vals[i] = (uint32_t)li;
 }
 
 __device__ __forceinline__ int kdelta(const unsigned long long* c, int n, int i, int j) {
@@ -88,9 +123,9 @@ __device__ __forceinline__ int kdelta(const unsigned long long* c, int n, int i,
     return __clzll((long long)(a ^ b));
 }
 
-__global__ void __launch_bounds__(256) k_emit(const unsigned long long* codes, const uint32_t* sorted, int n,
-                                              BNode* nodes, int* leaf_parent, uint32_t* perm) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Internal node i of one tree over its sorted codes [n] (and its leaf slot i).
+__device__ __forceinline__ void emit_node(const unsigned long long* codes, const uint32_t* sorted, int n, int i,
+                                          BNode* nodes, int* leaf_parent, uint32_t* perm, int* span) {
     if (i < n) perm[i] = sorted[i];
     if (n == 1 && i == 0) {
         BNode nd;
@@ -100,6 +135,7 @@ __global__ void __launch_bounds__(256) k_emit(const unsigned long long* codes, c
         nd.m = make_int4((int)EMRT_LEAF, (int)EMRT_LEAF, -1, 0);
         nodes[0] = nd;
         leaf_parent[0] = 0;
+        span[0] = 0;
         return;
     }
     if (i >= n - 1) return;
@@ -119,6 +155,7 @@ __global__ void __launch_bounds__(256) k_emit(const unsigned long long* codes, c
         if (kdelta(codes, n, i, i + (s + t) * d) > dnode) s += t;
     } while (t > 1);
     int gamma = i + s * d + (d < 0 ? -1 : 0);
+    span[i] = j;
     int lo = i < j ? i : j, hi = i < j ? j : i;
     int left = (lo == gamma) ? (int)(EMRT_LEAF | (uint32_t)gamma) : gamma;
     int right = (hi == gamma + 1) ? (int)(EMRT_LEAF | (uint32_t)(gamma + 1)) : gamma + 1;
@@ -139,37 +176,144 @@ __global__ void __launch_bounds__(256) k_emit(const unsigned long long* codes, c
     else ((int*)&nodes[gamma + 1].m)[2] = (int)((uint32_t)i | EMRT_SIDE);
 }
 
+__global__ void __launch_bounds__(256) k_emit(BuildSet S, const unsigned long long* codes, const uint32_t* sorted) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.off[S.nj]) return;
+    int j = job_of(S, i);
+    int o = S.off[j];
+    emit_node(codes + o, sorted + o, S.off[j + 1] - o, i - o, S.nodes[j], S.leaf_parent[j], S.perm[j], S.span[j]);
+}
+
 __device__ __forceinline__ float aload(const float* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) k_refit(const float* box, const uint32_t* perm, int n, BNode* nodes,
-                                               const int* leaf_parent, uint32_t* counters) {
-    int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n) return;
+// Leaf slot l climbs from its box towards the root (the second arrival at a
+// node merges both child boxes and goes on).  Nodes handed over between
+// threads of different blocks use device-scope atomics and a device-scope
+// acquire-release counter.
+__device__ __forceinline__ bool climb_global(float (&lo)[3], float (&hi)[3], int idx, int side, BNode* nodes,
+                                             uint32_t* counters) {
+    float* nb = (float*)&nodes[idx];
+    float* dst = nb + (side ? 6 : 0);
+    for (int c = 0; c < 3; c++) {
+        __hip_atomic_store(dst + c, lo[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + 3 + c, hi[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // release our box, acquire the sibling's: the second arrival sees both
+    uint32_t old = __hip_atomic_fetch_add(&counters[idx], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0u) return false;
+    const float* o = nb + (side ? 0 : 6);
+    for (int c = 0; c < 3; c++) {
+        lo[c] = fminf(lo[c], aload(o + c));
+        hi[c] = fmaxf(hi[c], aload(o + 3 + c));
+    }
+    return true;
+}
+
+__device__ __forceinline__ void refit_leaf(const float* box, const uint32_t* perm, int l, BNode* nodes,
+                                           const int* leaf_parent, uint32_t* counters) {
     const float* p = box + 6 * (long long)perm[l];
     float lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[3], p[4], p[5]};
     uint32_t par = (uint32_t)leaf_parent[l];
     while (true) {
         int idx = (int)(par & 0x7FFFFFFFu);
-        int side = (int)(par >> 31);
-        float* nb = (float*)&nodes[idx];
-        float* dst = nb + (side ? 6 : 0);
-        for (int c = 0; c < 3; c++) {
-            __hip_atomic_store(dst + c, lo[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(dst + 3 + c, hi[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // release our box, acquire the sibling's: the second arrival sees both
-        uint32_t old = __hip_atomic_fetch_add(&counters[idx], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0u) return;
-        const float* o = nb + (side ? 0 : 6);
-        for (int c = 0; c < 3; c++) {
-            lo[c] = fminf(lo[c], aload(o + c));
-            hi[c] = fmaxf(hi[c], aload(o + 3 + c));
-        }
+        if (!climb_global(lo, hi, idx, (int)(par >> 31), nodes, counters)) return;
         if (idx == 0) return;
         par = (uint32_t)__hip_atomic_load(&((int*)&nodes[idx].m)[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+__global__ void __launch_bounds__(256) k_refit(const float* box, const uint32_t* perm, int n, BNode* nodes,
+                                               const int* leaf_parent, uint32_t* counters) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n) refit_leaf(box, perm, l, nodes, leaf_parent, counters);
+}
+
+// LBVH refit in two tiers.  A block owns the leaf slots [b0, b0 + 256); an
+// internal node whose leaf range lies inside them (a Karras node is one end of
+// its own range, so its number lies inside too) is merged in LDS under a
+// workgroup-scope counter, and only the nodes whose range leaves the block
+// take the device-scope hand-over above.  Once a climb leaves its block every
+// ancestor's range does too.
+constexpr int kRefitTile = 256;
+
+__device__ __forceinline__ void refit_leaf_lbvh(const float* box, const uint32_t* perm, int l, int b0, int b1,
+                                                BNode* nodes, const int* leaf_parent, const int* span,
+                                                uint32_t* counters, uint32_t* lcnt, float (*lbox)[2][6]) {
+    const float* p = box + 6 * (long long)perm[l];
+    float lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[3], p[4], p[5]};
+    uint32_t par = (uint32_t)leaf_parent[l];
+    bool local = true;
+    while (true) {
+        int idx = (int)(par & 0x7FFFFFFFu);
+        int side = (int)(par >> 31);
+        if (local) {
+            int o = span[idx];
+            local = (idx < o ? idx : o) >= b0 && (idx < o ? o : idx) < b1;
+        }
+        if (local) {
+            float* dst = (float*)&nodes[idx] + (side ? 6 : 0);
+            float* mine = lbox[idx - b0][side];
+            for (int c = 0; c < 3; c++) {
+                dst[c] = lo[c];
+                dst[3 + c] = hi[c];
+                mine[c] = lo[c];
+                mine[3 + c] = hi[c];
+            }
+            uint32_t old = __hip_atomic_fetch_add(&lcnt[idx - b0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0u) return;
+            const float* other = lbox[idx - b0][side ^ 1];
+            for (int c = 0; c < 3; c++) {
+                lo[c] = fminf(lo[c], other[c]);
+                hi[c] = fmaxf(hi[c], other[3 + c]);
+            }
+        } else if (!climb_global(lo, hi, idx, side, nodes, counters)) {
+            return;
+        }
+        if (idx == 0) return;
+        par = (uint32_t)((const int*)&nodes[idx].m)[2];
+    }
+}
+
+__global__ void __launch_bounds__(kRefitTile) k_refit_lbvh(const float* box, const uint32_t* perm, int n,
+                                                           BNode* nodes, const int* leaf_parent, const int* span,
+                                                           uint32_t* counters) {
+    __shared__ uint32_t lcnt[kRefitTile];
+    __shared__ float lbox[kRefitTile][2][6];
+    lcnt[threadIdx.x] = 0u;
+    __syncthreads();
+    int b0 = blockIdx.x * kRefitTile;
+    int b1 = b0 + kRefitTile < n ? b0 + kRefitTile : n;
+    int l = b0 + (int)threadIdx.x;
+    if (l < n) refit_leaf_lbvh(box, perm, l, b0, b1, nodes, leaf_parent, span, counters, lcnt, lbox);
+}
+
+// arrival counters of every tree of a batch to zero ([max(n - 1, 1)] each)
+__global__ void __launch_bounds__(256) k_refit_clear(BuildSet S) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.off[S.nj]) return;
+    int j = job_of(S, i);
+    int li = i - S.off[j], n = S.off[j + 1] - S.off[j];
+    if (li < (n > 1 ? n - 1 : 1)) S.counters[j][li] = 0u;
+}
+
+// Every tree of a batch; a block covers kRefitTile leaf slots of one tree
+// (tree j's blocks start at blk[j]).
+__global__ void __launch_bounds__(kRefitTile) k_refit_batch(BuildSet S, RefitBlocks B) {
+    __shared__ uint32_t lcnt[kRefitTile];
+    __shared__ float lbox[kRefitTile][2][6];
+    lcnt[threadIdx.x] = 0u;
+    __syncthreads();
+    int j = 0;
+    while (j + 1 < S.nj && (int)blockIdx.x >= B.blk[j + 1]) j++;
+    int n = S.off[j + 1] - S.off[j];
+    int b0 = ((int)blockIdx.x - B.blk[j]) * kRefitTile;
+    int b1 = b0 + kRefitTile < n ? b0 + kRefitTile : n;
+    int l = b0 + (int)threadIdx.x;
+    if (l < n)
+        refit_leaf_lbvh(S.box[j], S.perm[j], l, b0, b1, S.nodes[j], S.leaf_parent[j], S.span[j], S.counters[j], lcnt,
+                        lbox);
 }
 
 __global__ void __launch_bounds__(256) k_sah(const BNode* nodes, int n_int, double* out) {
@@ -380,6 +524,7 @@ int bvh_build_sah(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hi
         return 0;
     }
     tree.n = n;
+    tree.lbvh = false;
     SahItem* items[2] = {(SahItem*)tmp.k0, (SahItem*)tmp.k1};  // each holds cap / 2 items >= n / 2
     uint32_t* idx[2] = {tmp.v0, tmp.v1};
     uint32_t* ctr = tmp.bounds;
@@ -405,7 +550,7 @@ size_t build_temp_bytes(long long cap) {
     size_t b = 0;
     b += 2 * sizeof(unsigned long long) * (size_t)cap;
     b += 2 * sizeof(uint32_t) * (size_t)cap;
-    b += 64;
+    b += 256;
     b += radix_temp_bytes(cap);
     return b + 5 * 256;
 }
@@ -419,30 +564,69 @@ void carve_build_temp(void* base, long long cap, BuildTemp& t) {
     t.k1 = (unsigned long long*)p; p = align256(p + sizeof(unsigned long long) * cap);
     t.v0 = (uint32_t*)p; p = align256(p + sizeof(uint32_t) * cap);
     t.v1 = (uint32_t*)p; p = align256(p + sizeof(uint32_t) * cap);
-    t.bounds = (uint32_t*)p; p = align256(p + 64);
+    t.bounds = (uint32_t*)p; p = align256(p + 256);
     t.radix = p;
 }
 
+// Morton bits per axis for trees of up to n primitives: about 2^12 cells or
+// more per primitive, at least 10 bits (a 32-bit sort key for four trees).
+static int morton_bits(int n) {
+    int lg = 0;
+    while (lg < 31 && (1LL << lg) < (long long)n) lg++;
+    int b = (lg + 2) / 3 + 4;
+    return b < 10 ? 10 : (b > 20 ? 20 : b);
+}
+
+void bvh_build_many(const BuildJob* jobs, int n_jobs, const BuildTemp& tmp, hipStream_t st) {
+    BuildSet S{};
+    int total = 0, n_max = 0;
+    for (int k = 0; k < n_jobs; k++) {
+        jobs[k].tree->n = jobs[k].n > 0 ? jobs[k].n : 0;
+        if (jobs[k].n <= 0) continue;
+        int j = S.nj++;
+        Tree& t = *jobs[k].tree;
+        S.box[j] = jobs[k].box6;
+        S.nodes[j] = t.nodes;
+        S.leaf_parent[j] = t.leaf_parent;
+        S.perm[j] = t.perm;
+        S.counters[j] = t.counters;
+        S.span[j] = t.span;
+        t.lbvh = true;
+        S.off[j] = total;
+        total += jobs[k].n;
+        n_max = jobs[k].n > n_max ? jobs[k].n : n_max;
+    }
+    S.off[S.nj] = total;
+    if (total == 0) return;
+    S.bits = morton_bits(n_max);
+    int job_bits = S.nj > 2 ? 2 : (S.nj > 1 ? 1 : 0);
+    int g = (total + 255) / 256;
+    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, tmp.bounds, S.nj);
+    hipLaunchKernelGGL(k_bounds, dim3(g), dim3(256), 0, st, S, tmp.bounds);
+    hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, st, S, tmp.bounds, tmp.k0, tmp.v0);
+    int which = radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, nullptr, total, 3 * S.bits + job_bits, tmp.radix, st);
+    hipLaunchKernelGGL(k_emit, dim3(g), dim3(256), 0, st, S, which ? tmp.k1 : tmp.k0, which ? tmp.v1 : tmp.v0);
+    RefitBlocks B{};
+    for (int j = 0; j < S.nj; j++) B.blk[j + 1] = B.blk[j] + (S.off[j + 1] - S.off[j] + kRefitTile - 1) / kRefitTile;
+    hipLaunchKernelGGL(k_refit_clear, dim3(g), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_refit_batch, dim3(B.blk[S.nj]), dim3(kRefitTile), 0, st, S, B);
+}
+
 void bvh_build(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st) {
-    tree.n = n;
-    if (n <= 0) return;
-    int g = (n + 255) / 256;
-    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, tmp.bounds);
-    hipLaunchKernelGGL(k_bounds, dim3(g), dim3(256), 0, st, box6, n, tmp.bounds);
-    hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, st, box6, n, tmp.bounds, tmp.k0, tmp.v0);
-    int which = radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, nullptr, n, 63, tmp.radix, st);
-    const unsigned long long* codes = which ? tmp.k1 : tmp.k0;
-    const uint32_t* vals = which ? tmp.v1 : tmp.v0;
-    hipLaunchKernelGGL(k_emit, dim3(g), dim3(256), 0, st, codes, vals, n, tree.nodes, tree.leaf_parent, tree.perm);
-    bvh_refit(box6, tree, st);
+    BuildJob job{box6, n, &tree};
+    bvh_build_many(&job, 1, tmp, st);
 }
 
 void bvh_refit(const float* box6, Tree& tree, hipStream_t st) {
     int n = tree.n;
     if (n <= 0) return;
     fill_u32(tree.counters, 0u, n > 1 ? n - 1 : 1, st);
-    hipLaunchKernelGGL(k_refit, dim3((n + 255) / 256), dim3(256), 0, st, box6, tree.perm, n, tree.nodes,
-                       tree.leaf_parent, tree.counters);
+    if (tree.lbvh)
+        hipLaunchKernelGGL(k_refit_lbvh, dim3((n + kRefitTile - 1) / kRefitTile), dim3(kRefitTile), 0, st, box6,
+                           tree.perm, n, tree.nodes, tree.leaf_parent, tree.span, tree.counters);
+    else
+        hipLaunchKernelGGL(k_refit, dim3((n + 255) / 256), dim3(256), 0, st, box6, tree.perm, n, tree.nodes,
+                           tree.leaf_parent, tree.counters);
 }
 
 void bvh_sah(const Tree& tree, double* out, hipStream_t st) {

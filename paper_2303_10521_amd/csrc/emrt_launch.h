@@ -25,6 +25,8 @@ struct Tree {
     int* leaf_parent = nullptr;   // [n] parent | side << 31
     uint32_t* counters = nullptr; // [max(n-1, 1)] refit arrival counters
     uint32_t* perm = nullptr;     // [n] leaf slot -> primitive index
+    int* span = nullptr;          // [max(n-1, 1)] LBVH: the far end of node i's leaf range (i is the other)
+    bool lbvh = false;            // built by bvh_build_many (span valid)
     int n = 0;
     int cap = 0;
     Bvh view() const { return Bvh{nodes, n}; }
@@ -35,12 +37,21 @@ struct BuildTemp {
     unsigned long long* k1;
     uint32_t* v0;
     uint32_t* v1;
-    uint32_t* bounds;  // [8]
+    uint32_t* bounds;  // [64]
     void* radix;
 };
 size_t build_temp_bytes(long long cap);
 void carve_build_temp(void* base, long long cap, BuildTemp& t);
 void bvh_build(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st);
+// up to kMaxBuildJobs trees in one batch (one sort, one launch per later stage);
+// `tmp` must hold the sum of their primitive counts
+constexpr int kMaxBuildJobs = 4;
+struct BuildJob {
+    const float* box6;
+    int n;
+    Tree* tree;
+};
+void bvh_build_many(const BuildJob* jobs, int n_jobs, const BuildTemp& tmp, hipStream_t st);
 void bvh_refit(const float* box6, Tree& tree, hipStream_t st);
 // top-down binned SAH build into the same node format (static scene, once): one launch per level,
 // synchronises per level; returns the number of levels, -1 on a HIP error
@@ -263,7 +274,9 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
 void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st);
 void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
                  int* cnt, long long n_links, hipStream_t st);
-void link_reduce(const ValidPaths& vp, uint32_t* order, const int* start, const int* cnt, long long n_links, int nf,
+void link_rank(const ValidPaths& vp, const unsigned long long* link_of, const uint32_t* in, const int* start,
+               const int* end, uint32_t* out, hipStream_t st);
+void link_reduce(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, long long n_links, int nf,
                  double p_tx, double* chan, hipStream_t st);
 void cache_counts(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, long long n_links,
                   uint32_t* per_link, hipStream_t st);

@@ -805,6 +805,35 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
 }
 
 // ----------------------------------------------------------- per link ----
+// Key order within each link, in parallel: every valid path counts the paths
+// of its link whose key sorts before its own and moves to that rank (equal
+// keys, which a deduplicated path set does not hold, would keep their
+// positions' order), so the link's later sums run in key order whatever order
+// validation produced them in.
+__global__ void k_link_rank(ValidPaths vp, const unsigned long long* link_of, const uint32_t* in, const int* start,
+                            const int* end, uint32_t* out) {
+    long long n = (long long)*vp.count;
+    if (n > vp.cap) n = vp.cap;
+    GRID_STRIDE(i, n) {
+        long long L = (long long)link_of[i];
+        int s = start[L], e = end[L];
+        uint32_t v = in[i];
+        KeyRec kv = vp.key[v];
+        int r = 0;
+        for (int j = s; j < e; j++) {
+            if (j == (int)i) continue;
+            KeyRec kj = vp.key[in[j]];
+            r += (key_less(kj, kv) || (j < (int)i && !key_less(kv, kj))) ? 1 : 0;
+        }
+        out[s + r] = v;
+    }
+}
+
+void link_rank(const ValidPaths& vp, const unsigned long long* link_of, const uint32_t* in, const int* start,
+               const int* end, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_link_rank, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, link_of, in, start, end, out);
+}
+
 __global__ void k_link_keys(ValidPaths vp, int n_rx, unsigned long long* keys, uint32_t* vals) {
     long long n = (long long)*vp.count;
     if (n > vp.cap) n = vp.cap;
@@ -840,14 +869,14 @@ void link_ranges(const unsigned long long* sorted_keys, const unsigned long long
     hipLaunchKernelGGL(k_link_ranges, dim3(grid_for(cap)), dim3(256), 0, st, sorted_keys, n, cap, start, end);
 }
 
-// One thread per link: order the link's paths by key (insertion sort; the
-// sums then run in a fixed order, so results are bit-reproducible), then
+// One thread per link, over the link's paths in key order (the sums then run
+// in a fixed order, so results are bit-reproducible):
 //   H = sum a, P_coh = P_tx |H|^2, P_inc = P_tx sum |a|^2,
 //   power-weighted mean and RMS of delay and Doppler (weights |a|^2).
 // chan[(f * n_links + link) * 8 + {H.re, H.im, P_coh, P_inc, tau_mean,
 // tau_rms, fd_mean, fd_rms}]; chan_i[link * 2 + {n_paths, los}].
-__global__ void k_link_reduce(ValidPaths vp, uint32_t* order, const int* start, const int* end, long long n_links,
-                              int nf, double p_tx, double* chan, int* chan_i) {
+__global__ void k_link_reduce(ValidPaths vp, const uint32_t* order, const int* start, const int* end,
+                              long long n_links, int nf, double p_tx, double* chan, int* chan_i) {
     GRID_STRIDE(Lk, n_links) {
         int s = start[Lk], e = end[Lk];
         if (s < 0) {
@@ -856,16 +885,6 @@ __global__ void k_link_reduce(ValidPaths vp, uint32_t* order, const int* start, 
             chan_i[2 * Lk] = 0;
             chan_i[2 * Lk + 1] = 0;
             continue;
-        }
-        for (int i = s + 1; i < e; i++) {
-            uint32_t v = order[i];
-            KeyRec kv = vp.key[v];
-            int j = i - 1;
-            while (j >= s && key_less(kv, vp.key[order[j]])) {
-                order[j + 1] = order[j];
-                j--;
-            }
-            order[j + 1] = v;
         }
         int los = (vp.key[order[s]].to & 0xff) == KT_LOS ? 1 : 0;
         for (int f = 0; f < nf; f++) {
@@ -905,7 +924,7 @@ __global__ void k_link_reduce(ValidPaths vp, uint32_t* order, const int* start, 
     }
 }
 
-void link_reduce(const ValidPaths& vp, uint32_t* order, const int* start, const int* end, long long n_links, int nf,
+void link_reduce(const ValidPaths& vp, const uint32_t* order, const int* start, const int* end, long long n_links, int nf,
                  double p_tx, double* chan, hipStream_t st) {
     int* chan_i = (int*)(chan + (long long)nf * n_links * 8);
     hipLaunchKernelGGL(k_link_reduce, dim3(grid_for(n_links, 128)), dim3(128), 0, st, vp, order, start, end, n_links,
