@@ -95,7 +95,10 @@ typedef struct emrt_sizes {
 int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out);
 int32_t emrt_ctx_destroy(emrt_ctx* ctx);
 
-/* Bytes of device workspace for the given sizes (host call, no GPU work). */
+/* Bytes of device workspace for the given sizes (host call, no GPU work).
+ * Errors: EMRT_E_INVALID (a size below 1), EMRT_E_UNSUPPORTED (n_tx > 4095,
+ * n_rx >= 2^26, n_tris or n_verts >= 2^31, n_tx x rays_per_tx >= 2^32,
+ * n_tx x n_rx + path_capacity >= 2^31). */
 int32_t emrt_workspace_size(emrt_ctx* ctx, const emrt_sizes* sizes, size_t* bytes);
 /* Bind a caller-allocated device workspace of at least emrt_workspace_size()
  * bytes (256-byte aligned).  The library carves all of its device state from

@@ -28,10 +28,11 @@ constexpr int C_NVALID = 17;
 constexpr int C_NCACHE = 18;   // [18, 19] cache sizes (double buffer)
 constexpr int C_STATS = 20;    // [20..23]
 constexpr int C_TRUNC = 24;    // path-list truncation flag
-constexpr int C_NLEGS = 25;    // shadow legs of the step
+constexpr int C_NLEGS = 25;    // shadow legs of the step besides the receiver legs
 constexpr int C_COH = 26;      // [26, 27] coherence read-back (min T_c bits, triggered links)
 constexpr int C_NPAIRS = 28;   // listed (source, face, edge) pairs
 constexpr int C_NEXTRA = 29;   // keys proposed into the extra-key array
+constexpr int C_NLIST = 31;    // of those, the ones traced after the receiver legs
 constexpr int C_SCRATCH = 32;  // ints for set_scene
 
 struct Carver {
@@ -241,9 +242,10 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->ctr = cv.take<unsigned long long>(kNumCounters);
     c->table = cv.take<unsigned long long>(c->table_slots);
-    c->ctmp.flags = cv.take<uint32_t>(c->table_slots);
-    c->ctmp.off = cv.take<uint32_t>(c->table_slots);
-    c->ctmp.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(c->table_slots) / 4 + 16);
+    const long long cw = compact_temp_elems((unsigned long long)c->table_slots);
+    c->ctmp.flags = cv.take<uint32_t>(cw);
+    c->ctmp.off = cv.take<uint32_t>(cw);
+    c->ctmp.scan_tmp = cv.take<uint32_t>((long long)scan_temp_bytes(cw) / 4 + 16);
     c->cand = cv.take<KeyRec>(c->P);
     c->cache[0] = cv.take<KeyRec>(c->P);
     c->cache[1] = cv.take<KeyRec>(c->P);
@@ -277,12 +279,14 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->sort_tmp = cv.take<char>((long long)radix_temp_bytes(c->vcap));
     LegBuf& lg = c->legs;
     lg.cap = 3 * c->vcap;
+    lg.cap_first = c->vcap;  // one receiver leg per key slot
     lg.ox = cv.take<float>(lg.cap); lg.oy = cv.take<float>(lg.cap); lg.oz = cv.take<float>(lg.cap);
     lg.dx = cv.take<float>(lg.cap); lg.dy = cv.take<float>(lg.cap); lg.dz = cv.take<float>(lg.cap);
     lg.xa = cv.take<int>(lg.cap);
     lg.xb = cv.take<int>(lg.cap);
     lg.xc = cv.take<int>(lg.cap);
     lg.key = cv.take<uint32_t>(lg.cap);
+    lg.list = cv.take<uint32_t>(lg.cap - lg.cap_first);
     c->kstate = cv.take<uint8_t>(c->vcap);
     c->occl = cv.take<uint32_t>(c->vcap);
     c->vtmp.flag = cv.take<uint32_t>(c->vcap);
@@ -407,6 +411,8 @@ int32_t emrt_workspace_size(emrt_ctx* c, const emrt_sizes* s, size_t* bytes) {
         return fail(c, EMRT_E_UNSUPPORTED, "scene too large (n_tx <= 4095, n_rx < 2^26, n_tris < 2^31)");
     if ((long long)s->n_tx * c->cfg.rays_per_tx >= (1LL << 32))
         return fail(c, EMRT_E_UNSUPPORTED, "n_tx * rays_per_tx must be below 2^32");
+    if ((long long)s->n_tx * s->n_rx + c->cfg.path_capacity >= (1LL << 31))  // key slots are 31-bit
+        return fail(c, EMRT_E_UNSUPPORTED, "n_tx * n_rx + path_capacity must be below 2^31");
     c->sz = *s;
     c->sized = true;
     derive(c);
@@ -643,6 +649,7 @@ static PathArgs path_args(emrt_ctx* c) {
     a.out = c->vp;
     a.legs = c->legs;
     a.legs.count = c->ctr + C_NLEGS;
+    a.legs.n_list = c->ctr + C_NLIST;
     a.state = c->kstate;
     a.occl = c->occl;
     a.ktri = c->ktri;

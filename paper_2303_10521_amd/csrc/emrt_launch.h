@@ -182,9 +182,14 @@ struct ValidPaths {
 struct LegBuf {
     float *ox, *oy, *oz, *dx, *dy, *dz;
     int *xa, *xb, *xc;  // faces excluded from the leg's shadow ray
-    uint32_t* key;
+    uint32_t* key;      // key slot
+    // [0, cap_first): slot q holds the leg of key q that ends at the
+    // receiver; [cap_first, cap): the keys' other legs (*count of them)
     unsigned long long* count;
+    long long cap_first;
     long long cap;
+    uint32_t* list;     // [cap - cap_first] other legs still to trace (*n_list)
+    unsigned long long* n_list;
 };
 
 // inputs of the field evaluation shared by the forward and the adjoint
@@ -250,12 +255,14 @@ void pair_candidates(const PathArgs& a, const unsigned long long* set, long long
 void diff_candidates_rx(const PathArgs& a, const uint32_t* illum, int e_words, const int* src_rx, int n_src,
                         unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
 void gather_rx(const double* rx_pos, const int* sel, int n, double* out, hipStream_t st);
-// scratch of the table compaction: [n_slots] flags and offsets + scan temp
+// scratch of the table compaction: per-wave counts and offsets
+// ([compact_temp_elems(n_slots)] each) + scan temp
 struct CompactTemp {
     uint32_t* flags;
     uint32_t* off;
     uint32_t* scan_tmp;
 };
+long long compact_temp_elems(unsigned long long n_slots);
 void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
                    unsigned long long* n_cand, long long cap, uint32_t* flags, const CompactTemp& t, hipStream_t st);
 // scratch of the validation: [n_links + cap_cand] survivor flags, offsets, list + scan temp

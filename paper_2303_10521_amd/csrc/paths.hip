@@ -44,38 +44,71 @@ void cache_insert(unsigned long long* table, unsigned long long mask, const KeyR
                        flags);
 }
 
-// Table compaction without a shared counter: occupied-slot flags, an
-// exclusive scan (the candidate index of every occupied slot, in slot
-// order), then each occupied slot expands its reference into the full key.
-__global__ void __launch_bounds__(256) k_slot_flags(const unsigned long long* table, unsigned long long n_slots,
-                                                    uint32_t* flags_out) {
-    GRID_STRIDE(i, (long long)n_slots) flags_out[i] = table[i] != 0ULL ? 1u : 0u;
+// Table compaction without a shared counter, in slot order.  Each wave owns
+// kCompactSpan consecutive slots: a first pass counts its occupied slots, an
+// exclusive scan of the per-wave counts gives every wave its first candidate
+// index, and a second pass re-reads the slots and places each occupied one by
+// a ballot prefix (the table is read twice; no per-slot flags or offsets).
+constexpr int kCompactIters = 64;
+constexpr long long kCompactSpan = 64LL * kCompactIters;
+
+__global__ void __launch_bounds__(256) k_slot_count(const unsigned long long* table, unsigned long long n_slots,
+                                                    uint32_t* wave_cnt, long long n_waves) {
+    const long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = (int)(threadIdx.x & 63);
+    if (w >= n_waves) return;
+    const long long base = w * kCompactSpan;
+    uint32_t c = 0;
+#pragma unroll 8
+    for (int it = 0; it < kCompactIters; it++) {
+        long long i = base + (long long)it * 64 + lane;
+        c += (i < (long long)n_slots && table[i] != 0ULL) ? 1u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) wave_cnt[w] = c;
 }
 
 __global__ void __launch_bounds__(256) k_table_emit(const unsigned long long* table, unsigned long long n_slots,
-                                                    const uint32_t* off, KeySrc src, KeyRec* cand, long long cap,
-                                                    uint32_t* flags) {
-    GRID_STRIDE(i, (long long)n_slots) {
-        unsigned long long ref = table[i];
-        if (ref == 0ULL) continue;
-        long long pos = (long long)off[i];
-        if (pos < cap) {
-            KeyRec k;
-            expand_ref(ref, src, k);
-            cand[pos] = k;
-        } else {
-            atomicOr(flags, FLAG_CAND_CAP);
+                                                    const uint32_t* wave_off, long long n_waves, KeySrc src,
+                                                    KeyRec* cand, long long cap, uint32_t* flags) {
+    const long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = (int)(threadIdx.x & 63);
+    if (w >= n_waves) return;
+    const long long base = w * kCompactSpan;
+    unsigned long long pos0 = wave_off[w];
+    bool over = false;
+    for (int it = 0; it < kCompactIters; it++) {
+        long long i = base + (long long)it * 64 + lane;
+        unsigned long long ref = i < (long long)n_slots ? table[i] : 0ULL;
+        uint64_t m = ballot64(ref != 0ULL);
+        if (ref != 0ULL) {
+            long long pos = (long long)(pos0 + (unsigned long long)prefix_below(m));
+            if (pos < cap) {
+                KeyRec k;
+                expand_ref(ref, src, k);
+                cand[pos] = k;
+            } else {
+                over = true;
+            }
         }
+        pos0 += (unsigned long long)__popcll(m);
     }
+    if (over) atomicOr(flags, FLAG_CAND_CAP);
+}
+
+long long compact_temp_elems(unsigned long long n_slots) {
+    return ((long long)n_slots + kCompactSpan - 1) / kCompactSpan + 1;
 }
 
 void table_compact(const unsigned long long* table, unsigned long long n_slots, KeySrc src, KeyRec* cand,
                    unsigned long long* n_cand, long long cap, uint32_t* flags, const CompactTemp& t, hipStream_t st) {
-    int g = grid_for((long long)n_slots, 256, 16384);
-    hipLaunchKernelGGL(k_slot_flags, dim3(g), dim3(256), 0, st, table, n_slots, t.flags);
+    const long long n_waves = ((long long)n_slots + kCompactSpan - 1) / kCompactSpan;
+    const int g = (int)((n_waves + 3) / 4);
+    hipLaunchKernelGGL(k_slot_count, dim3(g), dim3(256), 0, st, table, n_slots, t.flags, n_waves);
     // n_cand: low word = scan total (its high word is cleared with the step's counters)
-    exclusive_scan(t.flags, t.off, (long long)n_slots, t.scan_tmp, (uint32_t*)n_cand, st);
-    hipLaunchKernelGGL(k_table_emit, dim3(g), dim3(256), 0, st, table, n_slots, t.off, src, cand, cap, flags);
+    exclusive_scan(t.flags, t.off, n_waves, t.scan_tmp, (uint32_t*)n_cand, st);
+    hipLaunchKernelGGL(k_table_emit, dim3(g), dim3(256), 0, st, table, n_slots, t.off, n_waves, src, cand, cap,
+                       flags);
 }
 
 // ------------------------------------------------------------ geometry ----
@@ -649,39 +682,108 @@ __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links
                 for (int j = 0; j < EMRT_KMAX; j++) a.ktri[5 * q + j] = g.tri[j];
             }
         }
-        // one reservation per wave for all legs; a key whose legs do not all
-        // fit is invalid, but every slot below the capacity is still written
+        // The leg that ends at the receiver takes slot q of the first region
+        // [0, cap_first); the other legs go to [cap_first, cap), one
+        // reservation per wave.  A key whose legs do not all fit is invalid,
+        // but every reserved slot below the capacity is still written.
         const uint32_t nleg = ok ? (uint32_t)(g.np - 1) : 0u;
-        const unsigned long long pos = wave_reserve(a.legs.count, nleg);
-        const unsigned long long cap = (unsigned long long)a.legs.cap;
-        if (ok && pos + nleg > cap) {
+        const uint32_t n_other = nleg > 0u ? nleg - 1u : 0u;
+        const unsigned long long po = wave_reserve(a.legs.count, n_other);
+        const unsigned long long cap_f = (unsigned long long)a.legs.cap_first;
+        const unsigned long long cap_o = (unsigned long long)(a.legs.cap - a.legs.cap_first);
+        if (ok && po + n_other > cap_o) {
             atomicOr(a.flags, FLAG_PATH_CAP);
             a.state[q] = 0;
         }
         if (ok) {
             const uint32_t qq = (uint32_t)q;
-            if (pos + 0 < cap) write_leg<0>(a, g, key, pos + 0, qq);
-            if (nleg > 1 && pos + 1 < cap) write_leg<1>(a, g, key, pos + 1, qq);
-            if (nleg > 2 && pos + 2 < cap) write_leg<2>(a, g, key, pos + 2, qq);
-            if (nleg > 3 && pos + 3 < cap) write_leg<3>(a, g, key, pos + 3, qq);
-            if (nleg > 4 && pos + 4 < cap) write_leg<4>(a, g, key, pos + 4, qq);
-            if (nleg > 5 && pos + 5 < cap) write_leg<5>(a, g, key, pos + 5, qq);
+            // slot of leg j, or ~0 when it falls beyond its region
+            auto slot = [&](uint32_t j) -> unsigned long long {
+                if (j + 1u == nleg) return (unsigned long long)q;
+                return po + j < cap_o ? cap_f + po + j : ~0ULL;
+            };
+            unsigned long long s0 = slot(0), s1 = slot(1), s2 = slot(2), s3 = slot(3), s4 = slot(4), s5 = slot(5);
+            if (s0 != ~0ULL) write_leg<0>(a, g, key, s0, qq);
+            if (nleg > 1 && s1 != ~0ULL) write_leg<1>(a, g, key, s1, qq);
+            if (nleg > 2 && s2 != ~0ULL) write_leg<2>(a, g, key, s2, qq);
+            if (nleg > 3 && s3 != ~0ULL) write_leg<3>(a, g, key, s3, qq);
+            if (nleg > 4 && s4 != ~0ULL) write_leg<4>(a, g, key, s4, qq);
+            if (nleg > 5 && s5 != ~0ULL) write_leg<5>(a, g, key, s5, qq);
         }
     }
 }
 
 // Phase 2: float32 shadow rays over the open legs (t in (0, 1)), static and
-// dynamic LBVH; a blocked leg marks its key occluded.
-__global__ void __launch_bounds__(256) k_shadow(PathArgs a) {
+// dynamic LBVH; a blocked leg marks its key occluded.  The leg that ends at
+// the receiver goes first: it is the one most often blocked (the
+// rays that proposed the key reached its first interaction, not the
+// receiver), and a clear leg costs a full traversal where a blocked one stops
+// at its first hit.  The other legs of the keys still open are then listed
+// densely and traced.  Whether a key is occluded does not depend on the order
+// of its legs.
+__device__ __forceinline__ void shadow_leg(const PathArgs& a, long long i, uint32_t q) {
+    RayPre r = ray_pre(a.legs.ox[i], a.legs.oy[i], a.legs.oz[i], a.legs.dx[i], a.legs.dy[i], a.legs.dz[i]);
+    int xa = a.legs.xa[i], xb = a.legs.xb[i], xc = a.legs.xc[i];
+    if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc) || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc))
+        a.occl[q] = 1u;
+}
+
+__global__ void __launch_bounds__(256) k_shadow_first(PathArgs a, long long n_links, long long cap_cand) {
+    long long nc = (long long)*a.n_cand;
+    if (nc > cap_cand) nc = cap_cand;
+    GRID_STRIDE(q, n_links + nc) {
+        if (a.state[q]) shadow_leg(a, q, (uint32_t)q);
+    }
+}
+
+// The other legs of the keys still open, listed densely: a block takes
+// kPickTile consecutive legs, counts its survivors, reserves their room with
+// one atomic and writes them in leg order.
+constexpr int kPickItems = 8;
+constexpr long long kPickTile = 256LL * kPickItems;
+
+__global__ void __launch_bounds__(256) k_shadow_pick(PathArgs a) {
+    __shared__ uint32_t wcnt[4];
+    __shared__ unsigned long long blk_base;
+    const long long cap_o = a.legs.cap - a.legs.cap_first;
     long long n = (long long)*a.legs.count;
-    if (n > a.legs.cap) n = a.legs.cap;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    if (n > cap_o) n = cap_o;
+    const long long tile = (long long)blockIdx.x * kPickTile;
+    if (tile >= n) return;  // the whole block
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    uint64_t m[kPickItems];
+    uint32_t total = 0;
+#pragma unroll
+    for (int it = 0; it < kPickItems; it++) {
+        long long j = tile + (long long)it * 256 + threadIdx.x;
+        bool keep = j < n && !a.occl[a.legs.key[a.legs.cap_first + j]];
+        m[it] = ballot64(keep);
+        total += (uint32_t)__popcll(m[it]);
+    }
+    if (lane == 0) wcnt[w] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        blk_base = t ? atomicAdd(a.legs.n_list, (unsigned long long)t) : 0ULL;
+    }
+    __syncthreads();
+    unsigned long long base = blk_base;
+    for (int v = 0; v < w; v++) base += wcnt[v];
+#pragma unroll
+    for (int it = 0; it < kPickItems; it++) {
+        if ((m[it] >> lane) & 1ULL)
+            a.legs.list[base + (unsigned long long)prefix_below(m[it])] =
+                (uint32_t)(tile + (long long)it * 256 + threadIdx.x);
+        base += (unsigned long long)__popcll(m[it]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_shadow_rest(PathArgs a) {
+    long long n = (long long)*a.legs.n_list;
+    GRID_STRIDE(k, n) {
+        long long i = a.legs.cap_first + (long long)a.legs.list[k];
         uint32_t q = a.legs.key[i];
-        if (a.occl[q]) continue;
-        RayPre r = ray_pre(a.legs.ox[i], a.legs.oy[i], a.legs.oz[i], a.legs.dx[i], a.legs.dy[i], a.legs.dz[i]);
-        int xa = a.legs.xa[i], xb = a.legs.xb[i], xc = a.legs.xc[i];
-        if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc) || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc))
-            a.occl[q] = 1u;
+        if (!a.occl[q]) shadow_leg(a, i, q);
     }
 }
 
@@ -790,7 +892,10 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
 void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, const ValidTemp& t, hipStream_t st) {
     long long n = n_links + cap_cand;
     hipLaunchKernelGGL(k_construct, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, cap_cand);
-    hipLaunchKernelGGL(k_shadow, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_first, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, a, n_links, cap_cand);
+    const long long cap_o = a.legs.cap - a.legs.cap_first;
+    hipLaunchKernelGGL(k_shadow_pick, dim3((unsigned)((cap_o + kPickTile - 1) / kPickTile)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_rest, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
     int g = grid_for(n, 256, 16384);
     hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t);
     exclusive_scan(t.flag, t.off, n, t.scan_tmp, t.cnt, st);
