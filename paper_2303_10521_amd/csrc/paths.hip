@@ -201,19 +201,41 @@ __device__ __forceinline__ bool occluded(const PathArgs& a, dv3 p0, dv3 p1, int 
 }
 
 // Keller point (equal angles with the edge) strictly inside the edge, both
-// ends in the exterior wedge, receiver leg within diff_max_leg.
-__device__ __forceinline__ bool keller(const Wedge& w, dv3 s, dv3 r, double max_leg, dv3& Q) {
+// ends in the exterior wedge, receiver leg within diff_max_leg.  The source's
+// share (its edge coordinates and wedge angle) is computed once per edge and
+// reused for every receiver; the tests are the same pure expressions either
+// way, so the outcome does not depend on the split or on their order.
+struct KellerSrc {
+    double zs, rs;
+    bool ok;  // the source lies in the exterior wedge
+};
+
+__device__ __forceinline__ KellerSrc keller_src(const Wedge& w, dv3 s) {
 #pragma clang fp contract(off)
-    double zs = dot(s - w.P0, w.e), zr = dot(r - w.P0, w.e);
-    double rs = len(s - w.P0 - w.e * zs), rr = len(r - w.P0 - w.e * zr);
-    if (!(rs + rr > 0)) return false;
-    double zq = zs + (zr - zs) * rs / (rs + rr);
+    KellerSrc k;
+    k.zs = dot(s - w.P0, w.e);
+    k.rs = len(s - w.P0 - w.e * k.zs);
+    double php = wedge_angle(w, s);
+    k.ok = php > 0 && php < w.n * kPi;
+    return k;
+}
+
+__device__ __forceinline__ bool keller_rx(const Wedge& w, const KellerSrc& k, dv3 r, double max_leg, dv3& Q) {
+#pragma clang fp contract(off)
+    if (!k.ok) return false;
+    double zr = dot(r - w.P0, w.e);
+    double rr = len(r - w.P0 - w.e * zr);
+    if (!(k.rs + rr > 0)) return false;
+    double zq = k.zs + (zr - k.zs) * k.rs / (k.rs + rr);
     if (!(zq > 0.0 && zq < w.len)) return false;
     Q = w.P0 + w.e * zq;
-    double php = wedge_angle(w, s), ph = wedge_angle(w, r);
-    double lim = w.n * kPi;
-    if (!(php > 0 && php < lim && ph > 0 && ph < lim)) return false;
-    return len(Q - r) <= max_leg;
+    if (!(len(Q - r) <= max_leg)) return false;
+    double ph = wedge_angle(w, r);
+    return ph > 0 && ph < w.n * kPi;
+}
+
+__device__ __forceinline__ bool keller(const Wedge& w, dv3 s, dv3 r, double max_leg, dv3& Q) {
+    return keller_rx(w, keller_src(w, s), r, max_leg, Q);
 }
 
 // -------------------------------------------------------- diffraction ----
@@ -225,8 +247,10 @@ __device__ __forceinline__ bool keller(const Wedge& w, dv3 s, dv3 r, double max_
 // The receivers are binned per frame on a kGridN x kGridN grid over their
 // x-y bounding box (counting sort by cell), so the receivers of one row of
 // cells are contiguous; one wave takes one lit pair and its lanes test the
-// receivers of each overlapped row in parallel.  Cell indices are monotone
-// in the float32 coordinates, so the rows cover every receiver in the box.
+// receivers of the overlapped rows in parallel, as one range over all the
+// rows (a row holds a dozen receivers, far fewer than a wave's lanes).  Cell
+// indices are monotone in the float32 coordinates, so the rows cover every
+// receiver in the box.
 __device__ __forceinline__ int grid_cell(float v, float v0, float inv_h) {
     float f = floorf((v - v0) * inv_h);
     if (!(f >= 0.0f)) return 0;  // also NaN
@@ -301,21 +325,45 @@ __global__ void __launch_bounds__(256) k_diff_cand(PathArgs a, const uint32_t* i
         int tx = (int)(k / a.s.E), e = (int)(k - (long long)tx * a.s.E);
         if (!(illum[(long long)tx * e_words + (e >> 5)] & (1u << (e & 31)))) continue;
         Wedge w = wedge_of(a.s, e);
-        dv3 s = ldd3(a.f.tx_pos + 3 * tx);
+        const KellerSrc ks = keller_src(w, ldd3(a.f.tx_pos + 3 * tx));
+        if (!ks.ok) continue;  // no receiver can pass
         dv3 P1 = w.P0 + w.e * w.len;
         float g = (float)a.diff_max_leg + 1.0f;
         float qlx = (float)fmin(w.P0.x, P1.x) - g, qly = (float)fmin(w.P0.y, P1.y) - g, qlz = (float)fmin(w.P0.z, P1.z) - g;
         float qhx = (float)fmax(w.P0.x, P1.x) + g, qhy = (float)fmax(w.P0.y, P1.y) + g, qhz = (float)fmax(w.P0.z, P1.z) + g;
         int cx0 = grid_cell(qlx, gr.x0, gr.inv_h), cx1 = grid_cell(qhx, gr.x0, gr.inv_h);
         int cy0 = grid_cell(qly, gr.y0, gr.inv_h), cy1 = grid_cell(qhy, gr.y0, gr.inv_h);
-        for (int cy = cy0; cy <= cy1; cy++) {
-            uint32_t j0 = bins.start[cy * kGridN + cx0], j1 = bins.start[cy * kGridN + cx1 + 1];
-            for (uint32_t j = j0 + (uint32_t)lane; j < j1; j += 64u) {
-                float4 p = bins.sorted[j];
+        // up to 64 rows at a time: lane r holds row cy0 + r's receiver range;
+        // the lanes then walk the rows' receivers as one flat range
+        for (int rb = cy0; rb <= cy1; rb += 64) {
+            const int cy = rb + lane;
+            uint32_t j0 = 0, cnt = 0;
+            if (cy <= cy1) {
+                j0 = bins.start[cy * kGridN + cx0];
+                cnt = bins.start[cy * kGridN + cx1 + 1] - j0;
+            }
+            uint32_t incl = cnt;  // inclusive prefix of the row counts
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            const uint32_t total = __shfl(incl, 63);
+            for (uint32_t base = 0; base < total; base += 64u) {
+                const uint32_t idx = base + (uint32_t)lane;
+                int r = 0;  // the row holding flat index idx: rows whose prefix ends at or before it
+#pragma unroll
+                for (int st = 32; st >= 1; st >>= 1) {
+                    uint32_t v = __shfl(incl, r + st - 1);
+                    if (v <= idx) r += st;
+                }
+                const uint32_t row_j0 = __shfl(j0, r), row_before = __shfl(incl - cnt, r);
+                if (idx >= total) continue;
+                float4 p = bins.sorted[row_j0 + (idx - row_before)];
                 if (!(p.x >= qlx && p.x <= qhx && p.y >= qly && p.y <= qhy && p.z >= qlz && p.z <= qhz)) continue;
                 int rx = __float_as_int(p.w);
                 dv3 Q;
-                if (!keller(w, s, ldd3(a.f.rx_pos + 3 * rx), a.diff_max_leg, Q)) continue;
+                if (!keller_rx(w, ks, ldd3(a.f.rx_pos + 3 * rx), a.diff_max_leg, Q)) continue;
                 KeyRec key;
                 key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
                 key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
@@ -832,8 +880,18 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
     const long long lo = KIND == 1 ? 0 : (KIND == 2 ? c0 : c1);
     const long long hi = KIND == 1 ? c0 : (KIND == 2 ? c1 : c2);
     const SceneDev& S = a.s;
-    for (long long pos = lo + (long long)blockIdx.x * blockDim.x + threadIdx.x; pos < hi;
-         pos += (long long)gridDim.x * blockDim.x) {
+    // diffraction: one thread per (path, carrier), whose UTD coefficients are
+    // the long part; the geometry is recomputed by each of them
+    const int split = KIND == 2 ? a.fc.nf : 1;
+    for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < (hi - lo) * split;
+         it += (long long)gridDim.x * blockDim.x) {
+        const long long pos = lo + it / split;
+        const int f0 = (int)(it - (pos - lo) * split);
+        FieldCtx fc = a.fc;
+        if (split > 1) {
+            fc.nf = 1;
+            fc.freq[0] = a.fc.freq[f0];
+        }
         long long q = t.surv[pos];
         KeyRec key = key_at(a, q, n_links);
         dv3 sx = ldd3(a.f.tx_pos + 3 * key.tx), rx = ldd3(a.f.rx_pos + 3 * key.rx);
@@ -844,7 +902,7 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
         V3<double> kk[EMRT_KMAX + 1];
         double L;
         Cx<double> amp[EMRT_NF];
-        path_field<double, KIND>(S, a.fc, key, pg, th, phi, 0, kk, L, amp);
+        path_field<double, KIND>(S, fc, key, pg, th, phi, 0, kk, L, amp);
         const int nlegs = pg.np - 1;
         dv3 k0 = val3(kk[0]);
         dv3 kK = k0;
@@ -872,16 +930,18 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
             }
         }
         ValidPaths& o = a.out;
+        for (int j = 0; j < fc.nf; j++) {
+            const int fi = j + (split > 1 ? f0 : 0);
+            double lam = kC0 / a.fc.freq[fi];
+            o.a[2 * (pos * a.fc.nf + fi)] = amp[j].re;
+            o.a[2 * (pos * a.fc.nf + fi) + 1] = amp[j].im;
+            o.fd[pos * a.fc.nf + fi] = -dop / lam;
+        }
+        if (f0 != 0) continue;
         o.key[pos] = key;
 #pragma unroll
         for (int j = 0; j < 5; j++)
             o.tri[5 * pos + j] = (pg.type == KT_SPEC || pg.type >= KT_RD) ? a.ktri[5 * q + j] : -1;
-        for (int fi = 0; fi < a.fc.nf; fi++) {
-            double lam = kC0 / a.fc.freq[fi];
-            o.a[2 * (pos * a.fc.nf + fi)] = amp[fi].re;
-            o.a[2 * (pos * a.fc.nf + fi) + 1] = amp[fi].im;
-            o.fd[pos * a.fc.nf + fi] = -dop / lam;
-        }
         o.tau[pos] = L / kC0;
         float aod_az = (float)atan2(k0.y, k0.x), aod_el = (float)asin(fmin(1.0, fmax(-1.0, k0.z)));
         float aoa_az = (float)atan2(-kK.y, -kK.x), aoa_el = (float)asin(fmin(1.0, fmax(-1.0, -kK.z)));
