@@ -260,13 +260,18 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
+    // the first chunk of every wave is its own index (all waves start at
+    // once, and a burst of atomics on one counter would serialise them); the
+    // later ones come from the counter, after the grid's first chunks
+    const unsigned int n_waves = (gridDim.x * blockDim.x) >> 6;
+    unsigned int chunk = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     while (true) {
-        unsigned int chunk = 0;
-        if (lane == 0) chunk = atomicAdd(a.work, 1u);
-        chunk = __shfl(chunk, 0);
         unsigned long long base = (unsigned long long)chunk * 64ULL;
         if (base >= n_in) break;
         bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap);
+        unsigned int next = 0;
+        if (lane == 0) next = atomicAdd(a.work, 1u);
+        chunk = n_waves + (unsigned int)__shfl((int)next, 0);
     }
     flush_stats<STATS>(a.stats, lane, s_nodes, s_tris, s_seg, s_cap);
 }
@@ -318,10 +323,15 @@ __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restri
     const int lane = lane_id();
     const uint32_t total = chunk_off[n_scenes];
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
-    while (true) {
-        uint32_t g = 0;
-        if (lane == 0) g = atomicAdd(work, 1u);
-        g = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(g, 0));
+    // first chunk: the wave's own index; later ones from the counter
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    for (bool first = true;; first = false) {
+        if (!first) {
+            uint32_t next = 0;
+            if (lane == 0) next = atomicAdd(work, 1u);
+            g = n_waves + (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)next, 0));
+        }
         if (g >= total) break;
         int lo = 0, hi = n_scenes - 1;  // last scene with chunk_off[c] <= g
         while (lo < hi) {
