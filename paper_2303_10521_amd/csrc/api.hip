@@ -55,12 +55,6 @@ int64_t pow2_at_least(int64_t x) {
     return p;
 }
 
-int bits_for(long long n) {
-    int b = 1;
-    while ((1LL << b) < n) b++;
-    return b;
-}
-
 }  // namespace
 
 struct emrt_ctx {
@@ -115,9 +109,7 @@ struct emrt_ctx {
     LegBuf legs{};
     uint8_t* kstate = nullptr;
     uint32_t* occl = nullptr;
-    unsigned long long *sk0 = nullptr, *sk1 = nullptr;
-    uint32_t *sv0 = nullptr, *sv1 = nullptr;
-    void* sort_tmp = nullptr;
+    uint32_t *sv0 = nullptr, *sv1 = nullptr;  // valid paths grouped by link, then in key order per link
     uint32_t* order = nullptr;
     int *link_start = nullptr, *link_end = nullptr;
     uint32_t *link_cnt = nullptr, *link_off = nullptr, *scan_tmp = nullptr;
@@ -272,11 +264,8 @@ static void layout(emrt_ctx* c, Carver& cv) {
     vp.tau = cv.take<double>(c->vcap);
     vp.fd = cv.take<double>((long long)c->nf * c->vcap);
     vp.ang = cv.take<float4>(c->vcap);
-    c->sk0 = cv.take<unsigned long long>(c->vcap);
-    c->sk1 = cv.take<unsigned long long>(c->vcap);
     c->sv0 = cv.take<uint32_t>(c->vcap);
     c->sv1 = cv.take<uint32_t>(c->vcap);
-    c->sort_tmp = cv.take<char>((long long)radix_temp_bytes(c->vcap));
     LegBuf& lg = c->legs;
     lg.cap = 3 * c->vcap;
     lg.cap_first = c->vcap;  // one receiver leg per key slot
@@ -822,13 +811,10 @@ static void step_post(emrt_ctx* c, int discover) {
     validate_eval(pa, c->n_links, c->P, c->vtmp, st);
     ev_record(c);
     // ---- per-link reduction (Section V-D statistics)
-    link_keys(c->vp, c->sz.n_rx, c->sk0, c->sv0, st);
-    int which = radix_sort(c->sk0, c->sv0, c->sk1, c->sv1, (const long long*)c->vp.count, c->vcap, bits_for(c->n_links),
-                           c->sort_tmp, st);
-    unsigned long long* skeys = which ? c->sk1 : c->sk0;
-    link_ranges(skeys, c->vp.count, c->vcap, c->link_start, c->link_end, c->n_links, st);
-    link_rank(c->vp, skeys, which ? c->sv1 : c->sv0, c->link_start, c->link_end, which ? c->sv0 : c->sv1, st);
-    c->order = which ? c->sv0 : c->sv1;
+    link_group(c->vp, c->sz.n_rx, c->n_links, c->link_cnt, c->link_off, c->scan_tmp, c->link_start, c->link_end,
+               c->sv0, st);
+    link_rank(c->vp, c->sz.n_rx, c->sv0, c->link_start, c->link_end, c->sv1, st);
+    c->order = c->sv1;
     link_reduce(c->vp, c->order, c->link_start, c->link_end, c->n_links, c->nf, c->cfg.tx_power_w, c->chan, st);
     // ---- coherence statistics over frames (Section III-B)
     coherence_update(c->coh, c->vp, c->order, c->link_start, c->link_end, c->chan, c->n_links, c->nf, st);

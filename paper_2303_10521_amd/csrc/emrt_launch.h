@@ -11,6 +11,9 @@ namespace emrt {
 // ------------------------------------------------------------ sort.hip ----
 size_t scan_temp_bytes(long long n);
 void exclusive_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* temp, uint32_t* grand, hipStream_t st);
+// over the first min(*n_dev + add, cap) values (a device-side count); temp as for a scan of cap values
+void exclusive_scan_dev(const uint32_t* in, uint32_t* out, const unsigned long long* n_dev, long long add,
+                        long long cap, uint32_t* temp, uint32_t* grand, hipStream_t st);
 size_t radix_temp_bytes(long long cap);
 int radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1, const long long* n_dev,
                long long cap, int nbits, void* temp, hipStream_t st);
@@ -278,11 +281,11 @@ struct ValidTemp {
     uint32_t* scan_tmp;
 };
 void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, const ValidTemp& t, hipStream_t st);
-void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st);
-void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
-                 int* cnt, long long n_links, hipStream_t st);
-void link_rank(const ValidPaths& vp, const unsigned long long* link_of, const uint32_t* in, const int* start,
-               const int* end, uint32_t* out, hipStream_t st);
+// valid paths grouped by link (order[start[L], end[L]) are link L's paths; start -1 when empty)
+void link_group(const ValidPaths& vp, int n_rx, long long n_links, uint32_t* cnt, uint32_t* off, uint32_t* scan_tmp,
+                int* start, int* end, uint32_t* order, hipStream_t st);
+void link_rank(const ValidPaths& vp, int n_rx, const uint32_t* in, const int* start, const int* end, uint32_t* out,
+               hipStream_t st);
 void link_reduce(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, long long n_links, int nf,
                  double p_tx, double* chan, hipStream_t st);
 void cache_counts(const ValidPaths& vp, const uint32_t* order, const int* start, const int* cnt, long long n_links,

@@ -295,7 +295,10 @@ __device__ inline cd erfcx_diag(double v) {
         D = cdiv(C(1.0), D);
         cd delta = Cc * D;
         f = f * delta;
-        if (cabsd(delta - C(1.0)) < 1e-16) break;
+        // a few ulps of 1: the rounded product of converged factors can sit
+        // one ulp below 1 (1.1e-16 away) for good, so a tighter test may never
+        // be met
+        if (cabsd(delta - C(1.0)) < 1e-15) break;
     }
     return cdiv(C(1.0), f * sqrt(kPi));
 }

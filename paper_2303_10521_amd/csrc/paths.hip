@@ -847,8 +847,8 @@ __global__ void __launch_bounds__(256) k_valid_flags(PathArgs a, long long n_lin
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     long long n = n_links + nc;
-    GRID_STRIDE(q, n_links + cap_cand) {
-        bool keep = q < n && a.state[q] && !a.occl[q];
+    GRID_STRIDE(q, n) {  // the scans and the list read the first n flags only
+        bool keep = a.state[q] && !a.occl[q];
         int type = keep && q >= n_links ? (a.cand[q - n_links].to & 0xff) : KT_LOS;
         bool r = keep && type >= KT_RD, d = keep && type == KT_DIFF;
         t.flag[q] = (keep && !d && !r) ? 1u : 0u;
@@ -857,10 +857,13 @@ __global__ void __launch_bounds__(256) k_valid_flags(PathArgs a, long long n_lin
     }
 }
 
-__global__ void __launch_bounds__(256) k_valid_list(ValidTemp t, long long n, unsigned long long* count) {
+__global__ void __launch_bounds__(256) k_valid_list(ValidTemp t, const unsigned long long* n_cand, long long n_links,
+                                                   long long cap_cand, unsigned long long* count) {
     const uint32_t n0 = t.cnt[0], n1 = t.cnt[1];
     if (blockIdx.x == 0 && threadIdx.x == 0) *count = (unsigned long long)n0 + n1 + t.cnt[2];
-    GRID_STRIDE(q, n) {
+    long long nc = (long long)*n_cand;
+    if (nc > cap_cand) nc = cap_cand;
+    GRID_STRIDE(q, n_links + nc) {
         if (t.flag[q]) t.surv[t.off[q]] = (uint32_t)q;
         else if (t.flag_d[q]) t.surv[n0 + t.off_d[q]] = (uint32_t)q;
         else if (t.flag_r[q]) t.surv[n0 + n1 + t.off_r[q]] = (uint32_t)q;
@@ -958,11 +961,11 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
     hipLaunchKernelGGL(k_shadow_rest, dim3(grid_for(a.legs.cap, 256, 16384)), dim3(256), 0, st, a);
     int g = grid_for(n, 256, 16384);
     hipLaunchKernelGGL(k_valid_flags, dim3(g), dim3(256), 0, st, a, n_links, cap_cand, t);
-    exclusive_scan(t.flag, t.off, n, t.scan_tmp, t.cnt, st);
-    exclusive_scan(t.flag_d, t.off_d, n, t.scan_tmp, t.cnt + 1, st);
-    if (a.combined) exclusive_scan(t.flag_r, t.off_r, n, t.scan_tmp, t.cnt + 2, st);
+    exclusive_scan_dev(t.flag, t.off, a.n_cand, n_links, n, t.scan_tmp, t.cnt, st);
+    exclusive_scan_dev(t.flag_d, t.off_d, a.n_cand, n_links, n, t.scan_tmp, t.cnt + 1, st);
+    if (a.combined) exclusive_scan_dev(t.flag_r, t.off_r, a.n_cand, n_links, n, t.scan_tmp, t.cnt + 2, st);
     else fill_u32(t.cnt + 2, 0u, 1, st);  // no combined keys pass key_in_range
-    hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t, n, a.out.count);
+    hipLaunchKernelGGL(k_valid_list, dim3(g), dim3(256), 0, st, t, a.n_cand, n_links, cap_cand, a.out.count);
     hipLaunchKernelGGL(k_fields<1>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
     hipLaunchKernelGGL(k_fields<2>, dim3(grid_for(n, 128, 16384)), dim3(128), 0, st, a, n_links, t);
     if (a.combined)
@@ -975,15 +978,15 @@ void validate_eval(const PathArgs& a, long long n_links, long long cap_cand, con
 // keys, which a deduplicated path set does not hold, would keep their
 // positions' order), so the link's later sums run in key order whatever order
 // validation produced them in.
-__global__ void k_link_rank(ValidPaths vp, const unsigned long long* link_of, const uint32_t* in, const int* start,
-                            const int* end, uint32_t* out) {
+__global__ void k_link_rank(ValidPaths vp, int n_rx, const uint32_t* in, const int* start, const int* end,
+                            uint32_t* out) {
     long long n = (long long)*vp.count;
     if (n > vp.cap) n = vp.cap;
     GRID_STRIDE(i, n) {
-        long long L = (long long)link_of[i];
-        int s = start[L], e = end[L];
         uint32_t v = in[i];
         KeyRec kv = vp.key[v];
+        long long L = (long long)kv.tx * n_rx + kv.rx;
+        int s = start[L], e = end[L];
         int r = 0;
         for (int j = s; j < e; j++) {
             if (j == (int)i) continue;
@@ -994,44 +997,51 @@ __global__ void k_link_rank(ValidPaths vp, const unsigned long long* link_of, co
     }
 }
 
-void link_rank(const ValidPaths& vp, const unsigned long long* link_of, const uint32_t* in, const int* start,
-               const int* end, uint32_t* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_link_rank, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, link_of, in, start, end, out);
+void link_rank(const ValidPaths& vp, int n_rx, const uint32_t* in, const int* start, const int* end, uint32_t* out,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_link_rank, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, n_rx, in, start, end, out);
 }
 
-__global__ void k_link_keys(ValidPaths vp, int n_rx, unsigned long long* keys, uint32_t* vals) {
+// Valid paths grouped by link with a counting sort: per-link counts
+// (atomics on scattered addresses), an exclusive scan, then each path takes
+// the next slot of its link.  The order inside a link is then arbitrary;
+// k_link_rank puts it in key order.
+__global__ void k_link_count(ValidPaths vp, int n_rx, uint32_t* cnt) {
     long long n = (long long)*vp.count;
     if (n > vp.cap) n = vp.cap;
     GRID_STRIDE(i, n) {
         KeyRec k = vp.key[i];
-        keys[i] = (unsigned long long)((long long)k.tx * n_rx + k.rx);
-        vals[i] = (uint32_t)i;
+        atomicAdd(&cnt[(long long)k.tx * n_rx + k.rx], 1u);
     }
 }
 
-void link_keys(const ValidPaths& vp, int n_rx, unsigned long long* keys, uint32_t* vals, hipStream_t st) {
-    hipLaunchKernelGGL(k_link_keys, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, n_rx, keys, vals);
+// start / end of every link's run (start -1 when empty); cnt becomes the
+// scatter cursor (the run's start)
+__global__ void k_link_bounds(uint32_t* cnt, const uint32_t* off, int* start, int* end, long long n_links) {
+    GRID_STRIDE(L, n_links) {
+        uint32_t c = cnt[L], o = off[L];
+        start[L] = c ? (int)o : -1;
+        end[L] = (int)(o + c);
+        cnt[L] = o;
+    }
 }
 
-__global__ void k_link_init(int* start, int* end, long long n_links) {
-    GRID_STRIDE(i, n_links) { start[i] = -1; end[i] = -1; }
-}
-
-__global__ void k_link_ranges(const unsigned long long* key, const unsigned long long* n_dev, long long cap, int* start,
-                              int* end) {
-    long long n = (long long)*n_dev;
-    if (n > cap) n = cap;
+__global__ void k_link_scatter(ValidPaths vp, int n_rx, uint32_t* cursor, uint32_t* order) {
+    long long n = (long long)*vp.count;
+    if (n > vp.cap) n = vp.cap;
     GRID_STRIDE(i, n) {
-        unsigned long long L = key[i];
-        if (i == 0 || key[i - 1] != L) start[L] = (int)i;
-        if (i == n - 1 || key[i + 1] != L) end[L] = (int)(i + 1);
+        KeyRec k = vp.key[i];
+        order[atomicAdd(&cursor[(long long)k.tx * n_rx + k.rx], 1u)] = (uint32_t)i;
     }
 }
 
-void link_ranges(const unsigned long long* sorted_keys, const unsigned long long* n, long long cap, int* start,
-                 int* end, long long n_links, hipStream_t st) {
-    hipLaunchKernelGGL(k_link_init, dim3(grid_for(n_links)), dim3(256), 0, st, start, end, n_links);
-    hipLaunchKernelGGL(k_link_ranges, dim3(grid_for(cap)), dim3(256), 0, st, sorted_keys, n, cap, start, end);
+void link_group(const ValidPaths& vp, int n_rx, long long n_links, uint32_t* cnt, uint32_t* off, uint32_t* scan_tmp,
+                int* start, int* end, uint32_t* order, hipStream_t st) {
+    fill_u32(cnt, 0u, n_links, st);
+    hipLaunchKernelGGL(k_link_count, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, n_rx, cnt);
+    exclusive_scan(cnt, off, n_links, scan_tmp, nullptr, st);
+    hipLaunchKernelGGL(k_link_bounds, dim3(grid_for(n_links)), dim3(256), 0, st, cnt, off, start, end, n_links);
+    hipLaunchKernelGGL(k_link_scatter, dim3(grid_for(vp.cap)), dim3(256), 0, st, vp, n_rx, cnt, order);
 }
 
 // One thread per link, over the link's paths in key order (the sums then run

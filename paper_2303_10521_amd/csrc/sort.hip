@@ -136,6 +136,79 @@ void exclusive_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* te
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_THREADS), 0, st, in, out, n, temp);
 }
 
+// The same scan over the first min(*n_dev + add, cap) values, a count that
+// lives in device memory: blocks past it return at once (their outputs are
+// left unwritten) and the block sums are scanned up to it.
+__device__ __forceinline__ long long live_count(const unsigned long long* n_dev, long long add, long long cap) {
+    long long n = (long long)*n_dev + add;
+    return n < cap ? n : cap;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce_dev(const uint32_t* in, const unsigned long long* n_dev,
+                                                                 long long add, long long cap, uint32_t* sums) {
+    __shared__ uint32_t sh[4];
+    const long long n = live_count(n_dev, add, cap);
+    long long base = (long long)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;
+    uint32_t s = 0;
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        long long k = base + (long long)threadIdx.x * SCAN_ITEMS + i;
+        if (k < n) s += in[k];
+    }
+    uint32_t total;
+    block_excl_scan(s, sh, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_sums_dev(uint32_t* sums, const unsigned long long* n_dev,
+                                                               long long add, long long cap, uint32_t* grand) {
+    __shared__ uint32_t sh[4];
+    const long long n = live_count(n_dev, add, cap);
+    const int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += SCAN_THREADS) {
+        int k = base + (int)threadIdx.x;
+        uint32_t v = k < nb ? sums[k] : 0;
+        uint32_t total;
+        uint32_t ex = block_excl_scan(v, sh, total);
+        if (k < nb) sums[k] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0 && grand) *grand = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply_dev(const uint32_t* in, uint32_t* out,
+                                                                const unsigned long long* n_dev, long long add,
+                                                                long long cap, const uint32_t* sums) {
+    __shared__ uint32_t sh[4];
+    const long long n = live_count(n_dev, add, cap);
+    long long base = (long long)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        long long k = base + (long long)threadIdx.x * SCAN_ITEMS + i;
+        v[i] = k < n ? in[k] : 0;
+        s += v[i];
+    }
+    uint32_t total;
+    uint32_t ex = block_excl_scan(s, sh, total) + sums[blockIdx.x];
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        long long k = base + (long long)threadIdx.x * SCAN_ITEMS + i;
+        if (k < n) out[k] = ex;
+        ex += v[i];
+    }
+}
+
+void exclusive_scan_dev(const uint32_t* in, uint32_t* out, const unsigned long long* n_dev, long long add,
+                        long long cap, uint32_t* temp, uint32_t* grand, hipStream_t st) {
+    int nb = (int)((cap + SCAN_TILE - 1) / SCAN_TILE);
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce_dev, dim3(nb), dim3(SCAN_THREADS), 0, st, in, n_dev, add, cap, temp);
+    hipLaunchKernelGGL(k_scan_sums_dev, dim3(1), dim3(SCAN_THREADS), 0, st, temp, n_dev, add, cap, grand);
+    hipLaunchKernelGGL(k_scan_apply_dev, dim3(nb), dim3(SCAN_THREADS), 0, st, in, out, n_dev, add, cap, temp);
+}
+
 // ---------------------------------------------------------- radix sort ----
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const unsigned long long* keys, const long long* n_dev,
                                                             long long cap, int shift, int nblocks, uint32_t* hist) {
