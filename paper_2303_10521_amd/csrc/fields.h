@@ -268,7 +268,10 @@ __device__ __forceinline__ void material_x(const FieldCtx& fc, int m, R c, bool 
 
 // erfcx(w) = exp(w^2) erfc(w) on w = exp(j pi/4) v, v >= 0: power series of
 // erf for v < 2.5 (Abramowitz & Stegun 7.1.5), Laplace continued fraction
-// (A&S 7.1.14) by the modified Lentz method otherwise.
+// (A&S 7.1.14) by the modified Lentz method otherwise.  Moduli are compared
+// squared, and the reciprocals of the Lentz recurrences are conj(z) / |z|^2
+// with one real division for both (|z| stays between about 1 and 1e3 here,
+// far from overflow or underflow).
 __device__ inline cd erfcx_diag(double v) {
     const double h = 0.70710678118654752440;
     cd w = C(v * h, v * h);
@@ -279,7 +282,7 @@ __device__ inline cd erfcx_diag(double v) {
             term = term * (w2 * (-1.0 / (double)n));
             cd add = term * (1.0 / (double)(2 * n + 1));
             sum = sum + add;
-            if (cabsd(add) < 1e-18 * (cabsd(sum) + 1e-300)) break;
+            if (cabs2(add) < 1e-36 * cabs2(sum) + 1e-300) break;
         }
         cd erfc_w = C(1.0) - sum * (2.0 / sqrt(kPi));
         return cexpi(v * v) * erfc_w;  // exp(w^2), w^2 = j v^2
@@ -289,16 +292,19 @@ __device__ inline cd erfcx_diag(double v) {
     for (int n = 1; n < 5000; n++) {
         double an = 0.5 * n;
         D = w + D * an;
-        if (cabsd(D) < tiny) D = C(tiny);
-        Cc = w + cdiv(C(an), Cc);
-        if (cabsd(Cc) < tiny) Cc = C(tiny);
-        D = cdiv(C(1.0), D);
+        if (fmax(fabs(D.re), fabs(D.im)) < tiny) D = C(tiny);
+        // Cc = w + an / Cc and D = 1 / D, both through one division
+        const double nc = cabs2(Cc), nd = cabs2(D);
+        const double r = 1.0 / (nc * nd);
+        const double sc = an * nd * r, sd = nc * r;  // an / |Cc|^2, 1 / |D|^2
+        Cc = C(w.re + Cc.re * sc, w.im - Cc.im * sc);
+        if (fmax(fabs(Cc.re), fabs(Cc.im)) < tiny) Cc = C(tiny);
+        D = C(D.re * sd, -D.im * sd);
         cd delta = Cc * D;
         f = f * delta;
         // a few ulps of 1: the rounded product of converged factors can sit
-        // one ulp below 1 (1.1e-16 away) for good, so a tighter test may never
-        // be met
-        if (cabsd(delta - C(1.0)) < 1e-15) break;
+        // one ulp below 1 for good, so a tighter test may never be met
+        if (cabs2(delta - C(1.0)) < 1e-30) break;
     }
     return cdiv(C(1.0), f * sqrt(kPi));
 }
