@@ -158,6 +158,8 @@ def main() -> int:
     ap.add_argument("--cpu-stride", type=int, default=200, help="oracle traces every n-th launch direction")
     ap.add_argument("--timed-only", action="store_true", help="skip extra measurements (for profiler runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched measurements")
+    ap.add_argument("--cached-only", action="store_true",
+                    help="time cached (revalidation) frames only, after one discovery frame (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device-to-device before the warm-up (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -188,6 +190,23 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.cached_only:
+        tr.set_frame(frames[0], 0)
+        tr.step(True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(args.steps):
+            f = 1 + k % (n_frames - 1)
+            tr.set_frame(frames[f], f)
+            tr.step(False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "cached frames", "steps": args.steps,
+                          "ms_per_frame_cached": round(e0.elapsed_time(e1) / args.steps, 3),
+                          "cache_keys": int(tr.stats()["n_cache"])}))
+        return 0
 
     # warmup
     for i in range(args.warmup):
