@@ -32,6 +32,7 @@ constexpr int C_NLEGS = 25;    // shadow legs of the step besides the receiver l
 constexpr int C_COH = 26;      // [26, 27] coherence read-back (min T_c bits, triggered links)
 constexpr int C_NPAIRS = 28;   // listed (source, face, edge) pairs
 constexpr int C_NEXTRA = 29;   // keys proposed into the extra-key array
+constexpr int C_NFRESH = 30;   // transmitter-side diffraction keys not in the cache
 constexpr int C_NLIST = 31;    // of those, the ones traced after the receiver legs
 constexpr int C_SCRATCH = 32;  // ints for set_scene
 
@@ -98,6 +99,7 @@ struct emrt_ctx {
     BuildTemp tmp{};
     RaySoA rays[2]{};
     int* hitlog = nullptr;
+    unsigned long long* fresh = nullptr;  // [P] transmitter-side diffraction keys, in the order made
     uint32_t* dir_perm = nullptr;
     unsigned long long* ctr = nullptr;
     unsigned long long* table = nullptr;
@@ -234,6 +236,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->ctr = cv.take<unsigned long long>(kNumCounters);
     c->table = cv.take<unsigned long long>(c->table_slots);
+    c->fresh = cv.take<unsigned long long>(c->P);
     const long long cw = compact_temp_elems((unsigned long long)c->table_slots);
     c->ctmp.flags = cv.take<uint32_t>(cw);
     c->ctmp.off = cv.take<uint32_t>(cw);
@@ -657,6 +660,7 @@ static PathArgs path_args(emrt_ctx* c) {
 static long long launch_total(const emrt_ctx* c) {
     return c->rev_n > 0 ? (long long)c->rev_n * c->rev_rays : c->n_total;
 }
+static FreshKeys fresh_keys(const emrt_ctx* c) { return FreshKeys{c->fresh, c->ctr + C_NFRESH, c->P}; }
 static KeySrc key_src(const emrt_ctx* c, const KeyRec* cache) {
     const bool rev = c->rev_n > 0;
     return KeySrc{c->hitlog, c->S.tri_face, cache, launch_total(c), rev ? c->rev_rays : c->cfg.rays_per_tx,
@@ -789,7 +793,7 @@ static void step_post(emrt_ctx* c, int discover) {
             diff_candidates_rx(pa, c->illum, c->e_words, c->rev_rx, c->rev_n, c->table, mask, src, st);
         } else if (diff) {
             rx_grid_build(c->f_rx, c->sz.n_rx, c->bins, st);
-            diff_candidates(pa, c->illum, c->e_words, c->bins, c->table, mask, src, st);
+            diff_candidates(pa, c->illum, c->e_words, c->bins, c->table, mask, src, fresh_keys(c), st);
         }
         if (diff && c->pairs) {  // one reflection and one diffraction
             ExtraKeys xk{c->extra, c->ctr + C_NEXTRA, c->P};
@@ -798,6 +802,7 @@ static void step_post(emrt_ctx* c, int discover) {
         }
         table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags,
                       c->ctmp, st);
+        if (diff && c->rev_n == 0) fresh_append(fresh_keys(c), c->ctr + C_NCAND, c->cand, c->P, src, c->flags, st);
         pa.cand = c->cand;
         pa.n_cand = c->ctr + C_NCAND;
         c->discovered = true;

@@ -258,6 +258,27 @@ __device__ __forceinline__ int table_insert(unsigned long long* table, uint64_t 
     return -1;
 }
 
+// Whether a key equal to `mine` (hash h) is in the table: a read-only probe
+// (the table is not written while it runs).  Ray references always expand to
+// specular keys, so other keys skip them without reading the hit log.
+template <int SIDE = -1>
+__device__ __forceinline__ bool table_find(const unsigned long long* table, uint64_t mask, const KeyRec& mine,
+                                           uint64_t h, const KeySrc& src) {
+    const bool spec = (mine.to & 0xff) == KT_SPEC;
+    uint64_t slot = h & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        const unsigned long long cur = table[slot];
+        if (cur == 0ULL) return false;
+        if (spec || (cur >> 62) != 1ULL) {
+            KeyRec other;
+            expand_ref<SIDE>(cur, src, other);
+            if (key_eq(other, mine)) return true;
+        }
+        slot = (slot + 1) & mask;
+    }
+    return false;
+}
+
 // --------------------------------------------------------------------------
 // rays: precomputation for the slab test and the watertight triangle test
 // (Woop, Benthin & Wald, "Watertight ray/triangle intersection", JCGT 2013)

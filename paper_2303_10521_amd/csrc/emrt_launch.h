@@ -240,8 +240,18 @@ struct RxBins {
     float4* sorted;      // [n_rx] (x, y, z, receiver index) by cell
 };
 void rx_grid_build(const double* rx_pos, int n_rx, const RxBins& b, hipStream_t st);
+// transmitter-side diffraction keys not in the cache, in the order they are made ([cap] u64 references)
+struct FreshKeys {
+    unsigned long long* ref;
+    unsigned long long* count;
+    long long cap;
+};
 void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
-                     unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st);
+                     const unsigned long long* table, unsigned long long mask, KeySrc src, const FreshKeys& fk,
+                     hipStream_t st);
+// the fresh keys expanded into cand[*n_cand, ...) and added to *n_cand (after the table's compaction)
+void fresh_append(const FreshKeys& fk, unsigned long long* n_cand, KeyRec* cand, long long cap, KeySrc src,
+                  uint32_t* flags, hipStream_t st);
 // keys proposed outside the path table's own references (reflection-diffraction candidates)
 struct ExtraKeys {
     KeyRec* key;

@@ -314,10 +314,46 @@ void rx_grid_build(const double* rx_pos, int n_rx, const RxBins& b, hipStream_t 
     hipLaunchKernelGGL(k_rx_scatter, dim3(g), dim3(256), 0, st, rx_pos, n_rx, b.grid, b.start, b.cursor, b.sorted);
 }
 
+// Transmitter-side diffraction candidates are unique by construction (one
+// wave per lit (tx, edge), each receiver in exactly one grid cell), so they
+// do not enter the path table: a lookup drops the ones the cache already
+// holds, and the rest are appended to their own list in the order they are
+// made.  That keeps the keys of one edge and nearby receivers together for
+// the construction and shadow kernels (table slots are in hash order).  A
+// wave stages its keys in LDS and reserves room for kStage of them at a time.
+constexpr int kStage = 256;
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void stage_flush(unsigned long long* st, uint32_t& ns, const FreshKeys& fk, int lane,
+                                            uint32_t* flags) {
+    if (ns == 0u) return;
+    wave_sync_lds();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(fk.count, (unsigned long long)ns);
+    base = __shfl(base, 0);
+    bool over = false;
+    for (uint32_t i = (uint32_t)lane; i < ns; i += 64u) {
+        if (base + i < (unsigned long long)fk.cap) fk.ref[base + i] = st[i];
+        else over = true;
+    }
+    if (over) atomicOr(flags, FLAG_CAND_CAP);
+    ns = 0u;
+    wave_sync_lds();
+}
+
 __global__ void __launch_bounds__(256) k_diff_cand(PathArgs a, const uint32_t* illum, int e_words, RxBins bins,
-                                                   unsigned long long* table, unsigned long long mask, KeySrc src) {
+                                                   const unsigned long long* table, unsigned long long mask,
+                                                   KeySrc src, FreshKeys fk) {
+    __shared__ unsigned long long stage[4][kStage];
     const long long n = (long long)a.f.n_tx * a.s.E;
     const int lane = lane_id();
+    unsigned long long* st = stage[threadIdx.x >> 6];
+    uint32_t ns = 0;  // keys staged by this wave (wave-uniform)
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long long n_waves = ((long long)gridDim.x * blockDim.x) >> 6;
     const RxGrid gr = *bins.grid;
@@ -353,33 +389,73 @@ __global__ void __launch_bounds__(256) k_diff_cand(PathArgs a, const uint32_t* i
                 const uint32_t idx = base + (uint32_t)lane;
                 int r = 0;  // the row holding flat index idx: rows whose prefix ends at or before it
 #pragma unroll
-                for (int st = 32; st >= 1; st >>= 1) {
-                    uint32_t v = __shfl(incl, r + st - 1);
-                    if (v <= idx) r += st;
+                for (int sp = 32; sp >= 1; sp >>= 1) {
+                    uint32_t v = __shfl(incl, r + sp - 1);
+                    if (v <= idx) r += sp;
                 }
                 const uint32_t row_j0 = __shfl(j0, r), row_before = __shfl(incl - cnt, r);
-                if (idx >= total) continue;
-                float4 p = bins.sorted[row_j0 + (idx - row_before)];
-                if (!(p.x >= qlx && p.x <= qhx && p.y >= qly && p.y <= qhy && p.z >= qlz && p.z <= qhz)) continue;
-                int rx = __float_as_int(p.w);
-                dv3 Q;
-                if (!keller_rx(w, ks, ldd3(a.f.rx_pos + 3 * rx), a.diff_max_leg, Q)) continue;
-                KeyRec key;
-                key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
-                key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
-                uint64_t h = key_hash(key.tx, key.rx, key.to, key.ids);
-                if (table_insert(table, mask, ref_diff(tx, e, rx), key, h, src) < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
+                bool keep = false;
+                int rx = 0;
+                if (idx < total) {
+                    float4 p = bins.sorted[row_j0 + (idx - row_before)];
+                    rx = __float_as_int(p.w);
+                    dv3 Q;
+                    keep = p.x >= qlx && p.x <= qhx && p.y >= qly && p.y <= qhy && p.z >= qlz && p.z <= qhz &&
+                           keller_rx(w, ks, ldd3(a.f.rx_pos + 3 * rx), a.diff_max_leg, Q);
+                    if (keep) {
+                        KeyRec key;
+                        key.tx = tx; key.rx = rx; key.to = KT_DIFF | (1 << 8);
+                        key.ids[0] = e; key.ids[1] = key.ids[2] = key.ids[3] = key.ids[4] = -1;
+                        keep = !table_find(table, mask, key, key_hash(key.tx, key.rx, key.to, key.ids), src);
+                    }
+                }
+                const uint64_t m = ballot64(keep);
+                if (ns + (uint32_t)__popcll(m) > (uint32_t)kStage) stage_flush(st, ns, fk, lane, a.flags);
+                if (keep) st[ns + (uint32_t)prefix_below(m)] = ref_diff(tx, e, rx);
+                ns += (uint32_t)__popcll(m);
             }
+        }
+    }
+    stage_flush(st, ns, fk, lane, a.flags);
+}
+
+// The fresh diffraction keys, expanded behind the table's candidates.
+__global__ void __launch_bounds__(256) k_fresh_emit(FreshKeys fk, const unsigned long long* n_cand, KeyRec* cand,
+                                                    long long cap, KeySrc src, uint32_t* flags) {
+    long long nf = (long long)*fk.count;
+    if (nf > fk.cap) nf = fk.cap;
+    const long long base = (long long)*n_cand;
+    GRID_STRIDE(i, nf) {
+        const long long pos = base + i;
+        if (pos < cap) {
+            KeyRec k;
+            expand_ref(fk.ref[i], src, k);
+            cand[pos] = k;
+        } else if (pos == cap || i == 0) {
+            atomicOr(flags, FLAG_CAND_CAP);
         }
     }
 }
 
+__global__ void k_fresh_count(unsigned long long* n_cand, FreshKeys fk) {
+    long long nf = (long long)*fk.count;
+    if (nf > fk.cap) nf = fk.cap;
+    *n_cand += (unsigned long long)nf;
+}
+
+void fresh_append(const FreshKeys& fk, unsigned long long* n_cand, KeyRec* cand, long long cap, KeySrc src,
+                  uint32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_fresh_emit, dim3(grid_for(fk.cap)), dim3(256), 0, st, fk, n_cand, cand, cap, src, flags);
+    hipLaunchKernelGGL(k_fresh_count, dim3(1), dim3(1), 0, st, n_cand, fk);
+}
+
 void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
-                     unsigned long long* table, unsigned long long mask, KeySrc src, hipStream_t st) {
+                     const unsigned long long* table, unsigned long long mask, KeySrc src, const FreshKeys& fk,
+                     hipStream_t st) {
     long long n = (long long)a.f.n_tx * a.s.E;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_diff_cand, dim3(grid_for(n, 4, 16384)), dim3(256), 0, st, a, illum, e_words, bins, table,
-                       mask, src);
+                       mask, src, fk);
 }
 
 // Edges lit from receivers (a receiver-side launch): one wave per lit
