@@ -802,6 +802,7 @@ static void step_post(emrt_ctx* c, int discover) {
         }
         table_compact(c->table, (unsigned long long)c->table_slots, src, c->cand, c->ctr + C_NCAND, c->P, c->flags,
                       c->ctmp, st);
+        cache_append(c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, c->ctr + C_NCAND, c->cand, c->P, c->flags, st);
         if (diff && c->rev_n == 0) fresh_append(fresh_keys(c), c->ctr + C_NCAND, c->cand, c->P, src, c->flags, st);
         pa.cand = c->cand;
         pa.n_cand = c->ctr + C_NCAND;

@@ -249,6 +249,10 @@ struct FreshKeys {
 void diff_candidates(const PathArgs& a, const uint32_t* illum, int e_words, const RxBins& bins,
                      const unsigned long long* table, unsigned long long mask, KeySrc src, const FreshKeys& fk,
                      hipStream_t st);
+// the previous cache copied into cand[*n_cand, ...) and added to *n_cand (after the table's compaction,
+// which leaves cache references out)
+void cache_append(const KeyRec* cache, const unsigned long long* n_cache, long long cap_cache,
+                  unsigned long long* n_cand, KeyRec* cand, long long cap, uint32_t* flags, hipStream_t st);
 // the fresh keys expanded into cand[*n_cand, ...) and added to *n_cand (after the table's compaction)
 void fresh_append(const FreshKeys& fk, unsigned long long* n_cand, KeyRec* cand, long long cap, KeySrc src,
                   uint32_t* flags, hipStream_t st);

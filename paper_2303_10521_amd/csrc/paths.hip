@@ -44,13 +44,22 @@ void cache_insert(unsigned long long* table, unsigned long long mask, const KeyR
                        flags);
 }
 
-// Table compaction without a shared counter, in slot order.  Each wave owns
+// Table compaction without a shared counter, in slot order (cache
+// references excepted, see emitted_ref).  Each wave owns
 // kCompactSpan consecutive slots: a first pass counts its occupied slots, an
 // exclusive scan of the per-wave counts gives every wave its first candidate
 // index, and a second pass re-reads the slots and places each occupied one by
 // a ballot prefix (the table is read twice; no per-slot flags or offsets).
 constexpr int kCompactIters = 64;
 constexpr long long kCompactSpan = 64LL * kCompactIters;
+
+// Cache references stay in the table (they make the rays' and the diffraction
+// candidates' copies of cached keys duplicates) but are not emitted: the
+// cache itself is appended in its own (link, key) order, which keeps
+// neighbouring keys together for validation.
+__device__ __forceinline__ bool emitted_ref(unsigned long long r) {
+    return r != 0ULL && !((r >> 62) == 2ULL && !((r >> 61) & 1ULL));
+}
 
 __global__ void __launch_bounds__(256) k_slot_count(const unsigned long long* table, unsigned long long n_slots,
                                                     uint32_t* wave_cnt, long long n_waves) {
@@ -62,7 +71,7 @@ __global__ void __launch_bounds__(256) k_slot_count(const unsigned long long* ta
 #pragma unroll 8
     for (int it = 0; it < kCompactIters; it++) {
         long long i = base + (long long)it * 64 + lane;
-        c += (i < (long long)n_slots && table[i] != 0ULL) ? 1u : 0u;
+        c += (i < (long long)n_slots && emitted_ref(table[i])) ? 1u : 0u;
     }
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if (lane == 0) wave_cnt[w] = c;
@@ -80,8 +89,9 @@ __global__ void __launch_bounds__(256) k_table_emit(const unsigned long long* ta
     for (int it = 0; it < kCompactIters; it++) {
         long long i = base + (long long)it * 64 + lane;
         unsigned long long ref = i < (long long)n_slots ? table[i] : 0ULL;
-        uint64_t m = ballot64(ref != 0ULL);
-        if (ref != 0ULL) {
+        const bool emit = emitted_ref(ref);
+        uint64_t m = ballot64(emit);
+        if (emit) {
             long long pos = (long long)(pos0 + (unsigned long long)prefix_below(m));
             if (pos < cap) {
                 KeyRec k;
@@ -441,6 +451,33 @@ __global__ void k_fresh_count(unsigned long long* n_cand, FreshKeys fk) {
     long long nf = (long long)*fk.count;
     if (nf > fk.cap) nf = fk.cap;
     *n_cand += (unsigned long long)nf;
+}
+
+// The previous cache behind the table's candidates, in its own order.
+__global__ void __launch_bounds__(256) k_cache_emit(const KeyRec* cache, const unsigned long long* n_cache,
+                                                    long long cap_cache, const unsigned long long* n_cand,
+                                                    KeyRec* cand, long long cap, uint32_t* flags) {
+    long long nc = (long long)*n_cache;
+    if (nc > cap_cache) nc = cap_cache;
+    const long long base = (long long)*n_cand;
+    GRID_STRIDE(i, nc) {
+        const long long pos = base + i;
+        if (pos < cap) cand[pos] = cache[i];
+        else if (pos == cap || i == 0) atomicOr(flags, FLAG_CAND_CAP);
+    }
+}
+
+__global__ void k_cache_count(unsigned long long* n_cand, const unsigned long long* n_cache, long long cap_cache) {
+    long long nc = (long long)*n_cache;
+    if (nc > cap_cache) nc = cap_cache;
+    *n_cand += (unsigned long long)nc;
+}
+
+void cache_append(const KeyRec* cache, const unsigned long long* n_cache, long long cap_cache,
+                  unsigned long long* n_cand, KeyRec* cand, long long cap, uint32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_cache_emit, dim3(grid_for(cap_cache)), dim3(256), 0, st, cache, n_cache, cap_cache, n_cand,
+                       cand, cap, flags);
+    hipLaunchKernelGGL(k_cache_count, dim3(1), dim3(1), 0, st, n_cand, n_cache, cap_cache);
 }
 
 void fresh_append(const FreshKeys& fk, unsigned long long* n_cand, KeyRec* cand, long long cap, KeySrc src,
