@@ -100,6 +100,10 @@ struct emrt_ctx {
     RaySoA rays[2]{};
     int* hitlog = nullptr;
     unsigned long long* fresh = nullptr;  // [P] transmitter-side diffraction keys, in the order made
+    // last step's end points and static line-of-sight tests (reused when nothing moved)
+    double *prev_tx = nullptr, *prev_rx = nullptr;
+    uint8_t *moved_tx = nullptr, *moved_rx = nullptr, *los_sb = nullptr;
+    uint32_t* hist = nullptr;  // device flag: 1 once a step has run on this scene and cache
     uint32_t* dir_perm = nullptr;
     unsigned long long* ctr = nullptr;
     unsigned long long* table = nullptr;
@@ -237,6 +241,12 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->ctr = cv.take<unsigned long long>(kNumCounters);
     c->table = cv.take<unsigned long long>(c->table_slots);
     c->fresh = cv.take<unsigned long long>(c->P);
+    c->prev_tx = cv.take<double>(3LL * z.n_tx);
+    c->prev_rx = cv.take<double>(3LL * z.n_rx);
+    c->moved_tx = cv.take<uint8_t>(z.n_tx);
+    c->moved_rx = cv.take<uint8_t>(z.n_rx);
+    c->los_sb = cv.take<uint8_t>(c->n_links);
+    c->hist = cv.take<uint32_t>(1);
     const long long cw = compact_temp_elems((unsigned long long)c->table_slots);
     c->ctmp.flags = cv.take<uint32_t>(cw);
     c->ctmp.off = cv.take<uint32_t>(cw);
@@ -431,6 +441,7 @@ int32_t emrt_bind_workspace(emrt_ctx* c, void* ptr, size_t bytes) {
     c->scene_set = c->frame_set = c->stepped = false;
     fill_u64(c->ctr, 0ULL, kNumCounters, c->stream);
     fill_u32(c->flags, 0u, 16, c->stream);
+    fill_u32(c->hist, 0u, 1, c->stream);
     coherence_clear(c);
     return EMRT_OK;
 }
@@ -548,6 +559,7 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     c->dy.n = 0;
     ray_order(c->cfg.rays_per_tx, c->dir_perm, c->tmp, st);
     // empty cache
+    fill_u32(c->hist, 0u, 1, st);  // a new scene: nothing from an earlier step carries over
     fill_u64(c->ctr, 0ULL, kNumCounters, st);
     c->cur = 0;
     c->scene_set = true;
@@ -644,6 +656,9 @@ static PathArgs path_args(emrt_ctx* c) {
     a.legs.n_list = c->ctr + C_NLIST;
     a.state = c->kstate;
     a.occl = c->occl;
+    a.moved_tx = c->moved_tx;
+    a.moved_rx = c->moved_rx;
+    a.los_sb = c->los_sb;
     a.ktri = c->ktri;
     a.flags = c->flags;
     return a;
@@ -721,6 +736,9 @@ static void step_pre(emrt_ctx* c, int discover) {
         ev_flush(c, set);
         set.used = set.bounce_end = 0;
     }
+    // end points that moved since the last step (all of them when there is none)
+    endpoints_moved(c->f_tx, c->prev_tx, c->sz.n_tx, c->moved_tx, c->hist, st);
+    endpoints_moved(c->f_rx, c->prev_rx, c->sz.n_rx, c->moved_rx, c->hist, st);
     // ---- frame geometry (Section II-A: BVH updated between frames)
     scene_world(S, c->f_xf, c->flags, st);
     scene_planes(S, st);
@@ -811,6 +829,7 @@ static void step_post(emrt_ctx* c, int discover) {
     } else {
         pa.cand = c->cache[c->cur];
         pa.n_cand = c->ctr + C_NCACHE + c->cur;
+        pa.cand_cached = 1;
     }
     // ---- exact validation + fields (Sections II-A, III-B, III-C)
     ev_record(c);
@@ -830,6 +849,7 @@ static void step_post(emrt_ctx* c, int discover) {
     exclusive_scan(c->link_cnt, c->link_off, c->n_links, c->scan_tmp, (uint32_t*)(c->ctr + C_NCACHE + nxt), st);
     fill_u32(((uint32_t*)(c->ctr + C_NCACHE + nxt)) + 1, 0u, 1, st);  // high word of the u64 count
     cache_write(c->vp, c->order, c->link_start, c->link_end, c->link_off, c->n_links, c->cache[nxt], st);
+    fill_u32(c->hist, 1u, 1, st);  // the cache, end points and line-of-sight tests now belong together
     c->cur = nxt;
     c->stepped = true;
     c->frame_since_step = false;
@@ -1042,6 +1062,7 @@ int32_t emrt_cache_import(emrt_ctx* c, const int32_t* keys, int64_t n) {
     if (!c->scene_set) return fail(c, EMRT_E_STATE, "set_scene first");
     if (n > c->P) return fail(c, EMRT_E_INVALID, "more keys than path_capacity");
     keys_import(keys, n, c->cache[c->cur], c->stream);
+    fill_u32(c->hist, 0u, 1, c->stream);  // imported keys were not validated here
     unsigned long long v = (unsigned long long)n;
     HC(hipMemcpyAsync(c->ctr + C_NCACHE + c->cur, &v, sizeof(v), hipMemcpyHostToDevice, c->stream));
     return hip_check(c, hipStreamSynchronize(c->stream), "cache_import");

@@ -217,6 +217,11 @@ struct PathArgs {
     FieldCtx fc;
     double diff_max_leg;
     int combined;     // one reflection with one diffraction in use (types 3 and 4 valid)
+    // reuse of last step's tests against the static scene (the static tree never changes)
+    const uint8_t* moved_tx;  // [n_tx] 1 = moved since the last step (or no last step)
+    const uint8_t* moved_rx;  // [n_rx]
+    uint8_t* los_sb;          // [n_links] 1 = line of sight blocked by the static scene at the last test
+    int cand_cached;          // the candidates are last step's valid keys (a cached frame)
     // inputs
     const KeyRec* cand;
     const unsigned long long* n_cand;
@@ -224,6 +229,8 @@ struct PathArgs {
     uint32_t* flags;
 };
 
+// moved[i] = position i differs from prev (or *hist == 0); prev := position
+void endpoints_moved(const double* pos, double* prev, int n, uint8_t* moved, const uint32_t* hist, hipStream_t st);
 void cache_insert(unsigned long long* table, unsigned long long mask, const KeyRec* cache,
                   const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags, hipStream_t st);
 // receivers binned on a kGridN x kGridN grid over their x-y bounding box

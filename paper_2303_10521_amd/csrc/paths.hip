@@ -26,6 +26,45 @@ static int grid_for(long long n, int block = 256, int cap = 8192) {
     return (int)g;
 }
 
+// ------------------------------------------------- temporal coherence ----
+// The static tree is built once per scene.  A key whose end points did not
+// move since the last step and whose faces (and edge) are static has the
+// same legs as then, so its tests against the static tree give the same
+// answers: a key valid at the last step is clear of the static scene, and a
+// line of sight the static scene blocked is still blocked.  Only the dynamic
+// tree is tested for such keys; everything else is tested in full.
+__global__ void k_endpoints_moved(const double* pos, double* prev, int n, uint8_t* moved, const uint32_t* hist) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const bool same = *hist && x == prev[3 * i] && y == prev[3 * i + 1] && z == prev[3 * i + 2];
+    moved[i] = same ? 0 : 1;
+    prev[3 * i] = x;
+    prev[3 * i + 1] = y;
+    prev[3 * i + 2] = z;
+}
+
+void endpoints_moved(const double* pos, double* prev, int n, uint8_t* moved, const uint32_t* hist, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_endpoints_moved, dim3((n + 255) / 256), dim3(256), 0, st, pos, prev, n, moved, hist);
+}
+
+__device__ __forceinline__ bool key_static(const SceneDev& S, const KeyRec& key) {
+    const int type = key.to & 0xff, order = key.to >> 8;
+    if (type == KT_SPEC) {
+        bool st = true;
+#pragma unroll
+        for (int j = 0; j < EMRT_KMAX; j++)
+            if (j < order && S.face_dyn[key.ids[j]] >= 0) st = false;
+        return st;
+    }
+    if (type == KT_DIFF) return S.face_dyn[S.edge_i[6 * (long long)key.ids[0] + 2]] < 0;
+    if (type == KT_RD || type == KT_DR) {
+        const int f = type == KT_RD ? key.ids[0] : key.ids[1], e = type == KT_RD ? key.ids[1] : key.ids[0];
+        return S.face_dyn[f] < 0 && S.face_dyn[S.edge_i[6 * (long long)e + 2]] < 0;
+    }
+    return true;
+}
+
 // ------------------------------------------------------------- tables ----
 __global__ void k_cache_insert(unsigned long long* table, unsigned long long mask, const KeyRec* cache,
                                const unsigned long long* n_cache, long long cap, KeySrc src, uint32_t* flags) {
@@ -836,8 +875,20 @@ __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links
         if (ok) {
             key = key_at(a, q, n_links);
             ok = key_in_range(a, key) && construct(a, key, g);
-            a.state[q] = ok ? (uint8_t)1 : (uint8_t)0;
-            a.occl[q] = 0u;
+            // state: 0 not constructed, 1 test every leg in full, 3 the
+            // dynamic tree only (clear of the static scene, as at the last step)
+            uint8_t stv = ok ? (uint8_t)1 : (uint8_t)0;
+            uint32_t oc = 0u;
+            if (ok && !a.moved_tx[key.tx] && !a.moved_rx[key.rx]) {
+                if (q < n_links) {
+                    if (a.los_sb[q]) oc = 1u;  // still blocked by the static scene
+                    else stv = 3;
+                } else if (a.cand_cached && key_static(a.s, key)) {
+                    stv = 3;
+                }
+            }
+            a.state[q] = stv;
+            a.occl[q] = oc;
             if (ok) {
 #pragma unroll
                 for (int j = 0; j < EMRT_KMAX; j++) a.ktri[5 * q + j] = g.tri[j];
@@ -882,18 +933,25 @@ __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links
 // at its first hit.  The other legs of the keys still open are then listed
 // densely and traced.  Whether a key is occluded does not depend on the order
 // of its legs.
-__device__ __forceinline__ void shadow_leg(const PathArgs& a, long long i, uint32_t q) {
+// dyn_only: the leg is known clear of the static scene; los: a line of sight
+// tested in full, whose static result is kept for the next step
+__device__ __forceinline__ void shadow_leg(const PathArgs& a, long long i, uint32_t q, bool dyn_only, bool los) {
     RayPre r = ray_pre(a.legs.ox[i], a.legs.oy[i], a.legs.oz[i], a.legs.dx[i], a.legs.dy[i], a.legs.dz[i]);
     int xa = a.legs.xa[i], xb = a.legs.xb[i], xc = a.legs.xc[i];
-    if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc) || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc))
-        a.occl[q] = 1u;
+    bool hit = false;
+    if (!dyn_only) {
+        hit = any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc);
+        if (los) a.los_sb[q] = hit ? 1 : 0;
+    }
+    if (hit || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc)) a.occl[q] = 1u;
 }
 
 __global__ void __launch_bounds__(256) k_shadow_first(PathArgs a, long long n_links, long long cap_cand) {
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     GRID_STRIDE(q, n_links + nc) {
-        if (a.state[q]) shadow_leg(a, q, (uint32_t)q);
+        const uint8_t stv = a.state[q];
+        if (stv && !a.occl[q]) shadow_leg(a, q, (uint32_t)q, stv == 3, q < n_links);
     }
 }
 
@@ -944,7 +1002,7 @@ __global__ void __launch_bounds__(256) k_shadow_rest(PathArgs a) {
     GRID_STRIDE(k, n) {
         long long i = a.legs.cap_first + (long long)a.legs.list[k];
         uint32_t q = a.legs.key[i];
-        if (!a.occl[q]) shadow_leg(a, i, q);
+        if (!a.occl[q]) shadow_leg(a, i, q, a.state[q] == 3, false);
     }
 }
 

@@ -263,6 +263,36 @@ def test_district_resume_from_exported_cache(district):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_district_static_reuse_equals_full_tests(district):
+    """Cached frames reuse the last step's tests against the static scene for
+    keys whose end points did not move (static receivers, and every key when
+    a frame is stepped twice).  A context that imports the same cache has no
+    last step and tests everything in full: channels and the next cache are
+    identical, frame after frame."""
+    w, sc = district["w"], district["sc"]
+    tr = district["tr"]
+    tr.set_frame(district["frames"][0], 0)
+    tr.step(True)
+    tr2 = _tracer(sc, w, path_capacity=1 << 23)
+    for f in (1, 2, 2, 3):  # frame 2 twice: nothing moves between those steps
+        keys = tr.cache_export()
+        fr = district["frames"][f]
+        tr.set_frame(fr, f)
+        tr.step(False)
+        assert tr.sync() == 0
+        tr2.cache_import(keys)
+        tr2.set_frame(fr, f)
+        tr2.step(False)
+        assert tr2.sync() == 0
+        a, b = P.gpu_channels_np(tr.channels()), P.gpu_channels_np(tr2.channels())
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (f, k)
+        assert P.keyset(tr.cache_export()) == P.keyset(tr2.cache_export()), f
+    tr2.close()
+    tr.set_frame(district["frames"][0], 0)
+    tr.step(True)
+
+
 # ------------------------------------------- 2x2 km city at full size
 def test_city_full_size_sampled():
     """The benchmark workload (16 Tx x 1M rays, K = 5, diffraction, 10k Rx,
