@@ -104,7 +104,8 @@ struct emrt_ctx {
     double *prev_tx = nullptr, *prev_rx = nullptr;
     uint8_t *moved_tx = nullptr, *moved_rx = nullptr, *los_sb = nullptr;
     uint32_t* hist = nullptr;  // device flag: 1 once a step has run on this scene and cache
-    uint32_t* dir_perm = nullptr;
+    uint32_t* dir_perm = nullptr;  // launch slot -> direction index (direction-Morton order)
+    uint32_t* dir_slot = nullptr;  // direction index -> launch slot
     unsigned long long* ctr = nullptr;
     unsigned long long* table = nullptr;
     KeyRec* cand = nullptr;
@@ -238,6 +239,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     }
     c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
+    c->dir_slot = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->ctr = cv.take<unsigned long long>(kNumCounters);
     c->table = cv.take<unsigned long long>(c->table_slots);
     c->fresh = cv.take<unsigned long long>(c->P);
@@ -558,6 +560,7 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     }
     c->dy.n = 0;
     ray_order(c->cfg.rays_per_tx, c->dir_perm, c->tmp, st);
+    invert_perm(c->dir_perm, c->dir_slot, c->cfg.rays_per_tx, st);
     // empty cache
     fill_u32(c->hist, 0u, 1, st);  // a new scene: nothing from an earlier step carries over
     fill_u64(c->ctr, 0ULL, kNumCounters, st);
@@ -1032,7 +1035,7 @@ int32_t emrt_debug_ray_records(emrt_ctx* c, int32_t tx, const int32_t* ray_ids, 
     if (!c || (n > 0 && (!ray_ids || !out)) || tx < 0 || tx >= c->sz.n_tx) return fail(c, EMRT_E_INVALID, "bad arguments");
     if (!c->discovered) return fail(c, EMRT_E_STATE, "no discovery step yet");
     if (c->last_rev) return fail(c, EMRT_E_STATE, "the last discovery step launched from receivers");
-    debug_rays(c->hitlog, c->n_total, c->K, tx, c->cfg.rays_per_tx, ray_ids, n, out, c->stream);
+    debug_rays(c->hitlog, c->n_total, c->K, tx, c->cfg.rays_per_tx, c->dir_slot, ray_ids, n, out, c->stream);
     return hip_check(c, hipGetLastError(), "debug_ray_records");
 }
 

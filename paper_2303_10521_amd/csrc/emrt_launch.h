@@ -156,8 +156,10 @@ void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
 // one launch over several scenes' live rays (args device [n_scenes]; chunk_off [n_scenes + 1], work: scratch)
 void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid,
                   hipStream_t st);
-void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ray_ids, int n, int* out,
-                hipStream_t st);
+void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const uint32_t* slot_of,
+                const int* ray_ids, int n, int* out, hipStream_t st);
+// inv[perm[t]] = t
+void invert_perm(const uint32_t* perm, uint32_t* inv, int n, hipStream_t st);
 
 // ----------------------------------------------------------- paths.hip ----
 struct FrameDev {

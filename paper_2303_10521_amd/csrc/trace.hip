@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k_raygen(const double* tx_pos, int n_tx, 
     out.dy[k] = y;
     out.dz[k] = z;
     out.L[k] = 0.0f;
-    out.id[k] = (uint32_t)tx * (uint32_t)N + i;
+    out.id[k] = (uint32_t)k;  // the launch slot: the hit log rows are then written in launch order
     out.prev[k] = -1;
 }
 
@@ -353,19 +353,30 @@ void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uin
     hipLaunchKernelGGL(k_bounce_multi, dim3(grid), dim3(256), 0, st, args, chunk_off, work, n_scenes);
 }
 
-__global__ void k_debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ids, int n,
-                             int* out) {
+// Hit log of launch direction i of transmitter tx (slot_of[i]: its launch slot).
+__global__ void k_debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const uint32_t* slot_of,
+                             const int* ids, int n, int* out) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int i = ids[k];
+    const long long ray = (i >= 0 && i < N) ? (long long)tx * N + slot_of[i] : -1;
     for (int b = 0; b <= K; b++)
-        out[(long long)k * (K + 1) + b] = (i >= 0 && i < N) ? hitlog[(long long)b * n_total + (long long)tx * N + i] : -3;
+        out[(long long)k * (K + 1) + b] = ray >= 0 ? hitlog[(long long)b * n_total + ray] : -3;
 }
 
-void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const int* ray_ids, int n, int* out,
-                hipStream_t st) {
+void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const uint32_t* slot_of,
+                const int* ray_ids, int n, int* out, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_debug_rays, dim3((n + 255) / 256), dim3(256), 0, st, hitlog, n_total, K, tx, N,
-                                  ray_ids, n, out);
+                                  slot_of, ray_ids, n, out);
+}
+
+__global__ void k_invert_perm(const uint32_t* perm, uint32_t* inv, int n) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) inv[perm[t]] = (uint32_t)t;
+}
+
+void invert_perm(const uint32_t* perm, uint32_t* inv, int n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_invert_perm, dim3((n + 255) / 256), dim3(256), 0, st, perm, inv, n);
 }
 
 }  // namespace emrt
