@@ -106,6 +106,7 @@ struct emrt_ctx {
     uint32_t* hist = nullptr;  // device flag: 1 once a step has run on this scene and cache
     uint32_t* dir_perm = nullptr;  // launch slot -> direction index (direction-Morton order)
     uint32_t* dir_slot = nullptr;  // direction index -> launch slot
+    float4* dirs = nullptr;        // [rays_per_tx] launch directions in launch order
     unsigned long long* ctr = nullptr;
     unsigned long long* table = nullptr;
     KeyRec* cand = nullptr;
@@ -240,6 +241,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->dir_slot = cv.take<uint32_t>(c->cfg.rays_per_tx);
+    c->dirs = cv.take<float4>(c->cfg.rays_per_tx);
     c->ctr = cv.take<unsigned long long>(kNumCounters);
     c->table = cv.take<unsigned long long>(c->table_slots);
     c->fresh = cv.take<unsigned long long>(c->P);
@@ -561,6 +563,7 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     c->dy.n = 0;
     ray_order(c->cfg.rays_per_tx, c->dir_perm, c->tmp, st);
     invert_perm(c->dir_perm, c->dir_slot, c->cfg.rays_per_tx, st);
+    dir_table(c->dir_perm, c->cfg.rays_per_tx, c->dirs, st);
     // empty cache
     fill_u32(c->hist, 0u, 1, st);  // a new scene: nothing from an earlier step carries over
     fill_u64(c->ctr, 0ULL, kNumCounters, st);
@@ -721,6 +724,11 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.in = c->rays[k & 1];
     b.out = c->rays[(k + 1) & 1];
     b.n_in = c->ctr + C_RAYS + k;
+    if (k == 0 && !rev) {
+        b.gen_dirs = c->dirs;
+        b.gen_src = c->f_tx;
+        b.gen_N = c->cfg.rays_per_tx;
+    }
     b.n_out = c->ctr + C_RAYS + k + 1;
     b.work = (unsigned int*)(c->ctr + C_WORK + k);
     return b;
@@ -785,7 +793,8 @@ static void step_pre(emrt_ctx* c, int discover) {
             gather_rx(c->f_rx, c->rev_rx, c->rev_n, c->rev_pos, st);
             raygen(c->rev_pos, c->rev_n, c->rev_rays, nullptr, c->rays[0], c->ctr + C_RAYS, st);
         } else {
-            raygen(c->f_tx, c->sz.n_tx, c->cfg.rays_per_tx, c->dir_perm, c->rays[0], c->ctr + C_RAYS, st);
+            // the primary rays are made by the first bounce launch (bounce_args)
+            fill_u64(c->ctr + C_RAYS, (unsigned long long)c->n_total, 1, st);
         }
     }
 }

@@ -147,8 +147,15 @@ struct BounceArgs {
     int* hitlog;
     uint32_t* flags;
     unsigned long long* stats;  // [4] node visits, triangle tests, segments, captures (STATS only)
+    // bounce 0 of a transmitter-side launch makes its rays itself: ray k leaves
+    // source k / gen_N along gen_dirs[k % gen_N] (null: read `in`)
+    const float4* gen_dirs;
+    const double* gen_src;
+    int gen_N;
 };
 void ray_order(int N, uint32_t* perm, const BuildTemp& tmp, hipStream_t st);
+// the N launch directions in launch order (perm: direction index of each slot)
+void dir_table(const uint32_t* perm, int N, float4* dirs, hipStream_t st);
 // sources src_pos [n_src][3], N directions each; perm: launch order of the directions (null: index order)
 void raygen(const double* src_pos, int n_src, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
             hipStream_t st);

@@ -88,6 +88,18 @@ __global__ void __launch_bounds__(256) k_raygen(const double* tx_pos, int n_tx, 
     out.prev[k] = -1;
 }
 
+__global__ void k_dir_table(const uint32_t* perm, int N, float4* dirs) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    float x, y, z;
+    fib_dir(perm[t], N, x, y, z);
+    dirs[t] = make_float4(x, y, z, 0.0f);
+}
+
+void dir_table(const uint32_t* perm, int N, float4* dirs, hipStream_t st) {
+    if (N > 0) hipLaunchKernelGGL(k_dir_table, dim3((N + 255) / 256), dim3(256), 0, st, perm, N, dirs);
+}
+
 void raygen(const double* tx_pos, int n_tx, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
             hipStream_t st) {
     long long total = (long long)n_tx * N;
@@ -120,7 +132,13 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, L = 0;
     uint32_t id = 0;
     int prev = -1;
-    if (act) {
+    if (act && a.gen_dirs) {  // primary ray: the same values k_raygen would store
+        const long long src = (long long)(i / (unsigned long long)a.gen_N);
+        const float4 d = a.gen_dirs[i - (unsigned long long)src * (unsigned long long)a.gen_N];
+        ox = (float)a.gen_src[3 * src]; oy = (float)a.gen_src[3 * src + 1]; oz = (float)a.gen_src[3 * src + 2];
+        dx = d.x; dy = d.y; dz = d.z;
+        id = (uint32_t)i;
+    } else if (act) {
         ox = a.in.ox[i]; oy = a.in.oy[i]; oz = a.in.oz[i];
         dx = a.in.dx[i]; dy = a.in.dy[i]; dz = a.in.dz[i];
         L = a.in.L[i];
