@@ -99,6 +99,7 @@ struct emrt_ctx {
     BuildTemp tmp{};
     RaySoA rays[2]{};
     int* hitlog = nullptr;
+    uint8_t* depth = nullptr;  // [n_total] bounce at which each ray of the last discovery launch ended
     unsigned long long* fresh = nullptr;  // [P] transmitter-side diffraction keys, in the order made
     // last step's end points and static line-of-sight tests (reused when nothing moved)
     double *prev_tx = nullptr, *prev_rx = nullptr;
@@ -239,6 +240,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
         r.prev = cv.take<int>(c->n_total);
     }
     c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
+    c->depth = cv.take<uint8_t>(c->n_total);
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->dir_slot = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->dirs = cv.take<float4>(c->cfg.rays_per_tx);
@@ -718,6 +720,7 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.mask = (unsigned long long)c->table_slots - 1ULL;
     b.src = key_src(c, c->cache[parity]);
     b.hitlog = c->hitlog;
+    b.depth = c->depth;
     b.flags = c->flags;
     b.stats = c->ctr + C_STATS;
     b.b = k;
@@ -737,7 +740,6 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
 static void step_pre(emrt_ctx* c, int discover) {
     hipStream_t st = c->stream;
     SceneDev& S = c->S;
-    const int K = c->K;
     // counters: keep the cache sizes, clear the rest
     fill_u64(c->ctr + C_RAYS, 0ULL, C_NCACHE - C_RAYS, st);
     fill_u64(c->ctr + C_STATS, 0ULL, kNumCounters - C_STATS, st);
@@ -785,7 +787,6 @@ static void step_pre(emrt_ctx* c, int discover) {
         const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
         const int n_src = rev ? c->rev_n : c->sz.n_tx;
         fill_u64(c->table, 0ULL, c->table_slots, st);
-        fill_u32((uint32_t*)c->hitlog, 0xFFFFFFFEu, (long long)(K + 1) * launch_total(c), st);
         if (diff) fill_u32(c->illum, 0u, (long long)n_src * c->e_words, st);
         if (diff && c->pairs) fill_u64(c->pairs, 0ULL, c->pair_slots, st);
         cache_insert(c->table, mask, c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, src, c->flags, st);
@@ -1044,7 +1045,8 @@ int32_t emrt_debug_ray_records(emrt_ctx* c, int32_t tx, const int32_t* ray_ids, 
     if (!c || (n > 0 && (!ray_ids || !out)) || tx < 0 || tx >= c->sz.n_tx) return fail(c, EMRT_E_INVALID, "bad arguments");
     if (!c->discovered) return fail(c, EMRT_E_STATE, "no discovery step yet");
     if (c->last_rev) return fail(c, EMRT_E_STATE, "the last discovery step launched from receivers");
-    debug_rays(c->hitlog, c->n_total, c->K, tx, c->cfg.rays_per_tx, c->dir_slot, ray_ids, n, out, c->stream);
+    debug_rays(c->hitlog, c->depth, c->n_total, c->K, tx, c->cfg.rays_per_tx, c->dir_slot, ray_ids, n, out,
+               c->stream);
     return hip_check(c, hipGetLastError(), "debug_ray_records");
 }
 

@@ -145,6 +145,7 @@ struct BounceArgs {
     unsigned long long mask;
     KeySrc src;
     int* hitlog;
+    uint8_t* depth;             // [n_total] the bounce at which each ray ended (hit log rows beyond it are stale)
     uint32_t* flags;
     unsigned long long* stats;  // [4] node visits, triangle tests, segments, captures (STATS only)
     // bounce 0 of a transmitter-side launch makes its rays itself: ray k leaves
@@ -163,8 +164,8 @@ void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
 // one launch over several scenes' live rays (args device [n_scenes]; chunk_off [n_scenes + 1], work: scratch)
 void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid,
                   hipStream_t st);
-void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const uint32_t* slot_of,
-                const int* ray_ids, int n, int* out, hipStream_t st);
+void debug_rays(const int* hitlog, const uint8_t* depth, long long n_total, int K, int tx, int N,
+                const uint32_t* slot_of, const int* ray_ids, int n, int* out, hipStream_t st);
 // inv[perm[t]] = t
 void invert_perm(const uint32_t* perm, uint32_t* inv, int n, hipStream_t st);
 

@@ -235,6 +235,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
 
     // specular reflection about the face plane
     bool alive = hit && b < a.K;
+    if (act && !alive) a.depth[id] = (uint8_t)b;
     float nox = 0, noy = 0, noz = 0, ndx = 0, ndy = 0, ndz = 0;
     if (alive) {
         const double* pl = a.plane + 4 * (long long)best_face;
@@ -372,20 +373,23 @@ void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uin
 }
 
 // Hit log of launch direction i of transmitter tx (slot_of[i]: its launch slot).
-__global__ void k_debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const uint32_t* slot_of,
-                             const int* ids, int n, int* out) {
+// Hit log of launch direction i of transmitter tx (slot_of[i]: its launch
+// slot); rows after the bounce at which the ray ended read -2.
+__global__ void k_debug_rays(const int* hitlog, const uint8_t* depth, long long n_total, int K, int tx, int N,
+                             const uint32_t* slot_of, const int* ids, int n, int* out) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int i = ids[k];
     const long long ray = (i >= 0 && i < N) ? (long long)tx * N + slot_of[i] : -1;
+    const int last = ray >= 0 ? (int)depth[ray] : -1;
     for (int b = 0; b <= K; b++)
-        out[(long long)k * (K + 1) + b] = ray >= 0 ? hitlog[(long long)b * n_total + ray] : -3;
+        out[(long long)k * (K + 1) + b] = ray < 0 ? -3 : (b <= last ? hitlog[(long long)b * n_total + ray] : -2);
 }
 
-void debug_rays(const int* hitlog, long long n_total, int K, int tx, int N, const uint32_t* slot_of,
-                const int* ray_ids, int n, int* out, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_debug_rays, dim3((n + 255) / 256), dim3(256), 0, st, hitlog, n_total, K, tx, N,
-                                  slot_of, ray_ids, n, out);
+void debug_rays(const int* hitlog, const uint8_t* depth, long long n_total, int K, int tx, int N,
+                const uint32_t* slot_of, const int* ray_ids, int n, int* out, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_debug_rays, dim3((n + 255) / 256), dim3(256), 0, st, hitlog, depth, n_total, K,
+                                  tx, N, slot_of, ray_ids, n, out);
 }
 
 __global__ void k_invert_perm(const uint32_t* perm, uint32_t* inv, int n) {
