@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define EMRT_LEAF 0x80000000u
 #define EMRT_SIDE 0x80000000u
 #define EMRT_KMAX 5
@@ -407,6 +409,23 @@ __device__ __forceinline__ int near_side(const BNode& nd, const RayPre& r) {
     return (r.negmask >> axis) & 1;
 }
 
+// The per-ray stack of node ids.  A private array indexed by each lane's own
+// depth compiles to a chain of compares and selects over all its entries at
+// every push and pop; kernels that can spare the LDS hand the traversal one
+// column of a [kStackDepth][kStackStride] block array instead (one LDS access
+// per push or pop; lanes of a wave sit in distinct banks at any depths).
+struct RegStack {
+    int s[kStackDepth];
+    __device__ __forceinline__ int get(int i) const { return s[i]; }
+    __device__ __forceinline__ void set(int i, int v) { s[i] = v; }
+};
+constexpr int kStackStride = 256;  // threads per block of the kernels that use LdsStack
+struct LdsStack {
+    int* p;  // &column[0][threadIdx.x]
+    __device__ __forceinline__ int get(int i) const { return p[i * kStackStride]; }
+    __device__ __forceinline__ void set(int i, int v) { p[i * kStackStride] = v; }
+};
+
 // Stackless walk over parent links.  State per ray: the current internal
 // node and what is left to do there: 0 test the first child, 1 test the
 // second child, 2 climb to the parent, 3 just climbed back from child `came`
@@ -448,9 +467,8 @@ __device__ __forceinline__ void traverse_stackless(const BNode* nodes, const Ray
 // Generic driver.  test(box, child, tn) returns true to descend into `child`
 // (an internal node; tn = the box's entry distance); it handles leaves itself
 // and returns false for them.  Returns early when stop() is true.
-template <bool ORDERED, class Test, class Stop>
-__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Stop stop) {
-    int stk_node[kStackDepth];
+template <bool ORDERED, class Stk, class Test, class Stop>
+__device__ __forceinline__ void traverse_with(const BNode* nodes, const RayPre& r, Test test, Stop stop, Stk& stk) {
     int sp = 0, cur = 0;
     bool overflow = false;
     while (true) {
@@ -468,7 +486,7 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
         if (da) {
             if (db) {
                 if (sp == kStackDepth) { overflow = true; break; }
-                stk_node[sp] = cb;
+                stk.set(sp, cb);
                 sp++;
             }
             cur = ca;
@@ -479,9 +497,20 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
             continue;
         }
         if (sp == 0) return;
-        cur = stk_node[--sp];
+        cur = stk.get(--sp);
     }
     if (overflow) traverse_stackless<ORDERED>(nodes, r, test, stop);
+}
+
+// stk null: a private register stack
+template <bool ORDERED, class Stk, class Test, class Stop>
+__device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Test test, Stop stop, Stk* stk) {
+    if constexpr (std::is_same<Stk, RegStack>::value) {
+        RegStack own;
+        traverse_with<ORDERED>(nodes, r, test, stop, own);
+    } else {
+        traverse_with<ORDERED>(nodes, r, test, stop, *stk);
+    }
 }
 
 struct NoStop { __device__ bool operator()() const { return false; } };
@@ -489,10 +518,10 @@ struct NoStop { __device__ bool operator()() const { return false; } };
 // Closest hit among triangles not on face `skip_face`.  best_t / best_tri /
 // best_face carry the current best (ties broken by the lowest triangle id),
 // so the result does not depend on the tree or the visiting order.
-template <bool STATS>
+template <bool STATS, class Stk = RegStack>
 __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, int skip_face,
                                             float& best_t, int& best_tri, int& best_face, unsigned& n_nodes,
-                                            unsigned& n_tris) {
+                                            unsigned& n_tris, Stk* stk = nullptr) {
     if (bvh.n_prims <= 0) return;
     if (STATS) n_nodes++;
     traverse<true>(bvh.nodes, r,
@@ -509,13 +538,14 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
             }
             return false;
         },
-        NoStop());
+        NoStop(), stk);
 }
 
 // Any hit on the open segment t in (0, tmax) among triangles not on faces
 // xa / xb / xc (shadow rays of path validation).
+template <class Stk = RegStack>
 __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, float tmax, int xa, int xb,
-                                        int xc = -1) {
+                                        int xc = -1, Stk* stk = nullptr) {
     if (bvh.n_prims <= 0) return false;
     bool found = false;
     traverse<true>(bvh.nodes, r,
@@ -528,13 +558,14 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
             if (face != xa && face != xb && face != xc && tri_hit(p, r, t) && t < tmax) found = true;
             return false;
         },
-        [&]() { return found; });
+        [&]() { return found; }, stk);
     return found;
 }
 
 // Visit every leaf whose box, inflated by `grow`, meets the ray on [0, tmax].
-template <class Leaf>
-__device__ __forceinline__ void all_hits(const Bvh& bvh, const RayPre& r, float tmax, float grow, Leaf leaf) {
+template <class Leaf, class Stk = RegStack>
+__device__ __forceinline__ void all_hits(const Bvh& bvh, const RayPre& r, float tmax, float grow, Leaf leaf,
+                                         Stk* stk = nullptr) {
     if (bvh.n_prims <= 0) return;
     traverse<false>(bvh.nodes, r,
         [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
@@ -543,7 +574,7 @@ __device__ __forceinline__ void all_hits(const Bvh& bvh, const RayPre& r, float 
             leaf((int)((uint32_t)child & ~EMRT_LEAF));
             return false;
         },
-        NoStop());
+        NoStop(), stk);
 }
 
 // Visit every leaf whose box overlaps the query box [ql, qh].
@@ -561,7 +592,7 @@ __device__ __forceinline__ void box_query(const Bvh& bvh, float qlx, float qly, 
             leaf((int)((uint32_t)child & ~EMRT_LEAF));
             return false;
         },
-        NoStop());
+        NoStop(), (RegStack*)nullptr);
 }
 
 // wave helpers (wave64)

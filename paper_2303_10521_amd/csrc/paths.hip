@@ -935,23 +935,26 @@ __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links
 // of its legs.
 // dyn_only: the leg is known clear of the static scene; los: a line of sight
 // tested in full, whose static result is kept for the next step
-__device__ __forceinline__ void shadow_leg(const PathArgs& a, long long i, uint32_t q, bool dyn_only, bool los) {
+__device__ __forceinline__ void shadow_leg(const PathArgs& a, long long i, uint32_t q, bool dyn_only, bool los,
+                                           LdsStack* stk) {
     RayPre r = ray_pre(a.legs.ox[i], a.legs.oy[i], a.legs.oz[i], a.legs.dx[i], a.legs.dy[i], a.legs.dz[i]);
     int xa = a.legs.xa[i], xb = a.legs.xb[i], xc = a.legs.xc[i];
     bool hit = false;
     if (!dyn_only) {
-        hit = any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc);
+        hit = any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc, stk);
         if (los) a.los_sb[q] = hit ? 1 : 0;
     }
-    if (hit || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc)) a.occl[q] = 1u;
+    if (hit || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc, stk)) a.occl[q] = 1u;
 }
 
 __global__ void __launch_bounds__(256) k_shadow_first(PathArgs a, long long n_links, long long cap_cand) {
+    __shared__ int stk_lds[kStackDepth][kStackStride];
+    LdsStack stk{&stk_lds[0][threadIdx.x]};
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     GRID_STRIDE(q, n_links + nc) {
         const uint8_t stv = a.state[q];
-        if (stv && !a.occl[q]) shadow_leg(a, q, (uint32_t)q, stv == 3, q < n_links);
+        if (stv && !a.occl[q]) shadow_leg(a, q, (uint32_t)q, stv == 3, q < n_links, &stk);
     }
 }
 
@@ -998,11 +1001,13 @@ __global__ void __launch_bounds__(256) k_shadow_pick(PathArgs a) {
 }
 
 __global__ void __launch_bounds__(256) k_shadow_rest(PathArgs a) {
+    __shared__ int stk_lds[kStackDepth][kStackStride];
+    LdsStack stk{&stk_lds[0][threadIdx.x]};
     long long n = (long long)*a.legs.n_list;
     GRID_STRIDE(k, n) {
         long long i = a.legs.cap_first + (long long)a.legs.list[k];
         uint32_t q = a.legs.key[i];
-        if (!a.occl[q]) shadow_leg(a, i, q, a.state[q] == 3, false);
+        if (!a.occl[q]) shadow_leg(a, i, q, a.state[q] == 3, false, &stk);
     }
 }
 

@@ -125,7 +125,7 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
 template <bool STATS, bool REV>
 __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long long n_in, unsigned long long base,
                                              int lane, unsigned& s_nodes, unsigned& s_tris, unsigned& s_seg,
-                                             unsigned& s_cap) {
+                                             unsigned& s_cap, LdsStack* stk) {
     const int b = a.b;
     unsigned long long i = base + (unsigned long long)lane;
     bool act = i < n_in;
@@ -150,8 +150,8 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
     int best_tri = 0x7FFFFFFF, best_face = -1;
     if (act) {
         if (STATS) s_seg++;
-        closest_hit<STATS>(a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
-        closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris);
+        closest_hit<STATS>(a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris, stk);
+        closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris, stk);
     }
     bool hit = act && best_tri != 0x7FFFFFFF;
     if (act) a.hitlog[(long long)b * a.n_total + id] = hit ? best_tri : -1;
@@ -193,7 +193,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             int res = table_insert<REV ? 1 : 0>(a.table, a.mask, ref_ray(b, target, id), mine, h, a.src);
             if (res < 0) atomicOr(a.flags, FLAG_TABLE_FULL);
             if (STATS) s_cap++;
-        });
+        }, stk);
     }
 
     // edge capture on the first segment (and, for reflection-diffraction
@@ -230,7 +230,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             } else if (!pair_insert(a.pairs, a.pair_mask, pair_key(source, face1, e))) {
                 atomicOr(a.flags, FLAG_CAND_CAP);
             }
-        });
+        }, stk);
     }
 
     // specular reflection about the face plane
@@ -271,11 +271,14 @@ __device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane,
     }
 }
 
-// Persistent: waves pull 64-ray chunks from a device counter.  (Holding it to
-// six waves per SIMD with an 80-VGPR cap ran 1-2% faster but spilled 36 bytes
-// per lane, which raised its HBM traffic by 22%; it stays at the compiler's 93.)
+// Persistent: waves pull 64-ray chunks from a device counter.  The traversal
+// stacks live in LDS (one column per thread).  (Holding it to six waves per
+// SIMD with an 80-VGPR cap ran 1.5% faster but spilled 20 bytes per lane; it
+// stays at the compiler's 85.)
 template <bool STATS, bool REV>
 __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
+    __shared__ int stk_lds[kStackDepth][kStackStride];
+    LdsStack stk{&stk_lds[0][threadIdx.x]};
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
@@ -287,7 +290,7 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     while (true) {
         unsigned long long base = (unsigned long long)chunk * 64ULL;
         if (base >= n_in) break;
-        bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap);
+        bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap, &stk);
         unsigned int next = 0;
         if (lane == 0) next = atomicAdd(a.work, 1u);
         chunk = n_waves + (unsigned int)__shfl((int)next, 0);
@@ -339,6 +342,8 @@ __global__ void __launch_bounds__(256) k_chunk_table(const BounceArgs* __restric
 __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restrict__ args,
                                                       const uint32_t* __restrict__ chunk_off, uint32_t* work,
                                                       int n_scenes) {
+    __shared__ int stk_lds[kStackDepth][kStackStride];
+    LdsStack stk{&stk_lds[0][threadIdx.x]};
     const int lane = lane_id();
     const uint32_t total = chunk_off[n_scenes];
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
@@ -362,7 +367,7 @@ __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restri
         const BounceArgs& a = args[c];
         const unsigned long long n_in = *a.n_in;
         bounce_chunk<false, false>(a, n_in, (unsigned long long)(g - chunk_off[c]) * 64ULL, lane, s_nodes, s_tris,
-                                   s_seg, s_cap);
+                                   s_seg, s_cap, &stk);
     }
 }
 
