@@ -375,9 +375,9 @@ __device__ __forceinline__ bool tri_hit(const TriP& p, const RayPre& r, float& t
 // BVH traversal
 //
 // Main loop: a short per-ray stack.  At an internal node both child boxes
-// are tested; the near child (the child on the ray's side of the Morton
-// split axis, or the left child for the unordered queries) is entered and the
-// other pushed.  Each internal node is loaded once.
+// are tested (in stored order); the near child (the child on the ray's side
+// of the split axis, or the left child for the unordered queries) is entered
+// and the other pushed.  Each internal node is loaded once.
 //
 // The stack holds kStackDepth node ids; it only holds the pending far
 // children along the current path, and the LBVHs of a city are about 25
@@ -473,16 +473,16 @@ __device__ __forceinline__ void traverse_with(const BNode* nodes, const RayPre& 
     bool overflow = false;
     while (true) {
         BNode nd = ld_node(nodes, cur);
-        int first = ORDERED ? near_side(nd, r) : 0;
-        int ca, cb;
-        float la, lb;
-        float lx, ly, lz, hx, hy, hz;
-        child_box(nd, first, lx, ly, lz, hx, hy, hz, ca);
-        bool da = test(lx, ly, lz, hx, hy, hz, ca, la);
+        // both boxes in stored order (no per-lane selection of box fields),
+        // then the near one first
+        float l0, l1;
+        bool d0 = test(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, nd.m.x, l0);
         if (stop()) return;
-        child_box(nd, 1 - first, lx, ly, lz, hx, hy, hz, cb);
-        bool db = test(lx, ly, lz, hx, hy, hz, cb, lb);
+        bool d1 = test(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, nd.m.y, l1);
         if (stop()) return;
+        const int first = ORDERED ? near_side(nd, r) : 0;
+        const int ca = first ? nd.m.y : nd.m.x, cb = first ? nd.m.x : nd.m.y;
+        const bool da = first ? d1 : d0, db = first ? d0 : d1;
         if (da) {
             if (db) {
                 if (sp == kStackDepth) { overflow = true; break; }
