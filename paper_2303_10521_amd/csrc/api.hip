@@ -73,6 +73,11 @@ struct emrt_ctx {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
+    // second stream of a single-context discovery step: the diffraction
+    // candidates (they need only the first bounce) run beside bounces 1..K
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool diff_async = false;
     std::string err;
     int stats_on = 0, timing_on = 0;
     // kernel timing: two event sets used by alternate steps, read lazily so
@@ -404,6 +409,9 @@ int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
 
 int32_t emrt_ctx_destroy(emrt_ctx* c) {
     if (!c) return EMRT_E_INVALID;
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_created)
         for (auto& set : c->evs)
             for (auto e : set.ev) (void)hipEventDestroy(e);
@@ -800,7 +808,7 @@ static void step_pre(emrt_ctx* c, int discover) {
     }
 }
 
-static void step_bounces(emrt_ctx* c) {
+static void step_bounces(emrt_ctx* c, bool fork_diff = false) {
     long long g = (launch_total(c) + 255) / 256;
     int grid = (int)std::min<long long>(std::max<long long>(g, 1), 2048);
     for (int k = 0; k <= c->K; k++) {
@@ -808,6 +816,17 @@ static void step_bounces(emrt_ctx* c) {
         ev_record(c);
         bounce(b, c->stats_on != 0, grid, c->stream);
         ev_record(c);
+        if (k == 0 && fork_diff) {
+            // the edges lit by the first segments are known: candidates on the side stream
+            HC(hipEventRecord(c->ev_fork, c->stream));
+            HC(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+            const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
+            rx_grid_build(c->f_rx, c->sz.n_rx, c->bins, c->side);
+            diff_candidates(path_args(c), c->illum, c->e_words, c->bins, c->table, mask, key_src(c, c->cache[c->cur]),
+                            fresh_keys(c), c->side);
+            HC(hipEventRecord(c->ev_join, c->side));
+            c->diff_async = true;
+        }
     }
     c->evs[c->ev_parity].bounce_end = c->evs[c->ev_parity].used;
 }
@@ -822,6 +841,9 @@ static void step_post(emrt_ctx* c, int discover) {
     if (discover) {
         if (diff && c->rev_n > 0) {
             diff_candidates_rx(pa, c->illum, c->e_words, c->rev_rx, c->rev_n, c->table, mask, src, st);
+        } else if (diff && c->diff_async) {  // launched beside the bounces
+            HC(hipStreamWaitEvent(st, c->ev_join, 0));
+            c->diff_async = false;
         } else if (diff) {
             rx_grid_build(c->f_rx, c->sz.n_rx, c->bins, st);
             diff_candidates(pa, c->illum, c->e_words, c->bins, c->table, mask, src, fresh_keys(c), st);
@@ -877,7 +899,16 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
     if (!c->scene_set || !c->frame_set) return fail(c, EMRT_E_STATE, "set_scene and set_frame first");
     if (c->batched) return fail(c, EMRT_E_STATE, "context belongs to a batch: use emrt_batch_step");
     step_pre(c, discover);
-    if (discover) step_bounces(c);
+    if (discover) {
+        const bool fork = c->cfg.diffraction && c->S.E > 0 && c->K >= 1;
+        if (fork && !c->side) {
+            if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+                return fail(c, EMRT_E_HIP, "side stream");
+        }
+        step_bounces(c, fork);
+    }
     step_post(c, discover);
     return hip_check(c, hipGetLastError(), "step");
 }
