@@ -196,10 +196,11 @@ __device__ __forceinline__ bool in_tri(dv3 p, dv3 a, dv3 b, dv3 c) {
 // Larger faces (a tiled ground) are searched through the triangle LBVH of
 // their kind (static or dynamic): every triangle of the face whose box
 // overlaps p +- 1 mm is tested and the lowest accepted id kept, which is the
-// same triangle the scan in id order would find.
+// same triangle the scan in id order would find.  The search uses the
+// caller's LDS traversal stack.
 constexpr int kFaceLinearMax = 32;
 
-__device__ __forceinline__ int face_contains(const PathArgs& a, int f, dv3 p) {
+__device__ __forceinline__ int face_contains(const PathArgs& a, int f, dv3 p, LdsStack* stk) {
     const SceneDev& s = a.s;
     const int q0 = s.face_off[f], q1 = s.face_off[f + 1];
     if (q1 - q0 <= kFaceLinearMax) {
@@ -224,7 +225,7 @@ __device__ __forceinline__ int face_contains(const PathArgs& a, int f, dv3 p) {
     const float qhx = (float)(p.x + 1e-3), qhy = (float)(p.y + 1e-3), qhz = (float)(p.z + 1e-3);
     int found = -1;
     RayPre dummy{};
-    traverse_stackless<false>(t.nodes, dummy,
+    traverse<false>(t.nodes, dummy,
         [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
             tn = 0.0f;
             if (!(lx <= qhx && hx >= qlx && ly <= qhy && hy >= qly && lz <= qhz && hz >= qlz)) return false;
@@ -237,7 +238,7 @@ __device__ __forceinline__ int face_contains(const PathArgs& a, int f, dv3 p) {
             if (in_tri(p, v0, v1, v2)) found = id;
             return false;
         },
-        NoStop());
+        NoStop(), stk);
     return found;
 }
 
@@ -724,7 +725,7 @@ __device__ __forceinline__ bool key_in_range(const PathArgs& a, const KeyRec& ke
 //   reflection then diffraction / diffraction then reflection: the same with
 //   the image of Tx / of Rx in the face plane, plus the reflection point's
 //   parameter in (0, 1) and its face (not a face of the wedge).
-__device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, Built& g) {
+__device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, Built& g, LdsStack* stk) {
 #pragma clang fp contract(off)
     const SceneDev& S = a.s;
     g.type = key.to & 0xff;
@@ -764,7 +765,7 @@ __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, 
         double tt = (pl[3] - dot(nrm, Q)) / den;
         if (!(tt > 0.0 && tt < 1.0)) return false;
         dv3 P = Q + dv * tt;
-        int t = face_contains(a, f, P);
+        int t = face_contains(a, f, P, stk);
         if (t < 0) return false;
         g.P[1] = rd ? P : Q;
         g.P[2] = rd ? Q : P;
@@ -791,7 +792,7 @@ __device__ __forceinline__ bool construct(const PathArgs& a, const KeyRec& key, 
         if (!(tt > 0.0 && tt < 1.0)) return false;
         cur = cur + dv * tt;
         g.P[i] = cur;
-        int t = face_contains(a, key.ids[i - 1], cur);
+        int t = face_contains(a, key.ids[i - 1], cur, stk);
         if (t < 0) return false;
         g.tri[i - 1] = t;
     }
@@ -860,6 +861,8 @@ __device__ __forceinline__ void write_leg(const PathArgs& a, const Built& g, con
 // Phase 1: exact construction of every key (line of sight for every link,
 // then the candidates); surviving keys emit their legs as shadow rays.
 __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links, long long cap_cand) {
+    __shared__ int stk_lds[kStackDepth][kStackStride];  // columns of the first 128 threads used
+    LdsStack stk{&stk_lds[0][threadIdx.x]};
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
     long long n = n_links + nc;
@@ -874,7 +877,7 @@ __global__ void __launch_bounds__(128) k_construct(PathArgs a, long long n_links
         g.np = 0;
         if (ok) {
             key = key_at(a, q, n_links);
-            ok = key_in_range(a, key) && construct(a, key, g);
+            ok = key_in_range(a, key) && construct(a, key, g, &stk);
             // state: 0 not constructed, 1 test every leg in full, 3 the
             // dynamic tree only (clear of the static scene, as at the last step)
             uint8_t stv = ok ? (uint8_t)1 : (uint8_t)0;
