@@ -230,13 +230,13 @@ __global__ void __launch_bounds__(256) k_refit(const float* box, const uint32_t*
     if (l < n) refit_leaf(box, perm, l, nodes, leaf_parent, counters);
 }
 
-// LBVH refit in two tiers.  A block owns the leaf slots [b0, b0 + 256); an
+// LBVH refit in two tiers.  A block owns the leaf slots [b0, b0 + kRefitTile); an
 // internal node whose leaf range lies inside them (a Karras node is one end of
 // its own range, so its number lies inside too) is merged in LDS under a
 // workgroup-scope counter, and only the nodes whose range leaves the block
 // take the device-scope hand-over above.  Once a climb leaves its block every
 // ancestor's range does too.
-constexpr int kRefitTile = 256;
+constexpr int kRefitTile = 1024;
 
 __device__ __forceinline__ void refit_leaf_lbvh(const float* box, const uint32_t* perm, int l, int b0, int b1,
                                                 BNode* nodes, const int* leaf_parent, const int* span,
