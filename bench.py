@@ -164,8 +164,8 @@ def main() -> int:
                     help="copy 1 GiB device-to-device before the warm-up (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
-                                   "note only)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the path is not sharded "
+                                   "across GPUs)"}))
         return 2
 
     import numpy as np
