@@ -651,6 +651,44 @@ static double wedge_angle(const orc_wedge* w, v3 p) {
     return ph;
 }
 
+/* Range check of one key row [tx, rx, type, order, id0..id4] before any
+ * array is indexed with it: tx in [0, n_tx), rx in [0, n_rx); type 0 (line of
+ * sight) has order 0; type 1 (specular) order 1..5 with that many face ids in
+ * [0, F); type 2 (diffraction) order 1 with an edge id in [0, E); types 3 and
+ * 4 (one reflection and one diffraction) order 2 with (face, edge) or (edge,
+ * face).  A malformed key (from the code under test) is reported as such and
+ * never read further, so it fails a comparison instead of corrupting the
+ * oracle's own state. */
+static int key_ok(const int32_t* k, int32_t n_tx, int32_t n_rx, int32_t F, int32_t E) {
+    if (k[0] < 0 || k[0] >= n_tx || k[1] < 0 || k[1] >= n_rx) return 0;
+    const int32_t type = k[2], order = k[3];
+    switch (type) {
+        case 0: return order == 0;
+        case 1:
+            if (order < 1 || order > 5) return 0;
+            for (int i = 0; i < order; i++)
+                if (k[4 + i] < 0 || k[4 + i] >= F) return 0;
+            return 1;
+        case 2: return order == 1 && k[4] >= 0 && k[4] < E;
+        case 3: return order == 2 && k[4] >= 0 && k[4] < F && k[5] >= 0 && k[5] < E;
+        case 4: return order == 2 && k[4] >= 0 && k[4] < E && k[5] >= 0 && k[5] < F;
+        default: return 0;
+    }
+}
+
+/* Number of malformed rows among n_keys keys; bad[q] = 1 for each (bad may
+ * be NULL). */
+int32_t orc_check_keys(int32_t n_keys, const int32_t* keys, int32_t n_tx, int32_t n_rx, int32_t F, int32_t E,
+                       uint8_t* bad) {
+    int32_t nb = 0;
+    for (int32_t q = 0; q < n_keys; q++) {
+        const int ok = key_ok(keys + 9 * q, n_tx, n_rx, F, E);
+        if (bad) bad[q] = (uint8_t)!ok;
+        nb += !ok;
+    }
+    return nb;
+}
+
 /* Validation of path keys (Section II-A's direct, reflected and diffracted
  * rays; Section III-B's cache revalidation).  keys rows are
  * [tx, rx, type, order, id0..id4] with type 0 = line of sight, 1 = specular
@@ -676,20 +714,26 @@ static double wedge_angle(const orc_wedge* w, v3 p) {
  * shadow leg within 1 mm + 1e-6 |leg| of a triangle edge, a Keller point
  * within rob_m of an edge end, phi within 1e-4 rad of a face). */
 int32_t orc_validate(int32_t T, const float* tv, const int32_t* tri_face, const double* plane, int32_t F,
-                     const int32_t* face_off, const int32_t* face_tris, const float* verts,
-                     const int32_t* edges, const double* edge_n, const double* txp, const double* rxp,
-                     double diff_max_leg, int32_t n_keys, const int32_t* keys, uint8_t* valid, uint8_t* ambiguous,
-                     int32_t* tri_ids, double* points) {
-    (void)F;
-#pragma omp parallel for schedule(dynamic, 8)
+                     int32_t E, int32_t n_tx, int32_t n_rx, const int32_t* face_off, const int32_t* face_tris,
+                     const float* verts, const int32_t* edges, const double* edge_n, const double* txp,
+                     const double* rxp, double diff_max_leg, int32_t n_keys, const int32_t* keys, uint8_t* valid,
+                     uint8_t* ambiguous, int32_t* tri_ids, double* points) {
+    int32_t n_bad = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : n_bad)
     for (int32_t q = 0; q < n_keys; q++) {
         const int32_t* key = keys + 9 * q;
+        for (int i = 0; i < 5; i++) tri_ids[5 * q + i] = -1;
+        for (int i = 0; i < 15; i++) points[15 * q + i] = 0.0;
+        if (!key_ok(key, n_tx, n_rx, F, E)) {  /* malformed: invalid, never indexed */
+            valid[q] = 0;
+            ambiguous[q] = 0;
+            n_bad++;
+            continue;
+        }
         v3 s = ld3d(txp + 3 * key[0]);
         v3 r = ld3d(rxp + 3 * key[1]);
         int type = key[2], order = key[3];
         int ok = 1, amb = 0;
-        for (int i = 0; i < 5; i++) tri_ids[5 * q + i] = -1;
-        for (int i = 0; i < 15; i++) points[15 * q + i] = 0.0;
         if (type == 0) {
             if (occluded(T, tv, tri_face, s, r, -1, -1, &amb)) ok = 0;
         } else if (type == 1) {
@@ -839,7 +883,7 @@ int32_t orc_validate(int32_t T, const float* tv, const int32_t* tri_face, const 
         valid[q] = (uint8_t)ok;
         ambiguous[q] = (uint8_t)amb;
     }
-    return 0;
+    return n_bad;
 }
 
 /* Interaction points of fixed keys (the gradient reading: the topology is
@@ -848,16 +892,21 @@ int32_t orc_validate(int32_t T, const float* tv, const int32_t* tri_face, const 
  * back from Rx, x_k = segment(x_{k+1} -> s_k) meets plane f_k.  Diffraction:
  * the Keller point on the edge line, z_Q = z_s + (z_r - z_s) rho_s /
  * (rho_s + rho_r).  Line of sight has no points.  points [n][5][3]. */
-int32_t orc_image_points(int32_t n_keys, const int32_t* keys, const double* plane, const float* verts,
-                         const int32_t* edges, const double* edge_n, const double* txp, const double* rxp,
-                         double* points) {
-#pragma omp parallel for schedule(static)
+int32_t orc_image_points(int32_t n_keys, const int32_t* keys, int32_t F, int32_t E, int32_t n_tx, int32_t n_rx,
+                         const double* plane, const float* verts, const int32_t* edges, const double* edge_n,
+                         const double* txp, const double* rxp, double* points) {
+    int32_t n_bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
     for (int32_t q = 0; q < n_keys; q++) {
         const int32_t* key = keys + 9 * q;
+        for (int i = 0; i < 15; i++) points[15 * q + i] = 0.0;
+        if (!key_ok(key, n_tx, n_rx, F, E)) {  /* malformed: no points */
+            n_bad++;
+            continue;
+        }
         v3 s = ld3d(txp + 3 * key[0]);
         v3 r = ld3d(rxp + 3 * key[1]);
         int type = key[2], order = key[3];
-        for (int i = 0; i < 15; i++) points[15 * q + i] = 0.0;
         if (type == 1) {
             v3 img[6];
             img[0] = s;
@@ -904,7 +953,7 @@ int32_t orc_image_points(int32_t n_keys, const int32_t* keys, const double* plan
             points[15 * q + 3] = x2.x; points[15 * q + 4] = x2.y; points[15 * q + 5] = x2.z;
         }
     }
-    return 0;
+    return n_bad;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1131,16 +1180,28 @@ static double complex phase(double L, double lam) {
  *   station this is Eq (3) exactly.
  *   AoD = (azimuth, elevation) of k_0, AoA = (azimuth, elevation) of -k_K.
  * Outputs: a [n][nf][2], tau [n], fd [n][nf], aod [n][2], aoa [n][2]. */
-int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, const double* plane,
+int32_t orc_eval(int32_t n_paths, const int32_t* keys, int32_t F, int32_t E, int32_t n_tx, int32_t n_rx,
+                 const double* points, const double* plane,
                  const int32_t* face_material, const int32_t* face_dyn, const double* obj_vel,
                  const double* mat_eps, const double* mat_refl, const float* verts, const int32_t* edges,
                  const double* edge_n,
                  const double* txp, const double* txv, const double* txo, const double* rxp, const double* rxv,
                  int32_t ant_mode, int32_t nf, const double* freqs,
                  double* a_out, double* tau_out, double* fd_out, double* aod, double* aoa) {
-#pragma omp parallel for schedule(dynamic, 64)
+    int32_t n_bad = 0;
+    if (nf < 1 || nf > 8) return -1;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_bad)
     for (int32_t q = 0; q < n_paths; q++) {
         const int32_t* key = keys + 9 * q;
+        if (!key_ok(key, n_tx, n_rx, F, E)) {  /* malformed: NaN outputs */
+            for (int fi = 0; fi < nf; fi++) {
+                a_out[2 * (q * nf + fi)] = a_out[2 * (q * nf + fi) + 1] = NAN;
+                fd_out[q * nf + fi] = NAN;
+            }
+            tau_out[q] = aod[2 * q] = aod[2 * q + 1] = aoa[2 * q] = aoa[2 * q + 1] = NAN;
+            n_bad++;
+            continue;
+        }
         int tx = key[0], rx = key[1], type = key[2], order = key[3];
         v3 s = ld3d(txp + 3 * tx), r = ld3d(rxp + 3 * rx);
         v3 vt = ld3d(txv + 3 * tx), vr = ld3d(rxv + 3 * rx);
@@ -1253,7 +1314,7 @@ int32_t orc_eval(int32_t n_paths, const int32_t* keys, const double* points, con
         aoa[2 * q] = atan2(-kK.y, -kK.x);
         aoa[2 * q + 1] = asin(-kK.z > 1 ? 1 : (-kK.z < -1 ? -1 : -kK.z));
     }
-    return 0;
+    return n_bad;
 }
 
 int32_t orc_num_threads(void) { return omp_get_max_threads(); }

@@ -39,26 +39,38 @@ C0 = 299792458.0
 P_TX_W = 100.0  # 50 dBm (Section IV)
 
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (OpenMP, no floating-point contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", _SRC, "-o", tmp, "-lm"]
+# address and undefined-behaviour sanitizers (host code only): a build of the
+# same source that the pin suite can run under, to show that no pin reads or
+# writes outside the oracle's arrays
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force: bool = False, sanitize: bool = False, out: Optional[str] = None) -> str:
+    """Compile the C oracle with gcc (OpenMP, no floating-point contraction);
+    with ``sanitize`` into ``out`` with the address and undefined-behaviour
+    sanitizers."""
+    target = out or _LIB
+    if force or sanitize or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
+        tmp = target + ".tmp"
+        cmd = ["gcc", "-O1" if sanitize else "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", *(SANITIZE_FLAGS if sanitize else []), "-shared", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, target)
+    return target
 
 
 _lib = None
 
 
 def lib():
+    """The oracle's shared library: EMRT_ORACLE_LIB when set (e.g. the
+    sanitized build), else the default build next to the source."""
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        _lib = ctypes.CDLL(os.environ.get("EMRT_ORACLE_LIB") or build())
         _lib.orc_num_threads.restype = ctypes.c_int32
-        for name in ("orc_face_planes", "orc_edges", "orc_trace", "orc_validate", "orc_eval", "orc_image_points"):
+        for name in ("orc_face_planes", "orc_edges", "orc_trace", "orc_validate", "orc_eval", "orc_image_points",
+                     "orc_check_keys"):
             getattr(_lib, name).restype = ctypes.c_int32
     return _lib
 
@@ -282,9 +294,30 @@ def illuminated_edges(tr: TraceResult) -> Dict[int, bool]:
     return out
 
 
+class MalformedKey(ValueError):
+    """A key row outside the scene's index ranges (see ``check_keys``)."""
+
+
+def check_keys(os_: OracleScene, keys: np.ndarray, n_tx: int, n_rx: int) -> np.ndarray:
+    """Raise MalformedKey naming the first key row that is not well formed:
+    tx in [0, n_tx), rx in [0, n_rx), type 0 with order 0, type 1 with order
+    1..5 and face ids in [0, F), type 2 with order 1 and an edge id in [0, E),
+    types 3 / 4 with order 2 and (face, edge) / (edge, face).  The C routines
+    make the same check and never index with a malformed key."""
+    keys = _c(np.asarray(keys).reshape(-1, KEY_W), np.int32)
+    bad = np.zeros(len(keys), np.uint8)
+    nb = lib().orc_check_keys(ctypes.c_int32(len(keys)), _p(keys), ctypes.c_int32(n_tx), ctypes.c_int32(n_rx),
+                              ctypes.c_int32(os_.F), ctypes.c_int32(os_.E), _p(bad))
+    if nb:
+        i = int(np.nonzero(bad)[0][0])
+        raise MalformedKey(f"{nb} malformed key(s); first: row {i} = {keys[i].tolist()} "
+                           f"(n_tx {n_tx}, n_rx {n_rx}, faces {os_.F}, edges {os_.E})")
+    return keys
+
+
 def validate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, tx_pos: np.ndarray, rx_pos: np.ndarray,
              diff_max_leg: float = 250.0):
-    keys = _c(keys.reshape(-1, KEY_W), np.int32)
+    keys = check_keys(os_, keys, len(tx_pos), len(rx_pos))
     n = len(keys)
     valid = np.zeros(n, np.uint8)
     amb = np.zeros(n, np.uint8)
@@ -292,10 +325,13 @@ def validate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, tx_pos: np.ndarra
     pts = np.zeros((n, 5, 3))
     edges = os_.edges if os_.E else np.zeros((1, 6), np.int32)
     en = os_.edge_n if os_.E else np.zeros(1)
-    lib().orc_validate(ctypes.c_int32(os_.T), _p(g.tv), _p(os_.tri_face), _p(g.plane), ctypes.c_int32(os_.F),
-                       _p(os_.face_off), _p(os_.face_tris), _p(g.verts), _p(_c(edges, np.int32)), _p(_c(en, np.float64)),
-                       _p(_c(tx_pos, np.float64)), _p(_c(rx_pos, np.float64)), ctypes.c_double(diff_max_leg),
-                       ctypes.c_int32(n), _p(keys), _p(valid), _p(amb), _p(tri), _p(pts))
+    nb = lib().orc_validate(ctypes.c_int32(os_.T), _p(g.tv), _p(os_.tri_face), _p(g.plane), ctypes.c_int32(os_.F),
+                            ctypes.c_int32(os_.E), ctypes.c_int32(len(tx_pos)), ctypes.c_int32(len(rx_pos)),
+                            _p(os_.face_off), _p(os_.face_tris), _p(g.verts), _p(_c(edges, np.int32)),
+                            _p(_c(en, np.float64)), _p(_c(tx_pos, np.float64)), _p(_c(rx_pos, np.float64)),
+                            ctypes.c_double(diff_max_leg), ctypes.c_int32(n), _p(keys), _p(valid), _p(amb), _p(tri),
+                            _p(pts))
+    assert nb == 0, nb
     return valid.astype(bool), amb.astype(bool), tri, pts
 
 
@@ -303,7 +339,7 @@ def evaluate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, pts: np.ndarray, 
              ant_mode: int = 0, obj_vel: Optional[np.ndarray] = None, materials: Optional[np.ndarray] = None):
     """Fields of validated keys at the given interaction points.  ``materials``
     (complex [M]) overrides the scene permittivities."""
-    keys = _c(keys.reshape(-1, KEY_W), np.int32)
+    keys = check_keys(os_, keys, len(frame.tx_pos), len(frame.rx_pos))
     n = len(keys)
     nf = len(freqs)
     a = np.zeros((n, nf, 2))
@@ -320,12 +356,15 @@ def evaluate(os_: OracleScene, g: FrameGeom, keys: np.ndarray, pts: np.ndarray, 
     else:
         m = np.asarray(materials, np.complex128)
         mats = _c(np.stack([m.real, m.imag], 1), np.float64)
-    lib().orc_eval(ctypes.c_int32(n), _p(keys), _p(_c(pts, np.float64)), _p(g.plane), _p(os_.face_material),
+    nb = lib().orc_eval(ctypes.c_int32(n), _p(keys), ctypes.c_int32(os_.F), ctypes.c_int32(os_.E),
+                   ctypes.c_int32(len(frame.tx_pos)), ctypes.c_int32(len(frame.rx_pos)),
+                   _p(_c(pts, np.float64)), _p(g.plane), _p(os_.face_material),
                    _p(os_.face_dyn), _p(ov), _p(mats), _p(os_.material_refl), _p(g.verts), _p(_c(edges, np.int32)),
                    _p(_c(en, np.float64)), _p(_c(frame.tx_pos, np.float64)), _p(_c(frame.tx_vel, np.float64)),
                    _p(_c(frame.tx_orient, np.float64)), _p(_c(frame.rx_pos, np.float64)),
                    _p(_c(frame.rx_vel, np.float64)), ctypes.c_int32(ant_mode), ctypes.c_int32(nf),
                    _p(_c(np.asarray(freqs, np.float64), np.float64)), _p(a), _p(tau), _p(fd), _p(aod), _p(aoa))
+    assert nb == 0, nb
     return a[..., 0] + 1j * a[..., 1], tau, fd, aod, aoa
 
 
@@ -333,13 +372,16 @@ def image_points(os_: OracleScene, g: FrameGeom, keys: np.ndarray, tx_pos: np.nd
                  rx_pos: np.ndarray) -> np.ndarray:
     """Interaction points of fixed keys: image method / Keller point with no
     containment, range or occlusion test (the topology is held fixed)."""
-    keys = _c(keys.reshape(-1, KEY_W), np.int32)
+    keys = check_keys(os_, keys, len(tx_pos), len(rx_pos))
     n = len(keys)
     pts = np.zeros((n, 5, 3))
     edges = os_.edges if os_.E else np.zeros((1, 6), np.int32)
     en = os_.edge_n if os_.E else np.zeros(1)
-    lib().orc_image_points(ctypes.c_int32(n), _p(keys), _p(g.plane), _p(g.verts), _p(_c(edges, np.int32)),
-                           _p(_c(en, np.float64)), _p(_c(tx_pos, np.float64)), _p(_c(rx_pos, np.float64)), _p(pts))
+    nb = lib().orc_image_points(ctypes.c_int32(n), _p(keys), ctypes.c_int32(os_.F), ctypes.c_int32(os_.E),
+                                ctypes.c_int32(len(tx_pos)), ctypes.c_int32(len(rx_pos)), _p(g.plane), _p(g.verts),
+                                _p(_c(edges, np.int32)), _p(_c(en, np.float64)), _p(_c(tx_pos, np.float64)),
+                                _p(_c(rx_pos, np.float64)), _p(pts))
+    assert nb == 0, nb
     return pts
 
 

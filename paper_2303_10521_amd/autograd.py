@@ -8,7 +8,9 @@ the library's adjoint (emrt_backward): gradients with respect to the complex
 permittivities (PyTorch convention dL/dRe + j dL/dIm), the transmitter
 positions and the dipole orientation, with the path topology of the step
 held fixed.  The tracer must be created with ``adjoint_materials`` >= the
-number of materials.
+number of materials.  The library differentiates the tracer's last step, so a
+forward's backward must run before the tracer steps again (it raises
+otherwise).
 """
 from __future__ import annotations
 
@@ -32,11 +34,18 @@ class ChannelFunction(torch.autograd.Function):
         tracer.step(bool(discover))
         ch = tracer.channels()
         ctx.tracer = tracer
+        ctx.generation = tracer.generation
         ctx.devices = (eps.device, tx_pos.device, tx_orient.device)
         return ch["H"], ch["P_coh"]
 
     @staticmethod
     def backward(ctx, gH, gP):
+        if ctx.tracer.generation != ctx.generation:
+            # the library differentiates its last step; a later step, frame or
+            # material change would silently give another graph's gradients
+            raise RuntimeError("the tracer stepped (or changed frame or materials) after this forward; its "
+                               "adjoint would belong to the later state: run backward before the next step, "
+                               "or use one tracer per recorded forward")
         g = ctx.tracer.backward(gH, gP)
         de, dp, do = ctx.devices
         return (g["grad_eps"].to(de), g["grad_tx_pos"].to(dp), g["grad_tx_orient"].to(do), None, None, None)

@@ -68,6 +68,10 @@ class Tracer:
         self.stream = torch.cuda.current_stream(self.device)
         self._check(self.lib.emrt_set_stream(self.ctx, ctypes.c_void_p(self.stream.cuda_stream)))
         self._check(self.lib.emrt_bind_workspace(self.ctx, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
+        # state generation: advanced by every call that changes what the
+        # adjoint of the last step would differentiate (a step, a frame, the
+        # materials), so a recorded forward can tell whether it is still current
+        self.generation = 0
         self.set_scene(scene)
         self._frame_refs = None
 
@@ -118,16 +122,19 @@ class Tracer:
     def set_reflection_coefficients(self, refl: Sequence[float]) -> None:
         """Per material: 0 = Fresnel from the permittivity, g in (0, 1] = a
         constant reflection coefficient of magnitude g (Table I)."""
+        self.generation += 1
         self._refl_host = np.ascontiguousarray(np.asarray(refl, np.float64).reshape(-1))
         self._check(self.lib.emrt_set_reflection_coefficients(self.ctx, self._refl_host.ctypes.data,
                                                               len(self._refl_host)))
 
     def set_materials(self, eps: Sequence[complex]) -> None:
+        self.generation += 1
         e = np.asarray(eps, np.complex128)
         self._mat_host = np.ascontiguousarray(np.stack([e.real, e.imag], 1), np.float64)
         self._check(self.lib.emrt_set_materials(self.ctx, self._mat_host.ctypes.data, len(e)))
 
     def set_frame(self, fr, frame_index: int = 0) -> None:
+        self.generation += 1
         d = self.device
         nd = max(self.n_dynamic, 1)
         xf = np.zeros((nd, 3, 4)) if np.asarray(fr.obj_xform).size == 0 else fr.obj_xform
@@ -144,10 +151,12 @@ class Tracer:
         self._frame_refs = refs  # kept alive until the next frame (stream order)
 
     def step(self, discover: bool = True) -> int:
+        self.generation += 1
         return self._check(self.lib.emrt_step(self.ctx, 1 if discover else 0))
 
     def step_rx(self, rx_ids: Sequence[int], rays_per_rx: int) -> int:
         """Discovery step launched from the given receivers (emrt_step_rx)."""
+        self.generation += 1
         self._rev_host = np.ascontiguousarray(np.asarray(rx_ids, np.int32).reshape(-1))
         return self._check(self.lib.emrt_step_rx(self.ctx, self._rev_host.ctypes.data, len(self._rev_host),
                                                  int(rays_per_rx)))
@@ -311,6 +320,8 @@ class Batch:
         self._check(self.lib.emrt_batch_set_options(self.b, int(use_graph), int(n_streams), int(grid)))
 
     def step(self, discover: bool = True) -> int:
+        for t in self.tracers:
+            t.generation += 1
         return self._check(self.lib.emrt_batch_step(self.b, 1 if discover else 0))
 
     def autotune(self):

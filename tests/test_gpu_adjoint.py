@@ -177,3 +177,30 @@ def test_autograd_function_matches_backward():
     assert torch.allclose(eps.grad, ref["grad_eps"].cpu(), rtol=1e-12, atol=0)
     assert torch.allclose(txp.grad, ref["grad_tx_pos"].cpu(), rtol=1e-12, atol=0)
     tr.close()
+
+
+def test_autograd_refuses_a_stale_forward():
+    """The library differentiates the tracer's last step: a forward whose
+    tracer has stepped again since must not silently take the later step's
+    gradients (two forwards summed into one loss, or a re-evaluation)."""
+    from paper_2303_10521_amd import Tracer
+    from paper_2303_10521_amd.autograd import channels
+
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    tr = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections,
+                rays_per_tx=w.rays_per_tx, adjoint_materials=len(sc.materials), path_capacity=1 << 16)
+    eps = torch.tensor(np.asarray(sc.materials), dtype=torch.complex128, requires_grad=True)
+    txp = torch.tensor(fr.tx_pos, dtype=torch.float64, requires_grad=True)
+    txo = torch.tensor(fr.tx_orient, dtype=torch.float64, requires_grad=True)
+    H1, _ = channels(tr, fr, eps, txp, txo, True)
+    H2, _ = channels(tr, fr, eps, txp * 1.0, txo, True)
+    with pytest.raises(RuntimeError, match="stepped"):
+        ((H1.abs() ** 2).sum() + (H2.abs() ** 2).sum()).backward()
+    # the current forward alone still differentiates
+    eps.grad = None
+    H3, P3 = channels(tr, fr, eps, txp, txo, True)
+    P3.sum().backward()
+    assert eps.grad is not None and torch.isfinite(torch.view_as_real(eps.grad)).all()
+    tr.close()
