@@ -5,6 +5,8 @@ Tolerances (float parts), from the accuracy targets of the method:
                   otherwise |dH| <= 1e-3 sqrt(P_inc / P_tx)),
   delay           <= 1e-9 relative,
   Doppler         <= 1e-6 Hz.
+RMS delay spread <= 1e-9 of the mean delay; departure / arrival angles <= 1e-6
+rad (the library reports them in float32).
 Interaction sequences (triangle ids per bounce) are compared bit-exactly on
 rays the oracle marks robust; path sets are compared exactly except for keys
 whose discovery or validation the oracle marks ambiguous.
@@ -53,30 +55,47 @@ def compare_path_values(gk, gp, ok, op, nf):
     return worst
 
 
-def channel_ok(g: dict, o: dict, links: np.ndarray, p_tx: float, fi: int = 0):
-    """Check channel tolerances on the given links; returns list of failures."""
+def channel_ok(g: dict, o: dict, links: np.ndarray, p_tx: float, fi=None):
+    """Check the channel tolerances on the given links at carrier fi (every
+    carrier when fi is None): P_inc, P_coh (or H when the coherent sum is far
+    below the incoherent one), mean delay and RMS delay spread (1e-9 of the
+    mean delay), mean Doppler shift and RMS Doppler spread (1e-6 Hz).
+    Returns the list of failures (link, quantity, carrier, gpu, oracle)."""
     bad = []
-    for L in links:
-        pi_g, pi_o = g["P_inc"][fi][L], o["P_inc"][fi][L]
-        if pi_o == 0 and pi_g == 0:
-            continue
-        if not (pi_o > 0 and pi_g > 0) or db_err(pi_g, pi_o) > DB_TOL:
-            bad.append((int(L), "P_inc", pi_g, pi_o))
-            continue
-        pc_g, pc_o = g["P_coh"][fi][L], o["P_coh"][fi][L]
-        if pc_o >= 1e-3 * pi_o:
-            if db_err(pc_g, pc_o) > DB_TOL:
-                bad.append((int(L), "P_coh", pc_g, pc_o))
-        else:
-            if abs(g["H"][fi][L] - o["H"][fi][L]) > 1e-3 * np.sqrt(pi_o / p_tx):
-                bad.append((int(L), "H", g["H"][fi][L], o["H"][fi][L]))
-        if abs(g["tau_mean"][fi][L] - o["tau_mean"][fi][L]) > TAU_REL * o["tau_mean"][fi][L]:
-            bad.append((int(L), "tau_mean", g["tau_mean"][fi][L], o["tau_mean"][fi][L]))
-        if abs(g["fd_mean"][fi][L] - o["fd_mean"][fi][L]) > FD_ABS:
-            bad.append((int(L), "fd_mean", g["fd_mean"][fi][L], o["fd_mean"][fi][L]))
-        if abs(g["fd_rms"][fi][L] - o["fd_rms"][fi][L]) > FD_ABS:
-            bad.append((int(L), "fd_rms", g["fd_rms"][fi][L], o["fd_rms"][fi][L]))
+    carriers = range(np.asarray(o["P_inc"]).shape[0]) if fi is None else [fi]
+    for f in carriers:
+        for L in links:
+            pi_g, pi_o = g["P_inc"][f][L], o["P_inc"][f][L]
+            if pi_o == 0 and pi_g == 0:
+                continue
+            if not (pi_o > 0 and pi_g > 0) or db_err(pi_g, pi_o) > DB_TOL:
+                bad.append((int(L), "P_inc", f, pi_g, pi_o))
+                continue
+            pc_g, pc_o = g["P_coh"][f][L], o["P_coh"][f][L]
+            if pc_o >= 1e-3 * pi_o:
+                if db_err(pc_g, pc_o) > DB_TOL:
+                    bad.append((int(L), "P_coh", f, pc_g, pc_o))
+            else:
+                if abs(g["H"][f][L] - o["H"][f][L]) > 1e-3 * np.sqrt(pi_o / p_tx):
+                    bad.append((int(L), "H", f, g["H"][f][L], o["H"][f][L]))
+            tm = o["tau_mean"][f][L]
+            for name in ("tau_mean", "tau_rms"):
+                if abs(g[name][f][L] - o[name][f][L]) > TAU_REL * tm:
+                    bad.append((int(L), name, f, g[name][f][L], o[name][f][L]))
+            for name in ("fd_mean", "fd_rms"):
+                if abs(g[name][f][L] - o[name][f][L]) > FD_ABS:
+                    bad.append((int(L), name, f, g[name][f][L], o[name][f][L]))
     return bad
+
+
+def compare_angles(g_ang: np.ndarray, o_aod: np.ndarray, o_aoa: np.ndarray, tol: float = 1e-6) -> float:
+    """Largest difference between the library's float32 angles [n, 4] (AoD az,
+    el, AoA az, el) and the oracle's double ones, azimuths wrapped; the
+    library rounds the double angle to float32 (<= 2.4e-7 rad)."""
+    o = np.concatenate([np.asarray(o_aod), np.asarray(o_aoa)], axis=1)
+    d = np.asarray(g_ang, np.float64) - o
+    d[:, [0, 2]] = (d[:, [0, 2]] + np.pi) % (2 * np.pi) - np.pi
+    return float(np.max(np.abs(d))) if len(d) else 0.0
 
 
 def gpu_channels_np(ch: dict) -> dict:

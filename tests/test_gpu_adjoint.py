@@ -204,3 +204,51 @@ def test_autograd_refuses_a_stale_forward():
     P3.sum().backward()
     assert eps.grad is not None and torch.isfinite(torch.view_as_real(eps.grad)).all()
     tr.close()
+
+
+def test_adjoint_launch_size_three_frames():
+    """The 8-material district at its launch size (4 Tx x 1M rays, K = 4,
+    first-order diffraction), every 4th receiver (250), over a discovery
+    frame and two cached frames with moving vehicles.  The oracle
+    differentiates the GPU's own valid keys of each frame by central
+    differences (validated in the oracle; links holding an ambiguous key get
+    zero cotangents, so both sides differentiate the same function)."""
+    from paper_2303_10521_amd import Tracer
+
+    w = city.workload("adjoint")
+    sc = w.scene
+    M = len(sc.materials)
+    rx_idx = np.arange(0, sc.n_rx, 4)
+    tx_idx = np.arange(sc.n_tx)
+    n_tx, n_rx = len(tx_idx), len(rx_idx)
+    assert n_tx == 4 and n_rx >= 250
+    tr = Tracer(sc, n_tx, n_rx, freq_hz=list(w.freqs_hz), max_reflections=w.max_reflections,
+                rays_per_tx=w.rays_per_tx, diffraction=int(w.diffraction), adjoint_materials=M,
+                path_capacity=1 << 21)
+    os_ = O.OracleScene(sc)
+    nl = n_tx * n_rx
+    for f, disc in enumerate((True, False, False)):
+        fr = _subset_frame(sc.frame(f * w.frame_dt), tx_idx, rx_idx)
+        tr.set_frame(fr, f)
+        tr.step(disc)
+        assert tr.sync() == 0
+        p = tr.flat_paths(cap=256)
+        assert not p["truncated"]
+        gk = p["key"]
+        geo = os_.geometry(fr.obj_xform)
+        valid, amb, _, _ = O.validate(os_, geo, gk, fr.tx_pos, fr.rx_pos)
+        assert np.all(valid | amb)
+        link = gk[:, 0].astype(np.int64) * n_rx + gk[:, 1]
+        mask = np.ones(nl, bool)
+        mask[link[amb]] = False
+        assert mask.mean() >= 0.9 and (gk[:, 2] == 2).sum() > 50
+        GH, GP = _cotangents(len(w.freqs_hz), nl, 20 + f, 1e6)
+        GH[:, ~mask] = 0
+        GP[:, ~mask] = 0
+        g = tr.backward(torch.as_tensor(GH), torch.as_tensor(GP))
+        want = O.grad_fd(os_, geo, fr, gk[valid & ~amb], list(w.freqs_hz), GH, GP, n_rx)
+        got = {k: v.cpu().numpy() for k, v in g.items()}
+        for name in ("grad_tx_pos", "grad_eps"):
+            ok, err = _close(got[name], want[name])
+            assert ok, (f, name, err)
+    tr.close()

@@ -6,13 +6,17 @@ frames twice: once with one context per city stepped alone, and once as a
 batch (multi-scene persistent bounce launches, HIP-graph replay).  Every
 replay is checked against the separate steps, with eager host work and
 synchronisations in between.  The per-city results are deterministic, so
-channels and path lists must be identical.
+channels and path lists must be identical.  The batched results are also
+checked against the oracle itself: sampled paths of every city validate in it
+with the same gains, delays and Doppler shifts, and the channel sums of its
+links equal the oracle's sums over the same keys.
 """
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import oracle as O  # noqa: E402
 from synth import city  # noqa: E402
 from tests import parity as P  # noqa: E402
 
@@ -103,6 +107,70 @@ def test_batch_rules_and_autotune():
     assert grid in (1024, 2048, 4096, 8192) and ns in (1, 2, 4, 8)
     batch.step(True)
     assert batch.sync() == 0
+    batch.close()
+    for t in members:
+        t.close()
+
+
+def _oracle_check_member(w, tr, fr, n_pick=300, n_links=120, seed=0):
+    """Sampled paths and per-link sums of one batch member against the oracle."""
+    sc = w.scene
+    os_ = O.OracleScene(sc)
+    g = os_.geometry(fr.obj_xform)
+    p = tr.flat_paths(cap=256)
+    ch = P.gpu_channels_np(tr.channels())
+    assert not p["truncated"]
+    keys = p["key"]
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(keys), min(n_pick, len(keys)), replace=False)
+    valid, amb, tri, pts = O.validate(os_, g, keys[pick], fr.tx_pos, fr.rx_pos)
+    assert np.all(valid | amb)
+    ok = valid & ~amb
+    assert ok.sum() >= 0.95 * len(pick)
+    a, tau, fd, aod, aoa = O.evaluate(os_, g, keys[pick][ok], pts[ok], fr, w.freqs_hz)
+    assert np.all(np.abs(p["a"][pick][ok] - a) <= 1e-8 * np.abs(a))
+    assert np.all(np.abs(p["tau"][pick][ok] - tau) <= P.TAU_REL * tau)
+    assert np.all(np.abs(p["fd"][pick][ok] - fd) <= P.FD_ABS)
+    assert P.compare_angles(p["angles"][pick][ok], aod, aoa) <= 1e-6
+    spec = keys[pick][ok][:, 2] == 1
+    assert np.array_equal(p["tri_ids"][pick][ok][spec], tri[ok][spec])
+    # channel sums over every path of sampled links
+    link = keys[:, 0].astype(np.int64) * sc.n_rx + keys[:, 1]
+    have = np.unique(link)
+    links = rng.choice(have, min(n_links, len(have)), replace=False)
+    sel = np.isin(link, links)
+    valid, amb, tri, pts = O.validate(os_, g, keys[sel], fr.tx_pos, fr.rx_pos)
+    assert np.all(valid | amb)
+    a, tau, fd, _, _ = O.evaluate(os_, g, keys[sel], pts, fr, w.freqs_hz)
+    ref = O.reduce_links(keys[sel], a, tau, fd, sc.n_tx, sc.n_rx)
+    amb_links = set(link[sel][amb].tolist())
+    check = np.array([L for L in links if L not in amb_links])
+    assert len(check) >= 0.8 * len(links)
+    assert not P.channel_ok(ch, ref, check, 100.0)
+    return len(pick), len(check)
+
+
+def test_batch_cities_against_oracle():
+    """The batched form itself against the oracle: after graph-replayed
+    discovery, cached and discovery frames, every city's sampled paths and
+    link sums agree with the oracle at that frame."""
+    from paper_2303_10521_amd import Batch
+
+    ws = [city.batch_city(i) for i in CITIES]
+    members = [_tracer(w) for w in ws]
+    batch = Batch(members, use_graph=True, n_streams=4, grid=2048)
+    n_paths = n_links = 0
+    for f, disc in enumerate((True, False, True)):
+        frs = [w.scene.frame(f * w.frame_dt) for w in ws]
+        for t, fr in zip(members, frs):
+            t.set_frame(fr, f)
+        batch.step(disc)
+        assert batch.sync() == 0
+        for i, (w, t, fr) in enumerate(zip(ws, members, frs)):
+            a, b = _oracle_check_member(w, t, fr, seed=10 * f + i)
+            n_paths += a
+            n_links += b
+    assert n_paths >= 3 * 300 * len(CITIES) * 0.5 and n_links >= 3 * 90 * len(CITIES)
     batch.close()
     for t in members:
         t.close()

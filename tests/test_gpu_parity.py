@@ -88,6 +88,7 @@ def test_toy_path_values_and_triangles(toy):
         assert abs(p["fd"][i, 0] - ref.fd[j, 0]) <= P.FD_ABS
         if not ref.ambiguous[j]:
             assert np.array_equal(p["tri_ids"][i], ref.tri_ids[j])
+        assert P.compare_angles(p["angles"][i][None], ref.aod[j][None], ref.aoa[j][None]) <= 1e-6
     assert n >= 0.95 * len(ref.keys)
 
 
@@ -168,6 +169,7 @@ def test_district_paths_exact_in_oracle(district):
     a, tau, fd, aod, aoa = O.evaluate(os_, g, keys[pick][ok], pts[ok], fr, district["w"].freqs_hz)
     ga = p["a"][pick][ok]
     assert np.all(np.abs(ga - a) <= 1e-8 * np.abs(a))
+    assert P.compare_angles(p["angles"][pick][ok], aod, aoa) <= 1e-6
     assert np.all(np.abs(p["tau"][pick][ok] - tau) <= P.TAU_REL * tau)
     assert np.all(np.abs(p["fd"][pick][ok] - fd) <= P.FD_ABS)
     spec = keys[pick][ok][:, 2] == 1
@@ -294,9 +296,13 @@ def test_district_static_reuse_equals_full_tests(district):
 
 
 # ------------------------------------------- 2x2 km city at full size
-def test_city_full_size_sampled():
-    """The benchmark workload (16 Tx x 1M rays, K = 5, diffraction, 10k Rx,
-    two carriers): sampled rays bit-exact and sampled paths exact."""
+# The benchmark workload in the benchmark's launch configuration: 16 Tx x 1M
+# rays, K = 5, first-order diffraction, 10k moving receivers, 3.5 and 28 GHz.
+CITY_STRIDE = 7919  # every 7919th launch direction of every transmitter: 16 x 127 rays
+
+
+@pytest.fixture(scope="module")
+def city_run():
     w = city.workload("city")
     sc = w.scene
     tr = _tracer(sc, w, path_capacity=1 << 23)
@@ -304,26 +310,111 @@ def test_city_full_size_sampled():
     tr.set_frame(fr, 0)
     tr.step(True)
     assert tr.sync() == 0
-    st = tr.stats()
-    assert st["n_edges"] == 36800 and st["rays_per_bounce"][0] == 16_000_000
     os_ = O.OracleScene(sc)
-    g = os_.geometry(fr.obj_xform)
-    for t in (0, 7, 15):
-        ids = np.arange(t, w.rays_per_tx, 8191, dtype=np.int32)
-        hits = tr.debug_rays(t, ids)
-        res = O.trace(os_, g, fr.tx_pos[t], w.rays_per_tx, ids, w.max_reflections, fr.rx_pos, 1.0, True, True)
-        n_rob, mm_rob, _ = P.compare_hitlogs(hits, res.hit_tri, res.robust)
-        assert mm_rob == 0 and n_rob >= 0.9 * len(ids)
-    p = tr.flat_paths(cap=128)
+    out = dict(w=w, sc=sc, tr=tr, fr=fr, os=os_, g=os_.geometry(fr.obj_xform), stats=tr.stats())
+    out["ids"] = {t: np.arange(t * 37, w.rays_per_tx, CITY_STRIDE, dtype=np.int32) for t in range(sc.n_tx)}
+    out["hits"] = {t: tr.debug_rays(t, out["ids"][t]) for t in range(sc.n_tx)}
+    out["paths"] = tr.flat_paths(cap=128)
+    out["ch"] = P.gpu_channels_np(tr.channels())
+    # the oracle's traces of the same launch directions (receiver and edge capture, robust-ray mask)
+    out["traces"] = {t: O.trace(os_, out["g"], fr.tx_pos[t], w.rays_per_tx, out["ids"][t], w.max_reflections,
+                                fr.rx_pos, 1.0, True, True) for t in range(sc.n_tx)}
+    yield out
+    tr.close()
+
+
+def test_city_sizes(city_run):
+    st = city_run["stats"]
+    assert st["n_edges"] == 36800 and st["rays_per_bounce"][0] == 16_000_000
+    assert len(city_run["paths"]["key"]) == int(city_run["ch"]["n_paths"].sum()) or city_run["paths"]["truncated"]
+
+
+def test_city_hit_logs_all_transmitters(city_run):
+    """Per-ray interaction sequences, bit-exact on robust rays, for about 2,000
+    launch directions spread over all 16 transmitters."""
+    tot = rob = 0
+    for t, res in city_run["traces"].items():
+        n_rob, mm_rob, _ = P.compare_hitlogs(city_run["hits"][t], res.hit_tri, res.robust)
+        assert mm_rob == 0, (t, mm_rob)
+        tot += len(res.robust)
+        rob += n_rob
+    assert tot >= 2000 and rob >= 0.9 * tot
+
+
+def test_city_discovery_covers_oracle_subset(city_run):
+    """Specular keys the oracle's rays (the same launch directions) capture
+    robustly and validates unambiguously are in the GPU's path set; so are the
+    unambiguous diffraction keys of edges those rays light robustly (a sample
+    of them)."""
+    os_, g, fr, w = city_run["os"], city_run["g"], city_run["fr"], city_run["w"]
+    gset = P.keyset(city_run["paths"]["key"])
+    spec, diff = {}, {}
+    for t, res in city_run["traces"].items():
+        for k, rob in O.spec_keys(os_, res, t).items():
+            spec[k] = spec.get(k, False) or rob
+        for k, rob in O.diffraction_candidates(os_, g, t, O.illuminated_edges(res), fr.rx_pos,
+                                               w.diff_max_leg).items():
+            diff[k] = diff.get(k, False) or rob
+    ks = np.array([k for k, r in spec.items() if r], np.int32).reshape(-1, 9)
+    valid, amb, _, _ = O.validate(os_, g, ks, fr.tx_pos, fr.rx_pos, w.diff_max_leg)
+    want = P.keyset(ks[valid & ~amb])
+    assert len(want) > 200
+    assert want <= gset, sorted(want - gset)[:5]
+    kd = np.array([k for k, r in diff.items() if r], np.int32).reshape(-1, 9)
+    rng = np.random.default_rng(11)
+    kd = kd[rng.choice(len(kd), min(1500, len(kd)), replace=False)]
+    valid, amb, _, _ = O.validate(os_, g, kd, fr.tx_pos, fr.rx_pos, w.diff_max_leg)
+    want_d = P.keyset(kd[valid & ~amb])
+    assert len(want_d) > 20
+    assert want_d <= gset, sorted(want_d - gset)[:5]
+
+
+def test_city_paths_exact_in_oracle(city_run):
+    """Sampled GPU paths of every type validate in the oracle with the same
+    triangles; gain and Doppler at both carriers, delay and the departure /
+    arrival angles agree."""
+    os_, g, fr, w = city_run["os"], city_run["g"], city_run["fr"], city_run["w"]
+    p = city_run["paths"]
+    keys = p["key"]
     rng = np.random.default_rng(3)
-    pick = rng.choice(len(p["key"]), 300, replace=False)
-    valid, amb, tri, pts = O.validate(os_, g, p["key"][pick], fr.tx_pos, fr.rx_pos)
+    pick = np.concatenate([rng.choice(np.nonzero(keys[:, 2] == t)[0], min(300, int((keys[:, 2] == t).sum())),
+                                      replace=False) for t in (0, 1, 2)])
+    valid, amb, tri, pts = O.validate(os_, g, keys[pick], fr.tx_pos, fr.rx_pos, w.diff_max_leg)
     assert np.all(valid | amb)
     ok = valid & ~amb
-    a, tau, fd, _, _ = O.evaluate(os_, g, p["key"][pick][ok], pts[ok], fr, w.freqs_hz)
+    assert ok.sum() > 0.95 * len(pick)
+    a, tau, fd, aod, aoa = O.evaluate(os_, g, keys[pick][ok], pts[ok], fr, w.freqs_hz)
+    assert a.shape[1] == 2
     assert np.all(np.abs(p["a"][pick][ok] - a) <= 1e-8 * np.abs(a))
+    assert np.all(np.abs(p["tau"][pick][ok] - tau) <= P.TAU_REL * tau)
     assert np.all(np.abs(p["fd"][pick][ok] - fd) <= P.FD_ABS)
-    tr.close()
+    assert P.compare_angles(p["angles"][pick][ok], aod, aoa) <= 1e-6
+    spec = keys[pick][ok][:, 2] == 1
+    assert np.array_equal(p["tri_ids"][pick][ok][spec], tri[ok][spec])
+
+
+def test_city_channel_sums_both_carriers(city_run):
+    """Per-link sums at 3.5 and 28 GHz (power, delay and Doppler statistics)
+    over every path of about 200 sampled links equal the oracle's sums over
+    the same keys."""
+    os_, g, fr, w, sc = city_run["os"], city_run["g"], city_run["fr"], city_run["w"], city_run["sc"]
+    p, ch = city_run["paths"], city_run["ch"]
+    link = p["key"][:, 0].astype(np.int64) * sc.n_rx + p["key"][:, 1]
+    listed = np.bincount(link, minlength=sc.n_tx * sc.n_rx)
+    full = np.nonzero((ch["n_paths"] > 1) & (listed == ch["n_paths"]))[0]  # multipath links, none truncated
+    rng = np.random.default_rng(8)
+    links = rng.choice(full, min(220, len(full)), replace=False)
+    sel = np.isin(link, links)
+    keys = p["key"][sel]
+    valid, amb, tri, pts = O.validate(os_, g, keys, fr.tx_pos, fr.rx_pos, w.diff_max_leg)
+    assert np.all(valid | amb)
+    a, tau, fd, _, _ = O.evaluate(os_, g, keys, pts, fr, w.freqs_hz)
+    ref = O.reduce_links(keys, a, tau, fd, sc.n_tx, sc.n_rx)
+    amb_links = set(link[sel][amb].tolist())
+    check = np.array([L for L in links if L not in amb_links])
+    assert len(check) >= 150
+    assert not P.channel_ok(ch, ref, check, 100.0)
+    assert np.array_equal(ch["n_paths"][check], ref["n_paths"][check])
 
 
 # -------------------------------------------------------------- edge cases
