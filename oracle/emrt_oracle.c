@@ -286,9 +286,10 @@ void orc_fib_dirs(int32_t N, int32_t n, const int32_t* ids, float* out) {
 /* geometric primitives                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* Moller-Trumbore ray/triangle in double, two-sided, edges inclusive.
- * Returns 1 and t when o + t d meets the triangle with t > 0. */
-static int tri_hit(v3 o, v3 d, v3 a, v3 b, v3 c, double* t_out) {
+/* Moller-Trumbore line/triangle in double, two-sided, edges inclusive.
+ * Returns 1 and the line parameter t (any sign) when o + t d meets the
+ * triangle; 0 when it misses or lies in the triangle's plane. */
+static int line_tri_t(v3 o, v3 d, v3 a, v3 b, v3 c, double* t_out) {
     v3 e1 = vsub(b, a), e2 = vsub(c, a);
     v3 p = vcross(d, e2);
     double det = vdot(e1, p);
@@ -300,8 +301,14 @@ static int tri_hit(v3 o, v3 d, v3 a, v3 b, v3 c, double* t_out) {
     v3 q = vcross(s, e1);
     double v = vdot(d, q) * inv;
     if (v < 0.0 || u + v > 1.0) return 0;
-    double t = vdot(e2, q) * inv;
-    if (!(t > 0.0)) return 0;
+    *t_out = vdot(e2, q) * inv;
+    return 1;
+}
+
+/* The ray o + t d, t > 0, meets the triangle: returns 1 and t. */
+static int tri_hit(v3 o, v3 d, v3 a, v3 b, v3 c, double* t_out) {
+    double t;
+    if (!line_tri_t(o, d, a, b, c, &t) || !(t > 0.0)) return 0;
     *t_out = t;
     return 1;
 }
@@ -578,9 +585,12 @@ static int in_tri(v3 p, v3 a, v3 b, v3 c, double* edist) {
 
 /* Occlusion of the open segment p0 -> p1 (parameter in (0, 1)) by any
  * triangle outside the excluded faces (Section IV: opaque geometry, no
- * penetration).  Sets *amb when a triangle's edge passes within
- * 1 mm + 1e-6 * |p1 - p0| of the segment (the decision could flip under
- * float32 geometry). */
+ * penetration).  Sets *amb when the decision is within the margin
+ * m = 1 mm + 1e-6 * |p1 - p0| and could flip under float32 geometry: a
+ * triangle's edge passes within m of the segment, or a triangle meets the
+ * segment's line within m of an end point (a face coplanar with the face of
+ * an interaction point and overlapping it there, such as the roofs of two
+ * overlapping vehicles: whether it blocks is a matter of rounding). */
 static int occluded3(int32_t T, const float* tv, const int32_t* tri_face, v3 p0, v3 p1, int32_t xa, int32_t xb,
                      int32_t xc, int* amb) {
     v3 d = vsub(p1, p0);
@@ -592,7 +602,10 @@ static int occluded3(int32_t T, const float* tv, const int32_t* tri_face, v3 p0,
         if (f == xa || f == xb || f == xc) continue;
         v3 a = tvert(tv, t, 0), b = tvert(tv, t, 1), c = tvert(tv, t, 2);
         double th;
-        if (tri_hit(p0, d, a, b, c, &th) && th < 1.0) occ = 1;
+        if (line_tri_t(p0, d, a, b, c, &th)) {
+            if (th > 0.0 && th < 1.0) occ = 1;
+            if (amb && (fabs(th) * len < m || fabs(1.0 - th) * len < m)) *amb = 1;
+        }
         if (amb && !*amb) {
             double lo[3], hi[3];
             lo[0] = fmin(a.x, fmin(b.x, c.x)) - m; hi[0] = fmax(a.x, fmax(b.x, c.x)) + m;

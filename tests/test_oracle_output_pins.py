@@ -255,3 +255,25 @@ def test_cache_bookkeeping_cached_and_discovery_frames():
     assert key_set(disc.keys) == key_set(fresh.keys) | key_set(c1[v_c1])
     # the union is not trivial: the cache contributes keys the rays missed, or discovery adds new ones
     assert key_set(disc.keys) != key_set(c1[v_c1]) or key_set(disc.keys) != key_set(fresh.keys)
+
+
+def test_coplanar_overlapping_faces_make_a_reflection_ambiguous():
+    """Two squares of different objects in the plane z = 2 that overlap on
+    x in [5, 10] (like the roofs of two overlapping vehicles).  A reflection
+    off the first at x = 3 is valid and unambiguous; at x = 6 the second
+    square touches both legs at the reflection point, so whether it blocks
+    them is a rounding matter and the key is ambiguous."""
+    sq = lambda x0, x1: [(x0, 0.0, 2.0), (x1, 0.0, 2.0), (x1, 10.0, 2.0), (x0, 10.0, 2.0)]
+    g4 = [(-500.0, -500.0, 0.0), (500.0, -500.0, 0.0), (500.0, 500.0, 0.0), (-500.0, 500.0, 0.0)]
+    verts = np.array(g4 + sq(0.0, 10.0) + sq(5.0, 15.0), np.float32)
+    tris = np.array([(0, 1, 2), (0, 2, 3), (4, 5, 6), (4, 6, 7), (8, 9, 10), (8, 10, 11)], np.int32)
+    sc = city._static_scene(verts, tris, [0, 0, 1, 1, 2, 2], [0, 1, 2], 3, [city.EPS_GROUND, city.EPS_METAL],
+                            [0, 0, 10], 500, face_mat=[0, 1, 1])
+    os_ = O.OracleScene(sc)
+    g = os_.geometry(np.zeros((0, 3, 4)))
+    tx = np.array([[2.0, 5.0, 10.0]])
+    rx = np.array([[4.0, 5.0, 10.0], [10.0, 5.0, 10.0]])
+    keys = np.array([spec_key(0, 0, [1]), spec_key(0, 1, [1])], np.int32)
+    valid, amb, _, pts = O.validate(os_, g, keys, tx, rx)
+    assert valid[0] and not amb[0] and abs(pts[0, 0, 0] - 3.0) < 1e-12
+    assert amb[1] and abs(pts[1, 0, 0] - 6.0) < 1e-12
