@@ -342,14 +342,17 @@ def test_city_hit_logs_all_transmitters(city_run):
 
 
 def test_city_discovery_covers_oracle_subset(city_run):
-    """Specular keys the oracle's rays (the same launch directions) capture
-    robustly and validates unambiguously are in the GPU's path set; so are the
-    unambiguous diffraction keys of edges those rays light robustly (a sample
-    of them)."""
+    """Specular keys that the oracle's rays capture robustly on a launch
+    subset (every 256th direction of every transmitter, 62,500 rays; a key is
+    caught by a few rays of the full 1M-ray lattice) and validates
+    unambiguously are in the GPU's path set; so are the unambiguous
+    diffraction keys of edges those rays light robustly (a sample of them)."""
     os_, g, fr, w = city_run["os"], city_run["g"], city_run["fr"], city_run["w"]
     gset = P.keyset(city_run["paths"]["key"])
     spec, diff = {}, {}
-    for t, res in city_run["traces"].items():
+    ids = np.arange(5, w.rays_per_tx, 256, dtype=np.int32)
+    for t in range(city_run["sc"].n_tx):
+        res = O.trace(os_, g, fr.tx_pos[t], w.rays_per_tx, ids, w.max_reflections, fr.rx_pos, 1.0, True, True)
         for k, rob in O.spec_keys(os_, res, t).items():
             spec[k] = spec.get(k, False) or rob
         for k, rob in O.diffraction_candidates(os_, g, t, O.illuminated_edges(res), fr.rx_pos,
@@ -358,7 +361,7 @@ def test_city_discovery_covers_oracle_subset(city_run):
     ks = np.array([k for k, r in spec.items() if r], np.int32).reshape(-1, 9)
     valid, amb, _, _ = O.validate(os_, g, ks, fr.tx_pos, fr.rx_pos, w.diff_max_leg)
     want = P.keyset(ks[valid & ~amb])
-    assert len(want) > 200
+    assert len(want) > 100
     assert want <= gset, sorted(want - gset)[:5]
     kd = np.array([k for k, r in diff.items() if r], np.int32).reshape(-1, 9)
     rng = np.random.default_rng(11)
