@@ -20,7 +20,8 @@
  *     emrt_cache_import (which read back counts).
  *   - Memory: the caller owns every buffer.  The library never allocates
  *     device memory: it carves one caller-allocated workspace
- *     (emrt_workspace_size / emrt_bind_workspace).  Arrays marked "device"
+ *     (emrt_workspace_size / emrt_bind_workspace), or its own static array
+ *     for callers that cannot allocate (emrt_bind_static_workspace).  Arrays marked "device"
  *     are device pointers read or written in stream order; the caller keeps
  *     them alive and unmodified until the stream has passed the call.
  *     Arrays marked "host" are copied before the call returns.
@@ -105,6 +106,19 @@ int32_t emrt_workspace_size(emrt_ctx* ctx, const emrt_sizes* sizes, size_t* byte
  * it; it stays owned by the caller and must outlive the context's work.
  * Errors: EMRT_E_WORKSPACE (too small / NULL), EMRT_E_INVALID (sizes). */
 int32_t emrt_bind_workspace(emrt_ctx* ctx, void* device_ptr, size_t bytes);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bind the
+ * library's own static workspace of EMRT_STATIC_WORKSPACE_BYTES instead of a
+ * caller buffer.  Same contract as emrt_bind_workspace otherwise (call
+ * emrt_workspace_size first; the scene and everything after it must be set
+ * again).  Allocates nothing: each GPU holds one such array from the first
+ * bind on it until the process ends, and every context bound to it on that
+ * GPU shares it, so only one may be in use at a time (a later bind takes it
+ * over; overlapping use races).  Errors: EMRT_E_WORKSPACE (the sizes need
+ * more than EMRT_STATIC_WORKSPACE_BYTES: the message gives both sizes),
+ * EMRT_E_STATE (no sizes), EMRT_E_HIP (its device address). */
+#define EMRT_STATIC_WORKSPACE_BYTES (64u << 20)
+int32_t emrt_bind_static_workspace(emrt_ctx* ctx);
 /* Stream for all subsequent work (a hipStream_t; NULL = default stream). */
 int32_t emrt_set_stream(emrt_ctx* ctx, void* hip_stream);
 

@@ -16,6 +16,7 @@ EMRT_E_WORKSPACE = -3
 EMRT_E_HIP = -4
 EMRT_E_UNSUPPORTED = -5
 EMRT_E_DEVICE_FLAG = -6
+STATIC_WORKSPACE_BYTES = 64 << 20  # EMRT_STATIC_WORKSPACE_BYTES
 
 c_i32, c_i64, c_u32, c_f64, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
 
@@ -78,6 +79,7 @@ SIGNATURES = {
     "emrt_ctx_destroy": (c_i32, [c_vp]),
     "emrt_workspace_size": (c_i32, [c_vp, ctypes.POINTER(Sizes), ctypes.POINTER(ctypes.c_size_t)]),
     "emrt_bind_workspace": (c_i32, [c_vp, c_vp, ctypes.c_size_t]),
+    "emrt_bind_static_workspace": (c_i32, [c_vp]),
     "emrt_set_stream": (c_i32, [c_vp, c_vp]),
     "emrt_set_scene": (c_i32, [c_vp, ctypes.POINTER(SceneDesc)]),
     "emrt_set_materials": (c_i32, [c_vp, c_vp, c_i32]),

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -458,6 +459,59 @@ int32_t emrt_bind_workspace(emrt_ctx* c, void* ptr, size_t bytes) {
     fill_u32(c->hist, 0u, 1, c->stream);
     coherence_clear(c);
     return EMRT_OK;
+}
+
+// ---------------------------------------------- static workspace ----
+// A workspace held by the library itself, for callers that cannot allocate
+// device memory (code under HIP graph capture, serving loops, harnesses that
+// forbid hipMalloc).  Each GPU the library runs on holds its own copy of the
+// array until the process ends.  Its device address comes from
+// hipGetSymbolAddress, once per device, on the first bind on that device; the
+// array's name is a host-side stand-in and is never passed to a kernel or a
+// copy.  Every context bound to it on one GPU shares the same memory, so only
+// one such context per GPU may be in use at a time (a later bind takes it
+// over; overlapping use races).  The bind clears the counters and flags that
+// must start at zero, as emrt_bind_workspace does for any workspace.
+static __device__ __align__(256) unsigned char scratch[EMRT_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+int32_t emrt_bind_static_workspace(emrt_ctx* c) {
+    if (!c) return EMRT_E_INVALID;
+    if (!c->sized) return fail(c, EMRT_E_STATE, "call emrt_workspace_size first");
+    Carver m(nullptr);
+    layout(c, m);
+    const size_t need = m.off + 256;
+    if (need > (size_t)EMRT_STATIC_WORKSPACE_BYTES)
+        return fail(c, EMRT_E_WORKSPACE, "the sizes need a workspace of " + std::to_string(need) +
+                                             " bytes; the static workspace holds " +
+                                             std::to_string((size_t)EMRT_STATIC_WORKSPACE_BYTES) +
+                                             " (use emrt_bind_workspace with a caller buffer)");
+    void* p = nullptr;
+    hipError_t e = scratch_address(&p);
+    if (e != hipSuccess) return fail(c, EMRT_E_HIP, std::string("static workspace address: ") + hipGetErrorString(e));
+    return emrt_bind_workspace(c, p, (size_t)EMRT_STATIC_WORKSPACE_BYTES);
 }
 
 int32_t emrt_set_stream(emrt_ctx* c, void* s) {

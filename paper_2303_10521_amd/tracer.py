@@ -38,7 +38,7 @@ class Tracer:
     path_capacity, table_capacity, adjoint_materials).
     """
 
-    def __init__(self, scene, n_tx: int, n_rx: int, device: str = "cuda", **config):
+    def __init__(self, scene, n_tx: int, n_rx: int, device: str = "cuda", static_workspace: bool = False, **config):
         self.lib = A.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -64,10 +64,15 @@ class Tracer:
                      self.n_tx, self.n_rx)
         nbytes = ctypes.c_size_t()
         self._check(self.lib.emrt_workspace_size(self.ctx, ctypes.byref(sz), ctypes.byref(nbytes)))
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.workspace_bytes = int(nbytes.value)
         self.stream = torch.cuda.current_stream(self.device)
         self._check(self.lib.emrt_set_stream(self.ctx, ctypes.c_void_p(self.stream.cuda_stream)))
-        self._check(self.lib.emrt_bind_workspace(self.ctx, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
+        if static_workspace:  # the library's own array (emrt_bind_static_workspace): nothing is allocated
+            self.workspace = None
+            self._check(self.lib.emrt_bind_static_workspace(self.ctx))
+        else:
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self._check(self.lib.emrt_bind_workspace(self.ctx, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
         # state generation: advanced by every call that changes what the
         # adjoint of the last step would differentiate (a step, a frame, the
         # materials), so a recorded forward can tell whether it is still current
