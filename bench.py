@@ -162,6 +162,8 @@ def main() -> int:
                     help="time cached (revalidation) frames only, after one discovery frame (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device-to-device before the warm-up (reference dispatch for HBM counters)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint measurement (8-material district; for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the path is not sharded "
@@ -173,6 +175,14 @@ def main() -> int:
 
     from paper_2303_10521_amd import Tracer
     from synth import workload
+
+    if args.adjoint_only:
+        if args.calibrate_copy:
+            src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"mode": "adjoint only", "adjoint": bench_adjoint(torch, np, reps=1)}))
+        return 0
 
     w = workload(args.workload)
     sc = w.scene

@@ -292,6 +292,10 @@ struct RayPre {
     int kx, ky, kz;
     float Sx, Sy, Sz;
     int negmask;  // bit k set when d[k] < 0
+    // -o/d per axis pushed down (nm) and up (np) by 8 ulps of its magnitude, for
+    // the fused slab test: p/d - o/d evaluated as fma(p, 1/d, -o/d) stays
+    // conservative (see slab_fma)
+    float nmx, nmy, nmz, npx, npy, npz;
 };
 
 __device__ __forceinline__ float nz(float v) { return v != 0.0f ? v : 1e-30f; }
@@ -316,6 +320,14 @@ __device__ __forceinline__ RayPre ray_pre(float ox, float oy, float oz, float dx
     r.Sx = dkx / dkz;
     r.Sy = dky / dkz;
     r.Sz = 1.0f / dkz;
+    {
+#pragma clang fp contract(off)
+        const float qx = -(ox * r.ix), qy = -(oy * r.iy), qz = -(oz * r.iz);
+        // 8 ulps (2^-21 |q|, an exact scaling) cover the rounding of q and of q -+ e
+        const float ex = fabsf(qx) * 0x1p-21f, ey = fabsf(qy) * 0x1p-21f, ez = fabsf(qz) * 0x1p-21f;
+        r.nmx = qx - ex; r.nmy = qy - ey; r.nmz = qz - ez;
+        r.npx = qx + ex; r.npy = qy + ey; r.npz = qz + ez;
+    }
     return r;
 }
 
@@ -333,6 +345,27 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
     float b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.0000003576278687f;
     tn = a;
     return a <= fminf(b, tmax);
+}
+
+// Conservative slab test with fused multiply-adds, for the closest-hit
+// traversal.  The plane the ray meets first on an axis is the low one when
+// the direction component is positive (the high one otherwise), so per axis
+// one entry and one exit distance are computed, as fma(p, 1/d, -o/d -+ e):
+// with e = 8 ulps of |o/d| the entry is at most t (1 + 3u) + ... below and the
+// exit at least t (1 - 3u) (u = 2^-24, t the exact distance along the ray of
+// the rounded inverse, as in the plain form), so scaling the exit bound
+// (and the current closest distance) by 1 + 2^-20 never rejects a box the
+// exact ray meets before that distance.  Returns the entry distance in tn.
+__device__ __forceinline__ bool slab_fma(float lx, float ly, float lz, float hx, float hy, float hz, const RayPre& r,
+                                         float tmax, float& tn) {
+    const bool sx = r.negmask & 1, sy = r.negmask & 2, sz = r.negmask & 4;
+    const float nx = fmaf(sx ? hx : lx, r.ix, r.nmx), fx = fmaf(sx ? lx : hx, r.ix, r.npx);
+    const float ny = fmaf(sy ? hy : ly, r.iy, r.nmy), fy = fmaf(sy ? ly : hy, r.iy, r.npy);
+    const float nz = fmaf(sz ? hz : lz, r.iz, r.nmz), fz = fmaf(sz ? lz : hz, r.iz, r.npz);
+    const float a = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
+    const float b = fminf(fminf(fx, fy), fminf(fz, tmax)) * 1.00000095367431640625f;  // 1 + 2^-20
+    tn = a;
+    return a <= b;
 }
 
 // Watertight ray/triangle test, two-sided; hit when t > 0.  Edge functions
@@ -515,15 +548,27 @@ __device__ __forceinline__ void traverse(const BNode* nodes, const RayPre& r, Te
 
 struct NoStop { __device__ bool operator()() const { return false; } };
 
-// Closest hit among triangles not on face `skip_face`.  best_t / best_tri /
-// best_face carry the current best (ties broken by the lowest triangle id),
-// so the result does not depend on the tree or the visiting order.
+// One leaf triangle of the closest-hit query (ties to the lowest triangle id).
+template <bool STATS>
+__device__ __forceinline__ void leaf_closest(const TriP* prims, int child, const RayPre& r, int skip_face,
+                                             float& best_t, int& best_tri, int& best_face, unsigned& n_tris) {
+    TriP p = prims[(int)((uint32_t)child & ~EMRT_LEAF)];
+    if (STATS) n_tris++;
+    int face = __float_as_int(p.v1.w);
+    float t;
+    if (face != skip_face && tri_hit(p, r, t)) {
+        int id = __float_as_int(p.v0.w);
+        if (t < best_t || (t == best_t && id < best_tri)) { best_t = t; best_tri = id; best_face = face; }
+    }
+}
+
+// Closest hit with the query-independent generic traversal (the fallback of
+// closest_hit when its short stack overflows).
 template <bool STATS, class Stk = RegStack>
-__device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, int skip_face,
-                                            float& best_t, int& best_tri, int& best_face, unsigned& n_nodes,
-                                            unsigned& n_tris, Stk* stk = nullptr) {
+__device__ __forceinline__ void closest_hit_generic(const Bvh& bvh, const TriP* prims, const RayPre& r, int skip_face,
+                                                    float& best_t, int& best_tri, int& best_face, unsigned& n_nodes,
+                                                    unsigned& n_tris, Stk* stk = nullptr) {
     if (bvh.n_prims <= 0) return;
-    if (STATS) n_nodes++;
     traverse<true>(bvh.nodes, r,
         [&](float lx, float ly, float lz, float hx, float hy, float hz, int child, float& tn) -> bool {
             if (!slab(lx, ly, lz, hx, hy, hz, r, 0.0f, best_t, tn)) return false;
@@ -539,6 +584,57 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
             return false;
         },
         NoStop(), stk);
+}
+
+// Closest hit among triangles not on face `skip_face`.  best_t / best_tri /
+// best_face carry the current best (ties broken by the lowest triangle id),
+// so the result does not depend on the tree or the visiting order.
+//
+// Per node: both child boxes by the fused slab test (no branch), then the
+// leaf children that the ray meets (at most two triangles), then the
+// internal children: the one with the nearer entry is entered and the other
+// pushed.  Each node is loaded once.  If the short stack overflows, the query
+// starts over with the generic traversal, which needs no stack.
+template <bool STATS, class Stk = RegStack>
+__device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, const RayPre& r, int skip_face,
+                                            float& best_t, int& best_tri, int& best_face, unsigned& n_nodes,
+                                            unsigned& n_tris, Stk* stk = nullptr) {
+    if (bvh.n_prims <= 0) return;
+    if (STATS) n_nodes++;
+    RegStack own;
+    int sp = 0, cur = 0;
+    bool overflow = false;
+    while (true) {
+        const BNode nd = ld_node(bvh.nodes, cur);
+        float t0, t1;
+        const bool d0 = slab_fma(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, best_t, t0);
+        const bool d1 = slab_fma(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, best_t, t1);
+        const int c0 = nd.m.x, c1 = nd.m.y;
+        const bool leaf0 = (uint32_t)c0 & EMRT_LEAF, leaf1 = (uint32_t)c1 & EMRT_LEAF;
+        if ((d0 && leaf0) || (d1 && leaf1)) {
+            if (d0 && leaf0) leaf_closest<STATS>(prims, c0, r, skip_face, best_t, best_tri, best_face, n_tris);
+            if (d1 && leaf1) leaf_closest<STATS>(prims, c1, r, skip_face, best_t, best_tri, best_face, n_tris);
+        }
+        const bool i0 = d0 && !leaf0, i1 = d1 && !leaf1;
+        if (STATS) n_nodes += (i0 ? 1u : 0u) + (i1 ? 1u : 0u);
+        const bool second = i1 && (!i0 || t1 < t0);  // enter child 1 first
+        const int ca = second ? c1 : c0, cb = second ? c0 : c1;
+        if (i0 && i1) {
+            if (sp == kStackDepth) { overflow = true; break; }
+            if constexpr (std::is_same<Stk, RegStack>::value) own.set(sp, cb);
+            else stk->set(sp, cb);
+            sp++;
+        }
+        if (i0 || i1) {
+            cur = ca;
+            continue;
+        }
+        if (sp == 0) break;
+        --sp;
+        if constexpr (std::is_same<Stk, RegStack>::value) cur = own.get(sp);
+        else cur = stk->get(sp);
+    }
+    if (overflow) closest_hit_generic<false>(bvh, prims, r, skip_face, best_t, best_tri, best_face, n_nodes, n_tris, stk);
 }
 
 // Any hit on the open segment t in (0, tmax) among triangles not on faces
