@@ -28,9 +28,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (packed; 78.6 non-packed)
-FLOP_PER_NODE = 24  # two child-box slab tests: 6 sub + 6 mul each
-FLOP_PER_TRI = 36  # watertight test: 9 sub, 6 shear, 9 edge-function, 2 det, 3 scale, 6 T, 1 div
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32, published (packed)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # without packed FP32 instructions, which this library does not use
+# Counted work of the closest-hit traversal, FP32 operations as the code performs them (fma = 2):
+FLOP_PER_NODE = 34  # binary node (dynamic tree): two boxes x (6 fma + 4 min/max + 1 scale)
+FLOP_PER_WIDE_BOX = 29  # child box of a 4-wide node (static tree): 6 fma decode + 6 fma + 4 min/max + 1 scale
+FLOP_PER_TRI = 35  # watertight triangle test (shear, edge functions, determinant, distance)
 
 
 def committed_traffic():
@@ -270,29 +273,33 @@ def main() -> int:
     if not args.timed_only:
         # counted traversal work of the same steps (instrumented, untimed)
         tr.set_instrumentation(stats=True, timing=False)
-        nodes = tris = segs = 0
+        nodes = boxes = tris = segs = 0
         for k in range(args.steps):
             f = args.warmup + k
             tr.set_frame(frames[f], f)
             tr.step(True)
             st = tr.stats()
             nodes += st["node_visits"]
+            boxes += st["wide_box_tests"]
             tris += st["tri_tests"]
             segs += st["segments"]
         tr.set_instrumentation(stats=False, timing=False)
-        flops = FLOP_PER_NODE * nodes + FLOP_PER_TRI * tris
+        flops = FLOP_PER_NODE * nodes + FLOP_PER_WIDE_BOX * boxes + FLOP_PER_TRI * tris
         achieved = flops / (bounce_ms * 1e-3) / 1e12 if bounce_ms > 0 else 0.0
         out["roofline"] = {
             "kernel": "k_bounce (closest hit + receiver/edge capture + reflect + compaction)",
             "bound": "alu",
+            "limiter": "latency of divergent traversal (dependent node loads; VALU issue about 60% busy)",
             "achieved": round(achieved, 4),
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
+            "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 5),
             "traffic": committed_traffic(),
             "avg_launch_ms": round(bounce_ms / max(bounce_launches, 1), 4),
             "flops_per_launch": int(flops / max(bounce_launches, 1)),
             "segments_per_step": int(segs / args.steps),
+            "wide_box_tests_per_segment": round(boxes / max(segs, 1), 2),
             "node_visits_per_segment": round(nodes / max(segs, 1), 2),
             "tri_tests_per_segment": round(tris / max(segs, 1), 2),
             "static_tree_area": round(float(st["static_tree_area"]), 2),

@@ -348,6 +348,8 @@ typedef struct emrt_stats {
     int32_t validate_launches;
     double static_tree_area;    /* static tree quality: summed surface area of every node below the
                                    root over the root's (the expected box tests of a random ray) */
+    int64_t wide_box_tests;     /* child boxes tested in the static tree's 4-wide nodes (when stats are
+                                   enabled); node_visits then counts the binary (dynamic tree) nodes */
 } emrt_stats;
 int32_t emrt_read_stats(emrt_ctx* ctx, emrt_stats* out);
 /* Optional instrumentation: stats = count traversal work (slower), timing =

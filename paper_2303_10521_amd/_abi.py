@@ -69,7 +69,7 @@ class Stats(ctypes.Structure):
                 ("node_visits", c_i64), ("tri_tests", c_i64), ("segments", c_i64), ("captures", c_i64),
                 ("n_static_tris", c_i64), ("n_dynamic_tris", c_i64), ("n_edges", c_i64), ("device_flags", c_u32),
                 ("bounce_ms", c_f64), ("bounce_launches", c_i32), ("validate_ms", c_f64),
-                ("validate_launches", c_i32), ("static_tree_area", c_f64)]
+                ("validate_launches", c_i32), ("static_tree_area", c_f64), ("wide_box_tests", c_i64)]
 
 
 # name -> (restype, argtypes)

@@ -27,7 +27,7 @@ constexpr int C_WORK = 8;      // [8..15] work counters per bounce
 constexpr int C_NCAND = 16;
 constexpr int C_NVALID = 17;
 constexpr int C_NCACHE = 18;   // [18, 19] cache sizes (double buffer)
-constexpr int C_STATS = 20;    // [20..23]
+constexpr int C_STATS = 20;    // [20..23] and [36] (traversal counters)
 constexpr int C_TRUNC = 24;    // path-list truncation flag
 constexpr int C_NLEGS = 25;    // shadow legs of the step besides the receiver legs
 constexpr int C_COH = 26;      // [26, 27] coherence read-back (min T_c bits, triggered links)
@@ -100,6 +100,8 @@ struct emrt_ctx {
     SceneDev S{};
     Tree st, dy, rxt, edt;
     TriP *st_prims = nullptr, *dy_prims = nullptr;
+    QNode4* st4 = nullptr;     // [T] the static tree as 4-wide quantised nodes
+    int st4_n = 0;
     float4 *rx_prims = nullptr, *edge_prims = nullptr;
     float *box_st = nullptr, *box_dy = nullptr, *box_rx = nullptr, *box_ed = nullptr;
     BuildTemp tmp{};
@@ -223,6 +225,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     tree(c->rxt, z.n_rx);
     tree(c->edt, c->E_cap);
     tree(c->txt, z.n_tx);
+    c->st4 = cv.take<QNode4>(T);
     c->st_prims = cv.take<TriP>(T);
     c->dy_prims = cv.take<TriP>(T);
     c->rx_prims = cv.take<float4>(z.n_rx);
@@ -609,6 +612,18 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     tri_boxes(S, S.tris_static, S.T_s, c->box_st, st);
     if (bvh_build_sah(c->box_st, S.T_s, c->st, c->tmp, st) < 0) return fail(c, EMRT_E_HIP, "static tree build");
     tri_prims(S, S.tris_static, c->st, c->st_prims, st);
+    c->st4_n = 0;
+    if (S.T_s > 0) {  // the same tree as 4-wide quantised nodes (collapsed on the host, once per scene)
+        const int nb = std::max(S.T_s - 1, 1);
+        std::vector<BNode> hb((size_t)nb);
+        std::vector<QNode4> h4((size_t)nb);
+        if ((rc = sync_read(c, hb.data(), c->st.nodes, sizeof(BNode) * (size_t)nb))) return rc;
+        const int n4 = bvh4_collapse(hb.data(), S.T_s, h4.data(), nb);
+        if (n4 < 1) return fail(c, EMRT_E_HIP, "static tree collapse");
+        HC(hipMemcpyAsync(c->st4, h4.data(), sizeof(QNode4) * (size_t)n4, hipMemcpyHostToDevice, st));
+        HC(hipStreamSynchronize(st));  // h4 is a host temporary
+        c->st4_n = n4;
+    }
     c->st_area = 0.0;
     if (S.T_s > 1) {  // tree quality: child box areas over the root box area
         double* acc = (double*)c->tmp.bounds;
@@ -712,6 +727,7 @@ static PathArgs path_args(emrt_ctx* c) {
     a.f.tx_pos = c->f_tx; a.f.tx_vel = c->f_txv; a.f.tx_orient = c->f_txo;
     a.f.rx_pos = c->f_rx; a.f.rx_vel = c->f_rxv; a.f.obj_vel = c->f_ov;
     a.st = c->st.view(); a.dy = c->dy.view();
+    a.st4 = Bvh4{c->st4, c->S.T_s};
     a.st_prims = c->st_prims; a.dy_prims = c->dy_prims;
     a.fc.mat_eps = c->mat;
     a.fc.mat_refl = c->refl;
@@ -764,6 +780,7 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.n_total = launch_total(c);
     b.rays_per_tx = rays;
     b.st = Bvh{c->st.nodes, S.T_s};
+    b.st4 = Bvh4{c->st4, S.T_s};
     b.dy = Bvh{c->dy.nodes, S.T_d};
     b.st_prims = c->st_prims;
     b.dy_prims = c->dy_prims;
@@ -1184,6 +1201,7 @@ int32_t emrt_read_stats(emrt_ctx* c, emrt_stats* o) {
     o->tri_tests = (int64_t)h[C_STATS + 1];
     o->segments = (int64_t)h[C_STATS + 2];
     o->captures = (int64_t)h[C_STATS + 3];
+    o->wide_box_tests = (int64_t)h[C_STATS + 16];
     o->n_static_tris = c->S.T_s;
     o->n_dynamic_tris = c->S.T_d;
     o->n_edges = c->S.E;

@@ -16,6 +16,12 @@
 // child boxes and continues, so every node is written exactly once per refit.
 // Paper: Section II-A (a BVH updated between frames), Section III-A (only
 // subtrees change within a trajectory segment).
+#include <math.h>
+#include <string.h>
+
+#include <utility>
+#include <vector>
+
 #include "emrt_dev.h"
 #include "emrt_launch.h"
 
@@ -635,6 +641,159 @@ void bvh_sah(const Tree& tree, double* out, hipStream_t st) {
     int g = (n_int + 255) / 256;
     if (g > 1024) g = 1024;
     hipLaunchKernelGGL(k_sah, dim3(g), dim3(256), 0, st, tree.nodes, n_int, out);
+}
+
+
+// ------------------------------------------------------ 4-wide tree ----
+// Host-side collapse of a binary tree into 4-wide nodes: a node takes its
+// binary node's two children and keeps opening the internal child of
+// largest surface area until it has four (or only leaves).  Child boxes are
+// quantised to bytes on a per-node grid o + q 2^e: the low byte is the
+// largest q whose fused multiply-add fma(q, 2^e, o) lies at or below the
+// child's low bound, the high byte the smallest at or above its high bound,
+// evaluated with the same fma the traversal uses, so the decoded boxes
+// contain the children's boxes exactly.  A node's children get consecutive
+// indices, before the subtrees below them.
+namespace {
+struct HBox {
+    float lo[3], hi[3];
+};
+
+HBox child_box(const BNode& n, int side) {
+    HBox b;
+    if (side == 0) {
+        b.lo[0] = n.a.x; b.lo[1] = n.a.y; b.lo[2] = n.a.z;
+        b.hi[0] = n.a.w; b.hi[1] = n.b.x; b.hi[2] = n.b.y;
+    } else {
+        b.lo[0] = n.b.z; b.lo[1] = n.b.w; b.lo[2] = n.c.x;
+        b.hi[0] = n.c.y; b.hi[1] = n.c.z; b.hi[2] = n.c.w;
+    }
+    return b;
+}
+
+bool box_empty(const HBox& b) {
+    for (int k = 0; k < 3; k++)
+        if (!(b.lo[k] <= b.hi[k])) return true;
+    return false;
+}
+
+double box_area(const HBox& b) {
+    const double x = (double)b.hi[0] - b.lo[0], y = (double)b.hi[1] - b.lo[1], z = (double)b.hi[2] - b.lo[2];
+    return x * y + y * z + z * x;
+}
+
+float scale_of(uint32_t e) {
+    const uint32_t bits = e << 23;
+    float f;
+    memcpy(&f, &bits, sizeof(f));
+    return f;
+}
+
+// exponent byte e of the grid step 2^(e - 127) so that fma(255, step, o) >= hi
+// (0, a step of 0, when the node is flat on this axis)
+uint32_t grid_exp(float o, float hi) {
+    if (!(hi > o)) return 0;
+    int e2 = 0;
+    frexp(((double)hi - (double)o) / 255.0, &e2);
+    int e = e2 + 127;
+    if (e < 1) e = 1;
+    while (e < 254 && fmaf(255.0f, scale_of((uint32_t)e), o) < hi) e++;
+    return (uint32_t)e;
+}
+
+uint32_t q_low(float v, float o, float step) {
+    if (step == 0.0f) return 0u;
+    double q = floor(((double)v - (double)o) / (double)step);
+    q = q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q);
+    uint32_t k = (uint32_t)q;
+    while (k > 0 && fmaf((float)k, step, o) > v) k--;
+    while (k < 255 && fmaf((float)(k + 1), step, o) <= v) k++;
+    return k;
+}
+
+uint32_t q_high(float v, float o, float step) {
+    if (step == 0.0f) return 0u;
+    double q = ceil(((double)v - (double)o) / (double)step);
+    q = q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q);
+    uint32_t k = (uint32_t)q;
+    while (k < 255 && fmaf((float)k, step, o) < v) k++;
+    while (k > 0 && fmaf((float)(k - 1), step, o) >= v) k--;
+    return k;
+}
+
+struct Ent {
+    int ref;  // internal binary node index, or EMRT_LEAF | primitive slot (negative)
+    HBox box;
+};
+}  // namespace
+
+int bvh4_collapse(const BNode* bin, int n_prims, QNode4* out, int cap) {
+    if (n_prims <= 0 || cap < 1) return 0;
+    std::vector<std::pair<int, int>> work;  // (binary node, 4-wide slot)
+    int n_out = 1;
+    work.push_back({0, 0});
+    while (!work.empty()) {
+        const int nid = work.back().first, oi = work.back().second;
+        work.pop_back();
+        Ent ch[4];
+        int n = 0;
+        for (int side = 0; side < 2; side++) {
+            const HBox b = child_box(bin[nid], side);
+            if (!box_empty(b)) ch[n++] = Ent{side ? bin[nid].m.y : bin[nid].m.x, b};
+        }
+        while (n < 4) {  // open the internal child of largest area
+            int best = -1;
+            double ba = -1.0;
+            for (int k = 0; k < n; k++)
+                if (ch[k].ref >= 0 && box_area(ch[k].box) > ba) { ba = box_area(ch[k].box); best = k; }
+            if (best < 0) break;
+            const BNode& cn = bin[ch[best].ref];
+            Ent e[2];
+            int ne = 0;
+            for (int side = 0; side < 2; side++) {
+                const HBox b = child_box(cn, side);
+                if (!box_empty(b)) e[ne++] = Ent{side ? cn.m.y : cn.m.x, b};
+            }
+            if (ne == 0) { ch[best] = ch[--n]; continue; }
+            ch[best] = e[0];
+            if (ne == 2) ch[n++] = e[1];
+        }
+        QNode4 q{};
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int k = 0; k < n; k++)
+            for (int a = 0; a < 3; a++) {
+                lo[a] = fminf(lo[a], ch[k].box.lo[a]);
+                hi[a] = fmaxf(hi[a], ch[k].box.hi[a]);
+            }
+        if (n == 0)
+            for (int a = 0; a < 3; a++) lo[a] = hi[a] = 0.0f;
+        uint32_t e[3], qx[3] = {0, 0, 0}, rx[3] = {0, 0, 0};
+        for (int a = 0; a < 3; a++) e[a] = grid_exp(lo[a], hi[a]);
+        int c[4] = {0, 0, 0, 0};
+        for (int k = 0; k < n; k++) {
+            for (int a = 0; a < 3; a++) {
+                const float step = e[a] ? scale_of(e[a]) : 0.0f;
+                qx[a] |= q_low(ch[k].box.lo[a], lo[a], step) << (8 * k);
+                rx[a] |= q_high(ch[k].box.hi[a], lo[a], step) << (8 * k);
+            }
+            if (ch[k].ref >= 0) {  // an internal child becomes the next 4-wide slot
+                if (n_out >= cap) return -1;
+                c[k] = n_out;
+                work.push_back({ch[k].ref, n_out++});
+            } else {
+                c[k] = ch[k].ref;
+            }
+        }
+        const uint32_t meta = e[0] | (e[1] << 8) | (e[2] << 16) | ((uint32_t)n << 24);
+        float mw;
+        memcpy(&mw, &meta, sizeof(mw));
+        q.o = make_float4(lo[0], lo[1], lo[2], mw);
+        q.q = make_uint4(qx[0], qx[1], qx[2], 0u);
+        q.r = make_uint4(rx[0], rx[1], rx[2], 0u);
+        q.c = make_int4(c[0], c[1], c[2], c[3]);
+        out[oi] = q;
+    }
+    return n_out;
 }
 
 }  // namespace emrt

@@ -63,6 +63,25 @@ struct Bvh {
     int n_prims;  // 0: empty tree
 };
 
+// 4-wide node with quantised child boxes (the static tree, collapsed from
+// its binary SAH tree): child k's box on axis a is
+//   [fma(qlo, s_a, o_a), fma(qhi, s_a, o_a)],  s_a = 2^(e_a - 127) (0 when e_a = 0),
+// with byte k of q.{x,y,z} / r.{x,y,z} holding child k's qlo / qhi on x, y,
+// z.  The bytes are chosen at build time with the same fused multiply-add,
+// so every decoded box contains its child's box.  64 B, one node per four
+// children instead of two.
+struct __attribute__((aligned(16))) QNode4 {
+    float4 o;  // x, y, z: the node's low corner; w (bits): e_x | e_y << 8 | e_z << 16 | children << 24
+    uint4 q;   // qlo bytes (x, y, z; w unused)
+    uint4 r;   // qhi bytes (x, y, z; w unused)
+    int4 c;    // children: node index, or EMRT_LEAF | primitive slot
+};
+
+struct Bvh4 {
+    const QNode4* nodes;
+    int n_prims;  // 0: empty tree
+};
+
 // --------------------------------------------------------------------------
 // float / double vectors
 // --------------------------------------------------------------------------
@@ -428,6 +447,10 @@ __device__ __forceinline__ bool tri_hit(const TriP& p, const RayPre& r, float& t
 #define EMRT_STACK_DEPTH 12
 #endif
 constexpr int kStackDepth = EMRT_STACK_DEPTH;
+// The 4-wide tree pushes up to three children per level; its stack (the
+// same LDS columns) holds 16 entries.
+constexpr int kStackDepth4 = 16;
+constexpr int kStackRows = kStackDepth4 > kStackDepth ? kStackDepth4 : kStackDepth;
 
 __device__ __forceinline__ BNode ld_node(const BNode* n, int i) { return n[i]; }
 
@@ -634,8 +657,9 @@ __device__ __forceinline__ void closest_hit(const Bvh& bvh, const TriP* prims, c
         if constexpr (std::is_same<Stk, RegStack>::value) cur = own.get(sp);
         else cur = stk->get(sp);
     }
-    if (overflow) closest_hit_generic<false>(bvh, prims, r, skip_face, best_t, best_tri, best_face, n_nodes, n_tris, stk);
+    if (overflow) closest_hit_generic<STATS>(bvh, prims, r, skip_face, best_t, best_tri, best_face, n_nodes, n_tris, stk);
 }
+
 
 // Any hit on the open segment t in (0, tmax) among triangles not on faces
 // xa / xb / xc (shadow rays of path validation).
@@ -656,6 +680,145 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
         },
         [&]() { return found; }, stk);
     return found;
+}
+
+// Child k of a 4-wide node: decoded box (exact fma of the stored bytes, as at
+// build time) through the fused slab test.
+template <int K>
+__device__ __forceinline__ bool child4(const QNode4& nd, float sx, float sy, float sz, const RayPre& r, float tmax,
+                                       float& tn) {
+    const float lx = fmaf((float)((nd.q.x >> (8 * K)) & 255u), sx, nd.o.x);
+    const float ly = fmaf((float)((nd.q.y >> (8 * K)) & 255u), sy, nd.o.y);
+    const float lz = fmaf((float)((nd.q.z >> (8 * K)) & 255u), sz, nd.o.z);
+    const float hx = fmaf((float)((nd.r.x >> (8 * K)) & 255u), sx, nd.o.x);
+    const float hy = fmaf((float)((nd.r.y >> (8 * K)) & 255u), sy, nd.o.y);
+    const float hz = fmaf((float)((nd.r.z >> (8 * K)) & 255u), sz, nd.o.z);
+    return slab_fma(lx, ly, lz, hx, hy, hz, r, tmax, tn);
+}
+
+__device__ __forceinline__ float scale4(uint32_t bits, int shift) {
+    return __int_as_float((int)(((bits >> shift) & 255u) << 23));
+}
+
+// compare-exchange of (entry distance, child) pairs, nearer first
+__device__ __forceinline__ void cx4(float& ta, int& ca, float& tb, int& cb) {
+    const bool sw = tb < ta;
+    const float t = sw ? tb : ta;
+    const int c = sw ? cb : ca;
+    tb = sw ? ta : tb;
+    cb = sw ? ca : cb;
+    ta = t;
+    ca = c;
+}
+
+// Closest hit over a 4-wide tree (same query, result and tie rule as
+// closest_hit): the boxes of a node's children are tested, leaf children
+// (triangles) tested at once, and the internal children the ray meets are
+// sorted by entry distance: the nearest is entered and the others pushed so
+// that they pop nearest first.  A stack overflow restarts the query on the
+// binary tree `bin` with the generic traversal (same result).
+// STATS: n_boxes counts the child boxes tested (a node's children), n_nodes
+// the binary nodes of a fallback traversal.
+template <bool STATS, class Stk>
+__device__ __forceinline__ void closest_hit4(const Bvh4& bvh, const Bvh& bin, const TriP* prims, const RayPre& r,
+                                             int skip_face, float& best_t, int& best_tri, int& best_face,
+                                             unsigned& n_boxes, unsigned& n_nodes, unsigned& n_tris, Stk* stk) {
+    if (bvh.n_prims <= 0) return;
+    int sp = 0, cur = 0;
+    bool overflow = false;
+    while (true) {
+        const QNode4 nd = bvh.nodes[cur];
+        const uint32_t meta = __float_as_uint(nd.o.w);
+        const int cnt = (int)(meta >> 24);
+        if (STATS) n_boxes += (unsigned)cnt;
+        const float sx = scale4(meta, 0), sy = scale4(meta, 8), sz = scale4(meta, 16);
+        float t0, t1, t2, t3;
+        const bool h0 = child4<0>(nd, sx, sy, sz, r, best_t, t0) && cnt > 0;
+        const bool h1 = child4<1>(nd, sx, sy, sz, r, best_t, t1) && cnt > 1;
+        const bool h2 = child4<2>(nd, sx, sy, sz, r, best_t, t2) && cnt > 2;
+        const bool h3 = child4<3>(nd, sx, sy, sz, r, best_t, t3) && cnt > 3;
+        int c0 = nd.c.x, c1 = nd.c.y, c2 = nd.c.z, c3 = nd.c.w;
+        const bool f0 = h0 && c0 < 0, f1 = h1 && c1 < 0, f2 = h2 && c2 < 0, f3 = h3 && c3 < 0;
+        if (f0 || f1 || f2 || f3) {
+            if (f0) leaf_closest<STATS>(prims, c0, r, skip_face, best_t, best_tri, best_face, n_tris);
+            if (f1) leaf_closest<STATS>(prims, c1, r, skip_face, best_t, best_tri, best_face, n_tris);
+            if (f2) leaf_closest<STATS>(prims, c2, r, skip_face, best_t, best_tri, best_face, n_tris);
+            if (f3) leaf_closest<STATS>(prims, c3, r, skip_face, best_t, best_tri, best_face, n_tris);
+        }
+        // internal children met by the ray, by entry distance (others at +inf)
+        t0 = (h0 && c0 >= 0) ? t0 : INFINITY;
+        t1 = (h1 && c1 >= 0) ? t1 : INFINITY;
+        t2 = (h2 && c2 >= 0) ? t2 : INFINITY;
+        t3 = (h3 && c3 >= 0) ? t3 : INFINITY;
+        const int n_in = (t0 < INFINITY) + (t1 < INFINITY) + (t2 < INFINITY) + (t3 < INFINITY);
+        if (n_in == 0) {
+            if (sp == 0) break;
+            cur = stk->get(--sp);
+            continue;
+        }
+        cx4(t0, c0, t1, c1);
+        cx4(t2, c2, t3, c3);
+        cx4(t0, c0, t2, c2);
+        cx4(t1, c1, t3, c3);
+        cx4(t1, c1, t2, c2);
+        if (sp + n_in - 1 > kStackDepth4) { overflow = true; break; }
+        if (n_in > 3) stk->set(sp++, c3);
+        if (n_in > 2) stk->set(sp++, c2);
+        if (n_in > 1) stk->set(sp++, c1);
+        cur = c0;
+    }
+    if (overflow) closest_hit_generic<STATS>(bin, prims, r, skip_face, best_t, best_tri, best_face, n_nodes, n_tris, stk);
+}
+
+// Any hit on the open segment t in (0, tmax) over a 4-wide tree among
+// triangles not on faces xa / xb / xc (shadow rays).  Overflow restarts on
+// the binary tree.
+template <class Stk>
+__device__ __forceinline__ bool any_hit4(const Bvh4& bvh, const Bvh& bin, const TriP* prims, const RayPre& r,
+                                         float tmax, int xa, int xb, int xc, Stk* stk) {
+    if (bvh.n_prims <= 0) return false;
+    int sp = 0, cur = 0;
+    while (true) {
+        const QNode4 nd = bvh.nodes[cur];
+        const uint32_t meta = __float_as_uint(nd.o.w);
+        const int cnt = (int)(meta >> 24);
+        const float sx = scale4(meta, 0), sy = scale4(meta, 8), sz = scale4(meta, 16);
+        float t0, t1, t2, t3;
+        const bool h0 = child4<0>(nd, sx, sy, sz, r, tmax, t0) && cnt > 0;
+        const bool h1 = child4<1>(nd, sx, sy, sz, r, tmax, t1) && cnt > 1;
+        const bool h2 = child4<2>(nd, sx, sy, sz, r, tmax, t2) && cnt > 2;
+        const bool h3 = child4<3>(nd, sx, sy, sz, r, tmax, t3) && cnt > 3;
+        const int cs[4] = {nd.c.x, nd.c.y, nd.c.z, nd.c.w};
+        const bool hs[4] = {h0, h1, h2, h3};
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (hs[k] && cs[k] < 0) {
+                TriP p = prims[(int)((uint32_t)cs[k] & ~EMRT_LEAF)];
+                const int face = __float_as_int(p.v1.w);
+                float t;
+                if (face != xa && face != xb && face != xc && tri_hit(p, r, t) && t < tmax) found = true;
+            }
+        }
+        if (found) return true;
+        int next = -1;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (hs[k] && cs[k] >= 0) {
+                if (next < 0) next = cs[k];
+                else {
+                    if (sp == kStackDepth4) return any_hit(bin, prims, r, tmax, xa, xb, xc, stk);
+                    stk->set(sp++, cs[k]);
+                }
+            }
+        }
+        if (next >= 0) {
+            cur = next;
+            continue;
+        }
+        if (sp == 0) return false;
+        cur = stk->get(--sp);
+    }
 }
 
 // Visit every leaf whose box, inflated by `grow`, meets the ray on [0, tmax].

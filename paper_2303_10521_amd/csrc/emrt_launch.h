@@ -61,6 +61,10 @@ void bvh_refit(const float* box6, Tree& tree, hipStream_t st);
 int bvh_build_sah(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st);
 // extra tree statistics: surface-area sum of internal nodes (device double)
 void bvh_sah(const Tree& tree, double* out, hipStream_t st);
+// Host: collapse a binary tree (its internal nodes read back from the device,
+// root first) into 4-wide nodes with quantised child boxes (QNode4), root
+// first, parents before children.  Returns the node count.
+int bvh4_collapse(const BNode* bin, int n_prims, QNode4* out, int cap);
 
 // ----------------------------------------------------------- scene.hip ----
 struct SceneDev {
@@ -124,6 +128,7 @@ struct BounceArgs {
     int rays_per_tx;
     // scene
     Bvh st, dy;
+    Bvh4 st4;  // the static tree collapsed to 4-wide quantised nodes (same leaves as st)
     const TriP* st_prims;
     const TriP* dy_prims;
     const double* plane;
@@ -222,6 +227,7 @@ struct PathArgs {
     int* ktri;        // [n_links + cap_cand][5] triangle of each reflection point of a constructed key
     FrameDev f;
     Bvh st, dy;
+    Bvh4 st4;  // the static tree collapsed to 4-wide quantised nodes (same leaves as st)
     const TriP* st_prims;
     const TriP* dy_prims;
     FieldCtx fc;

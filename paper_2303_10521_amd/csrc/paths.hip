@@ -242,13 +242,6 @@ __device__ __forceinline__ int face_contains(const PathArgs& a, int f, dv3 p, Ld
     return found;
 }
 
-// float32 shadow ray over the open segment p0 -> p1
-__device__ __forceinline__ bool occluded(const PathArgs& a, dv3 p0, dv3 p1, int xa, int xb) {
-    dv3 d = p1 - p0;
-    RayPre r = ray_pre((float)p0.x, (float)p0.y, (float)p0.z, (float)d.x, (float)d.y, (float)d.z);
-    if (any_hit(a.st, a.st_prims, r, 1.0f, xa, xb)) return true;
-    return any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb);
-}
 
 // Keller point (equal angles with the edge) strictly inside the edge, both
 // ends in the exterior wedge, receiver leg within diff_max_leg.  The source's
@@ -944,14 +937,14 @@ __device__ __forceinline__ void shadow_leg(const PathArgs& a, long long i, uint3
     int xa = a.legs.xa[i], xb = a.legs.xb[i], xc = a.legs.xc[i];
     bool hit = false;
     if (!dyn_only) {
-        hit = any_hit(a.st, a.st_prims, r, 1.0f, xa, xb, xc, stk);
+        hit = any_hit4(a.st4, a.st, a.st_prims, r, 1.0f, xa, xb, xc, stk);
         if (los) a.los_sb[q] = hit ? 1 : 0;
     }
     if (hit || any_hit(a.dy, a.dy_prims, r, 1.0f, xa, xb, xc, stk)) a.occl[q] = 1u;
 }
 
 __global__ void __launch_bounds__(256) k_shadow_first(PathArgs a, long long n_links, long long cap_cand) {
-    __shared__ int stk_lds[kStackDepth][kStackStride];
+    __shared__ int stk_lds[kStackRows][kStackStride];
     LdsStack stk{&stk_lds[0][threadIdx.x]};
     long long nc = (long long)*a.n_cand;
     if (nc > cap_cand) nc = cap_cand;
@@ -1004,7 +997,7 @@ __global__ void __launch_bounds__(256) k_shadow_pick(PathArgs a) {
 }
 
 __global__ void __launch_bounds__(256) k_shadow_rest(PathArgs a) {
-    __shared__ int stk_lds[kStackDepth][kStackStride];
+    __shared__ int stk_lds[kStackRows][kStackStride];
     LdsStack stk{&stk_lds[0][threadIdx.x]};
     long long n = (long long)*a.legs.n_list;
     GRID_STRIDE(k, n) {

@@ -5,9 +5,9 @@
 // transmitter launches N rays on a Fibonacci sphere; every bounce is one
 // launch of k_bounce, a persistent kernel whose waves pull 64-ray chunks
 // from a device counter.  Per ray and bounce it
-//   1. finds the closest hit in the static and the dynamic LBVH (stackless,
-//      near child first, watertight triangle test, previous face excluded,
-//      ties to the lowest triangle id),
+//   1. finds the closest hit in the static tree (4-wide, quantised boxes) and
+//      the dynamic LBVH (short stack, nearer child first, watertight triangle
+//      test, previous face excluded, ties to the lowest triangle id),
 //   2. records the hit triangle in the per-bounce hit log,
 //   3. captures receivers whose reception sphere (radius k alpha (L + s),
 //      alpha = sqrt(4 pi / N)) the segment crosses, inserting the path key
@@ -125,7 +125,7 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
 template <bool STATS, bool REV>
 __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long long n_in, unsigned long long base,
                                              int lane, unsigned& s_nodes, unsigned& s_tris, unsigned& s_seg,
-                                             unsigned& s_cap, LdsStack* stk) {
+                                             unsigned& s_cap, unsigned& s_box4, LdsStack* stk) {
     const int b = a.b;
     unsigned long long i = base + (unsigned long long)lane;
     bool act = i < n_in;
@@ -150,7 +150,8 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
     int best_tri = 0x7FFFFFFF, best_face = -1;
     if (act) {
         if (STATS) s_seg++;
-        closest_hit<STATS>(a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris, stk);
+        closest_hit4<STATS>(a.st4, a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_box4, s_nodes, s_tris,
+                            stk);
         closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris, stk);
     }
     bool hit = act && best_tri != 0x7FFFFFFF;
@@ -260,13 +261,15 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
 
 template <bool STATS>
 __device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane, unsigned s_nodes, unsigned s_tris,
-                                            unsigned s_seg, unsigned s_cap) {
+                                            unsigned s_seg, unsigned s_cap, unsigned s_box4) {
     if (STATS) {
-        unsigned long long v[4] = {s_nodes, s_tris, s_seg, s_cap};
-        for (int k = 0; k < 4; k++) {
+        // [0] binary node visits, [1] triangle tests, [2] segments, [3] captures, [16] 4-wide child boxes tested
+        unsigned long long v[5] = {s_nodes, s_tris, s_seg, s_cap, s_box4};
+        const int slot[5] = {0, 1, 2, 3, 16};
+        for (int k = 0; k < 5; k++) {
             unsigned long long x = v[k];
             for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
-            if (lane == 0 && x) atomicAdd(&stats[k], x);
+            if (lane == 0 && x) atomicAdd(&stats[slot[k]], x);
         }
     }
 }
@@ -277,11 +280,11 @@ __device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane,
 // stays at the compiler's 85.)
 template <bool STATS, bool REV>
 __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
-    __shared__ int stk_lds[kStackDepth][kStackStride];
+    __shared__ int stk_lds[kStackRows][kStackStride];
     LdsStack stk{&stk_lds[0][threadIdx.x]};
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
-    unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
+    unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0, s_box4 = 0;
     // the first chunk of every wave is its own index (all waves start at
     // once, and a burst of atomics on one counter would serialise them); the
     // later ones come from the counter, after the grid's first chunks
@@ -290,12 +293,12 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     while (true) {
         unsigned long long base = (unsigned long long)chunk * 64ULL;
         if (base >= n_in) break;
-        bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap, &stk);
+        bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap, s_box4, &stk);
         unsigned int next = 0;
         if (lane == 0) next = atomicAdd(a.work, 1u);
         chunk = n_waves + (unsigned int)__shfl((int)next, 0);
     }
-    flush_stats<STATS>(a.stats, lane, s_nodes, s_tris, s_seg, s_cap);
+    flush_stats<STATS>(a.stats, lane, s_nodes, s_tris, s_seg, s_cap, s_box4);
 }
 
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {
@@ -342,11 +345,11 @@ __global__ void __launch_bounds__(256) k_chunk_table(const BounceArgs* __restric
 __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restrict__ args,
                                                       const uint32_t* __restrict__ chunk_off, uint32_t* work,
                                                       int n_scenes) {
-    __shared__ int stk_lds[kStackDepth][kStackStride];
+    __shared__ int stk_lds[kStackRows][kStackStride];
     LdsStack stk{&stk_lds[0][threadIdx.x]};
     const int lane = lane_id();
     const uint32_t total = chunk_off[n_scenes];
-    unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0;
+    unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0, s_box4 = 0;
     // first chunk: the wave's own index; later ones from the counter
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
@@ -367,7 +370,7 @@ __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restri
         const BounceArgs& a = args[c];
         const unsigned long long n_in = *a.n_in;
         bounce_chunk<false, false>(a, n_in, (unsigned long long)(g - chunk_off[c]) * 64ULL, lane, s_nodes, s_tris,
-                                   s_seg, s_cap, &stk);
+                                   s_seg, s_cap, s_box4, &stk);
     }
 }
 
