@@ -66,6 +66,7 @@ struct emrt_ctx {
     bool frame_since_step = false;  // set_frame after the last step (the adjoint needs the step's frame)
     bool batched = false;           // member of an emrt_batch
     double* adj_rows = nullptr;     // [5 + 2 adjoint_materials][n_links]
+    char* leg_block = nullptr;      // shadow legs of a step; per-path partials of emrt_backward
     CompactTemp ctmp{};             // table compaction scratch
     RxBins bins{};                  // receivers binned for the diffraction candidates
     ValidTemp vtmp{};               // validation survivors
@@ -297,12 +298,23 @@ static void layout(emrt_ctx* c, Carver& cv) {
     LegBuf& lg = c->legs;
     lg.cap = 3 * c->vcap;
     lg.cap_first = c->vcap;  // one receiver leg per key slot
-    lg.ox = cv.take<float>(lg.cap); lg.oy = cv.take<float>(lg.cap); lg.oz = cv.take<float>(lg.cap);
-    lg.dx = cv.take<float>(lg.cap); lg.dy = cv.take<float>(lg.cap); lg.dz = cv.take<float>(lg.cap);
-    lg.xa = cv.take<int>(lg.cap);
-    lg.xb = cv.take<int>(lg.cap);
-    lg.xc = cv.take<int>(lg.cap);
-    lg.key = cv.take<uint32_t>(lg.cap);
+    // the shadow legs live only during a step's validation; emrt_backward
+    // reuses their block for its per-path partial derivatives (15 doubles per
+    // path slot: the same 120 bytes as three legs)
+    {
+        const long long n = lg.cap;
+        char* blk = cv.take<char>(40LL * n + 10LL * 256);
+        c->leg_block = blk;
+        if (!cv.measure) {
+            auto carve = [&](long long k) { return (void*)(blk + k * (((4LL * n) + 255) / 256 * 256)); };
+            lg.ox = (float*)carve(0); lg.oy = (float*)carve(1); lg.oz = (float*)carve(2);
+            lg.dx = (float*)carve(3); lg.dy = (float*)carve(4); lg.dz = (float*)carve(5);
+            lg.xa = (int*)carve(6);
+            lg.xb = (int*)carve(7);
+            lg.xc = (int*)carve(8);
+            lg.key = (uint32_t*)carve(9);
+        }
+    }
     lg.list = cv.take<uint32_t>(lg.cap - lg.cap_first);
     c->kstate = cv.take<uint8_t>(c->vcap);
     c->occl = cv.take<uint32_t>(c->vcap);
@@ -1036,6 +1048,9 @@ int32_t emrt_backward(emrt_ctx* c, const double* dL_dH, const double* dL_dP, dou
     a.M = c->S.M;
     a.combined = c->cfg.diffraction == 2 ? 1 : 0;
     a.rows = c->adj_rows;
+    a.n_rx = c->sz.n_rx;
+    a.path_tan = (double*)c->leg_block;
+    a.path_eps = a.path_tan + 5LL * c->vcap;
     adjoint(a, c->sz.n_tx, c->sz.n_rx, grad_tx_pos, grad_tx_orient, grad_eps, c->stream);
     return hip_check(c, hipGetLastError(), "backward");
 }

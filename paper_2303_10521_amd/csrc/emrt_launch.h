@@ -380,6 +380,9 @@ struct AdjArgs {
     int M;                    // materials
     int combined;             // paths with one reflection and one diffraction can occur
     double* rows;             // [5 + 2 M][n_links] per-link partial gradients
+    int n_rx;
+    double* path_tan;         // [vp.cap][5] per path: sum over carriers of Re(conj(g) da/dx), x = tx.xyz, theta, phi
+    double* path_eps;         // [vp.cap][5][2] per path and interaction: g conj(da/deps) of its material
 };
 void adjoint(const AdjArgs& a, int n_tx, int n_rx, double* g_pos, double* g_ori, double* g_eps, hipStream_t st);
 

@@ -2,9 +2,9 @@
 // polarisation tracked bounce by bounce, UTD edge diffraction), written once
 // for a generic real type R:
 //   R = double  the forward evaluation (k_fields),
-//   R = DN      forward-mode dual numbers carrying the derivatives with
-//               respect to the transmitter position (3) and the dipole
-//               orientation (theta, phi) (k_adj_links).
+//   R = DNT<N>  forward-mode dual numbers carrying derivatives with respect
+//               to the transmitter position (3) and the dipole orientation
+//               (theta, phi) (the adjoint, k_adj_paths).
 // The permittivity derivatives use R = double with one interaction's
 // reflection coefficients replaced by their derivatives (dmode).
 //
@@ -26,124 +26,127 @@
 namespace emrt {
 
 // ------------------------------------------------------- dual numbers ----
-constexpr int kTan = 5;  // d/d tx.x, tx.y, tx.z, theta, phi
-struct DN {
+// DNT<N>: a value and its derivatives along N of the five tangent directions
+// (d/d tx.x, tx.y, tx.z, theta, phi); DN carries all five, DN1 one of them.
+constexpr int kTan = 5;
+template <int N> struct DNT {
     double v;
-    double d[kTan];
-};
-__device__ __forceinline__ DN dn(double v) {
-    DN r;
-    r.v = v;
+    double d[N];
+    static __device__ __forceinline__ DNT constant(double x) {
+        DNT r;
+        r.v = x;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) r.d[k] = 0.0;
+        for (int k = 0; k < N; k++) r.d[k] = 0.0;
+        return r;
+    }
+};
+using DN = DNT<kTan>;
+using DN1 = DNT<1>;
+__device__ __forceinline__ DN dn(double v) { return DN::constant(v); }
+// the value v of tangent direction k (0..4), carried by a number whose
+// derivative slots hold directions first .. first + N - 1
+template <int N> __device__ __forceinline__ DNT<N> dn_seed(double v, int k, int first = 0) {
+    DNT<N> r = DNT<N>::constant(v);
+#pragma unroll
+    for (int j = 0; j < N; j++) r.d[j] = (first + j == k) ? 1.0 : 0.0;
     return r;
 }
-__device__ __forceinline__ DN dn_seed(double v, int k) {
-    DN r = dn(v);
-    r.d[k] = 1.0;
-    return r;
-}
-__device__ __forceinline__ DN operator+(DN a, DN b) {
+__device__ __forceinline__ DN dn_seed(double v, int k) { return dn_seed<kTan>(v, k, 0); }
+template <int N> __device__ __forceinline__ DNT<N> operator+(DNT<N> a, DNT<N> b) {
     a.v += b.v;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) a.d[k] += b.d[k];
+    for (int k = 0; k < N; k++) a.d[k] += b.d[k];
     return a;
 }
-__device__ __forceinline__ DN operator-(DN a, DN b) {
+template <int N> __device__ __forceinline__ DNT<N> operator-(DNT<N> a, DNT<N> b) {
     a.v -= b.v;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) a.d[k] -= b.d[k];
+    for (int k = 0; k < N; k++) a.d[k] -= b.d[k];
     return a;
 }
-__device__ __forceinline__ DN operator-(DN a) {
+template <int N> __device__ __forceinline__ DNT<N> operator-(DNT<N> a) {
     a.v = -a.v;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) a.d[k] = -a.d[k];
+    for (int k = 0; k < N; k++) a.d[k] = -a.d[k];
     return a;
 }
-__device__ __forceinline__ DN operator*(DN a, DN b) {
-    DN r;
+template <int N> __device__ __forceinline__ DNT<N> operator*(DNT<N> a, DNT<N> b) {
+    DNT<N> r;
     r.v = a.v * b.v;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    for (int k = 0; k < N; k++) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
     return r;
 }
-__device__ __forceinline__ DN operator/(DN a, DN b) {
-    DN r;
+template <int N> __device__ __forceinline__ DNT<N> operator/(DNT<N> a, DNT<N> b) {
+    DNT<N> r;
     double inv = 1.0 / b.v;
     r.v = a.v * inv;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) r.d[k] = (a.d[k] - r.v * b.d[k]) * inv;
+    for (int k = 0; k < N; k++) r.d[k] = (a.d[k] - r.v * b.d[k]) * inv;
     return r;
 }
-__device__ __forceinline__ DN operator+(DN a, double b) { a.v += b; return a; }
-__device__ __forceinline__ DN operator+(double b, DN a) { a.v += b; return a; }
-__device__ __forceinline__ DN operator-(DN a, double b) { a.v -= b; return a; }
-__device__ __forceinline__ DN operator-(double b, DN a) { return dn(b) - a; }
-__device__ __forceinline__ DN operator*(DN a, double s) {
+template <int N> __device__ __forceinline__ DNT<N> operator+(DNT<N> a, double b) { a.v += b; return a; }
+template <int N> __device__ __forceinline__ DNT<N> operator+(double b, DNT<N> a) { a.v += b; return a; }
+template <int N> __device__ __forceinline__ DNT<N> operator-(DNT<N> a, double b) { a.v -= b; return a; }
+template <int N> __device__ __forceinline__ DNT<N> operator-(double b, DNT<N> a) { return DNT<N>::constant(b) - a; }
+template <int N> __device__ __forceinline__ DNT<N> operator*(DNT<N> a, double s) {
     a.v *= s;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) a.d[k] *= s;
+    for (int k = 0; k < N; k++) a.d[k] *= s;
     return a;
 }
-__device__ __forceinline__ DN operator*(double s, DN a) { return a * s; }
-__device__ __forceinline__ DN operator/(DN a, double s) { return a * (1.0 / s); }
-__device__ __forceinline__ DN operator/(double s, DN b) { return dn(s) / b; }
+template <int N> __device__ __forceinline__ DNT<N> operator*(double s, DNT<N> a) { return a * s; }
+template <int N> __device__ __forceinline__ DNT<N> operator/(DNT<N> a, double s) { return a * (1.0 / s); }
+template <int N> __device__ __forceinline__ DNT<N> operator/(double s, DNT<N> b) { return DNT<N>::constant(s) / b; }
 
 // scalar functions for both real types
 __device__ __forceinline__ double vv(double x) { return x; }
-__device__ __forceinline__ double vv(const DN& x) { return x.v; }
+template <int N> __device__ __forceinline__ double vv(const DNT<N>& x) { return x.v; }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-__device__ __forceinline__ DN sqrt_(DN a) {
+template <int N> __device__ __forceinline__ DNT<N> sqrt_(DNT<N> a) {
     double s = sqrt(a.v);
-    DN r = a * (0.5 / s);
+    DNT<N> r = a * (0.5 / s);
     r.v = s;
     return r;
 }
 __device__ __forceinline__ double sin_(double x) { return sin(x); }
 __device__ __forceinline__ double cos_(double x) { return cos(x); }
-__device__ __forceinline__ DN sin_(DN a) {
+template <int N> __device__ __forceinline__ DNT<N> sin_(DNT<N> a) {
     double s, c;
     sincos(a.v, &s, &c);
-    DN r = a * c;
+    DNT<N> r = a * c;
     r.v = s;
     return r;
 }
-__device__ __forceinline__ DN cos_(DN a) {
+template <int N> __device__ __forceinline__ DNT<N> cos_(DNT<N> a) {
     double s, c;
     sincos(a.v, &s, &c);
-    DN r = a * (-s);
+    DNT<N> r = a * (-s);
     r.v = c;
     return r;
 }
 __device__ __forceinline__ double acos_(double x) { return acos(x); }
-__device__ __forceinline__ DN acos_(DN a) {
-    DN r = a * (-1.0 / sqrt(1.0 - a.v * a.v));
+template <int N> __device__ __forceinline__ DNT<N> acos_(DNT<N> a) {
+    DNT<N> r = a * (-1.0 / sqrt(1.0 - a.v * a.v));
     r.v = acos(a.v);
     return r;
 }
 __device__ __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ DN atan2_(DN y, DN x) {
+template <int N> __device__ __forceinline__ DNT<N> atan2_(DNT<N> y, DNT<N> x) {
     double inv = 1.0 / (x.v * x.v + y.v * y.v);
-    DN r = (y * x.v - x * y.v) * inv;
+    DNT<N> r = (y * x.v - x * y.v) * inv;
     r.v = atan2(y.v, x.v);
     return r;
 }
 __device__ __forceinline__ double abs_(double x) { return fabs(x); }
-__device__ __forceinline__ DN abs_(DN a) { return a.v < 0 ? -a : a; }
-template <class R> __device__ __forceinline__ R clamp1(R x) {
-    if (vv(x) > 1.0) return R(1.0);
-    if (vv(x) < -1.0) return R(-1.0);
-    return x;
-}
-template <> __device__ __forceinline__ DN clamp1<DN>(DN x) {
-    if (x.v > 1.0) return dn(1.0);
-    if (x.v < -1.0) return dn(-1.0);
-    return x;
-}
-template <class R> __device__ __forceinline__ R rl(double x);
+template <int N> __device__ __forceinline__ DNT<N> abs_(DNT<N> a) { return a.v < 0 ? -a : a; }
+template <class R> __device__ __forceinline__ R rl(double x) { return R::constant(x); }
 template <> __device__ __forceinline__ double rl<double>(double x) { return x; }
-template <> __device__ __forceinline__ DN rl<DN>(double x) { return dn(x); }
+template <class R> __device__ __forceinline__ R clamp1(R x) {
+    if (vv(x) > 1.0) return rl<R>(1.0);
+    if (vv(x) < -1.0) return rl<R>(-1.0);
+    return x;
+}
 
 // ------------------------------------------------------------ vectors ----
 template <class R> struct V3 { R x, y, z; };
@@ -200,24 +203,24 @@ template <> __device__ __forceinline__ Cx<double> cdivx<double>(Cx<double> a, Cx
     cd r = cdiv(C(a.re, a.im), C(b.re, b.im));
     return {r.re, r.im};
 }
-template <class R> __device__ __forceinline__ Cx<R> csqrtx(Cx<R> z);
-template <> __device__ __forceinline__ Cx<double> csqrtx<double>(Cx<double> z) {
-    cd r = csqrtd(C(z.re, z.im));
-    return {r.re, r.im};
-}
-template <> __device__ __forceinline__ Cx<DN> csqrtx<DN>(Cx<DN> z) {
+template <int N> __device__ __forceinline__ Cx<DNT<N>> csqrt_dual(Cx<DNT<N>> z) {
     // w = sqrt(z): dw = dz / (2 w)
     cd w = csqrtd(C(z.re.v, z.im.v));
     cd h = cdiv(C(0.5), w);
-    Cx<DN> r;
+    Cx<DNT<N>> r;
     r.re.v = w.re;
     r.im.v = w.im;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) {
+    for (int k = 0; k < N; k++) {
         r.re.d[k] = z.re.d[k] * h.re - z.im.d[k] * h.im;
         r.im.d[k] = z.re.d[k] * h.im + z.im.d[k] * h.re;
     }
     return r;
+}
+template <class R> __device__ __forceinline__ Cx<R> csqrtx(Cx<R> z) { return csqrt_dual(z); }
+template <> __device__ __forceinline__ Cx<double> csqrtx<double>(Cx<double> z) {
+    cd r = csqrtd(C(z.re, z.im));
+    return {r.re, r.im};
 }
 template <class R> __device__ __forceinline__ Cx<R> cdotx(V3<R> a, const Cx<R>* E) {
     return {a.x * E[0].re + a.y * E[1].re + a.z * E[2].re, a.x * E[0].im + a.y * E[1].im + a.z * E[2].im};
@@ -316,23 +319,23 @@ __device__ inline cd utd_F(double X) {
     const double h = 0.70710678118654752440;
     return C(h, h) * erfcx_diag(sqrt(X)) * sqrt(kPi * X);
 }
-template <class R> __device__ __forceinline__ Cx<R> utd_Fx(R X);
-template <> __device__ __forceinline__ Cx<double> utd_Fx<double>(double X) {
-    cd f = utd_F(X);
-    return {f.re, f.im};
-}
-template <> __device__ __forceinline__ Cx<DN> utd_Fx<DN>(DN X) {
+template <int N> __device__ __forceinline__ Cx<DNT<N>> utd_F_dual(DNT<N> X) {
     cd f = utd_F(X.v);
     cd df = X.v > 0 ? f * C(0.5 / X.v, 1.0) - C(0.0, 1.0) : C(0.0);
-    Cx<DN> r;
+    Cx<DNT<N>> r;
     r.re.v = f.re;
     r.im.v = f.im;
 #pragma unroll
-    for (int k = 0; k < kTan; k++) {
+    for (int k = 0; k < N; k++) {
         r.re.d[k] = df.re * X.d[k];
         r.im.d[k] = df.im * X.d[k];
     }
     return r;
+}
+template <class R> __device__ __forceinline__ Cx<R> utd_Fx(R X) { return utd_F_dual(X); }
+template <> __device__ __forceinline__ Cx<double> utd_Fx<double>(double X) {
+    cd f = utd_F(X);
+    return {f.re, f.im};
 }
 
 // cot((pi + sg beta)/(2n)) F(kL a^{sg}(beta)), a = 2 cos^2((2 pi n N - beta)/2),
@@ -408,26 +411,26 @@ __device__ __forceinline__ V3<R> antenna_x(int mode, V3<R> k, R th, R ph) {
 }
 
 // exp(-j 2 pi frac(L / lambda)) (frac taken on the value; derivative -j k dL)
-template <class R> __device__ __forceinline__ Cx<R> phase_x(R L, double lam);
-template <> __device__ __forceinline__ Cx<double> phase_x<double>(double L, double lam) {
-    double x = L / lam;
-    cd p = cexpi(-2.0 * kPi * (x - rint(x)));
-    return {p.re, p.im};
-}
-template <> __device__ __forceinline__ Cx<DN> phase_x<DN>(DN L, double lam) {
+template <int N> __device__ __forceinline__ Cx<DNT<N>> phase_dual(DNT<N> L, double lam) {
     double x = L.v / lam;
     cd p = cexpi(-2.0 * kPi * (x - rint(x)));
     double kk = 2.0 * kPi / lam;
-    Cx<DN> r;
+    Cx<DNT<N>> r;
     r.re.v = p.re;
     r.im.v = p.im;
     // d p = -j k p dL
 #pragma unroll
-    for (int k = 0; k < kTan; k++) {
+    for (int k = 0; k < N; k++) {
         r.re.d[k] = kk * p.im * L.d[k];
         r.im.d[k] = -kk * p.re * L.d[k];
     }
     return r;
+}
+template <class R> __device__ __forceinline__ Cx<R> phase_x(R L, double lam) { return phase_dual(L, lam); }
+template <> __device__ __forceinline__ Cx<double> phase_x<double>(double L, double lam) {
+    double x = L / lam;
+    cd p = cexpi(-2.0 * kPi * (x - rint(x)));
+    return {p.re, p.im};
 }
 
 // ------------------------------------------------------ wedge geometry ----
