@@ -15,7 +15,8 @@ precision) and does the bookkeeping that the paper describes in words:
 * gradients of a loss of those channels with respect to the permittivities,
   the transmitter positions and the dipole orientation, by central
   differences with the path topology held fixed (a reading: the paper has no
-  gradients; ``grad_fd``).
+  gradients; ``grad_fd``); ``dual.py`` gives the same gradients by
+  forward-mode dual numbers.
 
 It shares no code with the GPU library (``paper_2303_10521_amd``) and never
 imports it.  The only common dependency is the seeded input generator

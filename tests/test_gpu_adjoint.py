@@ -1,9 +1,10 @@
-"""Adjoint (emrt_backward) vs the oracle's central-difference gradients.
+"""Adjoint (emrt_backward) vs the oracle's two gradients.
 
 The loss is L = sum_{f, link} Re(conj(G_H) H) + G_P P_coh with seeded random
 cotangents.  The oracle differentiates its own channel sums over its own
-valid keys (topology fixed) by central differences; the GPU differentiates
-the paths of its last step with forward-mode dual numbers.  Links whose path
+valid keys (topology fixed) twice: by central differences (``grad_fd``) and
+by forward-mode dual numbers in plain Python (``dual.grad_dual``); the GPU
+differentiates the paths of its last step with its own dual numbers.  Links whose path
 sets differ between the two (keys the oracle marks ambiguous) get zero
 cotangents, so both sides differentiate the same function.
 """
@@ -12,6 +13,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import dual as D  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from synth import city  # noqa: E402
 from synth.city import Frame  # noqa: E402
@@ -44,6 +46,20 @@ def _link_mask(gpu_keys, ref_keys, n_rx, nl):
     return ok
 
 
+def _oracle_grads(os_, geo, fr, keys, freqs, GH, GP, n_rx, ant_mode=0):
+    """The oracle's gradients by both methods."""
+    args = (os_, geo, fr, keys, list(freqs), GH, GP, n_rx)
+    return {"central differences": O.grad_fd(*args, ant_mode=ant_mode),
+            "dual numbers": D.grad_dual(*args, ant_mode=ant_mode)}
+
+
+def _check(got, wants, names, tag=""):
+    for method, want in wants.items():
+        for name in names:
+            ok, err = _close(got[name], want[name])
+            assert ok, (tag, method, name, err, got[name], want[name])
+
+
 def _close(got, want, rtol=RTOL):
     """Each row (a transmitter's components; the permittivities as one row)
     within rtol of that row's largest magnitude."""
@@ -73,19 +89,17 @@ def _run(sc, fr, n_tx, n_rx, K, N, freqs, diffraction, ant_mode, seed, p_scale=1
     GP[:, ~mask] = 0
     g = tr.backward(torch.as_tensor(GH), torch.as_tensor(GP))
     geo = os_.geometry(fr.obj_xform)
-    want = O.grad_fd(os_, geo, fr, ref.keys, list(freqs), GH, GP, n_rx, ant_mode=ant_mode)
+    wants = _oracle_grads(os_, geo, fr, ref.keys, freqs, GH, GP, n_rx, ant_mode)
     got = {k: v.cpu().numpy() for k, v in g.items()}
-    return tr, got, want, (GH, GP)
+    return tr, got, wants, (GH, GP)
 
 
 def test_adjoint_toy_iso():
     w = city.workload("toy")
     sc = w.scene
     fr = sc.frame(0.0)
-    tr, got, want, _ = _run(sc, fr, sc.n_tx, sc.n_rx, w.max_reflections, w.rays_per_tx, w.freqs_hz, False, 0, 1)
-    for name in ("grad_tx_pos", "grad_eps"):
-        ok, err = _close(got[name], want[name])
-        assert ok, (name, err, got[name], want[name])
+    tr, got, wants, _ = _run(sc, fr, sc.n_tx, sc.n_rx, w.max_reflections, w.rays_per_tx, w.freqs_hz, False, 0, 1)
+    _check(got, wants, ("grad_tx_pos", "grad_eps"))
     assert np.all(got["grad_tx_orient"] == 0)
     tr.close()
 
@@ -96,10 +110,8 @@ def test_adjoint_toy_dipole_two_carriers():
     fr = sc.frame(0.0)
     fr.tx_orient = np.array([[0.6, 0.4]])
     freqs = (3.5e9, 28e9)
-    tr, got, want, _ = _run(sc, fr, sc.n_tx, sc.n_rx, w.max_reflections, w.rays_per_tx, freqs, False, 1, 2)
-    for name in ("grad_tx_pos", "grad_tx_orient", "grad_eps"):
-        ok, err = _close(got[name], want[name])
-        assert ok, (name, err, got[name], want[name])
+    tr, got, wants, _ = _run(sc, fr, sc.n_tx, sc.n_rx, w.max_reflections, w.rays_per_tx, freqs, False, 1, 2)
+    _check(got, wants, ("grad_tx_pos", "grad_tx_orient", "grad_eps"))
     tr.close()
 
 
@@ -117,10 +129,8 @@ def test_adjoint_eight_materials_with_diffraction():
     fr0 = sc.frame(0.0)
     rx_idx = np.arange(0, len(fr0.rx_pos), 25)[:40]
     fr = _subset_frame(fr0, np.array([0, 3]), rx_idx)
-    tr, got, want, _ = _run(sc, fr, 2, len(rx_idx), w.max_reflections, 20000, w.freqs_hz, True, 0, 3)
-    for name in ("grad_tx_pos", "grad_eps"):
-        ok, err = _close(got[name], want[name])
-        assert ok, (name, err, got[name], want[name])
+    tr, got, wants, _ = _run(sc, fr, 2, len(rx_idx), w.max_reflections, 20000, w.freqs_hz, True, 0, 3)
+    _check(got, wants, ("grad_tx_pos", "grad_eps"))
     tr.close()
 
 
@@ -211,7 +221,7 @@ def test_adjoint_launch_size_three_frames():
     first-order diffraction), every 4th receiver (250), over a discovery
     frame and two cached frames with moving vehicles.  The oracle
     differentiates the GPU's own valid keys of each frame by central
-    differences (validated in the oracle; links holding an ambiguous key get
+    differences and by dual numbers (validated in the oracle; links holding an ambiguous key get
     zero cotangents, so both sides differentiate the same function)."""
     from paper_2303_10521_amd import Tracer
 
@@ -246,9 +256,7 @@ def test_adjoint_launch_size_three_frames():
         GH[:, ~mask] = 0
         GP[:, ~mask] = 0
         g = tr.backward(torch.as_tensor(GH), torch.as_tensor(GP))
-        want = O.grad_fd(os_, geo, fr, gk[valid & ~amb], list(w.freqs_hz), GH, GP, n_rx)
+        wants = _oracle_grads(os_, geo, fr, gk[valid & ~amb], w.freqs_hz, GH, GP, n_rx)
         got = {k: v.cpu().numpy() for k, v in g.items()}
-        for name in ("grad_tx_pos", "grad_eps"):
-            ok, err = _close(got[name], want[name])
-            assert ok, (f, name, err)
+        _check(got, wants, ("grad_tx_pos", "grad_eps"), tag=f"frame {f}")
     tr.close()

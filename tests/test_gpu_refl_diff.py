@@ -8,7 +8,7 @@ against the oracle, through the C ABI.
 * The toy city, transmitter side, with the first-order diffraction and the
   specular paths alongside.
 * The adjoint over such paths: gradients against the oracle's central
-  differences (the reflection face's permittivity enters them too).
+  differences and dual numbers (the reflection face's permittivity enters them too).
 """
 import numpy as np
 import pytest
@@ -90,7 +90,7 @@ def test_toy_city_with_combined_paths():
 
 
 def test_adjoint_over_combined_paths():
-    from tests.test_gpu_adjoint import _close, _cotangents, _link_mask
+    from tests.test_gpu_adjoint import _check, _cotangents, _link_mask, _oracle_grads
 
     sc, tx, rx = _box_scene()
     sc = city.with_static_rx(city.tiny_box_ground(refl=(0.0, 0.0)), rx)
@@ -111,9 +111,7 @@ def test_adjoint_over_combined_paths():
     GH[:, ~mask] = 0
     GP[:, ~mask] = 0
     g = tr.backward(torch.as_tensor(GH), torch.as_tensor(GP))
-    want = O.grad_fd(os_, os_.geometry(fr.obj_xform), fr, ref.keys, [28e9], GH, GP, len(rx))
+    wants = _oracle_grads(os_, os_.geometry(fr.obj_xform), fr, ref.keys, [28e9], GH, GP, len(rx))
     got = {k: v.cpu().numpy() for k, v in g.items()}
-    for name in ("grad_tx_pos", "grad_eps"):
-        ok, err = _close(got[name], want[name])
-        assert ok, (name, err, got[name], want[name])
+    _check(got, wants, ("grad_tx_pos", "grad_eps"))
     tr.close()

@@ -1,4 +1,5 @@
-"""Pins of the oracle's gradients (central differences over the FP64 oracle
+"""Pins of the oracle's two gradients (central differences over the FP64
+oracle, ``grad_fd``, and forward-mode dual numbers, ``dual.grad_dual``; both
 with the path topology held fixed) against closed forms.
 
 The gradients are those of a real loss of the per-link channels,
@@ -19,6 +20,7 @@ where the derivative has a closed form that does not go through the oracle:
 import numpy as np
 import pytest
 
+from oracle import dual as D
 from oracle import oracle as O
 from synth import city
 from tests.oracle_util import C0, spec_key, static_frame
@@ -32,6 +34,10 @@ def _build():
     O.build()
 
 
+# both gradient methods take the same arguments and return the same dict
+METHODS = pytest.mark.parametrize("grad", [O.grad_fd, D.grad_dual], ids=["central_differences", "dual_numbers"])
+
+
 def _rng_G(nf, nl, seed=0):
     r = np.random.default_rng(seed)
     return r.normal(size=(nf, nl)) + 1j * r.normal(size=(nf, nl)), r.normal(size=(nf, nl))
@@ -42,7 +48,8 @@ def _los_amp(tx, rx, lam):
     return lam / (4 * np.pi * d) * np.exp(-2j * np.pi * d / lam), d
 
 
-def test_los_position_gradient_closed_form():
+@METHODS
+def test_los_position_gradient_closed_form(grad):
     sc = city.tiny_ground()
     os_ = O.OracleScene(sc)
     g = os_.geometry(np.zeros((0, 3, 4)))
@@ -53,7 +60,7 @@ def test_los_position_gradient_closed_form():
     GH, GP = _rng_G(2, 1, 1)
     GP = GP * 1e6  # comparable weight of the power term (|a|^2 P_tx ~ 1e-6)
     keys = np.array([spec_key(0, 0, [])])
-    got = O.grad_fd(os_, g, fr, keys, freqs, GH, GP, 1)["grad_tx_pos"][0]
+    got = grad(os_, g, fr, keys, freqs, GH, GP, 1)["grad_tx_pos"][0]
     want = np.zeros(3)
     for fi, f in enumerate(freqs):
         lam = C0 / f
@@ -64,7 +71,8 @@ def test_los_position_gradient_closed_form():
     assert np.allclose(got, want, rtol=1e-6, atol=1e-9 * np.abs(want).max())
 
 
-def test_normal_incidence_permittivity_gradient_closed_form():
+@METHODS
+def test_normal_incidence_permittivity_gradient_closed_form(grad):
     eps = 15.0 - 1.5j
     sc = city.tiny_ground(eps=eps)
     os_ = O.OracleScene(sc)
@@ -72,7 +80,7 @@ def test_normal_incidence_permittivity_gradient_closed_form():
     fr = static_frame([[0.0, 0.0, 10.0]], [[0.0, 0.0, 5.0]])
     GH, _ = _rng_G(1, 1, 2)
     keys = np.array([spec_key(0, 0, [0])])
-    got = O.grad_fd(os_, g, fr, keys, [F28], GH, None, 1)["grad_eps"][0]
+    got = grad(os_, g, fr, keys, [F28], GH, None, 1)["grad_eps"][0]
     lam = C0 / F28
     L = 15.0
     C = lam / (4 * np.pi * L) * np.exp(-2j * np.pi * (L / lam - np.round(L / lam)))
@@ -82,7 +90,8 @@ def test_normal_incidence_permittivity_gradient_closed_form():
     assert abs(got - want) <= 1e-6 * abs(want)
 
 
-def test_dipole_orientation_gradient_closed_form():
+@METHODS
+def test_dipole_orientation_gradient_closed_form(grad):
     sc = city.tiny_ground()
     os_ = O.OracleScene(sc)
     g = os_.geometry(np.zeros((0, 3, 4)))
@@ -92,7 +101,7 @@ def test_dipole_orientation_gradient_closed_form():
     fr = static_frame([tx], [rx], tx_orient=[[th, ph]])
     GH, _ = _rng_G(1, 1, 3)
     keys = np.array([spec_key(0, 0, [])])
-    got = O.grad_fd(os_, g, fr, keys, [F28], GH, None, 1, ant_mode=1)["grad_tx_orient"][0]
+    got = grad(os_, g, fr, keys, [F28], GH, None, 1, ant_mode=1)["grad_tx_orient"][0]
     lam = C0 / F28
     k = (rx - tx) / np.linalg.norm(rx - tx)
     a0, _ = _los_amp(tx, rx, lam)
@@ -163,7 +172,8 @@ def test_keller_diffracted_length_gradient():
         assert np.allclose(grad, -k0, atol=1e-7)
 
 
-def test_gradient_loss_terms_add():
+@METHODS
+def test_gradient_loss_terms_add(grad):
     """The loss is linear in (G_H, G_P): gradients of the two terms add."""
     sc = city.tiny_ground_wall()
     os_ = O.OracleScene(sc)
@@ -171,8 +181,8 @@ def test_gradient_loss_terms_add():
     fr = static_frame([[0.0, 0.0, 10.0]], [[30.0, 20.0, 6.0]])
     keys = np.array([spec_key(0, 0, f) for f in ([], [0], [1], [0, 1])])
     GH, GP = _rng_G(1, 1, 4)
-    a = O.grad_fd(os_, g, fr, keys, [F28], GH, None, 1)
-    b = O.grad_fd(os_, g, fr, keys, [F28], 0 * GH, GP, 1)
-    c = O.grad_fd(os_, g, fr, keys, [F28], GH, GP, 1)
+    a = grad(os_, g, fr, keys, [F28], GH, None, 1)
+    b = grad(os_, g, fr, keys, [F28], 0 * GH, GP, 1)
+    c = grad(os_, g, fr, keys, [F28], GH, GP, 1)
     for name in ("grad_tx_pos", "grad_eps"):
         assert np.allclose(a[name] + b[name], c[name], rtol=1e-6, atol=1e-12)
