@@ -130,7 +130,7 @@ def bench_batched(torch, reps: int = 3) -> dict:
     plain_step()
     plain_ms = _ev_ms(torch, plain_step, reps)
     b = Batch(trs)
-    grid, streams = b.autotune()
+    tune = b.autotune(repeats=3, cache=os.environ.get("EMRT_TUNE_CACHE"))
     b.step(True)
     batched_ms = _ev_ms(torch, lambda: b.step(True), reps, b.stream)
     rc = b.sync()
@@ -145,8 +145,10 @@ def bench_batched(torch, reps: int = 3) -> dict:
         "plain_mrays_s": round(rays / (plain_ms * 1e-3) / 1e6, 3),
         "batched_mrays_s": round(rays / (batched_ms * 1e-3) / 1e6, 3),
         "speedup": round(plain_ms / batched_ms, 3),
-        "grid": grid,
-        "streams": streams,
+        "grid": tune["grid"],
+        "streams": tune["streams"],
+        "chunk": tune["chunk"],
+        "tuned": "cache" if tune["from_cache"] else f"timed ({tune['repeats']} repeats per combination, median)",
         "status": rc,
     }
 

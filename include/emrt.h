@@ -304,15 +304,21 @@ int32_t emrt_batch_bind_workspace(emrt_batch* batch, void* device_ptr, size_t by
 /* hipStream_t of the batch (and of every member from now on). */
 int32_t emrt_batch_set_stream(emrt_batch* batch, void* stream);
 /* use_graph 0/1 (default 1), n_streams 1..16 (default 4), grid = workgroups
- * of the persistent multi-scene bounce launch (default 2048). */
-int32_t emrt_batch_set_options(emrt_batch* batch, int32_t use_graph, int32_t n_streams, int32_t grid);
+ * of the persistent multi-scene bounce launch (default 2048), chunk = rays a
+ * wave takes per fetch from the launch's work counter: 32, 64 (default), 128
+ * or 256 (EMRT_E_INVALID otherwise). */
+int32_t emrt_batch_set_options(emrt_batch* batch, int32_t use_graph, int32_t n_streams, int32_t grid, int32_t chunk);
 /* Step every member (discover as in emrt_step).  Errors: EMRT_E_STATE (a
  * member without frame, or members at different cache parities),
  * EMRT_E_WORKSPACE, EMRT_E_HIP (graph capture or launch). */
 int32_t emrt_batch_step(emrt_batch* batch, int32_t discover);
-/* Choose grid and n_streams by timing real discovery steps of the members'
- * current frames (about nine steps; synchronises). */
-int32_t emrt_batch_autotune(emrt_batch* batch, int32_t* best_grid, int32_t* best_streams);
+/* Choose grid, n_streams and chunk by timing real discovery steps of the
+ * members' current frames: every combination of grid 1024..8192 (powers of
+ * two), n_streams 1, 2, 4, 8 and chunk 32, 64, 128, timed `repeats` times
+ * (1..15) each after one warm-up step, the median compared (48 x repeats + 1
+ * steps; synchronises).  Any output pointer may be null. */
+int32_t emrt_batch_autotune(emrt_batch* batch, int32_t repeats, int32_t* best_grid, int32_t* best_streams,
+                            int32_t* best_chunk);
 /* emrt_sync of every member; returns the most severe status. */
 int32_t emrt_batch_sync(emrt_batch* batch);
 int32_t emrt_batch_last_error(emrt_batch* batch, char* buf, size_t len);
@@ -322,6 +328,24 @@ int32_t emrt_batch_last_error(emrt_batch* batch, char* buf, size_t len);
  * -2 not traced (the ray ended earlier).  EMRT_E_STATE when the last
  * discovery step was a receiver-side one (emrt_step_rx). */
 int32_t emrt_debug_ray_records(emrt_ctx* ctx, int32_t tx, const int32_t* ray_ids, int32_t n, int32_t* out);
+
+/* Per-ray capture decisions (Section II-A: reception spheres of radius
+ * k alpha (L + s) on the receivers; edge capture for diffraction), for
+ * comparing them ray by ray.  emrt_debug_select_rays marks launch directions
+ * ray_ids (device [n], each in [0, rays_per_tx)) of transmitter tx; n = 0
+ * clears every mark.  The marks persist, and every later transmitter-side
+ * discovery step logs each receiver and edge capture of a marked ray, up to
+ * EMRT_CAPTURE_LOG_ROWS rows per step (EMRT_E_INVALID for a direction out of
+ * range, EMRT_E_STATE before emrt_set_scene; batched steps log nothing).
+ * emrt_debug_ray_captures copies the last discovery step's log into out
+ * (device [cap][5] int32: tx, launch direction, bounce, kind (0 receiver,
+ * 1 edge), receiver or edge id; in no particular order), sets *n_rows
+ * (host) to the rows written and synchronises.  Returns
+ * EMRT_W_PATHS_TRUNCATED when rows were dropped (the step logged more than
+ * EMRT_CAPTURE_LOG_ROWS, or more than cap). */
+#define EMRT_CAPTURE_LOG_ROWS (1 << 16)
+int32_t emrt_debug_select_rays(emrt_ctx* ctx, int32_t tx, const int32_t* ray_ids, int32_t n);
+int32_t emrt_debug_ray_captures(emrt_ctx* ctx, int32_t* out, int64_t cap, int64_t* n_rows);
 
 /* Path cache (checkpoint / resume): the valid non-line-of-sight keys after
  * the last step, rows of 9 int32 as in emrt_path_view.key.  size and export

@@ -17,6 +17,7 @@ EMRT_E_HIP = -4
 EMRT_E_UNSUPPORTED = -5
 EMRT_E_DEVICE_FLAG = -6
 STATIC_WORKSPACE_BYTES = 64 << 20  # EMRT_STATIC_WORKSPACE_BYTES
+CAPTURE_LOG_ROWS = 1 << 16  # EMRT_CAPTURE_LOG_ROWS
 
 c_i32, c_i64, c_u32, c_f64, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
 
@@ -98,12 +99,15 @@ SIGNATURES = {
     "emrt_batch_workspace_size": (c_i32, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "emrt_batch_bind_workspace": (c_i32, [c_vp, c_vp, ctypes.c_size_t]),
     "emrt_batch_set_stream": (c_i32, [c_vp, c_vp]),
-    "emrt_batch_set_options": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
+    "emrt_batch_set_options": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32]),
     "emrt_batch_step": (c_i32, [c_vp, c_i32]),
-    "emrt_batch_autotune": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "emrt_batch_autotune": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                                    ctypes.POINTER(c_i32)]),
     "emrt_batch_sync": (c_i32, [c_vp]),
     "emrt_batch_last_error": (c_i32, [c_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "emrt_debug_ray_records": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_vp]),
+    "emrt_debug_select_rays": (c_i32, [c_vp, c_i32, c_vp, c_i32]),
+    "emrt_debug_ray_captures": (c_i32, [c_vp, c_vp, c_i64, c_vp]),
     "emrt_cache_size": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "emrt_cache_export": (c_i32, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
     "emrt_cache_import": (c_i32, [c_vp, c_vp, c_i64]),

@@ -22,7 +22,8 @@
 //     its material (a diffraction has two: its wedge faces; a path with one
 //     reflection and one diffraction has three).
 // Each item writes its path's partial sums (over carriers); then one thread
-// per link adds its paths' partials in key order into rows [5 + 2 M][n_links],
+// per (row, link) adds the link's partials in key order into rows
+// [5 + 2 M][n_links],
 // and one block per output scalar sums the rows in a fixed order, so the
 // result is bit-for-bit repeatable.
 #include "emrt_dev.h"
@@ -145,36 +146,37 @@ __global__ void __launch_bounds__(128) k_adj_eps(AdjArgs a) {
     }
 }
 
-// One thread per link: its paths' partials, in key order, into the rows.
+// One thread per (row, link): the link's paths' partials of that row, in key
+// order (rows 0..4: the real tangents; 5 + 2 m, 6 + 2 m: Re and Im of the
+// permittivity of material m).  Consecutive threads take consecutive links
+// of one row, so the row writes are coalesced.
 __global__ void __launch_bounds__(256) k_adj_links(AdjArgs a) {
     const SceneDev& S = a.s;
     const long long nl = a.n_links;
-    for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < nl;
-         l += (long long)gridDim.x * blockDim.x) {
-        for (int r = 0; r < 2 * a.M; r++) a.rows[(5 + r) * nl + l] = 0.0;
-        double acc[kTan];
-#pragma unroll
-        for (int k = 0; k < kTan; k++) acc[k] = 0.0;
+    const long long n = (long long)(kTan + 2 * a.M) * nl;
+    for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < n;
+         it += (long long)gridDim.x * blockDim.x) {
+        const int row = (int)(it / nl);
+        const long long l = it - (long long)row * nl;
+        double acc = 0.0;
         const int p0 = a.start[l], p1 = a.end[l];
         if (p0 >= 0) {
             for (int p = p0; p < p1; p++) {
                 const uint32_t q = a.order[p];
+                if (row < kTan) {
+                    acc += a.path_tan[kTan * (long long)q + row];
+                    continue;
+                }
+                const int m = (row - kTan) >> 1, part = (row - kTan) & 1;
                 const KeyRec key = a.vp.key[q];
                 const int type = key.to & 0xff, order = key.to >> 8;
-#pragma unroll
-                for (int k = 0; k < kTan; k++) acc[k] += a.path_tan[kTan * (long long)q + k];
                 const int nm = n_modes(type, order);
-                for (int md = 1; md <= nm; md++) {
-                    const int m = mode_material(S, key, type, md);
-                    if (m < 0 || m >= a.M) continue;
-                    const double* v = a.path_eps + 2 * (kAdjEps * (long long)q + (md - 1));
-                    a.rows[(5 + 2 * m) * nl + l] += v[0];
-                    a.rows[(5 + 2 * m + 1) * nl + l] += v[1];
-                }
+                for (int md = 1; md <= nm; md++)
+                    if (mode_material(S, key, type, md) == m)
+                        acc += a.path_eps[2 * (kAdjEps * (long long)q + (md - 1)) + part];
             }
         }
-#pragma unroll
-        for (int k = 0; k < kTan; k++) a.rows[k * nl + l] = acc[k];
+        a.rows[row * nl + l] = acc;
     }
 }
 
@@ -225,7 +227,7 @@ void adjoint(const AdjArgs& a, int n_tx, int n_rx, double* g_pos, double* g_ori,
         hipLaunchKernelGGL(k_adj_dual<4>, dim3(grid(a.vp.cap * kAdjDual)), dim3(128), 0, st, a);
         hipLaunchKernelGGL(k_adj_eps<4>, dim3(grid(a.vp.cap * kAdjEps)), dim3(128), 0, st, a);
     }
-    long long gl = (a.n_links + 255) / 256;
+    long long gl = ((long long)(kTan + 2 * a.M) * a.n_links + 255) / 256;
     if (gl < 1) gl = 1;
     if (gl > 16384) gl = 16384;
     hipLaunchKernelGGL(k_adj_links, dim3((unsigned)gl), dim3(256), 0, st, a);

@@ -67,6 +67,10 @@ struct emrt_ctx {
     bool batched = false;           // member of an emrt_batch
     double* adj_rows = nullptr;     // [5 + 2 adjoint_materials][n_links]
     char* leg_block = nullptr;      // shadow legs of a step; per-path partials of emrt_backward
+    uint32_t* dbg_sel = nullptr;    // capture log: mark bit per launch slot
+    int* dbg_log = nullptr;         // [EMRT_CAPTURE_LOG_ROWS][3]
+    unsigned long long* dbg_n = nullptr;
+    bool dbg_on = false;            // some ray is marked
     CompactTemp ctmp{};             // table compaction scratch
     RxBins bins{};                  // receivers binned for the diffraction candidates
     ValidTemp vtmp{};               // validation survivors
@@ -251,6 +255,9 @@ static void layout(emrt_ctx* c, Carver& cv) {
     }
     c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
     c->depth = cv.take<uint8_t>(c->n_total);
+    c->dbg_sel = cv.take<uint32_t>(c->n_total / 32 + 1);
+    c->dbg_log = cv.take<int>(3LL * EMRT_CAPTURE_LOG_ROWS);
+    c->dbg_n = cv.take<unsigned long long>(1);
     c->dir_perm = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->dir_slot = cv.take<uint32_t>(c->cfg.rays_per_tx);
     c->dirs = cv.take<float4>(c->cfg.rays_per_tx);
@@ -472,6 +479,9 @@ int32_t emrt_bind_workspace(emrt_ctx* c, void* ptr, size_t bytes) {
     fill_u64(c->ctr, 0ULL, kNumCounters, c->stream);
     fill_u32(c->flags, 0u, 16, c->stream);
     fill_u32(c->hist, 0u, 1, c->stream);
+    fill_u32(c->dbg_sel, 0u, c->n_total / 32 + 1, c->stream);
+    fill_u64(c->dbg_n, 0ULL, 1, c->stream);
+    c->dbg_on = false;
     coherence_clear(c);
     return EMRT_OK;
 }
@@ -825,6 +835,12 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     }
     b.n_out = c->ctr + C_RAYS + k + 1;
     b.work = (unsigned int*)(c->ctr + C_WORK + k);
+    if (c->dbg_on && !rev) {
+        b.dbg_sel = c->dbg_sel;
+        b.dbg_log = c->dbg_log;
+        b.dbg_n = c->dbg_n;
+        b.dbg_cap = EMRT_CAPTURE_LOG_ROWS;
+    }
     return b;
 }
 
@@ -878,6 +894,7 @@ static void step_pre(emrt_ctx* c, int discover) {
         const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;
         const int n_src = rev ? c->rev_n : c->sz.n_tx;
         fill_u64(c->table, 0ULL, c->table_slots, st);
+        if (!rev) fill_u64(c->dbg_n, 0ULL, 1, st);  // the capture log holds the last transmitter-side discovery
         if (diff) fill_u32(c->illum, 0u, (long long)n_src * c->e_words, st);
         if (diff && c->pairs) fill_u64(c->pairs, 0ULL, c->pair_slots, st);
         cache_insert(c->table, mask, c->cache[c->cur], c->ctr + C_NCACHE + c->cur, c->P, src, c->flags, st);
@@ -1167,6 +1184,38 @@ int32_t emrt_debug_ray_records(emrt_ctx* c, int32_t tx, const int32_t* ray_ids, 
     return hip_check(c, hipGetLastError(), "debug_ray_records");
 }
 
+int32_t emrt_debug_select_rays(emrt_ctx* c, int32_t tx, const int32_t* ray_ids, int32_t n) {
+    if (!c || n < 0 || (n > 0 && !ray_ids) || tx < 0 || tx >= c->sz.n_tx) return fail(c, EMRT_E_INVALID, "bad arguments");
+    if (!c->scene_set) return fail(c, EMRT_E_STATE, "set_scene first");
+    if (n == 0) {
+        fill_u32(c->dbg_sel, 0u, c->n_total / 32 + 1, c->stream);
+        c->dbg_on = false;
+        return hip_check(c, hipGetLastError(), "debug_select_rays");
+    }
+    uint32_t* bad = (uint32_t*)(c->ctr + C_SCRATCH);
+    fill_u32(bad, 0u, 1, c->stream);
+    debug_mark(c->dbg_sel, tx, c->cfg.rays_per_tx, c->dir_slot, ray_ids, n, bad, c->stream);
+    uint32_t h = 0;
+    int32_t rc = sync_read(c, &h, bad, sizeof(h));
+    if (rc) return rc;
+    c->dbg_on = true;
+    return h ? fail(c, EMRT_E_INVALID, "launch direction outside [0, rays_per_tx)") : EMRT_OK;
+}
+
+int32_t emrt_debug_ray_captures(emrt_ctx* c, int32_t* out, int64_t cap, int64_t* n_rows) {
+    if (!c || !n_rows || cap < 0 || (cap > 0 && !out)) return fail(c, EMRT_E_INVALID, "bad arguments");
+    if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace");
+    if (cap > 0)
+        debug_captures(c->dbg_log, c->dbg_n, EMRT_CAPTURE_LOG_ROWS, c->cfg.rays_per_tx, c->dir_perm, out, cap,
+                       c->stream);
+    unsigned long long n = 0;
+    int32_t rc = sync_read(c, &n, c->dbg_n, sizeof(n));
+    if (rc) return rc;
+    const unsigned long long kept = std::min<unsigned long long>(n, (unsigned long long)EMRT_CAPTURE_LOG_ROWS);
+    *n_rows = (int64_t)std::min<unsigned long long>(kept, (unsigned long long)cap);
+    return n > (unsigned long long)*n_rows ? EMRT_W_PATHS_TRUNCATED : EMRT_OK;
+}
+
 int32_t emrt_cache_size(emrt_ctx* c, int64_t* n) {
     if (!c || !n) return EMRT_E_INVALID;
     if (!c->bound) return fail(c, EMRT_E_STATE, "no workspace");
@@ -1269,7 +1318,7 @@ struct emrt_batch {
     std::vector<hipStream_t> side;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;
-    int n_streams = 4, grid = 2048;
+    int n_streams = 4, grid = 2048, chunk = 64;
     bool use_graph = true;
     // workspace
     char* ws = nullptr;
@@ -1341,7 +1390,7 @@ static void batch_enqueue(emrt_batch* b, int discover, int parity) {
         long long n = (long long)b->ctx.size();
         for (int k = 0; k <= b->kmax; k++)
             bounce_multi(b->args + ((long long)parity * (b->kmax + 1) + k) * n, (int)n,
-                         b->chunk_off + (long long)k * (n + 1), b->work + k, b->grid, b->stream);
+                         b->chunk_off + (long long)k * (n + 1), b->work + k, b->grid, b->chunk, b->stream);
     }
     batch_fan(b, [&](emrt_ctx* c) { step_post(c, discover); });
 }
@@ -1427,12 +1476,14 @@ int32_t emrt_batch_set_stream(emrt_batch* b, void* s) {
     return EMRT_OK;
 }
 
-int32_t emrt_batch_set_options(emrt_batch* b, int32_t use_graph, int32_t n_streams, int32_t grid) {
+int32_t emrt_batch_set_options(emrt_batch* b, int32_t use_graph, int32_t n_streams, int32_t grid, int32_t chunk) {
     if (!b || n_streams < 1 || n_streams > 16 || grid < 1 || grid > (1 << 20)) return EMRT_E_INVALID;
+    if (chunk != 32 && chunk != 64 && chunk != 128 && chunk != 256) return EMRT_E_INVALID;
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graphs(b);
     b->use_graph = use_graph != 0;
     b->grid = grid;
+    b->chunk = chunk;
     if (n_streams != b->n_streams) {
         b->n_streams = n_streams;
         batch_streams(b);
@@ -1457,6 +1508,7 @@ int32_t emrt_batch_step(emrt_batch* b, int32_t discover) {
                 emrt_ctx* c = b->ctx[i];
                 BounceArgs a = bounce_args(c, std::min(k, c->K), parity);
                 if (k > c->K) a.n_in = b->zero;  // scene with fewer bounces: nothing to trace
+                a.dbg_sel = nullptr;  // the capture log is a single-context tool (the table outlives marks)
                 h[(size_t)k * n + i] = a;
             }
         BounceArgs* dst = b->args + (long long)parity * (b->kmax + 1) * n;
@@ -1534,49 +1586,60 @@ int32_t emrt_batch_step(emrt_batch* b, int32_t discover) {
 // set): the persistent grid of the multi-scene bounce, then the number of
 // streams the per-scene phases are spread over.  Each trial is one eager
 // discovery step timed with HIP events on the batch stream.
-int32_t emrt_batch_autotune(emrt_batch* b, int32_t* best_grid, int32_t* best_streams) {
-    if (!b) return EMRT_E_INVALID;
+int32_t emrt_batch_autotune(emrt_batch* b, int32_t repeats, int32_t* best_grid, int32_t* best_streams,
+                            int32_t* best_chunk) {
+    if (!b || repeats < 1 || repeats > 15) return EMRT_E_INVALID;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return batch_fail(b, EMRT_E_HIP, "event");
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return batch_fail(b, EMRT_E_HIP, "event");
     }
-    bool graph = b->use_graph;
-    auto trial = [&](int grid, int ns, float& ms) -> int32_t {
-        int32_t rc = emrt_batch_set_options(b, 0, ns, grid);
+    const bool graph = b->use_graph;
+    // one trial: `repeats` timed discovery steps (no graph: the options change
+    // every trial), their median
+    auto trial = [&](int grid, int ns, int chunk, int reps, float& med) -> int32_t {
+        int32_t rc = emrt_batch_set_options(b, 0, ns, grid, chunk);
         if (rc) return rc;
-        (void)hipEventRecord(e0, b->stream);
-        rc = emrt_batch_step(b, 1);
-        (void)hipEventRecord(e1, b->stream);
-        if (rc) return rc;
-        if (hipEventSynchronize(e1) != hipSuccess) return batch_fail(b, EMRT_E_HIP, "autotune sync");
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        float t[15];
+        for (int r = 0; r < reps; r++) {
+            (void)hipEventRecord(e0, b->stream);
+            rc = emrt_batch_step(b, 1);
+            (void)hipEventRecord(e1, b->stream);
+            if (rc) return rc;
+            if (hipEventSynchronize(e1) != hipSuccess) return batch_fail(b, EMRT_E_HIP, "autotune sync");
+            (void)hipEventElapsedTime(&t[r], e0, e1);
+        }
+        std::sort(t, t + reps);
+        med = t[reps / 2];
         return EMRT_OK;
     };
-    int32_t rc = EMRT_OK;
     float warm = 0;
-    rc = trial(b->grid, b->n_streams, warm);  // warm-up (first-touch, code loading)
-    int g_best = b->grid, s_best = b->n_streams;
+    int32_t rc = trial(b->grid, b->n_streams, b->chunk, 1, warm);  // first touch, code loading
+    int g_best = b->grid, s_best = b->n_streams, c_best = b->chunk;
     float t_best = 1e30f;
     const int grids[] = {1024, 2048, 4096, 8192};
-    for (int g : grids) {
-        float ms = 0;
-        if (rc == EMRT_OK) rc = trial(g, s_best, ms);
-        if (rc == EMRT_OK && ms < t_best) { t_best = ms; g_best = g; }
-    }
     const int streams[] = {1, 2, 4, 8};
-    for (int ns : streams) {
-        float ms = 0;
-        if (rc == EMRT_OK) rc = trial(g_best, ns, ms);
-        if (rc == EMRT_OK && ms < t_best) { t_best = ms; s_best = ns; }
-    }
+    const int chunks[] = {32, 64, 128};
+    for (int ns : streams)
+        for (int g : grids)
+            for (int ch : chunks) {
+                float ms = 0;
+                if (rc == EMRT_OK) rc = trial(g, ns, ch, repeats, ms);
+                if (rc == EMRT_OK && ms < t_best) {
+                    t_best = ms;
+                    g_best = g;
+                    s_best = ns;
+                    c_best = ch;
+                }
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != EMRT_OK) return rc;
-    rc = emrt_batch_set_options(b, graph ? 1 : 0, s_best, g_best);
+    rc = emrt_batch_set_options(b, graph ? 1 : 0, s_best, g_best, c_best);
     if (best_grid) *best_grid = g_best;
     if (best_streams) *best_streams = s_best;
+    if (best_chunk) *best_chunk = c_best;
     return rc;
 }
 

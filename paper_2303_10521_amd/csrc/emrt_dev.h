@@ -427,21 +427,20 @@ __device__ __forceinline__ bool tri_hit(const TriP& p, const RayPre& r, float& t
 // BVH traversal
 //
 // Main loop: a short per-ray stack.  At an internal node both child boxes
-// are tested (in stored order); the near child (the child on the ray's side
-// of the split axis, or the left child for the unordered queries) is entered
-// and the other pushed.  Each internal node is loaded once.
+// are tested; the nearer child is entered and the other pushed.  Each
+// internal node is loaded once.
 //
 // The stack holds kStackDepth node ids; it only holds the pending far
 // children along the current path, and the LBVHs of a city are about 25
-// levels deep.  The compiler keeps the stack in registers, so a deeper stack
-// costs occupancy.  On the city's bounces 10, 12 and 14 entries ran alike and
-// about 7% faster than 16 (storing entry distances to re-check at the pop
-// cost another 6%); at 12 a restart is rare (0.0001% more node visits than
-// with no overflow).  If a deeper tree overflows it, the traversal starts over
-// with the stackless walk over parent links below, which needs no stack; all
-// queries are idempotent (closest hit with a fixed tie rule, any hit, leaf
-// visits whose effects are set inserts), so work done before the restart
-// does not change the result.
+// levels deep.  The bounce and shadow kernels keep it in one column of a
+// block-wide LDS array (LdsStack below); kernels without that LDS keep it in
+// a private array (RegStack), where a deeper stack costs registers.  On the
+// city's bounces 10 and 12 entries ran alike and 16 or 20 cost about 6%; at
+// 12 a restart is rare (0.0001% more node visits than with no overflow).  If
+// a deeper tree overflows it, the traversal starts over with the walk over
+// parent links below, which needs no stack; all queries are idempotent
+// (closest hit with a fixed tie rule, any hit, leaf visits whose effects are
+// set inserts), so work done before the restart does not change the result.
 // --------------------------------------------------------------------------
 #ifndef EMRT_STACK_DEPTH
 #define EMRT_STACK_DEPTH 12

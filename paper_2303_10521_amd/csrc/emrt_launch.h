@@ -158,6 +158,12 @@ struct BounceArgs {
     const float4* gen_dirs;
     const double* gen_src;
     int gen_N;
+    // capture log of marked rays (transmitter-side discovery; null: off):
+    // rows (launch slot, bounce | kind << 8, receiver or edge)
+    const uint32_t* dbg_sel;  // [n_total / 32 + 1] mark bit per launch slot
+    int* dbg_log;             // [dbg_cap][3]
+    unsigned long long* dbg_n;
+    long long dbg_cap;
 };
 void ray_order(int N, uint32_t* perm, const BuildTemp& tmp, hipStream_t st);
 // the N launch directions in launch order (perm: direction index of each slot)
@@ -167,10 +173,16 @@ void raygen(const double* src_pos, int n_src, int N, const uint32_t* perm, RaySo
             hipStream_t st);
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
 // one launch over several scenes' live rays (args device [n_scenes]; chunk_off [n_scenes + 1], work: scratch)
-void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid,
+void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid, int chunk,
                   hipStream_t st);
 void debug_rays(const int* hitlog, const uint8_t* depth, long long n_total, int K, int tx, int N,
                 const uint32_t* slot_of, const int* ray_ids, int n, int* out, hipStream_t st);
+// mark the launch slots of directions ray_ids of transmitter tx (bad: set when one is out of range)
+void debug_mark(uint32_t* sel, int tx, int N, const uint32_t* slot_of, const int* ray_ids, int n, uint32_t* bad,
+                hipStream_t st);
+// log rows -> (tx, direction, bounce, kind, id) through the launch order perm (direction of each slot)
+void debug_captures(const int* log, const unsigned long long* n_log, long long log_cap, int N, const uint32_t* perm,
+                    int* out, long long cap, hipStream_t st);
 // inv[perm[t]] = t
 void invert_perm(const uint32_t* perm, uint32_t* inv, int n, hipStream_t st);
 

@@ -16,6 +16,8 @@
 //      k alpha s of (diffraction candidates),
 //   5. reflects specularly and appends the surviving ray to the next
 //      bounce's buffer with one atomic per wave (ballot + mbcnt prefix).
+#include <algorithm>
+
 #include "emrt_dev.h"
 #include "emrt_launch.h"
 
@@ -118,6 +120,16 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
     return sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1.0f;
 }
 
+// capture of a marked ray into the debug log
+__device__ __forceinline__ void debug_log(const BounceArgs& a, uint32_t id, int b, int kind, int target) {
+    if (!((a.dbg_sel[id >> 5] >> (id & 31)) & 1u)) return;
+    const unsigned long long k = atomicAdd(a.dbg_n, 1ULL);
+    if (k >= (unsigned long long)a.dbg_cap) return;
+    a.dbg_log[3 * k] = (int)id;
+    a.dbg_log[3 * k + 1] = b | (kind << 8);
+    a.dbg_log[3 * k + 2] = target;
+}
+
 // One 64-ray chunk of a bounce: rays [base, base + 64) of the live buffer.
 // REV: a launch from receivers (a.src.src_rx) whose spheres sit on the
 // transmitters; the captured key is reversed into transmitter-to-receiver
@@ -125,10 +137,10 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
 template <bool STATS, bool REV>
 __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long long n_in, unsigned long long base,
                                              int lane, unsigned& s_nodes, unsigned& s_tris, unsigned& s_seg,
-                                             unsigned& s_cap, unsigned& s_box4, LdsStack* stk) {
+                                             unsigned& s_cap, unsigned& s_box4, LdsStack* stk, int width = 64) {
     const int b = a.b;
     unsigned long long i = base + (unsigned long long)lane;
-    bool act = i < n_in;
+    bool act = lane < width && i < n_in;
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, L = 0;
     uint32_t id = 0;
     int prev = -1;
@@ -174,6 +186,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             float rs = a.alpha_k * (L + s);
             if (!(rho2 < rs * rs)) return;
             int target = __float_as_int(p.w);
+            if (!REV && a.dbg_sel) debug_log(a, id, b, 0, target);
             if (!have) {
                 const int source = (int)(id / (uint32_t)a.rays_per_tx);
                 mine.to = KT_SPEC | (b << 8);
@@ -224,6 +237,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             float re = a.alpha_k * (L + s);
             if (!(qx * qx + qy * qy + qz * qz < re * re)) return;
             int e = __float_as_int(P0.w);
+            if (!REV && a.dbg_sel) debug_log(a, id, b, 1, e);
             if (b == 0) {
                 uint32_t* w = a.illum + (long long)source * a.e_words + (e >> 5);
                 uint32_t bit = 1u << (e & 31);
@@ -315,14 +329,19 @@ void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {
 // Several scenes in one launch (batched stepping): chunk_off[c] is the first
 // global chunk of scene c (an exclusive scan of its live-ray chunks, built on
 // the device by k_chunk_table); a wave takes the next global chunk, finds its
-// scene by binary search and runs that scene's bounce on it.
+// scene by binary search and runs that scene's bounce on it.  A chunk holds
+// `chunk` rays (32, 64, 128 or 256): a wave traces them 64 at a time (32:
+// with half its lanes), so larger chunks take fewer counter atomics and
+// binary searches, smaller ones balance the tail better.
 __global__ void __launch_bounds__(256) k_chunk_table(const BounceArgs* __restrict__ args, int n_scenes,
-                                                     uint32_t* chunk_off, uint32_t* work) {
+                                                     uint32_t* chunk_off, uint32_t* work, int chunk) {
     __shared__ uint32_t sh[256];
     uint32_t carry = 0;
     for (int base = 0; base < n_scenes; base += 256) {
         int c = base + (int)threadIdx.x;
-        uint32_t v = c < n_scenes ? (uint32_t)((*args[c].n_in + 63ULL) / 64ULL) : 0u;
+        uint32_t v = c < n_scenes ? (uint32_t)((*args[c].n_in + (unsigned long long)chunk - 1ULL) /
+                                               (unsigned long long)chunk)
+                                  : 0u;
         sh[threadIdx.x] = v;
         __syncthreads();
         // inclusive Hillis-Steele scan of 256 values
@@ -344,7 +363,7 @@ __global__ void __launch_bounds__(256) k_chunk_table(const BounceArgs* __restric
 
 __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restrict__ args,
                                                       const uint32_t* __restrict__ chunk_off, uint32_t* work,
-                                                      int n_scenes) {
+                                                      int n_scenes, int chunk) {
     __shared__ int stk_lds[kStackRows][kStackStride];
     LdsStack stk{&stk_lds[0][threadIdx.x]};
     const int lane = lane_id();
@@ -369,18 +388,20 @@ __global__ void __launch_bounds__(256) k_bounce_multi(const BounceArgs* __restri
         const int c = __builtin_amdgcn_readfirstlane(lo);
         const BounceArgs& a = args[c];
         const unsigned long long n_in = *a.n_in;
-        bounce_chunk<false, false>(a, n_in, (unsigned long long)(g - chunk_off[c]) * 64ULL, lane, s_nodes, s_tris,
-                                   s_seg, s_cap, s_box4, &stk);
+        // a chunk of `chunk` rays: 64 per pass (32: half the lanes)
+        const unsigned long long base = (unsigned long long)(g - chunk_off[c]) * (unsigned long long)chunk;
+        for (int j = 0; j < chunk; j += 64)
+            bounce_chunk<false, false>(a, n_in, base + (unsigned long long)j, lane, s_nodes, s_tris, s_seg, s_cap,
+                                       s_box4, &stk, chunk < 64 ? chunk : 64);
     }
 }
 
-void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid,
+void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid, int chunk,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(256), 0, st, args, n_scenes, chunk_off, work);
-    hipLaunchKernelGGL(k_bounce_multi, dim3(grid), dim3(256), 0, st, args, chunk_off, work, n_scenes);
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(256), 0, st, args, n_scenes, chunk_off, work, chunk);
+    hipLaunchKernelGGL(k_bounce_multi, dim3(grid), dim3(256), 0, st, args, chunk_off, work, n_scenes, chunk);
 }
 
-// Hit log of launch direction i of transmitter tx (slot_of[i]: its launch slot).
 // Hit log of launch direction i of transmitter tx (slot_of[i]: its launch
 // slot); rows after the bounce at which the ray ended read -2.
 __global__ void k_debug_rays(const int* hitlog, const uint8_t* depth, long long n_total, int K, int tx, int N,
@@ -407,6 +428,48 @@ __global__ void k_invert_perm(const uint32_t* perm, uint32_t* inv, int n) {
 
 void invert_perm(const uint32_t* perm, uint32_t* inv, int n, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_invert_perm, dim3((n + 255) / 256), dim3(256), 0, st, perm, inv, n);
+}
+
+__global__ void k_debug_mark(uint32_t* sel, int tx, int N, const uint32_t* slot_of, const int* ids, int n,
+                             uint32_t* bad) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int i = ids[k];
+    if (i < 0 || i >= N) {
+        atomicOr(bad, 1u);
+        return;
+    }
+    const long long slot = (long long)tx * N + slot_of[i];
+    atomicOr(&sel[slot >> 5], 1u << (slot & 31));
+}
+
+void debug_mark(uint32_t* sel, int tx, int N, const uint32_t* slot_of, const int* ray_ids, int n, uint32_t* bad,
+                hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_debug_mark, dim3((n + 255) / 256), dim3(256), 0, st, sel, tx, N, slot_of, ray_ids,
+                                  n, bad);
+}
+
+__global__ void k_debug_captures(const int* log, const unsigned long long* n_log, long long log_cap, int N,
+                                 const uint32_t* perm, int* out, long long cap) {
+    long long n = (long long)*n_log;
+    if (n > log_cap) n = log_cap;
+    if (n > cap) n = cap;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const long long slot = (unsigned)log[3 * k];
+        const int tx = (int)(slot / N);
+        out[5 * k] = tx;
+        out[5 * k + 1] = (int)perm[slot - (long long)tx * N];
+        out[5 * k + 2] = log[3 * k + 1] & 0xff;
+        out[5 * k + 3] = log[3 * k + 1] >> 8;
+        out[5 * k + 4] = log[3 * k + 2];
+    }
+}
+
+void debug_captures(const int* log, const unsigned long long* n_log, long long log_cap, int N, const uint32_t* perm,
+                    int* out, long long cap, hipStream_t st) {
+    const long long g = (std::min(log_cap, cap) + 255) / 256;
+    hipLaunchKernelGGL(k_debug_captures, dim3((unsigned)std::max(1LL, std::min(g, 4096LL))), dim3(256), 0, st, log,
+                       n_log, log_cap, N, perm, out, cap);
 }
 
 }  // namespace emrt

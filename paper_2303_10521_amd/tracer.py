@@ -4,6 +4,9 @@ allocates device buffers (torch), passes pointers and reads results back."""
 from __future__ import annotations
 
 import ctypes
+import json
+import math
+import os
 from typing import Dict, Optional, Sequence
 
 import numpy as np
@@ -267,6 +270,23 @@ class Tracer:
         self._check(self.lib.emrt_debug_ray_records(self.ctx, int(tx), _ptr(ids), len(ids), _ptr(out)))
         return out.cpu().numpy()
 
+    def debug_select_rays(self, tx: int, ray_ids) -> None:
+        """Mark launch directions ray_ids of transmitter tx for the capture log
+        of later transmitter-side discovery steps (an empty list clears all)."""
+        ids = _dev(np.asarray(ray_ids, np.int32).reshape(-1), torch.int32, self.device)
+        self._check(self.lib.emrt_debug_select_rays(self.ctx, int(tx), _ptr(ids) if len(ids) else None, len(ids)))
+
+    def debug_ray_captures(self) -> np.ndarray:
+        """Capture log of the last transmitter-side discovery step: rows (tx,
+        launch direction, bounce, kind 0 receiver / 1 edge, receiver or edge
+        id).  Raises when rows were dropped."""
+        out = torch.empty((A.CAPTURE_LOG_ROWS, 5), dtype=torch.int32, device=self.device)
+        n = ctypes.c_int64()
+        st = self._check(self.lib.emrt_debug_ray_captures(self.ctx, _ptr(out), A.CAPTURE_LOG_ROWS, ctypes.byref(n)))
+        if st == A.EMRT_W_PATHS_TRUNCATED:
+            raise EmrtError(st, "capture log overflow: mark fewer rays")
+        return out[: n.value].cpu().numpy()
+
     def cache_export(self) -> np.ndarray:
         n = ctypes.c_int64()
         self._check(self.lib.emrt_cache_size(self.ctx, ctypes.byref(n)))
@@ -293,7 +313,8 @@ class Batch:
     from a HIP graph.  Frames are set and results read on the member
     Tracers; ``step`` replaces their individual ``step``."""
 
-    def __init__(self, tracers: Sequence[Tracer], use_graph: bool = True, n_streams: int = 4, grid: int = 2048):
+    def __init__(self, tracers: Sequence[Tracer], use_graph: bool = True, n_streams: int = 4, grid: int = 2048,
+                 chunk: int = 64):
         self.lib = A.load()
         self.tracers = list(tracers)
         n = len(self.tracers)
@@ -312,7 +333,8 @@ class Batch:
         torch.cuda.current_stream(dev).synchronize()
         self._check(self.lib.emrt_batch_set_stream(self.b, ctypes.c_void_p(self.stream.cuda_stream)))
         self._check(self.lib.emrt_batch_bind_workspace(self.b, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
-        self.set_options(use_graph, n_streams, grid)
+        self.use_graph = bool(use_graph)
+        self.set_options(use_graph, n_streams, grid, chunk)
 
     def _check(self, st: int) -> int:
         if st < 0:
@@ -321,18 +343,51 @@ class Batch:
             raise EmrtError(st, buf.value.decode() or A.load().emrt_status_string(st).decode())
         return st
 
-    def set_options(self, use_graph: bool = True, n_streams: int = 4, grid: int = 2048) -> None:
-        self._check(self.lib.emrt_batch_set_options(self.b, int(use_graph), int(n_streams), int(grid)))
+    def set_options(self, use_graph: bool = True, n_streams: int = 4, grid: int = 2048, chunk: int = 64) -> None:
+        self.use_graph = bool(use_graph)
+        self.options = dict(n_streams=int(n_streams), grid=int(grid), chunk=int(chunk))
+        self._check(self.lib.emrt_batch_set_options(self.b, int(use_graph), int(n_streams), int(grid), int(chunk)))
 
     def step(self, discover: bool = True) -> int:
         for t in self.tracers:
             t.generation += 1
         return self._check(self.lib.emrt_batch_step(self.b, 1 if discover else 0))
 
-    def autotune(self):
-        g, s = ctypes.c_int32(), ctypes.c_int32()
-        self._check(self.lib.emrt_batch_autotune(self.b, ctypes.byref(g), ctypes.byref(s)))
-        return g.value, s.value
+    def tune_key(self) -> str:
+        """Autotuning cache key: the GPU architecture and size buckets (powers
+        of two of the members' primary rays and of the member count)."""
+        dev = self.tracers[0].device
+        arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
+        rays = sum(int(t.n_tx) * int(t.cfg.rays_per_tx) for t in self.tracers)
+        return f"{arch}|rays_2^{round(math.log2(max(rays, 1)))}|scenes_2^{round(math.log2(len(self.tracers)))}"
+
+    def autotune(self, repeats: int = 3, cache: Optional[str] = None) -> Dict[str, object]:
+        """Launch shape (grid, streams, chunk) from the JSON cache file `cache`
+        when it holds this batch's key, else timed by emrt_batch_autotune
+        (`repeats` timed steps per combination, median) and stored there."""
+        key = self.tune_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            o = table[key]
+            self.set_options(self.use_graph, o["streams"], o["grid"], o["chunk"])
+            return dict(o, key=key, from_cache=True)
+        g, s, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.emrt_batch_autotune(self.b, int(repeats), ctypes.byref(g), ctypes.byref(s),
+                                                 ctypes.byref(c)))
+        self.options = dict(n_streams=s.value, grid=g.value, chunk=c.value)
+        o = {"grid": g.value, "streams": s.value, "chunk": c.value, "repeats": int(repeats)}
+        if cache:
+            table[key] = o
+            d = os.path.dirname(os.path.abspath(cache))
+            os.makedirs(d, exist_ok=True)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(o, key=key, from_cache=False)
 
     def sync(self) -> int:
         return self._check(self.lib.emrt_batch_sync(self.b))

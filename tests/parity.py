@@ -100,3 +100,31 @@ def compare_angles(g_ang: np.ndarray, o_aod: np.ndarray, o_aoa: np.ndarray, tol:
 
 def gpu_channels_np(ch: dict) -> dict:
     return {k: v.cpu().numpy() for k, v in ch.items()}
+
+
+def compare_captures(rows: np.ndarray, tx: int, ray_ids: np.ndarray, trace, strict: bool = True) -> tuple:
+    """Per-ray capture sets of the GPU's capture log (rows of tx, launch
+    direction, bounce, kind, id) against an oracle ``TraceResult`` of the
+    same directions of transmitter tx.  strict: every row of tx must belong
+    to one of ray_ids (else rows of other marked directions are skipped).
+    Returns (robust rays compared, rays whose receiver or edge capture set
+    differs)."""
+    rows = np.asarray(rows).reshape(-1, 5)
+    rows = rows[rows[:, 0] == tx]
+    pos = {int(r): k for k, r in enumerate(ray_ids)}
+    g_rx = [set() for _ in ray_ids]
+    g_ed = [set() for _ in ray_ids]
+    for _, d, b, kind, i in rows:
+        k = pos.get(int(d))
+        if k is None:
+            assert not strict, f"capture of an unmarked direction {d}"
+            continue
+        (g_ed if kind == 1 else g_rx)[k].add((int(b), int(i)))
+    o_rx = [set() for _ in ray_ids]
+    o_ed = [set() for _ in ray_ids]
+    for k, b, r in trace.captures:
+        o_rx[k].add((int(b), int(r)))
+    for k, e, b in trace.edge_hits:
+        o_ed[k].add((int(b), int(e)))
+    bad = [k for k in range(len(ray_ids)) if trace.robust[k] and (g_rx[k] != o_rx[k] or g_ed[k] != o_ed[k])]
+    return int(trace.robust.sum()), bad

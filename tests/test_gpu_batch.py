@@ -50,7 +50,7 @@ def _equal(a, b):
         assert np.array_equal(a[k], b[k]), k
 
 
-def _run_schedule(use_graph, n_streams, grid, ks=None):
+def _run_schedule(use_graph, n_streams, grid, ks=None, chunk=64):
     from paper_2303_10521_amd import Batch
 
     ws = [city.batch_city(i) for i in CITIES]
@@ -59,7 +59,7 @@ def _run_schedule(use_graph, n_streams, grid, ks=None):
             w.max_reflections = k
     solo = [_tracer(w) for w in ws]
     members = [_tracer(w) for w in ws]
-    batch = Batch(members, use_graph=use_graph, n_streams=n_streams, grid=grid)
+    batch = Batch(members, use_graph=use_graph, n_streams=n_streams, grid=grid, chunk=chunk)
     for f, disc in enumerate(SCHEDULE):
         for w, a, b in zip(ws, solo, members):
             fr = w.scene.frame(f * w.frame_dt)
@@ -88,7 +88,14 @@ def test_batch_mixed_bounce_depths():
     _run_schedule(True, 2, 1024, ks=(4, 2, 4, 3, 0, 4))
 
 
-def test_batch_rules_and_autotune():
+@pytest.mark.parametrize("chunk", [32, 128, 256])
+def test_batch_chunk_sizes_match_separate_steps(chunk):
+    """Every chunk size of the multi-scene bounce (half-wave chunks of 32
+    rays, two and four passes of 64) gives the separate steps' results."""
+    _run_schedule(True, 4, 2048, chunk=chunk)
+
+
+def test_batch_rules_and_autotune(tmp_path):
     from paper_2303_10521_amd import Batch
     from paper_2303_10521_amd.tracer import EmrtError
 
@@ -103,8 +110,15 @@ def test_batch_rules_and_autotune():
         members[0].step(True)  # members step through the batch only
     with pytest.raises(EmrtError):
         Batch([members[0]])  # already batched
-    grid, ns = batch.autotune()
-    assert grid in (1024, 2048, 4096, 8192) and ns in (1, 2, 4, 8)
+    with pytest.raises(EmrtError):
+        batch.set_options(True, 4, 2048, chunk=48)  # not a supported chunk size
+    cache = str(tmp_path / "tune.json")
+    o = batch.autotune(repeats=1, cache=cache)
+    assert not o["from_cache"] and o["key"].startswith("gfx950|")
+    assert o["grid"] in (1024, 2048, 4096, 8192) and o["streams"] in (1, 2, 4, 8) and o["chunk"] in (32, 64, 128)
+    again = batch.autotune(repeats=1, cache=cache)  # the cached shape, no timing
+    assert again["from_cache"] and {k: again[k] for k in ("grid", "streams", "chunk")} == {
+        k: o[k] for k in ("grid", "streams", "chunk")}
     batch.step(True)
     assert batch.sync() == 0
     batch.close()

@@ -308,17 +308,26 @@ def city_run():
     tr = _tracer(sc, w, path_capacity=1 << 23)
     fr = sc.frame(0.0)
     tr.set_frame(fr, 0)
+    ids = {t: np.arange(t * 37, w.rays_per_tx, CITY_STRIDE, dtype=np.int32) for t in range(sc.n_tx)}
+    cov_ids = np.arange(5, w.rays_per_tx, 256, dtype=np.int32)  # the discovery-coverage subset
+    for t in range(sc.n_tx):  # the capture decisions of both subsets are logged
+        tr.debug_select_rays(t, ids[t])
+        tr.debug_select_rays(t, cov_ids)
     tr.step(True)
     assert tr.sync() == 0
     os_ = O.OracleScene(sc)
     out = dict(w=w, sc=sc, tr=tr, fr=fr, os=os_, g=os_.geometry(fr.obj_xform), stats=tr.stats())
-    out["ids"] = {t: np.arange(t * 37, w.rays_per_tx, CITY_STRIDE, dtype=np.int32) for t in range(sc.n_tx)}
+    out["ids"] = ids
+    out["cov_ids"] = cov_ids
+    out["captures"] = tr.debug_ray_captures()
     out["hits"] = {t: tr.debug_rays(t, out["ids"][t]) for t in range(sc.n_tx)}
     out["paths"] = tr.flat_paths(cap=128)
     out["ch"] = P.gpu_channels_np(tr.channels())
     # the oracle's traces of the same launch directions (receiver and edge capture, robust-ray mask)
     out["traces"] = {t: O.trace(os_, out["g"], fr.tx_pos[t], w.rays_per_tx, out["ids"][t], w.max_reflections,
                                 fr.rx_pos, 1.0, True, True) for t in range(sc.n_tx)}
+    out["cov_traces"] = {t: O.trace(os_, out["g"], fr.tx_pos[t], w.rays_per_tx, cov_ids, w.max_reflections,
+                                    fr.rx_pos, 1.0, True, True) for t in range(sc.n_tx)}
     yield out
     tr.close()
 
@@ -341,6 +350,52 @@ def test_city_hit_logs_all_transmitters(city_run):
     assert tot >= 2000 and rob >= 0.9 * tot
 
 
+def test_city_capture_sets_per_ray(city_run):
+    """Receiver captures (reception spheres on the segments after a
+    reflection) and edge captures (first segment) ray by ray: on every robust
+    ray of both sampled subsets (about 64,500 launch directions over all 16
+    transmitters), the GPU's logged set of (bounce, receiver) and (bounce,
+    edge) equals the oracle's."""
+    rows = city_run["captures"]
+    assert (rows[:, 3] == 0).sum() >= 200 and (rows[:, 3] == 1).sum() >= 200, np.bincount(rows[:, 3])
+    tot = 0
+    for t in range(city_run["sc"].n_tx):
+        for ids, res in ((city_run["ids"][t], city_run["traces"][t]), (city_run["cov_ids"], city_run["cov_traces"][t])):
+            n, bad = P.compare_captures(rows, t, ids, res, strict=False)
+            assert not bad, (t, bad[:5])
+            tot += n
+    assert tot >= 60000
+
+
+def test_capture_log_marks_and_errors():
+    """Marks persist until cleared, a cleared context logs nothing, and a
+    direction outside [0, rays_per_tx) is refused."""
+    from paper_2303_10521_amd.tracer import EmrtError
+
+    w = city.workload("toy")
+    sc = w.scene
+    tr = _tracer(sc, w)
+    fr = sc.frame(0.0)
+    tr.set_frame(fr)
+    with pytest.raises(EmrtError):
+        tr.debug_select_rays(0, [w.rays_per_tx])
+    ids = np.arange(0, w.rays_per_tx, 3, dtype=np.int32)
+    tr.debug_select_rays(0, ids)
+    tr.step(True)
+    a = tr.debug_ray_captures()
+    tr.step(True)  # same frame, same marks: the same log
+    b = tr.debug_ray_captures()
+    assert len(a) > 0 and sorted(map(tuple, a)) == sorted(map(tuple, b))
+    res = O.trace(O.OracleScene(sc), O.OracleScene(sc).geometry(fr.obj_xform), fr.tx_pos[0], w.rays_per_tx, ids,
+                  w.max_reflections, fr.rx_pos, 1.0, 0, True)
+    n, bad = P.compare_captures(a, 0, ids, res)
+    assert n >= 0.9 * len(ids) and not bad
+    tr.debug_select_rays(0, [])
+    tr.step(True)
+    assert len(tr.debug_ray_captures()) == 0
+    tr.close()
+
+
 def test_city_discovery_covers_oracle_subset(city_run):
     """Specular keys that the oracle's rays capture robustly on a launch
     subset (every 256th direction of every transmitter, 62,500 rays; a key is
@@ -350,9 +405,8 @@ def test_city_discovery_covers_oracle_subset(city_run):
     os_, g, fr, w = city_run["os"], city_run["g"], city_run["fr"], city_run["w"]
     gset = P.keyset(city_run["paths"]["key"])
     spec, diff = {}, {}
-    ids = np.arange(5, w.rays_per_tx, 256, dtype=np.int32)
     for t in range(city_run["sc"].n_tx):
-        res = O.trace(os_, g, fr.tx_pos[t], w.rays_per_tx, ids, w.max_reflections, fr.rx_pos, 1.0, True, True)
+        res = city_run["cov_traces"][t]
         for k, rob in O.spec_keys(os_, res, t).items():
             spec[k] = spec.get(k, False) or rob
         for k, rob in O.diffraction_candidates(os_, g, t, O.illuminated_edges(res), fr.rx_pos,
