@@ -169,6 +169,8 @@ def main() -> int:
                     help="copy 1 GiB device-to-device before the warm-up (reference dispatch for HBM counters)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint measurement (8-material district; for profiler runs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched measurement (64 cities; for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the path is not sharded "
@@ -187,6 +189,9 @@ def main() -> int:
             torch.empty_like(src).copy_(src)
             torch.cuda.synchronize()
         print(json.dumps({"mode": "adjoint only", "adjoint": bench_adjoint(torch, np, reps=1)}))
+        return 0
+    if args.batched_only:
+        print(json.dumps({"mode": "batched only", "batched": bench_batched(torch)}))
         return 0
 
     w = workload(args.workload)

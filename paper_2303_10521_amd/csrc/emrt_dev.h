@@ -683,16 +683,34 @@ __device__ __forceinline__ bool any_hit(const Bvh& bvh, const TriP* prims, const
 
 // Child k of a 4-wide node: decoded box (exact fma of the stored bytes, as at
 // build time) through the fused slab test.
+// The byte words of a node's entry and exit planes for this ray: on an axis
+// where the ray runs backwards the entry plane is the high one.  Chosen once
+// per node for all four children (the per-child choice of slab_fma, hoisted).
+struct Planes4 {
+    uint32_t ex, ey, ez;  // entry-plane bytes (child k in byte k)
+    uint32_t fx, fy, fz;  // exit-plane bytes
+};
+__device__ __forceinline__ Planes4 planes4(const QNode4& nd, const RayPre& r) {
+    const bool sx = r.negmask & 1, sy = r.negmask & 2, sz = r.negmask & 4;
+    return Planes4{sx ? nd.r.x : nd.q.x, sy ? nd.r.y : nd.q.y, sz ? nd.r.z : nd.q.z,
+                   sx ? nd.q.x : nd.r.x, sy ? nd.q.y : nd.r.y, sz ? nd.q.z : nd.r.z};
+}
+
+// Child K's box against the ray: the same decode (fma of the byte with the
+// axis scale, onto the node's corner) and fused slab test as slab_fma.
 template <int K>
-__device__ __forceinline__ bool child4(const QNode4& nd, float sx, float sy, float sz, const RayPre& r, float tmax,
-                                       float& tn) {
-    const float lx = fmaf((float)((nd.q.x >> (8 * K)) & 255u), sx, nd.o.x);
-    const float ly = fmaf((float)((nd.q.y >> (8 * K)) & 255u), sy, nd.o.y);
-    const float lz = fmaf((float)((nd.q.z >> (8 * K)) & 255u), sz, nd.o.z);
-    const float hx = fmaf((float)((nd.r.x >> (8 * K)) & 255u), sx, nd.o.x);
-    const float hy = fmaf((float)((nd.r.y >> (8 * K)) & 255u), sy, nd.o.y);
-    const float hz = fmaf((float)((nd.r.z >> (8 * K)) & 255u), sz, nd.o.z);
-    return slab_fma(lx, ly, lz, hx, hy, hz, r, tmax, tn);
+__device__ __forceinline__ bool child4(const QNode4& nd, const Planes4& pl, float sx, float sy, float sz,
+                                       const RayPre& r, float tmax, float& tn) {
+    const float nx = fmaf(fmaf((float)((pl.ex >> (8 * K)) & 255u), sx, nd.o.x), r.ix, r.nmx);
+    const float ny = fmaf(fmaf((float)((pl.ey >> (8 * K)) & 255u), sy, nd.o.y), r.iy, r.nmy);
+    const float nz = fmaf(fmaf((float)((pl.ez >> (8 * K)) & 255u), sz, nd.o.z), r.iz, r.nmz);
+    const float fx = fmaf(fmaf((float)((pl.fx >> (8 * K)) & 255u), sx, nd.o.x), r.ix, r.npx);
+    const float fy = fmaf(fmaf((float)((pl.fy >> (8 * K)) & 255u), sy, nd.o.y), r.iy, r.npy);
+    const float fz = fmaf(fmaf((float)((pl.fz >> (8 * K)) & 255u), sz, nd.o.z), r.iz, r.npz);
+    const float a = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
+    const float b = fminf(fminf(fx, fy), fminf(fz, tmax)) * 1.00000095367431640625f;  // 1 + 2^-20
+    tn = a;
+    return a <= b;
 }
 
 __device__ __forceinline__ float scale4(uint32_t bits, int shift) {
@@ -731,11 +749,12 @@ __device__ __forceinline__ void closest_hit4(const Bvh4& bvh, const Bvh& bin, co
         const int cnt = (int)(meta >> 24);
         if (STATS) n_boxes += (unsigned)cnt;
         const float sx = scale4(meta, 0), sy = scale4(meta, 8), sz = scale4(meta, 16);
+        const Planes4 pl = planes4(nd, r);
         float t0, t1, t2, t3;
-        const bool h0 = child4<0>(nd, sx, sy, sz, r, best_t, t0) && cnt > 0;
-        const bool h1 = child4<1>(nd, sx, sy, sz, r, best_t, t1) && cnt > 1;
-        const bool h2 = child4<2>(nd, sx, sy, sz, r, best_t, t2) && cnt > 2;
-        const bool h3 = child4<3>(nd, sx, sy, sz, r, best_t, t3) && cnt > 3;
+        const bool h0 = child4<0>(nd, pl, sx, sy, sz, r, best_t, t0) && cnt > 0;
+        const bool h1 = child4<1>(nd, pl, sx, sy, sz, r, best_t, t1) && cnt > 1;
+        const bool h2 = child4<2>(nd, pl, sx, sy, sz, r, best_t, t2) && cnt > 2;
+        const bool h3 = child4<3>(nd, pl, sx, sy, sz, r, best_t, t3) && cnt > 3;
         int c0 = nd.c.x, c1 = nd.c.y, c2 = nd.c.z, c3 = nd.c.w;
         const bool f0 = h0 && c0 < 0, f1 = h1 && c1 < 0, f2 = h2 && c2 < 0, f3 = h3 && c3 < 0;
         if (f0 || f1 || f2 || f3) {
@@ -782,11 +801,12 @@ __device__ __forceinline__ bool any_hit4(const Bvh4& bvh, const Bvh& bin, const 
         const uint32_t meta = __float_as_uint(nd.o.w);
         const int cnt = (int)(meta >> 24);
         const float sx = scale4(meta, 0), sy = scale4(meta, 8), sz = scale4(meta, 16);
+        const Planes4 pl = planes4(nd, r);
         float t0, t1, t2, t3;
-        const bool h0 = child4<0>(nd, sx, sy, sz, r, tmax, t0) && cnt > 0;
-        const bool h1 = child4<1>(nd, sx, sy, sz, r, tmax, t1) && cnt > 1;
-        const bool h2 = child4<2>(nd, sx, sy, sz, r, tmax, t2) && cnt > 2;
-        const bool h3 = child4<3>(nd, sx, sy, sz, r, tmax, t3) && cnt > 3;
+        const bool h0 = child4<0>(nd, pl, sx, sy, sz, r, tmax, t0) && cnt > 0;
+        const bool h1 = child4<1>(nd, pl, sx, sy, sz, r, tmax, t1) && cnt > 1;
+        const bool h2 = child4<2>(nd, pl, sx, sy, sz, r, tmax, t2) && cnt > 2;
+        const bool h3 = child4<3>(nd, pl, sx, sy, sz, r, tmax, t3) && cnt > 3;
         const int cs[4] = {nd.c.x, nd.c.y, nd.c.z, nd.c.w};
         const bool hs[4] = {h0, h1, h2, h3};
         bool found = false;
