@@ -291,7 +291,8 @@ int32_t emrt_coherence_reset(emrt_ctx* ctx);
  * captured once per (discover, cache parity) as a HIP graph and replayed.
  * Frames are set and results read through the member contexts
  * (emrt_set_frame, emrt_read_channels, ...); while batched, emrt_step on a
- * member returns EMRT_E_STATE.  The batch workspace (device, caller-owned,
+ * member returns EMRT_E_STATE.  emrt_batch_destroy gives every member back
+ * the stream it had when the batch was created.  The batch workspace (device, caller-owned,
  * from emrt_batch_workspace_size) holds the per-level bounce arguments and
  * the chunk tables. */
 typedef struct emrt_batch emrt_batch;

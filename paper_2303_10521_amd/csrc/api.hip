@@ -1313,6 +1313,7 @@ int32_t emrt_last_error(emrt_ctx* c, char* buf, size_t len) {
 // and replayed.  Results are those of stepping each context alone.
 struct emrt_batch {
     std::vector<emrt_ctx*> ctx;
+    std::vector<hipStream_t> own_stream;  // each member's stream before the batch took it over
     int kmax = 0;
     hipStream_t stream = nullptr;
     std::vector<hipStream_t> side;
@@ -1418,6 +1419,7 @@ int32_t emrt_batch_create(emrt_ctx* const* ctxs, int32_t n, emrt_batch** out) {
                 return EMRT_E_INVALID;
             }
         b->ctx.push_back(c);
+        b->own_stream.push_back(c->stream);
         b->kmax = std::max(b->kmax, c->K);
     }
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
@@ -1442,7 +1444,12 @@ int32_t emrt_batch_destroy(emrt_batch* b) {
     for (auto s : b->side) (void)hipStreamDestroy(s);
     for (auto e : b->join) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
-    for (auto c : b->ctx) c->batched = false;
+    // members go back to their own streams: the batch stream belongs to the
+    // batch's caller and may be destroyed with it
+    for (size_t i = 0; i < b->ctx.size(); i++) {
+        b->ctx[i]->batched = false;
+        b->ctx[i]->stream = b->own_stream[i];
+    }
     delete b;
     return EMRT_OK;
 }

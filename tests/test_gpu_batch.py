@@ -126,6 +126,47 @@ def test_batch_rules_and_autotune(tmp_path):
         t.close()
 
 
+def test_members_step_alone_and_rebatch_after_close():
+    """A closed batch gives its members their own streams back: each steps
+    alone again with the results of a never-batched context, and the same
+    members form a new batch (the first batch's stream is gone by then)."""
+    import gc
+
+    from paper_2303_10521_amd import Batch
+
+    ws = [city.batch_city(i) for i in CITIES[:3]]
+    members = [_tracer(w) for w in ws]
+    solo = [_tracer(w) for w in ws]
+    for w, t, s in zip(ws, members, solo):
+        fr = w.scene.frame(0.0)
+        t.set_frame(fr)
+        s.set_frame(fr)
+    b1 = Batch(members, n_streams=2)
+    b1.step(True)
+    assert b1.sync() == 0
+    for s in solo:
+        s.step(True)
+    b1.close()
+    del b1
+    gc.collect()  # the first batch's stream is released
+    for w, t, s in zip(ws, members, solo):
+        fr = w.scene.frame(w.frame_dt)
+        t.set_frame(fr, 1)
+        s.set_frame(fr, 1)
+        t.step(True)
+        s.step(True)
+        assert t.sync() == 0 and s.sync() == 0
+        _equal(_snapshot(s), _snapshot(t))
+    b2 = Batch(members, n_streams=4, chunk=32)
+    for w, t in zip(ws, members):
+        t.set_frame(w.scene.frame(2 * w.frame_dt), 2)
+    b2.step(True)
+    assert b2.sync() == 0
+    b2.close()
+    for t in members + solo:
+        t.close()
+
+
 def _oracle_check_member(w, tr, fr, n_pick=300, n_links=120, seed=0):
     """Sampled paths and per-link sums of one batch member against the oracle."""
     sc = w.scene
