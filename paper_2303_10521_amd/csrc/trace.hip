@@ -292,6 +292,11 @@ __device__ __forceinline__ void flush_stats(unsigned long long* stats, int lane,
 // stacks live in LDS (one column per thread).  (Holding it to six waves per
 // SIMD with an 80-VGPR cap ran 1.5% faster but spilled 20 bytes per lane; it
 // stays at the compiler's 85.)
+#ifndef EMRT_BOUNCE_CHUNK
+#define EMRT_BOUNCE_CHUNK 128
+#endif
+constexpr int kBounceChunk = EMRT_BOUNCE_CHUNK;  // rays per fetch from the launch's counter (a multiple of 64)
+
 template <bool STATS, bool REV>
 __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     __shared__ int stk_lds[kStackRows][kStackStride];
@@ -301,13 +306,16 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0, s_box4 = 0;
     // the first chunk of every wave is its own index (all waves start at
     // once, and a burst of atomics on one counter would serialise them); the
-    // later ones come from the counter, after the grid's first chunks
+    // later ones come from the counter, after the grid's first chunks.  A
+    // chunk is kBounceChunk rays, traced 64 at a time.
     const unsigned int n_waves = (gridDim.x * blockDim.x) >> 6;
     unsigned int chunk = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     while (true) {
-        unsigned long long base = (unsigned long long)chunk * 64ULL;
+        unsigned long long base = (unsigned long long)chunk * (unsigned long long)kBounceChunk;
         if (base >= n_in) break;
-        bounce_chunk<STATS, REV>(a, n_in, base, lane, s_nodes, s_tris, s_seg, s_cap, s_box4, &stk);
+        for (int j = 0; j < kBounceChunk; j += 64)
+            bounce_chunk<STATS, REV>(a, n_in, base + (unsigned long long)j, lane, s_nodes, s_tris, s_seg, s_cap, s_box4,
+                                     &stk);
         unsigned int next = 0;
         if (lane == 0) next = atomicAdd(a.work, 1u);
         chunk = n_waves + (unsigned int)__shfl((int)next, 0);
