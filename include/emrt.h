@@ -139,7 +139,8 @@ typedef struct emrt_scene_desc {
     const double* material_eps;    /* host [n_materials][2] relative permittivity (re, im) */
 } emrt_scene_desc;
 /* Upload and preprocess a scene: index checks, face planes and triangle lists,
- * wedge edges, the static LBVH.  Synchronises.  Errors: EMRT_E_INVALID
+ * wedge edges, the trees over the static triangles and the static objects'
+ * wedge edges (binned SAH, built once per scene).  Synchronises.  Errors: EMRT_E_INVALID
  * (sizes differ from the workspace's, index out of range, degenerate or
  * non-finite triangle), EMRT_E_STATE (no workspace). */
 int32_t emrt_set_scene(emrt_ctx* ctx, const emrt_scene_desc* scene);

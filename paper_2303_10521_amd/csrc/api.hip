@@ -103,7 +103,7 @@ struct emrt_ctx {
     int K = 0, nf = 1, e_words = 1, E_cap = 0;
 
     SceneDev S{};
-    Tree st, dy, rxt, edt;
+    Tree st, dy, rxt, ets, etd;
     TriP *st_prims = nullptr, *dy_prims = nullptr;
     QNode4* st4 = nullptr;     // [T] the static tree as 4-wide quantised nodes
     int st4_n = 0;
@@ -210,10 +210,12 @@ static void layout(emrt_ctx* c, Carver& cv) {
     S.tris_dynamic = cv.take<int>(T);
     S.edge_i = cv.take<int>(2 * 6 * (long long)c->E_cap);
     S.edge_n = cv.take<double>(2 * (long long)c->E_cap);
+    S.edges_static = cv.take<int>(c->E_cap);
+    S.edges_dynamic = cv.take<int>(c->E_cap);
     c->obj_dyn = cv.take<uint8_t>(O);
     c->obj_off = cv.take<int>(O + 1);
     c->obj_faces = cv.take<int>(F);
-    long long big = std::max(std::max(T, O), F);
+    long long big = std::max(std::max(std::max(T, O), F), (long long)c->E_cap);
     c->scene_scratch = cv.take<uint32_t>(3 * big + 16 + (long long)scan_temp_bytes(big) / 4 + 64);
     // trees: worst case every triangle in one tree
     auto tree = [&](Tree& t, long long n) {
@@ -228,7 +230,8 @@ static void layout(emrt_ctx* c, Carver& cv) {
     tree(c->st, T);
     tree(c->dy, T);
     tree(c->rxt, z.n_rx);
-    tree(c->edt, c->E_cap);
+    tree(c->ets, c->E_cap);
+    tree(c->etd, c->E_cap);
     tree(c->txt, z.n_tx);
     c->st4 = cv.take<QNode4>(T);
     c->st_prims = cv.take<TriP>(T);
@@ -627,8 +630,8 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     S.T_d = S.T - S.T_s;
     int E = scene_edges(S, c->obj_off, c->obj_faces, counts + 4, c->tmp, st);
     if (E < 0) return fail(c, EMRT_E_UNSUPPORTED, "too many wedge edges");
-    // edges on dynamic objects
-    S.E_dyn = 0;
+    // edges of static objects in a tree built once (below), those of moving ones per frame
+    if (edge_partition(S, c->scene_scratch, counts + 6, st) < 0) return fail(c, EMRT_E_HIP, "edge partition");
     // static tree (world == local for static vertices)
     scene_planes(S, st);
     tri_boxes(S, S.tris_static, S.T_s, c->box_st, st);
@@ -645,6 +648,14 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
         HC(hipMemcpyAsync(c->st4, h4.data(), sizeof(QNode4) * (size_t)n4, hipMemcpyHostToDevice, st));
         HC(hipStreamSynchronize(st));  // h4 is a host temporary
         c->st4_n = n4;
+    }
+    // static edges: binned SAH once per scene (the tree the reception cones of
+    // every primary ray walk), their primitives at the front of edge_prims
+    c->ets.n = 0;
+    if (S.E_s > 0) {
+        edge_boxes(S, S.edges_static, S.E_s, c->box_ed, st);
+        if (bvh_build_sah(c->box_ed, S.E_s, c->ets, c->tmp, st) < 0) return fail(c, EMRT_E_HIP, "static edge tree build");
+        edge_prims(S, S.edges_static, c->ets, c->edge_prims, st);
     }
     c->st_area = 0.0;
     if (S.T_s > 1) {  // tree quality: child box areas over the root box area
@@ -749,7 +760,7 @@ static PathArgs path_args(emrt_ctx* c) {
     a.f.tx_pos = c->f_tx; a.f.tx_vel = c->f_txv; a.f.tx_orient = c->f_txo;
     a.f.rx_pos = c->f_rx; a.f.rx_vel = c->f_rxv; a.f.obj_vel = c->f_ov;
     a.st = c->st.view(); a.dy = c->dy.view();
-    a.st4 = Bvh4{c->st4, c->S.T_s};
+    a.st4 = Bvh4{c->st4, c->S.T_s, c->st4_n};
     a.st_prims = c->st_prims; a.dy_prims = c->dy_prims;
     a.fc.mat_eps = c->mat;
     a.fc.mat_refl = c->refl;
@@ -802,7 +813,7 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.n_total = launch_total(c);
     b.rays_per_tx = rays;
     b.st = Bvh{c->st.nodes, S.T_s};
-    b.st4 = Bvh4{c->st4, S.T_s};
+    b.st4 = Bvh4{c->st4, S.T_s, c->st4_n};
     b.dy = Bvh{c->dy.nodes, S.T_d};
     b.st_prims = c->st_prims;
     b.dy_prims = c->dy_prims;
@@ -813,8 +824,10 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.diffraction = diff ? c->cfg.diffraction : 0;
     b.pairs = c->pairs;
     b.pair_mask = c->pair_slots ? (unsigned long long)c->pair_slots - 1ULL : 0ULL;
-    b.edt = Bvh{c->edt.nodes, diff ? S.E : 0};
-    b.edge_prims = c->edge_prims;
+    b.ets = Bvh{c->ets.nodes, diff ? S.E_s : 0};
+    b.etd = Bvh{c->etd.nodes, diff ? S.E_dyn : 0};
+    b.eprims_s = c->edge_prims;
+    b.eprims_d = c->edge_prims + 2LL * S.E_s;
     b.illum = c->illum;
     b.e_words = c->e_words;
     b.table = c->table;
@@ -879,16 +892,16 @@ static void step_pre(emrt_ctx* c, int discover) {
         rx_boxes(c->f_tx, c->sz.n_tx, c->box_tx, st);
         jobs[nj++] = BuildJob{c->box_tx, c->sz.n_tx, &c->txt};
     }
-    if (diff && discover) {
-        edge_boxes(S, c->box_ed, st);
-        jobs[nj++] = BuildJob{c->box_ed, S.E, &c->edt};
+    if (diff && discover && S.E_dyn > 0) {
+        edge_boxes(S, S.edges_dynamic, S.E_dyn, c->box_ed, st);
+        jobs[nj++] = BuildJob{c->box_ed, S.E_dyn, &c->etd};
     }
     bvh_build_many(jobs, nj, c->tmp, st);  // the frame's rebuilt trees, in one batch
     if (S.T_d > 0 && !build_dy) bvh_refit(c->box_dy, c->dy, st);
     if (S.T_d > 0) tri_prims(S, S.tris_dynamic, c->dy, c->dy_prims, st);
     if (discover && !rev) rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
     if (rev) rx_prims(c->f_tx, c->txt, c->tx_prims, st);
-    if (diff && discover) edge_prims(S, c->edt, c->edge_prims, st);
+    if (diff && discover && S.E_dyn > 0) edge_prims(S, S.edges_dynamic, c->etd, c->edge_prims + 2LL * S.E_s, st);
     if (discover) {
         KeySrc src = key_src(c, c->cache[c->cur]);
         const unsigned long long mask = (unsigned long long)c->table_slots - 1ULL;

@@ -16,6 +16,7 @@
 // child boxes and continues, so every node is written exactly once per refit.
 // Paper: Section II-A (a BVH updated between frames), Section III-A (only
 // subtrees change within a trajectory segment).
+#include <deque>
 #include <math.h>
 #include <string.h>
 
@@ -653,7 +654,9 @@ void bvh_sah(const Tree& tree, double* out, hipStream_t st) {
 // child's low bound, the high byte the smallest at or above its high bound,
 // evaluated with the same fma the traversal uses, so the decoded boxes
 // contain the children's boxes exactly.  A node's children get consecutive
-// indices, before the subtrees below them.
+// indices, before the subtrees below them.  The nodes of the top
+// kBvh4TopLevels levels are numbered breadth first (so the tree's top is an
+// index prefix, which the traversal keeps in LDS), the rest depth first.
 namespace {
 struct HBox {
     float lo[3], hi[3];
@@ -729,12 +732,20 @@ struct Ent {
 
 int bvh4_collapse(const BNode* bin, int n_prims, QNode4* out, int cap) {
     if (n_prims <= 0 || cap < 1) return 0;
-    std::vector<std::pair<int, int>> work;  // (binary node, 4-wide slot)
+    struct Work {
+        int nid, slot, depth;  // binary node, 4-wide slot, depth of the 4-wide node
+    };
+    std::deque<Work> work;
     int n_out = 1;
-    work.push_back({0, 0});
+    work.push_back({0, 0, 0});
     while (!work.empty()) {
-        const int nid = work.back().first, oi = work.back().second;
-        work.pop_back();
+        // breadth first while the oldest entry is above the staged depth
+        // (then every entry left is at that depth), depth first below
+        const bool bfs = work.front().depth < kBvh4TopLevels;
+        const Work w = bfs ? work.front() : work.back();
+        if (bfs) work.pop_front();
+        else work.pop_back();
+        const int nid = w.nid, oi = w.slot;
         Ent ch[4];
         int n = 0;
         for (int side = 0; side < 2; side++) {
@@ -779,7 +790,7 @@ int bvh4_collapse(const BNode* bin, int n_prims, QNode4* out, int cap) {
             if (ch[k].ref >= 0) {  // an internal child becomes the next 4-wide slot
                 if (n_out >= cap) return -1;
                 c[k] = n_out;
-                work.push_back({ch[k].ref, n_out++});
+                work.push_back({ch[k].ref, n_out++, w.depth + 1});
             } else {
                 c[k] = ch[k].ref;
             }

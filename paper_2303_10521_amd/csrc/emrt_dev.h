@@ -80,7 +80,21 @@ struct __attribute__((aligned(16))) QNode4 {
 struct Bvh4 {
     const QNode4* nodes;
     int n_prims;  // 0: empty tree
+    int n_nodes;
 };
+
+// Depth of the 4-wide tree's top that the builder numbers breadth first
+// (levels 0 .. kBvh4TopLevels, at most 85 nodes) and the bounce kernel keeps
+// in LDS: every ray starts at the root, so these nodes are read by every
+// query, and from LDS their loads do not wait on the cache hierarchy.
+#ifndef EMRT_TOP4_LEVELS
+#define EMRT_TOP4_LEVELS 3
+#endif
+constexpr int kBvh4TopLevels = EMRT_TOP4_LEVELS;
+#ifndef EMRT_TOP4
+#define EMRT_TOP4 85
+#endif
+constexpr int kTop4 = EMRT_TOP4;  // nodes staged (1 + 4 + 16 + 64 = 85)
 
 // --------------------------------------------------------------------------
 // float / double vectors
@@ -736,15 +750,19 @@ __device__ __forceinline__ void cx4(float& ta, int& ca, float& tb, int& cb) {
 // binary tree `bin` with the generic traversal (same result).
 // STATS: n_boxes counts the child boxes tested (a node's children), n_nodes
 // the binary nodes of a fallback traversal.
+// top: copies of the nodes [0, n_top) (in LDS), read in place of bvh.nodes.
 template <bool STATS, class Stk>
 __device__ __forceinline__ void closest_hit4(const Bvh4& bvh, const Bvh& bin, const TriP* prims, const RayPre& r,
                                              int skip_face, float& best_t, int& best_tri, int& best_face,
-                                             unsigned& n_boxes, unsigned& n_nodes, unsigned& n_tris, Stk* stk) {
+                                             unsigned& n_boxes, unsigned& n_nodes, unsigned& n_tris, Stk* stk,
+                                             const QNode4* top = nullptr, int n_top = 0) {
     if (bvh.n_prims <= 0) return;
     int sp = 0, cur = 0;
     bool overflow = false;
     while (true) {
-        const QNode4 nd = bvh.nodes[cur];
+        QNode4 nd;
+        if (cur < n_top) nd = top[cur];
+        else nd = bvh.nodes[cur];
         const uint32_t meta = __float_as_uint(nd.o.w);
         const int cnt = (int)(meta >> 24);
         if (STATS) n_boxes += (unsigned)cnt;
@@ -756,12 +774,16 @@ __device__ __forceinline__ void closest_hit4(const Bvh4& bvh, const Bvh& bin, co
         const bool h2 = child4<2>(nd, pl, sx, sy, sz, r, best_t, t2) && cnt > 2;
         const bool h3 = child4<3>(nd, pl, sx, sy, sz, r, best_t, t3) && cnt > 3;
         int c0 = nd.c.x, c1 = nd.c.y, c2 = nd.c.z, c3 = nd.c.w;
-        const bool f0 = h0 && c0 < 0, f1 = h1 && c1 < 0, f2 = h2 && c2 < 0, f3 = h3 && c3 < 0;
-        if (f0 || f1 || f2 || f3) {
-            if (f0) leaf_closest<STATS>(prims, c0, r, skip_face, best_t, best_tri, best_face, n_tris);
-            if (f1) leaf_closest<STATS>(prims, c1, r, skip_face, best_t, best_tri, best_face, n_tris);
-            if (f2) leaf_closest<STATS>(prims, c2, r, skip_face, best_t, best_tri, best_face, n_tris);
-            if (f3) leaf_closest<STATS>(prims, c3, r, skip_face, best_t, best_tri, best_face, n_tris);
+        // the leaf children the ray meets, tested one per pass of a loop over
+        // this lane's own set: the wave runs the triangle test as many times
+        // as its busiest lane needs, not once per child slot any lane needs
+        unsigned lm = (h0 && c0 < 0 ? 1u : 0u) | (h1 && c1 < 0 ? 2u : 0u) | (h2 && c2 < 0 ? 4u : 0u) |
+                      (h3 && c3 < 0 ? 8u : 0u);
+#pragma unroll 1
+        for (; lm; lm &= lm - 1u) {
+            const int k = __builtin_ctz(lm);
+            const int ck = k == 0 ? c0 : (k == 1 ? c1 : (k == 2 ? c2 : c3));
+            leaf_closest<STATS>(prims, ck, r, skip_face, best_t, best_tri, best_face, n_tris);
         }
         // internal children met by the ray, by entry distance (others at +inf)
         t0 = (h0 && c0 >= 0) ? t0 : INFINITY;
@@ -810,14 +832,17 @@ __device__ __forceinline__ bool any_hit4(const Bvh4& bvh, const Bvh& bin, const 
         const int cs[4] = {nd.c.x, nd.c.y, nd.c.z, nd.c.w};
         const bool hs[4] = {h0, h1, h2, h3};
         bool found = false;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if (hs[k] && cs[k] < 0) {
-                TriP p = prims[(int)((uint32_t)cs[k] & ~EMRT_LEAF)];
-                const int face = __float_as_int(p.v1.w);
-                float t;
-                if (face != xa && face != xb && face != xc && tri_hit(p, r, t) && t < tmax) found = true;
-            }
+        // leaf children met, one per pass over this lane's own set (as in closest_hit4)
+        unsigned lm = (h0 && cs[0] < 0 ? 1u : 0u) | (h1 && cs[1] < 0 ? 2u : 0u) | (h2 && cs[2] < 0 ? 4u : 0u) |
+                      (h3 && cs[3] < 0 ? 8u : 0u);
+#pragma unroll 1
+        for (; lm; lm &= lm - 1u) {
+            const int k = __builtin_ctz(lm);
+            const int ck = k == 0 ? cs[0] : (k == 1 ? cs[1] : (k == 2 ? cs[2] : cs[3]));
+            TriP p = prims[(int)((uint32_t)ck & ~EMRT_LEAF)];
+            const int face = __float_as_int(p.v1.w);
+            float t;
+            if (face != xa && face != xb && face != xc && tri_hit(p, r, t) && t < tmax) found = true;
         }
         if (found) return true;
         int next = -1;

@@ -92,7 +92,9 @@ struct SceneDev {
     int E, E_cap;
     int* edge_i;                // [E][6] va, vb, f0, fn, w0, wn
     double* edge_n;             // [E]
-    int E_dyn;                  // edges on dynamic objects
+    int* edges_static;          // [E_s] ids of the edges of static objects, in edge order
+    int* edges_dynamic;         // [E_dyn] ids of the edges of moving objects, in edge order
+    int E_s, E_dyn;
 };
 
 // validate indices; returns flags via device word
@@ -106,8 +108,15 @@ void scene_planes(const SceneDev& s, hipStream_t st);
 void scene_face_tv(const SceneDev& s, hipStream_t st);
 void tri_boxes(const SceneDev& s, const int* list, int n, float* box6, hipStream_t st);
 void tri_prims(const SceneDev& s, const int* list, const Tree& tree, TriP* prims, hipStream_t st);
-void edge_boxes(const SceneDev& s, float* box6, hipStream_t st);
-void edge_prims(const SceneDev& s, const Tree& tree, float4* prims, hipStream_t st);
+void edge_boxes(const SceneDev& s, const int* list, int n, float* box6, hipStream_t st);
+// Splits the wedge edges into those of static and of moving objects
+// (s.edges_static / s.edges_dynamic, s.E_s / s.E_dyn).  scratch: 2 E + 16
+// u32 and a scan temp of E; count_dev: one device int.  Returns E_s, or -1 on
+// a HIP error (synchronises the stream).
+int edge_partition(SceneDev& s, uint32_t* scratch, int* count_dev, hipStream_t st);
+// boxes / leaf primitives of the edges list[0, n) (prims by the tree's leaf
+// order; each primitive carries its edge id)
+void edge_prims(const SceneDev& s, const int* list, const Tree& tree, float4* prims, hipStream_t st);
 void rx_boxes(const double* rx_pos, int n_rx, float* box6, hipStream_t st);
 void rx_prims(const double* rx_pos, const Tree& tree, float4* prims, hipStream_t st);
 
@@ -139,8 +148,8 @@ struct BounceArgs {
     float4 rx_root_lo, rx_root_hi;  // unused when the tree is read on device
     // edges
     int diffraction;
-    Bvh edt;
-    const float4* edge_prims;  // [E][2]
+    Bvh ets, etd;                               // edges of static objects (built once) and of moving ones
+    const float4 *eprims_s, *eprims_d;          // their leaf primitives, [E_s][2] and [E_dyn][2]
     uint32_t* illum;           // [N_tx][E_words]
     int e_words;
     unsigned long long* pairs; // (source, face, edge) lit by second segments (diffraction = 2)

@@ -409,24 +409,50 @@ void tri_prims(const SceneDev& s, const int* list, const Tree& tree, TriP* prims
                            s.tri_face, s.verts, prims);
 }
 
-__global__ void k_edge_boxes(int E, const int* rows, const float* verts, float* box) {
-    GRID_STRIDE(e, (long long)E) {
+__global__ void k_edge_static(int E, const int* rows, const int* face_dyn, uint32_t* is_static) {
+    GRID_STRIDE(e, (long long)E) is_static[e] = face_dyn[rows[6 * e + 2]] < 0 ? 1u : 0u;
+}
+
+int edge_partition(SceneDev& s, uint32_t* scratch, int* count_dev, hipStream_t st) {
+    s.E_s = 0;
+    s.E_dyn = 0;
+    if (s.E <= 0) return 0;
+    uint32_t* flag = scratch;
+    uint32_t* pos = flag + s.E;
+    uint32_t* stemp = pos + s.E + 16;
+    hipLaunchKernelGGL(k_edge_static, dim3(grid_for(s.E)), dim3(256), 0, st, s.E, s.edge_i, s.face_dyn, flag);
+    exclusive_scan(flag, pos, s.E, stemp, (uint32_t*)count_dev, st);
+    hipLaunchKernelGGL(k_partition, dim3(grid_for(s.E)), dim3(256), 0, st, s.E, flag, pos, s.edges_static,
+                       s.edges_dynamic);
+    int n = 0;
+    hipError_t err = hipMemcpyAsync(&n, count_dev, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return -1;
+    s.E_s = n;
+    s.E_dyn = s.E - n;
+    return n;
+}
+
+__global__ void k_edge_boxes(int n, const int* list, const int* rows, const float* verts, float* box) {
+    GRID_STRIDE(i, (long long)n) {
+        const int e = list[i];
         const float* a = verts + 3 * rows[6 * e];
         const float* b = verts + 3 * rows[6 * e + 1];
-        for (int i = 0; i < 3; i++) {
-            box[6 * e + i] = fminf(a[i], b[i]);
-            box[6 * e + 3 + i] = fmaxf(a[i], b[i]);
+        for (int k = 0; k < 3; k++) {
+            box[6 * i + k] = fminf(a[k], b[k]);
+            box[6 * i + 3 + k] = fmaxf(a[k], b[k]);
         }
     }
 }
 
-void edge_boxes(const SceneDev& s, float* box6, hipStream_t st) {
-    if (s.E > 0) hipLaunchKernelGGL(k_edge_boxes, dim3(grid_for(s.E)), dim3(256), 0, st, s.E, s.edge_i, s.verts, box6);
+void edge_boxes(const SceneDev& s, const int* list, int n, float* box6, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_edge_boxes, dim3(grid_for(n)), dim3(256), 0, st, n, list, s.edge_i, s.verts, box6);
 }
 
-__global__ void k_edge_prims(const uint32_t* perm, int n, const int* rows, const float* verts, float4* prims) {
+__global__ void k_edge_prims(const int* list, const uint32_t* perm, int n, const int* rows, const float* verts,
+                             float4* prims) {
     GRID_STRIDE(sl, (long long)n) {
-        int e = (int)perm[sl];
+        const int e = list[perm[sl]];
         const float* a = verts + 3 * rows[6 * e];
         const float* b = verts + 3 * rows[6 * e + 1];
         prims[2 * sl] = make_float4(a[0], a[1], a[2], __int_as_float(e));
@@ -434,9 +460,9 @@ __global__ void k_edge_prims(const uint32_t* perm, int n, const int* rows, const
     }
 }
 
-void edge_prims(const SceneDev& s, const Tree& tree, float4* prims, hipStream_t st) {
+void edge_prims(const SceneDev& s, const int* list, const Tree& tree, float4* prims, hipStream_t st) {
     if (tree.n > 0)
-        hipLaunchKernelGGL(k_edge_prims, dim3(grid_for(tree.n)), dim3(256), 0, st, tree.perm, tree.n, s.edge_i,
+        hipLaunchKernelGGL(k_edge_prims, dim3(grid_for(tree.n)), dim3(256), 0, st, list, tree.perm, tree.n, s.edge_i,
                            s.verts, prims);
 }
 

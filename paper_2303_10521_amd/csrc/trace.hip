@@ -137,7 +137,8 @@ __device__ __forceinline__ void debug_log(const BounceArgs& a, uint32_t id, int 
 template <bool STATS, bool REV>
 __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long long n_in, unsigned long long base,
                                              int lane, unsigned& s_nodes, unsigned& s_tris, unsigned& s_seg,
-                                             unsigned& s_cap, unsigned& s_box4, LdsStack* stk, int width = 64) {
+                                             unsigned& s_cap, unsigned& s_box4, LdsStack* stk, int width = 64,
+                                             const QNode4* top = nullptr, int n_top = 0) {
     const int b = a.b;
     unsigned long long i = base + (unsigned long long)lane;
     bool act = lane < width && i < n_in;
@@ -163,7 +164,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
     if (act) {
         if (STATS) s_seg++;
         closest_hit4<STATS>(a.st4, a.st, a.st_prims, r, prev, best_t, best_tri, best_face, s_box4, s_nodes, s_tris,
-                            stk);
+                            stk, top, n_top);
         closest_hit<STATS>(a.dy, a.dy_prims, r, prev, best_t, best_tri, best_face, s_nodes, s_tris, stk);
     }
     bool hit = act && best_tri != 0x7FFFFFFF;
@@ -211,14 +212,14 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
     }
 
     // edge capture on the first segment (and, for reflection-diffraction
-    // paths, on the second): radius k_rx alpha (L + s) as for receivers
-    if (act && (b == 0 || (b == 1 && a.diffraction == 2)) && a.diffraction && a.edt.n_prims > 0) {
-        float tcap = fminf(t_end, root_far(a.edt, ox, oy, oz));
-        float grow = a.alpha_k * (L + tcap);
+    // paths, on the second): radius k_rx alpha (L + s) as for receivers.  The
+    // edges of static objects and of moving ones sit in two trees.
+    if (act && (b == 0 || (b == 1 && a.diffraction == 2)) && a.diffraction &&
+        (a.ets.n_prims > 0 || a.etd.n_prims > 0)) {
         const int source = (int)(id / (uint32_t)a.rays_per_tx);  // row of the illumination bitmap
         const int face1 = b == 1 ? a.src.tri_face[a.hitlog[id]] : -1;  // face of the first reflection
-        all_hits(a.edt, r, tcap, grow, [&](int slot) {
-            float4 P0 = a.edge_prims[2 * slot], P1 = a.edge_prims[2 * slot + 1];
+        auto edge_leaf = [&](const float4* prims, int slot) {
+            float4 P0 = prims[2 * slot], P1 = prims[2 * slot + 1];
             float ex = P1.x - P0.x, ey = P1.y - P0.y, ez = P1.z - P0.z;
             float wx = ox - P0.x, wy = oy - P0.y, wz = oz - P0.z;
             float aa = dx * dx + dy * dy + dz * dz;
@@ -245,7 +246,15 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
             } else if (!pair_insert(a.pairs, a.pair_mask, pair_key(source, face1, e))) {
                 atomicOr(a.flags, FLAG_CAND_CAP);
             }
-        }, stk);
+        };
+        if (a.ets.n_prims > 0) {
+            const float tcap = fminf(t_end, root_far(a.ets, ox, oy, oz));
+            all_hits(a.ets, r, tcap, a.alpha_k * (L + tcap), [&](int slot) { edge_leaf(a.eprims_s, slot); }, stk);
+        }
+        if (a.etd.n_prims > 0) {
+            const float tcap = fminf(t_end, root_far(a.etd, ox, oy, oz));
+            all_hits(a.etd, r, tcap, a.alpha_k * (L + tcap), [&](int slot) { edge_leaf(a.eprims_d, slot); }, stk);
+        }
     }
 
     // specular reflection about the face plane
@@ -300,9 +309,14 @@ constexpr int kBounceChunk = EMRT_BOUNCE_CHUNK;  // rays per fetch from the laun
 template <bool STATS, bool REV>
 __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
     __shared__ int stk_lds[kStackRows][kStackStride];
+    __shared__ QNode4 top[kTop4 > 0 ? kTop4 : 1];
     LdsStack stk{&stk_lds[0][threadIdx.x]};
     const int lane = lane_id();
     const unsigned long long n_in = *a.n_in;
+    // the static tree's top levels, one copy per block
+    const int n_top = kTop4 < a.st4.n_nodes ? kTop4 : a.st4.n_nodes;
+    for (int k = threadIdx.x; k < n_top; k += blockDim.x) top[k] = a.st4.nodes[k];
+    __syncthreads();
     unsigned s_nodes = 0, s_tris = 0, s_seg = 0, s_cap = 0, s_box4 = 0;
     // the first chunk of every wave is its own index (all waves start at
     // once, and a burst of atomics on one counter would serialise them); the
@@ -315,7 +329,7 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
         if (base >= n_in) break;
         for (int j = 0; j < kBounceChunk; j += 64)
             bounce_chunk<STATS, REV>(a, n_in, base + (unsigned long long)j, lane, s_nodes, s_tris, s_seg, s_cap, s_box4,
-                                     &stk);
+                                     &stk, 64, top, n_top);
         unsigned int next = 0;
         if (lane == 0) next = atomicAdd(a.work, 1u);
         chunk = n_waves + (unsigned int)__shfl((int)next, 0);
