@@ -592,7 +592,10 @@ __device__ __forceinline__ void leaf_closest(const TriP* prims, int child, const
     if (STATS) n_tris++;
     int face = __float_as_int(p.v1.w);
     float t;
-    if (face != skip_face && tri_hit(p, r, t)) {
+    // the test runs whatever the face (it has no side effects), so the whole
+    // primitive is fetched in one round trip instead of the face id first
+    const bool h = tri_hit(p, r, t);
+    if (h && face != skip_face) {
         int id = __float_as_int(p.v0.w);
         if (t < best_t || (t == best_t && id < best_tri)) { best_t = t; best_tri = id; best_face = face; }
     }
@@ -782,8 +785,8 @@ __device__ __forceinline__ void closest_hit4(const Bvh4& bvh, const Bvh& bin, co
 #pragma unroll 1
         for (; lm; lm &= lm - 1u) {
             const int k = __builtin_ctz(lm);
-            const int ck = k == 0 ? c0 : (k == 1 ? c1 : (k == 2 ? c2 : c3));
-            leaf_closest<STATS>(prims, ck, r, skip_face, best_t, best_tri, best_face, n_tris);
+            const int lo = (k & 1) ? c1 : c0, hi = (k & 1) ? c3 : c2;
+            leaf_closest<STATS>(prims, (k & 2) ? hi : lo, r, skip_face, best_t, best_tri, best_face, n_tris);
         }
         // internal children met by the ray, by entry distance (others at +inf)
         t0 = (h0 && c0 >= 0) ? t0 : INFINITY;
@@ -838,11 +841,12 @@ __device__ __forceinline__ bool any_hit4(const Bvh4& bvh, const Bvh& bin, const 
 #pragma unroll 1
         for (; lm; lm &= lm - 1u) {
             const int k = __builtin_ctz(lm);
-            const int ck = k == 0 ? cs[0] : (k == 1 ? cs[1] : (k == 2 ? cs[2] : cs[3]));
-            TriP p = prims[(int)((uint32_t)ck & ~EMRT_LEAF)];
+            const int lo = (k & 1) ? cs[1] : cs[0], hi = (k & 1) ? cs[3] : cs[2];
+            TriP p = prims[(int)((uint32_t)((k & 2) ? hi : lo) & ~EMRT_LEAF)];
             const int face = __float_as_int(p.v1.w);
             float t;
-            if (face != xa && face != xb && face != xc && tri_hit(p, r, t) && t < tmax) found = true;
+            const bool h = tri_hit(p, r, t);  // whatever the face: one fetch of the primitive
+            if (h && face != xa && face != xb && face != xc && t < tmax) found = true;
         }
         if (found) return true;
         int next = -1;
