@@ -79,10 +79,17 @@ typedef struct emrt_config {
     int64_t table_capacity;     /* path-table slots, rounded up to a power of two (default 4 x path_capacity) */
     int32_t adjoint_materials;  /* 0: no adjoint; else the most materials emrt_backward supports (<= 256);
                                    adds 8 (5 + 2 adjoint_materials) bytes per link to the workspace */
+    int32_t ray_regroup;        /* 1: the rays entering bounces 2..K are regrouped by origin cell and
+                                   direction octant (one counting sort per bounce), so a wave traces
+                                   neighbouring rays; 0 (default): they stay in the order the previous
+                                   bounce appended them.  Results are the same either way.  On the
+                                   2 x 2 km city the sorts cost more than the traversal gains (it is
+                                   a choice for scenes with longer ray paths); adds 2 bytes per
+                                   launched ray to the workspace */
 } emrt_config;
 
 /* Fill *cfg with the defaults above (one 28 GHz carrier, K = 3, no
- * diffraction, 10,000 rays per transmitter). */
+ * diffraction, 10,000 rays per transmitter, no regrouping between bounces). */
 void emrt_config_default(emrt_config* cfg);
 
 /* Sizes that fix the workspace layout. */

@@ -27,7 +27,7 @@ class Config(ctypes.Structure):
         ("n_freq", c_i32), ("freq_hz", c_f64 * 4), ("max_reflections", c_i32), ("diffraction", c_i32),
         ("rays_per_tx", c_i32), ("rx_sphere_k", c_f64), ("diff_max_leg_m", c_f64), ("tx_power_w", c_f64),
         ("antenna_mode", c_i32), ("path_cap_per_link", c_i32), ("path_capacity", c_i64), ("table_capacity", c_i64),
-        ("adjoint_materials", c_i32),
+        ("adjoint_materials", c_i32), ("ray_regroup", c_i32),
     ]
 
 

@@ -111,6 +111,14 @@ struct emrt_ctx {
     float *box_st = nullptr, *box_dy = nullptr, *box_rx = nullptr, *box_ed = nullptr;
     BuildTemp tmp{};
     RaySoA rays[2]{};
+    // regrouping between bounces: keys of the appended rays, the counting
+    // sort's temp, which buffer holds bounce k's input (k + ray_flip) & 1, and
+    // the key grid over the scene's x, y extent
+    uint16_t* ray_key = nullptr;
+    uint32_t* rg_temp = nullptr;
+    int ray_flip = 0;
+    bool regroup_now = false;
+    float key_ox = 0.0f, key_oy = 0.0f, key_sx = 0.0f, key_sy = 0.0f;
     int* hitlog = nullptr;
     uint8_t* depth = nullptr;  // [n_total] bounce at which each ray of the last discovery launch ended
     unsigned long long* fresh = nullptr;  // [P] transmitter-side diffraction keys, in the order made
@@ -255,6 +263,10 @@ static void layout(emrt_ctx* c, Carver& cv) {
         r.L = cv.take<float>(c->n_total);
         r.id = cv.take<uint32_t>(c->n_total);
         r.prev = cv.take<int>(c->n_total);
+    }
+    if (c->cfg.ray_regroup && c->K >= 2) {
+        c->ray_key = cv.take<uint16_t>(c->n_total);
+        c->rg_temp = cv.take<uint32_t>((long long)regroup_temp_u32(c->n_total));
     }
     c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
     c->depth = cv.take<uint8_t>(c->n_total);
@@ -407,6 +419,7 @@ void emrt_config_default(emrt_config* cfg) {
     cfg->path_cap_per_link = 64;
     cfg->path_capacity = 4LL << 20;
     cfg->table_capacity = 0;
+    cfg->ray_regroup = 0;
 }
 
 int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
@@ -417,7 +430,7 @@ int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
     if (cfg->rays_per_tx < 1 || !(cfg->rx_sphere_k > 0) || !(cfg->diff_max_leg_m >= 0) || cfg->path_capacity < 1 ||
         cfg->path_capacity > (1LL << 31) || cfg->antenna_mode < 0 || cfg->antenna_mode > 1 ||
         cfg->adjoint_materials < 0 || cfg->adjoint_materials > kMaxMaterials || cfg->diffraction < 0 ||
-        cfg->diffraction > 2)
+        cfg->diffraction > 2 || (cfg->ray_regroup != 0 && cfg->ray_regroup != 1))
         return EMRT_E_INVALID;
     // one reflection combined with one diffraction: the kernels below are
     // complete (k_pair_list, k_pair_cand, the combined construction and
@@ -649,6 +662,18 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
         HC(hipStreamSynchronize(st));  // h4 is a host temporary
         c->st4_n = n4;
     }
+    // regroup key grid: the static scene's x, y extent in 16 cells per axis
+    c->key_ox = c->key_oy = c->key_sx = c->key_sy = 0.0f;
+    if (S.T_s >= 2) {
+        BNode root;
+        if ((rc = sync_read(c, &root, c->st.nodes, sizeof(root)))) return rc;
+        const float lx = fminf(root.a.x, root.b.z), ly = fminf(root.a.y, root.b.w);
+        const float hx = fmaxf(root.a.w, root.c.y), hy = fmaxf(root.b.x, root.c.z);
+        c->key_ox = lx;
+        c->key_oy = ly;
+        c->key_sx = hx > lx ? 16.0f / (hx - lx) : 0.0f;
+        c->key_sy = hy > ly ? 16.0f / (hy - ly) : 0.0f;
+    }
     // static edges: binned SAH once per scene (the tree the reception cones of
     // every primary ray walk), their primitives at the front of edge_prims
     c->ets.n = 0;
@@ -811,6 +836,10 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     BounceArgs b{};
     b.K = c->K;
     b.n_total = launch_total(c);
+    if (c->regroup_now && c->ray_key && k >= 1 && k < c->K) {
+        b.out_key = c->ray_key;
+        b.key_ox = c->key_ox; b.key_oy = c->key_oy; b.key_sx = c->key_sx; b.key_sy = c->key_sy;
+    }
     b.rays_per_tx = rays;
     b.st = Bvh{c->st.nodes, S.T_s};
     b.st4 = Bvh4{c->st4, S.T_s, c->st4_n};
@@ -838,8 +867,8 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     b.flags = c->flags;
     b.stats = c->ctr + C_STATS;
     b.b = k;
-    b.in = c->rays[k & 1];
-    b.out = c->rays[(k + 1) & 1];
+    b.in = c->rays[(k + c->ray_flip) & 1];
+    b.out = c->rays[(k + 1 + c->ray_flip) & 1];
     b.n_in = c->ctr + C_RAYS + k;
     if (k == 0 && !rev) {
         b.gen_dirs = c->dirs;
@@ -924,11 +953,17 @@ static void step_pre(emrt_ctx* c, int discover) {
 static void step_bounces(emrt_ctx* c, bool fork_diff = false) {
     long long g = (launch_total(c) + 255) / 256;
     int grid = (int)std::min<long long>(std::max<long long>(g, 1), 2048);
+    c->ray_flip = 0;
+    c->regroup_now = true;
     for (int k = 0; k <= c->K; k++) {
         BounceArgs b = bounce_args(c, k, c->cur);
         ev_record(c);
         bounce(b, c->stats_on != 0, grid, c->stream);
         ev_record(c);
+        if (b.out_key) {  // the next bounce's rays, grouped by origin cell and direction
+            regroup(b.out, b.in, c->ray_key, c->ctr + C_RAYS + k + 1, c->n_total, c->rg_temp, c->stream);
+            c->ray_flip ^= 1;
+        }
         if (k == 0 && fork_diff) {
             // the edges lit by the first segments are known: candidates on the side stream
             HC(hipEventRecord(c->ev_fork, c->stream));
@@ -942,6 +977,8 @@ static void step_bounces(emrt_ctx* c, bool fork_diff = false) {
         }
     }
     c->evs[c->ev_parity].bounce_end = c->evs[c->ev_parity].used;
+    c->ray_flip = 0;
+    c->regroup_now = false;
 }
 
 static void step_post(emrt_ctx* c, int discover) {

@@ -131,6 +131,11 @@ struct BounceArgs {
     RaySoA in, out;
     const unsigned long long* n_in;
     unsigned long long* n_out;
+    // regroup key of every surviving ray (null: none): its origin's cell on a
+    // 16 x 16 grid over the scene's x, y extent (cell = (x - key_ox) key_sx)
+    // in Morton order, then its direction octant
+    uint16_t* out_key;
+    float key_ox, key_oy, key_sx, key_sy;
     unsigned int* work;
     int b, K;
     long long n_total;
@@ -181,6 +186,15 @@ void dir_table(const uint32_t* perm, int N, float4* dirs, hipStream_t st);
 void raygen(const double* src_pos, int n_src, int N, const uint32_t* perm, RaySoA out, unsigned long long* n_out,
             hipStream_t st);
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st);
+// Regrouping of the rays between bounces: constants and workspace.
+constexpr int kRegroupBins = 2048;  // 256 origin cells x 8 direction octants
+int regroup_blocks(long long n_total);
+size_t regroup_temp_u32(long long n_total);  // u32 of per-block histograms, their offsets and the scan temp
+// Rays [0, *n_dev) of src into dst, grouped by key (one counting sort: per-block
+// histograms in LDS, an exclusive scan, a scatter); within a key the blocks'
+// ranges keep their order.  temp: regroup_temp_u32(cap) u32.
+void regroup(const RaySoA& src, const RaySoA& dst, const uint16_t* key, const unsigned long long* n_dev, long long cap,
+             uint32_t* temp, hipStream_t st);
 // one launch over several scenes' live rays (args device [n_scenes]; chunk_off [n_scenes + 1], work: scratch)
 void bounce_multi(const BounceArgs* args, int n_scenes, uint32_t* chunk_off, uint32_t* work, int grid, int chunk,
                   hipStream_t st);

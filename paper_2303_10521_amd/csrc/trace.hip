@@ -120,6 +120,19 @@ __device__ __forceinline__ float root_far(const Bvh& t, float ox, float oy, floa
     return sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1.0f;
 }
 
+// Regroup key of a ray (BounceArgs::out_key): Morton order of its origin's
+// cell on a 16 x 16 grid, then the octant of its direction.
+__device__ __forceinline__ uint16_t regroup_key(const BounceArgs& a, float ox, float oy, float dx, float dy, float dz) {
+    const float fx = (ox - a.key_ox) * a.key_sx, fy = (oy - a.key_oy) * a.key_sy;
+    const uint32_t cx = fx > 0.0f ? (fx < 15.0f ? (uint32_t)fx : 15u) : 0u;
+    const uint32_t cy = fy > 0.0f ? (fy < 15.0f ? (uint32_t)fy : 15u) : 0u;
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) m |= ((cx >> k) & 1u) << (2 * k) | ((cy >> k) & 1u) << (2 * k + 1);
+    const uint32_t oct = (dx < 0.0f ? 1u : 0u) | (dy < 0.0f ? 2u : 0u) | (dz < 0.0f ? 4u : 0u);
+    return (uint16_t)((m << 3) | oct);
+}
+
 // capture of a marked ray into the debug log
 __device__ __forceinline__ void debug_log(const BounceArgs& a, uint32_t id, int b, int kind, int target) {
     if (!((a.dbg_sel[id >> 5] >> (id & 31)) & 1u)) return;
@@ -279,6 +292,7 @@ __device__ __forceinline__ void bounce_chunk(const BounceArgs& a, unsigned long 
         a.out.L[o] = L + best_t;
         a.out.id[o] = id;
         a.out.prev[o] = best_face;
+        if (a.out_key) a.out_key[o] = regroup_key(a, nox, noy, ndx, ndy, ndz);
     }
 }
 
@@ -335,6 +349,68 @@ __global__ void __launch_bounds__(256) k_bounce(BounceArgs a) {
         chunk = n_waves + (unsigned int)__shfl((int)next, 0);
     }
     flush_stats<STATS>(a.stats, lane, s_nodes, s_tris, s_seg, s_cap, s_box4);
+}
+
+// ------------------------------------------------- regroup between bounces ----
+// Block b of the histogram and scatter kernels owns the rays [b n / B, (b+1) n / B)
+// of the live buffer (B = gridDim.x, n read on the device).  Histogram rows are
+// bin-major ([bin][block]), so one exclusive scan gives every (bin, block) its
+// first output slot.
+int regroup_blocks(long long n_total) {
+    long long b = n_total / 4096;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+size_t regroup_temp_u32(long long n_total) {
+    const long long n = (long long)kRegroupBins * regroup_blocks(n_total);
+    return (size_t)(2 * n + 64) + scan_temp_bytes(n) / 4 + 64;
+}
+
+__device__ __forceinline__ void block_range(const unsigned long long* n_dev, long long& beg, long long& end) {
+    const long long n = (long long)*n_dev, nb = gridDim.x;
+    beg = n * (long long)blockIdx.x / nb;
+    end = n * ((long long)blockIdx.x + 1) / nb;
+}
+
+__global__ void __launch_bounds__(256) k_regroup_hist(const uint16_t* key, const unsigned long long* n_dev,
+                                                      uint32_t* hist) {
+    __shared__ uint32_t h[kRegroupBins];
+    for (int k = threadIdx.x; k < kRegroupBins; k += blockDim.x) h[k] = 0u;
+    __syncthreads();
+    long long beg, end;
+    block_range(n_dev, beg, end);
+    for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&h[key[i]], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kRegroupBins; k += blockDim.x) hist[(long long)k * gridDim.x + blockIdx.x] = h[k];
+}
+
+__global__ void __launch_bounds__(256) k_regroup_scatter(RaySoA src, RaySoA dst, const uint16_t* key,
+                                                         const unsigned long long* n_dev, const uint32_t* off) {
+    __shared__ uint32_t cur[kRegroupBins];
+    for (int k = threadIdx.x; k < kRegroupBins; k += blockDim.x) cur[k] = off[(long long)k * gridDim.x + blockIdx.x];
+    __syncthreads();
+    long long beg, end;
+    block_range(n_dev, beg, end);
+    for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const long long o = atomicAdd(&cur[key[i]], 1u);
+        dst.ox[o] = src.ox[i]; dst.oy[o] = src.oy[i]; dst.oz[o] = src.oz[i];
+        dst.dx[o] = src.dx[i]; dst.dy[o] = src.dy[i]; dst.dz[o] = src.dz[i];
+        dst.L[o] = src.L[i];
+        dst.id[o] = src.id[i];
+        dst.prev[o] = src.prev[i];
+    }
+}
+
+void regroup(const RaySoA& src, const RaySoA& dst, const uint16_t* key, const unsigned long long* n_dev, long long cap,
+             uint32_t* temp, hipStream_t st) {
+    const int nb = regroup_blocks(cap);
+    const long long n = (long long)kRegroupBins * nb;
+    uint32_t* hist = temp;
+    uint32_t* off = hist + n;
+    uint32_t* stemp = off + n + 64;
+    hipLaunchKernelGGL(k_regroup_hist, dim3(nb), dim3(256), 0, st, key, n_dev, hist);
+    exclusive_scan(hist, off, n, stemp, nullptr, st);
+    hipLaunchKernelGGL(k_regroup_scatter, dim3(nb), dim3(256), 0, st, src, dst, key, n_dev, off);
 }
 
 void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {

@@ -305,7 +305,9 @@ CITY_STRIDE = 7919  # every 7919th launch direction of every transmitter: 16 x 1
 def city_run():
     w = city.workload("city")
     sc = w.scene
-    tr = _tracer(sc, w, path_capacity=1 << 23)
+    # rays regrouped between bounces (ray_regroup = 1): the full-size frame checks
+    # that path against the oracle, the other tests run the default append order
+    tr = _tracer(sc, w, path_capacity=1 << 23, ray_regroup=1)
     fr = sc.frame(0.0)
     tr.set_frame(fr, 0)
     ids = {t: np.arange(t * 37, w.rays_per_tx, CITY_STRIDE, dtype=np.int32) for t in range(sc.n_tx)}
