@@ -711,6 +711,27 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
     return hip_check(c, hipStreamSynchronize(st), "set_scene");
 }
 
+// The frame's arrays into the context in one launch (up to seven device
+// arrays of doubles; a null source writes zeros).
+struct FrameCopy {
+    const double* src[7];
+    double* dst[7];
+    long long n[7];
+    int k;
+};
+
+__global__ void k_frame_copy(FrameCopy fc) {
+    long long total = 0;
+    for (int j = 0; j < fc.k; j++) total += fc.n[j];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        long long r = i;
+        int j = 0;
+        while (r >= fc.n[j]) r -= fc.n[j++];
+        fc.dst[j][r] = fc.src[j] ? fc.src[j][r] : 0.0;
+    }
+}
+
 int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
     if (!c || !f) return EMRT_E_INVALID;
     if (!c->scene_set) return fail(c, EMRT_E_STATE, "set_scene first");
@@ -718,17 +739,25 @@ int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
     if (!f->tx_pos || !f->rx_pos || !f->tx_vel || !f->rx_vel) return fail(c, EMRT_E_INVALID, "null frame array");
     if (c->S.O_d > 0 && (!f->obj_xform || !f->obj_vel)) return fail(c, EMRT_E_INVALID, "dynamic objects need transforms");
     hipStream_t st = c->stream;
-    int ntx = c->sz.n_tx, nrx = c->sz.n_rx;
-    HC(hipMemcpyAsync(c->f_tx, f->tx_pos, sizeof(double) * 3 * ntx, hipMemcpyDeviceToDevice, st));
-    HC(hipMemcpyAsync(c->f_txv, f->tx_vel, sizeof(double) * 3 * ntx, hipMemcpyDeviceToDevice, st));
-    if (f->tx_orient) HC(hipMemcpyAsync(c->f_txo, f->tx_orient, sizeof(double) * 2 * ntx, hipMemcpyDeviceToDevice, st));
-    else fill_u64((unsigned long long*)c->f_txo, 0ULL, 2LL * ntx, st);
-    HC(hipMemcpyAsync(c->f_rx, f->rx_pos, sizeof(double) * 3 * nrx, hipMemcpyDeviceToDevice, st));
-    HC(hipMemcpyAsync(c->f_rxv, f->rx_vel, sizeof(double) * 3 * nrx, hipMemcpyDeviceToDevice, st));
-    if (c->S.O_d > 0) {
-        HC(hipMemcpyAsync(c->f_xf, f->obj_xform, sizeof(double) * 12 * c->S.O_d, hipMemcpyDeviceToDevice, st));
-        HC(hipMemcpyAsync(c->f_ov, f->obj_vel, sizeof(double) * 3 * c->S.O_d, hipMemcpyDeviceToDevice, st));
+    const long long ntx = c->sz.n_tx, nrx = c->sz.n_rx, nd = c->S.O_d;
+    FrameCopy fc{};
+    auto add = [&](const double* src, double* dst, long long n) {
+        fc.src[fc.k] = src;
+        fc.dst[fc.k] = dst;
+        fc.n[fc.k++] = n;
+    };
+    add(f->tx_pos, c->f_tx, 3 * ntx);
+    add(f->tx_vel, c->f_txv, 3 * ntx);
+    add(f->tx_orient, c->f_txo, 2 * ntx);  // null: zeros
+    add(f->rx_pos, c->f_rx, 3 * nrx);
+    add(f->rx_vel, c->f_rxv, 3 * nrx);
+    if (nd > 0) {
+        add(f->obj_xform, c->f_xf, 12 * nd);
+        add(f->obj_vel, c->f_ov, 3 * nd);
     }
+    const long long total = 8 * ntx + 6 * nrx + 15 * nd;
+    hipLaunchKernelGGL(k_frame_copy, dim3((unsigned)std::min<long long>((total + 255) / 256, 1024)), dim3(256), 0, st,
+                       fc);
     c->frame_set = true;
     c->frame_since_step = true;
     c->frame_idx = f->frame;

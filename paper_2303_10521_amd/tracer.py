@@ -70,6 +70,7 @@ class Tracer:
         self.workspace_bytes = int(nbytes.value)
         self.stream = torch.cuda.current_stream(self.device)
         self._check(self.lib.emrt_set_stream(self.ctx, ctypes.c_void_p(self.stream.cuda_stream)))
+        self._lib_stream = self.stream  # the stream the context works on (a Batch's while it is a member)
         if static_workspace:  # the library's own array (emrt_bind_static_workspace): nothing is allocated
             self.workspace = None
             self._check(self.lib.emrt_bind_static_workspace(self.ctx))
@@ -147,16 +148,44 @@ class Tracer:
         nd = max(self.n_dynamic, 1)
         xf = np.zeros((nd, 3, 4)) if np.asarray(fr.obj_xform).size == 0 else fr.obj_xform
         ov = np.zeros((nd, 3)) if np.asarray(fr.obj_vel).size == 0 else fr.obj_vel
-        refs = dict(
-            xf=_dev(xf, torch.float64, d), ov=_dev(ov, torch.float64, d), tx=_dev(fr.tx_pos, torch.float64, d),
-            txv=_dev(fr.tx_vel, torch.float64, d), txo=_dev(fr.tx_orient, torch.float64, d),
-            rx=_dev(fr.rx_pos, torch.float64, d), rxv=_dev(fr.rx_vel, torch.float64, d),
-        )
-        desc = A.FrameDesc(int(frame_index), float(getattr(fr, "t", 0.0)), self.n_tx, self.n_rx, _ptr(refs["xf"]),
-                           _ptr(refs["ov"]), _ptr(refs["tx"]), _ptr(refs["txv"]), _ptr(refs["txo"]),
-                           _ptr(refs["rx"]), _ptr(refs["rxv"]))
+        arrays = dict(xf=xf, ov=ov, tx=fr.tx_pos, txv=fr.tx_vel, txo=fr.tx_orient, rx=fr.rx_pos, rxv=fr.rx_vel)
+        if any(isinstance(v, torch.Tensor) for v in arrays.values()):
+            refs = {k: _dev(v, torch.float64, d) for k, v in arrays.items()}
+            ptrs = {k: _ptr(v) for k, v in refs.items()}
+            self._frame_refs = refs  # kept alive until the next frame (stream order)
+        else:
+            ptrs = self._stage_frame(arrays)
+        desc = A.FrameDesc(int(frame_index), float(getattr(fr, "t", 0.0)), self.n_tx, self.n_rx, ptrs["xf"],
+                           ptrs["ov"], ptrs["tx"], ptrs["txv"], ptrs["txo"], ptrs["rx"], ptrs["rxv"])
         self._check(self.lib.emrt_set_frame(self.ctx, ctypes.byref(desc)))
-        self._frame_refs = refs  # kept alive until the next frame (stream order)
+
+    def _stage_frame(self, arrays) -> Dict[str, ctypes.c_void_p]:
+        """Host frame arrays packed into one pinned buffer and uploaded with one
+        asynchronous copy into a device staging buffer; returns device pointers
+        into it (the library copies them into its workspace in one launch).
+        The call first waits for the work already queued on the context's
+        stream, as a copy from pageable memory would: the staging buffers are
+        then free, and the host stays at most one step ahead of the GPU (with
+        several discovery steps queued behind each other the bounce kernels
+        were measured to run up to 20% slower)."""
+        flat = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)).reshape(-1) for v in arrays.values()]
+        total = sum(a.size for a in flat)
+        if getattr(self, "_stage_n", -1) != total:
+            self._stage_host = torch.empty(total, dtype=torch.float64, pin_memory=True)
+            self._stage_dev = torch.empty(total, dtype=torch.float64, device=self.device)
+            self._stage_n = total
+        stream = self._lib_stream
+        stream.synchronize()
+        host = self._stage_host.numpy()
+        ptrs, off = {}, 0
+        base = self._stage_dev.data_ptr()
+        for k, a in zip(arrays, flat):
+            host[off:off + a.size] = a
+            ptrs[k] = ctypes.c_void_p(base + 8 * off)
+            off += a.size
+        with torch.cuda.stream(stream):
+            self._stage_dev.copy_(self._stage_host, non_blocking=True)
+        return ptrs
 
     def step(self, discover: bool = True) -> int:
         self.generation += 1
@@ -332,6 +361,8 @@ class Batch:
         self.stream = torch.cuda.Stream(device=dev)
         torch.cuda.current_stream(dev).synchronize()
         self._check(self.lib.emrt_batch_set_stream(self.b, ctypes.c_void_p(self.stream.cuda_stream)))
+        for t in self.tracers:
+            t._lib_stream = self.stream
         self._check(self.lib.emrt_batch_bind_workspace(self.b, ctypes.c_void_p(_ptr(self.workspace)), nbytes.value))
         self.use_graph = bool(use_graph)
         self.set_options(use_graph, n_streams, grid, chunk)
@@ -397,6 +428,8 @@ class Batch:
             torch.cuda.synchronize(self.tracers[0].device)
             self.lib.emrt_batch_destroy(self.b)
             self.b = None
+            for t in self.tracers:  # the members work on their own streams again
+                t._lib_stream = t.stream
 
     def __del__(self):
         try:
