@@ -79,6 +79,15 @@ typedef struct emrt_config {
     int64_t table_capacity;     /* path-table slots, rounded up to a power of two (default 4 x path_capacity) */
     int32_t adjoint_materials;  /* 0: no adjoint; else the most materials emrt_backward supports (<= 256);
                                    adds 8 (5 + 2 adjoint_materials) bytes per link to the workspace */
+    double dyn_rebuild_ratio;   /* > 0: the tree over the moving objects' triangles is refitted on
+                                   every frame and rebuilt on a discovery frame only once its quality
+                                   (summed child box areas over the root's, read back one step late)
+                                   exceeds this multiple of its value when last built (Section III-A:
+                                   only what changed is rebuilt); 0 (default): rebuilt on every
+                                   discovery frame, refitted on cached ones.  Batched steps always
+                                   rebuild.  Results do not depend on the tree; a choice for scenes
+                                   whose moving geometry is large (on the city's 24,000 vehicle
+                                   triangles a rebuild costs less than a looser tree) */
     int32_t ray_regroup;        /* 1: the rays entering bounces 2..K are regrouped by origin cell and
                                    direction octant (one counting sort per bounce), so a wave traces
                                    neighbouring rays; 0 (default): they stay in the order the previous
@@ -383,6 +392,9 @@ typedef struct emrt_stats {
                                    root over the root's (the expected box tests of a random ray) */
     int64_t wide_box_tests;     /* child boxes tested in the static tree's 4-wide nodes (when stats are
                                    enabled); node_visits then counts the binary (dynamic tree) nodes */
+    int64_t dyn_rebuilds;       /* builds of the moving objects' tree since the scene was set (steps
+                                   outside a batch) */
+    double dyn_tree_quality;    /* its quality at the last completed read-back (0: none yet) */
 } emrt_stats;
 int32_t emrt_read_stats(emrt_ctx* ctx, emrt_stats* out);
 /* Optional instrumentation: stats = count traversal work (slower), timing =

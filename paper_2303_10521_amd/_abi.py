@@ -27,7 +27,7 @@ class Config(ctypes.Structure):
         ("n_freq", c_i32), ("freq_hz", c_f64 * 4), ("max_reflections", c_i32), ("diffraction", c_i32),
         ("rays_per_tx", c_i32), ("rx_sphere_k", c_f64), ("diff_max_leg_m", c_f64), ("tx_power_w", c_f64),
         ("antenna_mode", c_i32), ("path_cap_per_link", c_i32), ("path_capacity", c_i64), ("table_capacity", c_i64),
-        ("adjoint_materials", c_i32), ("ray_regroup", c_i32),
+        ("adjoint_materials", c_i32), ("dyn_rebuild_ratio", c_f64), ("ray_regroup", c_i32),
     ]
 
 
@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
                 ("node_visits", c_i64), ("tri_tests", c_i64), ("segments", c_i64), ("captures", c_i64),
                 ("n_static_tris", c_i64), ("n_dynamic_tris", c_i64), ("n_edges", c_i64), ("device_flags", c_u32),
                 ("bounce_ms", c_f64), ("bounce_launches", c_i32), ("validate_ms", c_f64),
-                ("validate_launches", c_i32), ("static_tree_area", c_f64), ("wide_box_tests", c_i64)]
+                ("validate_launches", c_i32), ("static_tree_area", c_f64), ("wide_box_tests", c_i64),
+                ("dyn_rebuilds", c_i64), ("dyn_tree_quality", c_f64)]
 
 
 # name -> (restype, argtypes)

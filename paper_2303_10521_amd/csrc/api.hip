@@ -83,6 +83,15 @@ struct emrt_ctx {
     // candidates (they need only the first bounce) run beside bounces 1..K
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // quality of the moving objects' tree, read back one step late (the
+    // rebuild-on-degradation policy): device pair, pinned copy, its event
+    double* dyq_dev = nullptr;
+    double* dyq_host = nullptr;
+    hipEvent_t ev_dyq = nullptr;
+    bool dyq_pending = false, dyq_pending_build = false;
+    bool dy_updated = false, dy_updated_build = false;  // this step built or refitted the tree
+    double dyq_built = 0.0, dyq_last = 0.0;
+    int64_t dyn_rebuilds = 0;
     bool diff_async = false;
     std::string err;
     int stats_on = 0, timing_on = 0;
@@ -268,6 +277,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
         c->ray_key = cv.take<uint16_t>(c->n_total);
         c->rg_temp = cv.take<uint32_t>((long long)regroup_temp_u32(c->n_total));
     }
+    c->dyq_dev = cv.take<double>(2);
     c->hitlog = cv.take<int>((long long)(c->K + 1) * c->n_total);
     c->depth = cv.take<uint8_t>(c->n_total);
     c->dbg_sel = cv.take<uint32_t>(c->n_total / 32 + 1);
@@ -420,6 +430,7 @@ void emrt_config_default(emrt_config* cfg) {
     cfg->path_capacity = 4LL << 20;
     cfg->table_capacity = 0;
     cfg->ray_regroup = 0;
+    cfg->dyn_rebuild_ratio = 0.0;
 }
 
 int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
@@ -430,7 +441,7 @@ int32_t emrt_ctx_create(const emrt_config* cfg, emrt_ctx** out) {
     if (cfg->rays_per_tx < 1 || !(cfg->rx_sphere_k > 0) || !(cfg->diff_max_leg_m >= 0) || cfg->path_capacity < 1 ||
         cfg->path_capacity > (1LL << 31) || cfg->antenna_mode < 0 || cfg->antenna_mode > 1 ||
         cfg->adjoint_materials < 0 || cfg->adjoint_materials > kMaxMaterials || cfg->diffraction < 0 ||
-        cfg->diffraction > 2 || (cfg->ray_regroup != 0 && cfg->ray_regroup != 1))
+        cfg->diffraction > 2 || (cfg->ray_regroup != 0 && cfg->ray_regroup != 1) || !(cfg->dyn_rebuild_ratio >= 0.0))
         return EMRT_E_INVALID;
     // one reflection combined with one diffraction: the kernels below are
     // complete (k_pair_list, k_pair_cand, the combined construction and
@@ -451,6 +462,8 @@ int32_t emrt_ctx_destroy(emrt_ctx* c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_dyq) (void)hipEventDestroy(c->ev_dyq);
+    if (c->dyq_host) (void)hipHostFree(c->dyq_host);
     if (c->ev_created)
         for (auto& set : c->evs)
             for (auto e : set.ev) (void)hipEventDestroy(e);
@@ -697,7 +710,10 @@ int32_t emrt_set_scene(emrt_ctx* c, const emrt_scene_desc* d) {
         double ra = 2.0 * (ex * ey + ey * ez + ez * ex);
         c->st_area = ra > 0.0 ? sum / ra : 0.0;
     }
-    c->dy.n = 0;
+    c->dy.n = 0;  // the first frame builds the moving objects' tree
+    c->dyq_pending = false;
+    c->dyq_built = c->dyq_last = 0.0;
+    c->dyn_rebuilds = 0;
     ray_order(c->cfg.rays_per_tx, c->dir_perm, c->tmp, st);
     invert_perm(c->dir_perm, c->dir_slot, c->cfg.rays_per_tx, st);
     dir_table(c->dir_perm, c->cfg.rays_per_tx, c->dirs, st);
@@ -915,6 +931,61 @@ static BounceArgs bounce_args(emrt_ctx* c, int k, int parity) {
     return b;
 }
 
+// ---- rebuild-on-degradation of the moving objects' tree (Section III-A:
+// between rediscoveries only parts of the scene change).  Refitting keeps
+// the tree's topology while the objects move, so its boxes loosen; its
+// quality (summed child box areas over the root's) is read back after every
+// update, and a discovery frame rebuilds once the last known quality exceeds
+// dyn_rebuild_ratio times the quality the last build had.  A read-back that
+// has not completed, no known build quality, a ratio of 0, batched steps and
+// steps under stream capture all rebuild, as before.
+static bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+static void dy_quality_collect(emrt_ctx* c) {
+    if (!c->dyq_pending || hipEventQuery(c->ev_dyq) != hipSuccess) return;
+    c->dyq_pending = false;
+    const double q = c->dyq_host[1] > 0.0 ? c->dyq_host[0] / c->dyq_host[1] : 0.0;
+    c->dyq_last = q;
+    if (c->dyq_pending_build) c->dyq_built = q;
+}
+
+static bool dy_rebuild_due(emrt_ctx* c) {
+    if (c->batched || !(c->cfg.dyn_rebuild_ratio > 0.0) || capturing(c->stream)) return true;
+    dy_quality_collect(c);
+    if (c->dyq_pending || !(c->dyq_built > 0.0) || !(c->dyq_last > 0.0)) return true;
+    return c->dyq_last > c->dyq_built * c->cfg.dyn_rebuild_ratio;
+}
+
+static void dy_quality_readback(emrt_ctx* c, bool built) {
+    if (c->batched || !(c->cfg.dyn_rebuild_ratio > 0.0) || capturing(c->stream)) return;
+    if (!c->dyq_host) {
+        if (hipHostMalloc((void**)&c->dyq_host, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            c->dyq_host = nullptr;
+            return;
+        }
+        if (hipEventCreateWithFlags(&c->ev_dyq, hipEventDisableTiming) != hipSuccess) {
+            c->ev_dyq = nullptr;
+            return;
+        }
+    }
+    if (!c->ev_dyq) return;
+    tree_quality(c->dy, c->dyq_dev, c->stream);
+    if (hipMemcpyAsync(c->dyq_host, c->dyq_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipEventRecord(c->ev_dyq, c->stream) != hipSuccess)
+        return;
+    c->dyq_pending = true;
+    c->dyq_pending_build = built;
+}
+
+// after the step's last kernel: the quality of the tree this step updated
+static void step_finish(emrt_ctx* c) {
+    if (c->dy_updated) dy_quality_readback(c, c->dy_updated_build);
+    c->dy_updated = false;
+}
+
 static void step_pre(emrt_ctx* c, int discover) {
     hipStream_t st = c->stream;
     SceneDev& S = c->S;
@@ -937,7 +1008,7 @@ static void step_pre(emrt_ctx* c, int discover) {
     // capture trees: only the bounce kernel reads them, so cached frames skip them
     const bool rev = discover && c->rev_n > 0;
     bool diff = c->cfg.diffraction && S.E > 0;
-    const bool build_dy = S.T_d > 0 && (discover || c->dy.n != S.T_d);
+    const bool build_dy = S.T_d > 0 && (c->dy.n != S.T_d || (discover && dy_rebuild_due(c)));
     BuildJob jobs[3];
     int nj = 0;
     if (S.T_d > 0) tri_boxes(S, S.tris_dynamic, S.T_d, c->box_dy, st);
@@ -956,6 +1027,12 @@ static void step_pre(emrt_ctx* c, int discover) {
     }
     bvh_build_many(jobs, nj, c->tmp, st);  // the frame's rebuilt trees, in one batch
     if (S.T_d > 0 && !build_dy) bvh_refit(c->box_dy, c->dy, st);
+    if (build_dy && !c->batched) {
+        c->dyn_rebuilds++;
+        c->dyq_built = 0.0;  // known once this build's quality is read back
+    }
+    c->dy_updated = S.T_d > 1 && !c->batched;  // its quality is read back at the end of the step
+    c->dy_updated_build = build_dy;
     if (S.T_d > 0) tri_prims(S, S.tris_dynamic, c->dy, c->dy_prims, st);
     if (discover && !rev) rx_prims(c->f_rx, c->rxt, c->rx_prims, st);
     if (rev) rx_prims(c->f_tx, c->txt, c->tx_prims, st);
@@ -1089,6 +1166,7 @@ int32_t emrt_step(emrt_ctx* c, int32_t discover) {
         step_bounces(c, fork);
     }
     step_post(c, discover);
+    step_finish(c);
     return hip_check(c, hipGetLastError(), "step");
 }
 
@@ -1108,6 +1186,7 @@ int32_t emrt_step_rx(emrt_ctx* c, const int32_t* rx_ids, int32_t n_src, int32_t 
     step_pre(c, 1);
     step_bounces(c);
     step_post(c, 1);
+    step_finish(c);
     c->rev_n = 0;
     c->rev_rays = 0;
     return hip_check(c, hipGetLastError(), "step_rx");
@@ -1355,6 +1434,9 @@ int32_t emrt_read_stats(emrt_ctx* c, emrt_stats* o) {
     o->validate_ms = c->t_validate_ms;
     o->validate_launches = c->t_validate_n;
     o->static_tree_area = c->st_area;
+    dy_quality_collect(c);
+    o->dyn_rebuilds = c->dyn_rebuilds;
+    o->dyn_tree_quality = c->dyq_last;
     return EMRT_OK;
 }
 

@@ -16,6 +16,7 @@
 // child boxes and continues, so every node is written exactly once per refit.
 // Paper: Section II-A (a BVH updated between frames), Section III-A (only
 // subtrees change within a trajectory segment).
+#include <algorithm>
 #include <deque>
 #include <math.h>
 #include <string.h>
@@ -622,6 +623,44 @@ void bvh_build_many(const BuildJob* jobs, int n_jobs, const BuildTemp& tmp, hipS
 void bvh_build(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st) {
     BuildJob job{box6, n, &tree};
     bvh_build_many(&job, 1, tmp, st);
+}
+
+// Tree quality for the rebuild-on-degradation policy: out[0] = the summed
+// surface area of every node's two child boxes, out[1] = the root box's
+// (their ratio is the expected number of box tests of a random ray).
+__device__ __forceinline__ double half_area(float lx, float ly, float lz, float hx, float hy, float hz) {
+    const double x = fmax((double)hx - lx, 0.0), y = fmax((double)hy - ly, 0.0), z = fmax((double)hz - lz, 0.0);
+    return x * y + y * z + z * x;
+}
+
+__global__ void __launch_bounds__(256) k_tree_quality(const BNode* nodes, int n_int, double* out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_int; i += gridDim.x * blockDim.x) {
+        const BNode nd = nodes[i];
+        s += half_area(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y) +
+             half_area(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&out[0], sh[0]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const BNode r = nodes[0];
+        out[1] = half_area(fminf(r.a.x, r.b.z), fminf(r.a.y, r.b.w), fminf(r.a.z, r.c.x), fmaxf(r.a.w, r.c.y),
+                           fmaxf(r.b.x, r.c.z), fmaxf(r.b.y, r.c.w));
+    }
+}
+
+void tree_quality(const Tree& tree, double* out2, hipStream_t st) {
+    fill_u64((unsigned long long*)out2, 0ULL, 2, st);
+    const int n_int = tree.n - 1;
+    if (n_int < 1) return;
+    const int g = std::min((n_int + 255) / 256, 64);
+    hipLaunchKernelGGL(k_tree_quality, dim3(g), dim3(256), 0, st, tree.nodes, n_int, out2);
 }
 
 void bvh_refit(const float* box6, Tree& tree, hipStream_t st) {

@@ -56,6 +56,8 @@ struct BuildJob {
 };
 void bvh_build_many(const BuildJob* jobs, int n_jobs, const BuildTemp& tmp, hipStream_t st);
 void bvh_refit(const float* box6, Tree& tree, hipStream_t st);
+// out2 (device, 2 doubles): summed child box areas over all nodes, root box area
+void tree_quality(const Tree& tree, double* out2, hipStream_t st);
 // top-down binned SAH build into the same node format (static scene, once): one launch per level,
 // synchronises per level; returns the number of levels, -1 on a HIP error
 int bvh_build_sah(const float* box6, int n, Tree& tree, const BuildTemp& tmp, hipStream_t st);

@@ -38,7 +38,7 @@ class Tracer:
     object_dynamic, materials`` (numpy or torch); ``config`` keys mirror
     ``emrt_config`` (freq_hz list, max_reflections, diffraction, rays_per_tx,
     rx_sphere_k, diff_max_leg_m, tx_power_w, antenna_mode, path_cap_per_link,
-    path_capacity, table_capacity, adjoint_materials, ray_regroup).
+    path_capacity, table_capacity, adjoint_materials, dyn_rebuild_ratio, ray_regroup).
     """
 
     def __init__(self, scene, n_tx: int, n_rx: int, device: str = "cuda", static_workspace: bool = False, **config):

@@ -45,7 +45,7 @@ def test_config_defaults(lib):
     c = _cfg(lib)
     assert c.n_freq == 1 and c.freq_hz[0] == 28e9 and c.max_reflections == 3
     assert c.tx_power_w == 100.0 and c.rx_sphere_k == 1.0 and c.diff_max_leg_m == 250.0
-    assert c.ray_regroup == 0
+    assert c.ray_regroup == 0 and c.dyn_rebuild_ratio == 0.0
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -60,6 +60,8 @@ def test_config_defaults(lib):
     (dict(diffraction=2), A.EMRT_E_UNSUPPORTED),
     (dict(ray_regroup=2), A.EMRT_E_INVALID),
     (dict(ray_regroup=-1), A.EMRT_E_INVALID),
+    (dict(dyn_rebuild_ratio=-1.0), A.EMRT_E_INVALID),
+    (dict(dyn_rebuild_ratio=float("nan")), A.EMRT_E_INVALID),
 ])
 def test_ctx_create_rejects_bad_config(lib, kw, status):
     c = _cfg(lib, **kw)
