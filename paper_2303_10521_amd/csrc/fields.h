@@ -377,13 +377,22 @@ __device__ __forceinline__ void utd_D_x(double n, double k, R L, R beta0, R php,
     R cmag = 1.0 / ((2.0 * n * sqrt(2.0 * kPi * k)) * sb);
     Cx<R> Cc = cx<R>(cmag * (-h), cmag * h);
     R kL = L * k;
-    Cx<R> t3 = utd_term_x<R>(+1, ph + php, n, kL);
-    Cx<R> t4 = utd_term_x<R>(-1, ph + php, n, kL);
+    // the four terms one at a time (one transition function live, not four):
+    // k = 0, 1 the incident-shadow pair (ph - php, summed), 2, 3 the
+    // reflection-shadow terms (ph + php); derivative modes need only one
+    Cx<R> t12 = cx<R>(rl<R>(0.0), rl<R>(0.0)), t3 = t12, t4 = t12;
+#pragma unroll 1
+    for (int j = 0; j < 4; j++) {
+        if ((dmode == 1 && j != 3) || (dmode == 2 && j != 2)) continue;
+        const Cx<R> t = utd_term_x<R>((j & 1) ? -1 : +1, j < 2 ? ph - php : ph + php, n, kL);
+        if (j < 2) t12 = t12 + t;
+        else if (j == 2) t3 = t;
+        else t4 = t;
+    }
     Cx<R> r0te, r0tm, rnte, rntm;
     material_x<R>(fc, m0, sb * abs_(sin_(php)), dmode == 1, r0te, r0tm);
     material_x<R>(fc, mn, sb * abs_(sin_(n * kPi - ph)), dmode == 2, rnte, rntm);
     if (dmode == 0) {
-        Cx<R> t12 = utd_term_x<R>(+1, ph - php, n, kL) + utd_term_x<R>(-1, ph - php, n, kL);
         Ds = Cc * (t12 + rnte * t3 + r0te * t4);
         Dh = Cc * (t12 + rntm * t3 + r0tm * t4);
     } else if (dmode == 1) {
@@ -506,7 +515,8 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
         g.np = 2;
         return;
     }
-    if ((KIND == 0 || KIND == 2 || KIND == 4) && g.type == KT_DIFF) {
+    // KIND 2 and 3 take only their own type: the branches below it are not compiled in
+    if (KIND == 2 || ((KIND == 0 || KIND == 4) && g.type == KT_DIFF)) {
         g.np = 3;
         Wedge w = wedge_of(S, key.ids[0]);
         R zs = dot3(w.e, s - w.P0);
@@ -518,7 +528,7 @@ __device__ __forceinline__ void path_points(const SceneDev& S, const KeyRec& key
         g.P[1] = scale(w.e, zq) + w.P0;
         return;
     }
-    if ((KIND == 0 || KIND == 3) && (g.type == KT_RD || g.type == KT_DR)) {
+    if (KIND == 3 || (KIND == 0 && (g.type == KT_RD || g.type == KT_DR))) {
         // the Keller point between the unfolded ends (Tx's image and Rx, or Tx
         // and Rx's image), then the reflection point on the segment from it to
         // the image
@@ -605,8 +615,10 @@ template <class R, int KIND = 0>
 __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc, const KeyRec& key, const PathGeo<R>& g,
                                            R th, R phi, int dmode, V3<R>* kk, R& L, Cx<R>* amp) {
     L = rl<R>(0.0);
+    // legs of a path of this kind at most (diffraction alone: 2, with one reflection: 3)
+    constexpr int kLegs = KIND == 2 ? 2 : (KIND == 3 ? 3 : EMRT_KMAX + 1);
 #pragma unroll
-    for (int i = 0; i <= EMRT_KMAX; i++) {
+    for (int i = 0; i < kLegs; i++) {
         if (i + 1 >= g.np) break;
         V3<R> p1 = (i + 2 == g.np) ? g.Rx : g.P[i + 1 <= EMRT_KMAX + 1 ? i + 1 : EMRT_KMAX + 1];
         V3<R> dv = p1 - g.P[i];
@@ -618,7 +630,7 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
     V3<R> k0 = kk[0];
     V3<R> kK = kk[0];
 #pragma unroll
-    for (int i = 1; i <= EMRT_KMAX; i++)
+    for (int i = 1; i < kLegs; i++)
         if (i == nlegs - 1) kK = kk[i];
     const bool diffracted = (KIND == 2 || KIND == 3) ? true : (KIND == 1 ? false : g.type >= KT_DIFF);
     if (!diffracted) {
@@ -673,7 +685,9 @@ __device__ __forceinline__ void path_field(const SceneDev& S, const FieldCtx& fc
         if (KIND != 3 && !rd && !dr) {
             R cs = rl<R>(0.0) - dot3(er, bo) * dot3(bp, et);
             R ch = dot3(er, fo) * dot3(fp, et);
-            for (int fi = 0; fi < fc.nf; fi++) {
+            // KIND 2 is called one carrier at a time (the field kernel splits the carriers)
+            const int nf = KIND == 2 ? 1 : fc.nf;
+            for (int fi = 0; fi < nf; fi++) {
                 double lam = kC0 / fc.freq[fi];
                 double k = 2.0 * kPi / lam;
                 Cx<R> Ds, Dh;

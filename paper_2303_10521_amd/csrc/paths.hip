@@ -1079,10 +1079,11 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
         Cx<double> amp[EMRT_NF];
         path_field<double, KIND>(S, fc, key, pg, th, phi, 0, kk, L, amp);
         const int nlegs = pg.np - 1;
+        constexpr int kLegs = KIND == 2 ? 2 : (KIND == 3 ? 3 : EMRT_KMAX + 1);  // at most, for this kind
         dv3 k0 = val3(kk[0]);
         dv3 kK = k0;
 #pragma unroll
-        for (int i = 1; i <= EMRT_KMAX; i++)
+        for (int i = 1; i < kLegs; i++)
             if (i == nlegs - 1) kK = val3(kk[i]);
         double dop = dot(kK, vr) - dot(k0, vt);
         if (KIND == 1) {
@@ -1105,7 +1106,8 @@ __global__ void __launch_bounds__(128) k_fields(PathArgs a, long long n_links, V
             }
         }
         ValidPaths& o = a.out;
-        for (int j = 0; j < fc.nf; j++) {
+        const int nf_here = KIND == 2 ? 1 : fc.nf;  // KIND 2: this thread's carrier only
+        for (int j = 0; j < nf_here; j++) {
             const int fi = j + (split > 1 ? f0 : 0);
             double lam = kC0 / a.fc.freq[fi];
             o.a[2 * (pos * a.fc.nf + fi)] = amp[j].re;
