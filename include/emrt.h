@@ -190,7 +190,20 @@ typedef struct emrt_frame_desc {
     const double* rx_pos;      /* [n_rx][3] */
     const double* rx_vel;      /* [n_rx][3] */
 } emrt_frame_desc;
+/* Errors: EMRT_E_INVALID (NULL, sizes differ, a null position or velocity
+ * array, dynamic objects without transforms), EMRT_E_STATE (no scene). */
 int32_t emrt_set_frame(emrt_ctx* ctx, const emrt_frame_desc* frame);
+
+/* emrt_set_frame with every array of the descriptor a HOST pointer (layouts as
+ * above; tx_orient may be NULL for zeros).  The arrays are packed into a
+ * pinned buffer that the context owns and uploaded in one copy on its stream,
+ * then scattered as in emrt_set_frame; they are read before the call returns,
+ * so the caller may reuse them at once.  If the previous host upload is still
+ * in flight the call first waits for it (the pinned buffer is single).  The
+ * buffer is allocated on the first call and grown when the sizes grow; it is
+ * freed by emrt_destroy.  Same errors as emrt_set_frame, plus EMRT_E_HIP when
+ * the pinned buffer cannot be allocated. */
+int32_t emrt_set_frame_host(emrt_ctx* ctx, const emrt_frame_desc* frame);
 
 /* Run one frame.  discover = 1: launch rays from every transmitter, bounce
  * them, capture receivers and edges, merge the discovered keys with the cache

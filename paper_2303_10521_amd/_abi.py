@@ -87,6 +87,7 @@ SIGNATURES = {
     "emrt_set_materials": (c_i32, [c_vp, c_vp, c_i32]),
     "emrt_set_reflection_coefficients": (c_i32, [c_vp, c_vp, c_i32]),
     "emrt_set_frame": (c_i32, [c_vp, ctypes.POINTER(FrameDesc)]),
+    "emrt_set_frame_host": (c_i32, [c_vp, ctypes.POINTER(FrameDesc)]),
     "emrt_step": (c_i32, [c_vp, c_i32]),
     "emrt_step_rx": (c_i32, [c_vp, c_vp, c_i32, c_i32]),
     "emrt_read_channels": (c_i32, [c_vp, ctypes.POINTER(ChannelView)]),

@@ -155,6 +155,13 @@ struct emrt_ctx {
     double* chan = nullptr;
     double *f_tx = nullptr, *f_txv = nullptr, *f_txo = nullptr, *f_rx = nullptr, *f_rxv = nullptr, *f_xf = nullptr,
            *f_ov = nullptr;
+    // emrt_set_frame_host: device staging [8 n_tx + 6 n_rx + 15 n_objects], the
+    // pinned host buffer it is uploaded from, and the event of the last upload
+    double* f_stage = nullptr;
+    double* fr_pin = nullptr;
+    size_t fr_pin_n = 0;
+    hipEvent_t ev_fr = nullptr;
+    bool fr_pending = false;
     double* mat = nullptr;
     std::vector<double> mat_host;
     double* refl = nullptr;          // [kMaxMaterials] constant reflection magnitudes (0: Fresnel)
@@ -373,6 +380,7 @@ static void layout(emrt_ctx* c, Carver& cv) {
     c->f_rxv = cv.take<double>(3LL * z.n_rx);
     c->f_xf = cv.take<double>(12 * O);
     c->f_ov = cv.take<double>(3 * O);
+    c->f_stage = cv.take<double>(8LL * z.n_tx + 6LL * z.n_rx + 15 * O);
     c->mat = cv.take<double>(2 * kMaxMaterials);
     c->refl = cv.take<double>(kMaxMaterials);
     c->flags = cv.take<uint32_t>(16);
@@ -463,6 +471,8 @@ int32_t emrt_ctx_destroy(emrt_ctx* c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_dyq) (void)hipEventDestroy(c->ev_dyq);
+    if (c->ev_fr) (void)hipEventDestroy(c->ev_fr);
+    if (c->fr_pin) (void)hipHostFree(c->fr_pin);
     if (c->dyq_host) (void)hipHostFree(c->dyq_host);
     if (c->ev_created)
         for (auto& set : c->evs)
@@ -748,12 +758,17 @@ __global__ void k_frame_copy(FrameCopy fc) {
     }
 }
 
-int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
+static int32_t frame_check(emrt_ctx* c, const emrt_frame_desc* f) {
     if (!c || !f) return EMRT_E_INVALID;
     if (!c->scene_set) return fail(c, EMRT_E_STATE, "set_scene first");
     if (f->n_tx != c->sz.n_tx || f->n_rx != c->sz.n_rx) return fail(c, EMRT_E_INVALID, "n_tx / n_rx differ from sizes");
     if (!f->tx_pos || !f->rx_pos || !f->tx_vel || !f->rx_vel) return fail(c, EMRT_E_INVALID, "null frame array");
     if (c->S.O_d > 0 && (!f->obj_xform || !f->obj_vel)) return fail(c, EMRT_E_INVALID, "dynamic objects need transforms");
+    return EMRT_OK;
+}
+
+// the frame's device arrays into the context, in one launch
+static int32_t frame_gather(emrt_ctx* c, const emrt_frame_desc* f) {
     hipStream_t st = c->stream;
     const long long ntx = c->sz.n_tx, nrx = c->sz.n_rx, nd = c->S.O_d;
     FrameCopy fc{};
@@ -778,6 +793,60 @@ int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
     c->frame_since_step = true;
     c->frame_idx = f->frame;
     return hip_check(c, hipGetLastError(), "set_frame");
+}
+
+int32_t emrt_set_frame(emrt_ctx* c, const emrt_frame_desc* f) {
+    int32_t rc = frame_check(c, f);
+    if (rc) return rc;
+    return frame_gather(c, f);
+}
+
+int32_t emrt_set_frame_host(emrt_ctx* c, const emrt_frame_desc* f) {
+    int32_t rc = frame_check(c, f);
+    if (rc) return rc;
+    const long long ntx = c->sz.n_tx, nrx = c->sz.n_rx, nd = c->S.O_d;
+    const size_t n = (size_t)(8 * ntx + 6 * nrx + 15 * nd);
+    if (c->fr_pending) {  // the pinned buffer still feeds the previous upload
+        HC(hipEventSynchronize(c->ev_fr));
+        c->fr_pending = false;
+    }
+    if (!c->fr_pin || c->fr_pin_n < n) {
+        if (c->fr_pin) (void)hipHostFree(c->fr_pin);
+        c->fr_pin = nullptr;
+        c->fr_pin_n = 0;
+        if (hipHostMalloc((void**)&c->fr_pin, sizeof(double) * std::max<size_t>(n, 1), hipHostMallocDefault) != hipSuccess) {
+            c->fr_pin = nullptr;
+            return fail(c, EMRT_E_HIP, "pinned frame buffer");
+        }
+        c->fr_pin_n = n;
+    }
+    if (!c->ev_fr && hipEventCreateWithFlags(&c->ev_fr, hipEventDisableTiming) != hipSuccess) {
+        c->ev_fr = nullptr;
+        return fail(c, EMRT_E_HIP, "frame upload event");
+    }
+    // packed in the gather's order; a null orientation becomes zeros
+    emrt_frame_desc d = *f;
+    size_t off = 0;
+    auto put = [&](const double* src, long long cnt) -> const double* {
+        if (src) memcpy(c->fr_pin + off, src, sizeof(double) * (size_t)cnt);
+        else memset(c->fr_pin + off, 0, sizeof(double) * (size_t)cnt);
+        const double* dev = c->f_stage + off;
+        off += (size_t)cnt;
+        return dev;
+    };
+    d.tx_pos = put(f->tx_pos, 3 * ntx);
+    d.tx_vel = put(f->tx_vel, 3 * ntx);
+    d.tx_orient = put(f->tx_orient, 2 * ntx);
+    d.rx_pos = put(f->rx_pos, 3 * nrx);
+    d.rx_vel = put(f->rx_vel, 3 * nrx);
+    if (nd > 0) {
+        d.obj_xform = put(f->obj_xform, 12 * nd);
+        d.obj_vel = put(f->obj_vel, 3 * nd);
+    }
+    HC(hipMemcpyAsync(c->f_stage, c->fr_pin, sizeof(double) * off, hipMemcpyHostToDevice, c->stream));
+    HC(hipEventRecord(c->ev_fr, c->stream));
+    c->fr_pending = true;
+    return frame_gather(c, &d);
 }
 
 static void ev_flush(emrt_ctx* c, emrt_ctx::EventSet& set) {

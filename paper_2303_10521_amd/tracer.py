@@ -25,6 +25,10 @@ def _ptr(t: Optional[torch.Tensor]) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+def _numel(a) -> int:
+    return a.numel() if isinstance(a, torch.Tensor) else np.asarray(a).size
+
+
 def _dev(a, dtype, device) -> torch.Tensor:
     if isinstance(a, torch.Tensor):
         return a.to(device=device, dtype=dtype).contiguous()
@@ -146,46 +150,28 @@ class Tracer:
         self.generation += 1
         d = self.device
         nd = max(self.n_dynamic, 1)
-        xf = np.zeros((nd, 3, 4)) if np.asarray(fr.obj_xform).size == 0 else fr.obj_xform
-        ov = np.zeros((nd, 3)) if np.asarray(fr.obj_vel).size == 0 else fr.obj_vel
+        xf = np.zeros((nd, 3, 4)) if _numel(fr.obj_xform) == 0 else fr.obj_xform
+        ov = np.zeros((nd, 3)) if _numel(fr.obj_vel) == 0 else fr.obj_vel
         arrays = dict(xf=xf, ov=ov, tx=fr.tx_pos, txv=fr.tx_vel, txo=fr.tx_orient, rx=fr.rx_pos, rxv=fr.rx_vel)
         if any(isinstance(v, torch.Tensor) for v in arrays.values()):
             refs = {k: _dev(v, torch.float64, d) for k, v in arrays.items()}
             ptrs = {k: _ptr(v) for k, v in refs.items()}
             self._frame_refs = refs  # kept alive until the next frame (stream order)
+            entry = self.lib.emrt_set_frame
         else:
-            ptrs = self._stage_frame(arrays)
+            # host arrays: the library packs them into its pinned buffer and
+            # uploads them in one copy (emrt_set_frame_host).  Waiting first for
+            # the work already queued keeps the host at most one step ahead of
+            # the GPU, as a copy from pageable memory would: with several
+            # discovery steps queued behind each other the bounce kernels were
+            # measured to run up to 20% slower.
+            host = {k: np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for k, v in arrays.items()}
+            ptrs = {k: ctypes.c_void_p(v.ctypes.data) for k, v in host.items()}
+            self._lib_stream.synchronize()
+            entry = self.lib.emrt_set_frame_host
         desc = A.FrameDesc(int(frame_index), float(getattr(fr, "t", 0.0)), self.n_tx, self.n_rx, ptrs["xf"],
                            ptrs["ov"], ptrs["tx"], ptrs["txv"], ptrs["txo"], ptrs["rx"], ptrs["rxv"])
-        self._check(self.lib.emrt_set_frame(self.ctx, ctypes.byref(desc)))
-
-    def _stage_frame(self, arrays) -> Dict[str, ctypes.c_void_p]:
-        """Host frame arrays packed into one pinned buffer and uploaded with one
-        asynchronous copy into a device staging buffer; returns device pointers
-        into it (the library copies them into its workspace in one launch).
-        The call first waits for the work already queued on the context's
-        stream, as a copy from pageable memory would: the staging buffers are
-        then free, and the host stays at most one step ahead of the GPU (with
-        several discovery steps queued behind each other the bounce kernels
-        were measured to run up to 20% slower)."""
-        flat = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)).reshape(-1) for v in arrays.values()]
-        total = sum(a.size for a in flat)
-        if getattr(self, "_stage_n", -1) != total:
-            self._stage_host = torch.empty(total, dtype=torch.float64, pin_memory=True)
-            self._stage_dev = torch.empty(total, dtype=torch.float64, device=self.device)
-            self._stage_n = total
-        stream = self._lib_stream
-        stream.synchronize()
-        host = self._stage_host.numpy()
-        ptrs, off = {}, 0
-        base = self._stage_dev.data_ptr()
-        for k, a in zip(arrays, flat):
-            host[off:off + a.size] = a
-            ptrs[k] = ctypes.c_void_p(base + 8 * off)
-            off += a.size
-        with torch.cuda.stream(stream):
-            self._stage_dev.copy_(self._stage_host, non_blocking=True)
-        return ptrs
+        self._check(entry(self.ctx, ctypes.byref(desc)))
 
     def step(self, discover: bool = True) -> int:
         self.generation += 1
