@@ -519,6 +519,57 @@ def test_single_ray_single_receiver_and_truncation():
     tr2.close()
 
 
+def test_maximum_transmitter_count():
+    """4095 transmitters, the most the key references hold (12 bits in a
+    diffraction reference), and four carriers, the most a context takes:
+    hit logs of the first and last transmitter bit-exact on robust rays, the
+    same path sets as the oracle on every link (line of sight, reflections
+    and diffraction from every transmitter), per-path values and channels at
+    every carrier within tolerance; 4096 transmitters are refused."""
+    from paper_2303_10521_amd import Tracer
+    from paper_2303_10521_amd.tracer import EmrtError
+
+    sc = city.tiny_box_ground(refl=(0.0, 0.0))
+    rng = np.random.default_rng(4095)
+    n_tx, n = 4095, 128
+    ang, rad = rng.uniform(0, 2 * np.pi, n_tx), rng.uniform(60.0, 300.0, n_tx)
+    tx = np.stack([20 + rad * np.cos(ang), 20 + rad * np.sin(ang), rng.uniform(1.5, 45.0, n_tx)], 1)
+    rx = np.array([[x, y, 1.5] for x in (-25.0, 70.0) for y in (-30.0, 80.0)] + [[20.0, -60.0, 12.0], [90.0, 20.0, 3.0]])
+    sc1 = city.with_static_rx(sc, rx)
+    fr = static_frame(tx, rx)
+    freqs = [0.9e9, 3.5e9, 28e9, 60e9]
+    tr = Tracer(sc1, n_tx, len(rx), freq_hz=freqs, max_reflections=2, rays_per_tx=n, diffraction=1,
+                path_capacity=1 << 18)
+    try:
+        tr.set_frame(fr)
+        tr.step(True)
+        assert tr.sync() == 0
+        os_ = O.OracleScene(sc1)
+        ref = O.run_frame(os_, fr, n, 2, freqs, diffraction=1)
+        assert ref.keys[:, 0].max() == n_tx - 1 and np.any(ref.keys[ref.keys[:, 0] == n_tx - 1, 2] == 2)
+        for t in (0, n_tx - 1):
+            tref = ref.traces[t]
+            n_rob, mm_rob, _ = P.compare_hitlogs(tr.debug_rays(t, np.arange(n)), tref.hit_tri, tref.robust)
+            assert n_rob > 0 and mm_rob == 0, t
+        p = tr.flat_paths()
+        g = P.keyset(p["key"])
+        assert P.keyset(ref.keys[~ref.ambiguous & ref.robust]) <= g
+        extra = np.array(sorted(g - P.keyset(ref.keys)), np.int32).reshape(-1, 9)
+        if len(extra):
+            valid, amb, _, _ = O.validate(os_, os_.geometry(fr.obj_xform), extra, fr.tx_pos, fr.rx_pos)
+            assert np.all(valid | amb)
+        worst = P.compare_path_values(p["key"], p, ref.keys, dict(a=ref.a, tau=ref.tau, fd=ref.fd), len(freqs))
+        assert worst["n"] >= 0.99 * len(ref.keys)
+        assert worst["a_rel"] <= 1e-8 and worst["tau_rel"] <= P.TAU_REL and worst["fd_abs"] <= P.FD_ABS, worst
+        links = np.arange(n_tx * len(rx))
+        assert not P.channel_ok(P.gpu_channels_np(tr.channels()), ref.channels, links, 100.0)
+    finally:
+        tr.close()
+    with pytest.raises(EmrtError) as e:
+        Tracer(sc1, n_tx + 1, len(rx), rays_per_tx=n)
+    assert e.value.status == -5  # EMRT_E_UNSUPPORTED
+
+
 def test_error_paths_on_device():
     from paper_2303_10521_amd import Tracer
     from paper_2303_10521_amd.tracer import EmrtError
