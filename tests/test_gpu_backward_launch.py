@@ -8,6 +8,7 @@ oracle's receiver-side launch, through the C ABI.
   the same comparison, each side carrying its own cache.
 * Reciprocity: in the street canyon the receiver-side launch yields exactly
   the transmitter-side path set and the same channel.
+* The most receivers one step launches from (1024), against the oracle.
 * Argument and state errors.
 """
 import numpy as np
@@ -116,6 +117,37 @@ def test_canyon_reciprocity(K):
     assert torch.equal(a.channels()["H"], b.channels()["H"])
     a.close()
     b.close()
+
+
+def test_launch_from_the_most_receivers():
+    """1024 receivers launching at once, the most one receiver-side step
+    takes (64 rays each, K = 2, diffraction on): path sets, per-path values
+    and channels against the oracle's receiver-side launch; 1025 are
+    refused."""
+    from paper_2303_10521_amd.tracer import EmrtError
+
+    sc = city.tiny_box_ground(refl=(0.0, 0.0))
+    rng = np.random.default_rng(1024)
+    n_rx, per = 1024, 64
+    ang, rad = rng.uniform(0, 2 * np.pi, n_rx), rng.uniform(45.0, 250.0, n_rx)
+    rx = np.stack([20 + rad * np.cos(ang), 20 + rad * np.sin(ang), rng.uniform(1.5, 20.0, n_rx)], 1)
+    tx = np.array([[-40.0, 20.0, 25.0], [80.0, 70.0, 10.0]])
+    sc1 = city.with_static_rx(sc, rx)
+    fr = static_frame(tx, rx)
+    tr = _tracer(sc1, len(tx), n_rx, n_rx * per // len(tx), 2, True)
+    try:
+        tr.set_frame(fr)
+        tr.step_rx(list(range(n_rx)), per)
+        assert tr.sync() == 0
+        p = tr.flat_paths(cap=64)
+        os_ = O.OracleScene(sc1)
+        ref = O.run_frame(os_, fr, per, 2, [28e9], diffraction=True, rx_sources=list(range(n_rx)))
+        assert set(np.unique(ref.keys[:, 2]).tolist()) == {0, 1, 2}
+        _compare(p, P.gpu_channels_np(tr.channels()), ref, os_, fr, len(tx) * n_rx)
+        with pytest.raises(EmrtError):
+            tr.step_rx([0] * (n_rx + 1), 1)
+    finally:
+        tr.close()
 
 
 def test_receiver_launch_errors():
