@@ -477,6 +477,51 @@ def test_city_channel_sums_both_carriers(city_run):
 
 
 # -------------------------------------------------------------- edge cases
+def test_toy_at_the_most_reflections():
+    """K = 5, the most reflections a context takes, on the toy city with
+    diffraction and two carriers, compared in full: hit logs bit-exact on
+    robust rays, path sets (specular paths of every order up to 5), per-path
+    values and triangles, and every link's channels."""
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    n, freqs = 50_000, [3.5e9, 28e9]
+    tr = _tracer(sc, w, max_reflections=5, rays_per_tx=n, diffraction=1, freq_hz=freqs, path_capacity=1 << 16)
+    try:
+        tr.set_frame(fr)
+        tr.step(True)
+        assert tr.sync() == 0
+        os_ = O.OracleScene(sc)
+        ref = O.run_frame(os_, fr, n, 5, freqs, diffraction=True)
+        spec = ref.keys[ref.keys[:, 2] == 1]
+        assert set(np.unique(spec[:, 3]).tolist()) == {1, 2, 3, 4, 5}
+        t0 = ref.traces[0]
+        n_rob, mm_rob, _ = P.compare_hitlogs(tr.debug_rays(0, np.arange(n)), t0.hit_tri, t0.robust)
+        assert n_rob >= 0.98 * n and mm_rob == 0
+        p = tr.flat_paths(cap=256)
+        g = P.keyset(p["key"])
+        assert P.keyset(ref.keys[~ref.ambiguous & ref.robust]) <= g
+        extra = np.array(sorted(g - P.keyset(ref.keys)), np.int32).reshape(-1, 9)
+        if len(extra):
+            valid, amb, _, _ = O.validate(os_, os_.geometry(fr.obj_xform), extra, fr.tx_pos, fr.rx_pos)
+            assert np.all(valid | amb)
+        worst = P.compare_path_values(p["key"], p, ref.keys, dict(a=ref.a, tau=ref.tau, fd=ref.fd), len(freqs))
+        assert worst["n"] >= 0.95 * len(ref.keys)
+        assert worst["a_rel"] <= 1e-8 and worst["tau_rel"] <= P.TAU_REL and worst["fd_abs"] <= P.FD_ABS, worst
+        gi = {tuple(int(x) for x in k): i for i, k in enumerate(p["key"])}
+        for j in np.nonzero(~ref.ambiguous)[0]:
+            i = gi.get(tuple(int(x) for x in ref.keys[j]))
+            if i is not None:
+                assert np.array_equal(p["tri_ids"][i], ref.tri_ids[j])
+        mask = np.ones(sc.n_tx * sc.n_rx, bool)
+        for k in g ^ P.keyset(ref.keys):
+            mask[k[0] * sc.n_rx + k[1]] = False
+        assert mask.mean() >= 0.9
+        assert not P.channel_ok(P.gpu_channels_np(tr.channels()), ref.channels, np.nonzero(mask)[0], 100.0)
+    finally:
+        tr.close()
+
+
 def test_no_reflections_only_line_of_sight():
     w = city.workload("toy")
     sc = w.scene
