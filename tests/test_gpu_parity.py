@@ -101,6 +101,43 @@ def test_toy_channels(toy):
     assert np.array_equal(g["flags"] & 1, ref.channels["los"].astype(np.int32))
 
 
+def test_toy_dipole_forward_values():
+    """Dipole transmitters (antenna mode 1) at a tilted orientation, with
+    diffraction, at two carriers: per-path complex gains, delays and
+    Dopplers, and every link's channels, against the oracle's dipole
+    evaluation (the isotropic runs do not reach the pattern terms)."""
+    from paper_2303_10521_amd import Tracer
+
+    w = city.workload("toy")
+    sc = w.scene
+    fr = sc.frame(0.0)
+    fr.tx_orient = np.array([[0.6, 0.4]])
+    freqs = [3.5e9, 28e9]
+    tr = Tracer(sc, sc.n_tx, sc.n_rx, freq_hz=freqs, max_reflections=w.max_reflections, rays_per_tx=w.rays_per_tx,
+                diffraction=1, antenna_mode=1, path_capacity=1 << 16)
+    try:
+        tr.set_frame(fr)
+        tr.step(True)
+        assert tr.sync() == 0
+        os_ = O.OracleScene(sc)
+        ref = O.run_frame(os_, fr, w.rays_per_tx, w.max_reflections, freqs, diffraction=True, ant_mode=1)
+        iso = O.run_frame(os_, fr, w.rays_per_tx, w.max_reflections, freqs, diffraction=True, ant_mode=0)
+        assert np.abs(ref.a - iso.a).max() > 0.1 * np.abs(iso.a).max()  # the pattern matters here
+        assert set(np.unique(ref.keys[:, 2]).tolist()) == {0, 1, 2}
+        p = tr.flat_paths(cap=256)
+        worst = P.compare_path_values(p["key"], p, ref.keys, dict(a=ref.a, tau=ref.tau, fd=ref.fd), len(freqs))
+        assert worst["n"] >= 0.95 * len(ref.keys)
+        assert worst["a_rel"] <= 1e-8 and worst["tau_rel"] <= P.TAU_REL and worst["fd_abs"] <= P.FD_ABS, worst
+        g = P.keyset(p["key"])
+        mask = np.ones(sc.n_tx * sc.n_rx, bool)
+        for k in g ^ P.keyset(ref.keys):
+            mask[k[0] * sc.n_rx + k[1]] = False
+        assert mask.mean() >= 0.9
+        assert not P.channel_ok(P.gpu_channels_np(tr.channels()), ref.channels, np.nonzero(mask)[0], 100.0)
+    finally:
+        tr.close()
+
+
 def test_toy_deterministic_and_cached_frame(toy):
     tr, fr = toy["tr"], toy["fr"]
     tr.set_frame(fr)
