@@ -336,8 +336,8 @@ int32_t emrt_batch_bind_workspace(emrt_batch* batch, void* device_ptr, size_t by
 int32_t emrt_batch_set_stream(emrt_batch* batch, void* stream);
 /* use_graph 0/1 (default 1), n_streams 1..16 (default 4), grid = workgroups
  * of the persistent multi-scene bounce launch (default 2048), chunk = rays a
- * wave takes per fetch from the launch's work counter: 32, 64 (default), 128
- * or 256 (EMRT_E_INVALID otherwise). */
+ * wave takes per fetch from the launch's work counter: 32, 64 (default), 128,
+ * 256, 512 or 1024 (EMRT_E_INVALID otherwise). */
 int32_t emrt_batch_set_options(emrt_batch* batch, int32_t use_graph, int32_t n_streams, int32_t grid, int32_t chunk);
 /* Step every member (discover as in emrt_step).  Errors: EMRT_E_STATE (a
  * member without frame, or members at different cache parities),
@@ -345,9 +345,9 @@ int32_t emrt_batch_set_options(emrt_batch* batch, int32_t use_graph, int32_t n_s
 int32_t emrt_batch_step(emrt_batch* batch, int32_t discover);
 /* Choose grid, n_streams and chunk by timing real discovery steps of the
  * members' current frames: every combination of grid 1024..8192 (powers of
- * two), n_streams 1, 2, 4, 8 and chunk 32, 64, 128, timed `repeats` times
- * (1..15) each after one warm-up step, the median compared (48 x repeats + 1
- * steps; synchronises).  Any output pointer may be null. */
+ * two), n_streams 1, 2, 4, 8 and chunk 64, 128, 256, 512, timed `repeats`
+ * times (1..15) each after one warm-up step, the median compared (64 x
+ * repeats + 1 steps; synchronises).  Any output pointer may be null. */
 int32_t emrt_batch_autotune(emrt_batch* batch, int32_t repeats, int32_t* best_grid, int32_t* best_streams,
                             int32_t* best_chunk);
 /* emrt_sync of every member; returns the most severe status. */

@@ -1715,7 +1715,8 @@ int32_t emrt_batch_set_stream(emrt_batch* b, void* s) {
 
 int32_t emrt_batch_set_options(emrt_batch* b, int32_t use_graph, int32_t n_streams, int32_t grid, int32_t chunk) {
     if (!b || n_streams < 1 || n_streams > 16 || grid < 1 || grid > (1 << 20)) return EMRT_E_INVALID;
-    if (chunk != 32 && chunk != 64 && chunk != 128 && chunk != 256) return EMRT_E_INVALID;
+    if (chunk != 32 && chunk != 64 && chunk != 128 && chunk != 256 && chunk != 512 && chunk != 1024)
+        return EMRT_E_INVALID;
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graphs(b);
     b->use_graph = use_graph != 0;
@@ -1857,7 +1858,7 @@ int32_t emrt_batch_autotune(emrt_batch* b, int32_t repeats, int32_t* best_grid, 
     float t_best = 1e30f;
     const int grids[] = {1024, 2048, 4096, 8192};
     const int streams[] = {1, 2, 4, 8};
-    const int chunks[] = {32, 64, 128};
+    const int chunks[] = {64, 128, 256, 512};
     for (int ns : streams)
         for (int g : grids)
             for (int ch : chunks) {

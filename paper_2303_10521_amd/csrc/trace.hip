@@ -428,9 +428,9 @@ void bounce(const BounceArgs& a, bool stats, int grid, hipStream_t st) {
 // global chunk of scene c (an exclusive scan of its live-ray chunks, built on
 // the device by k_chunk_table); a wave takes the next global chunk, finds its
 // scene by binary search and runs that scene's bounce on it.  A chunk holds
-// `chunk` rays (32, 64, 128 or 256): a wave traces them 64 at a time (32:
-// with half its lanes), so larger chunks take fewer counter atomics and
-// binary searches, smaller ones balance the tail better.
+// `chunk` rays (32, 64, 128, 256, 512 or 1024): a wave traces them 64 at a
+// time (32: with half its lanes), so larger chunks take fewer counter atomics
+// and binary searches, smaller ones balance the tail better.
 __global__ void __launch_bounds__(256) k_chunk_table(const BounceArgs* __restrict__ args, int n_scenes,
                                                      uint32_t* chunk_off, uint32_t* work, int chunk) {
     __shared__ uint32_t sh[256];

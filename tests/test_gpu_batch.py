@@ -88,7 +88,7 @@ def test_batch_mixed_bounce_depths():
     _run_schedule(True, 2, 1024, ks=(4, 2, 4, 3, 0, 4))
 
 
-@pytest.mark.parametrize("chunk", [32, 128, 256])
+@pytest.mark.parametrize("chunk", [32, 128, 256, 1024])
 def test_batch_chunk_sizes_match_separate_steps(chunk):
     """Every chunk size of the multi-scene bounce (half-wave chunks of 32
     rays, two and four passes of 64) gives the separate steps' results."""
@@ -115,7 +115,7 @@ def test_batch_rules_and_autotune(tmp_path):
     cache = str(tmp_path / "tune.json")
     o = batch.autotune(repeats=1, cache=cache)
     assert not o["from_cache"] and o["key"].startswith("gfx950|")
-    assert o["grid"] in (1024, 2048, 4096, 8192) and o["streams"] in (1, 2, 4, 8) and o["chunk"] in (32, 64, 128)
+    assert o["grid"] in (1024, 2048, 4096, 8192) and o["streams"] in (1, 2, 4, 8) and o["chunk"] in (64, 128, 256, 512)
     again = batch.autotune(repeats=1, cache=cache)  # the cached shape, no timing
     assert again["from_cache"] and {k: again[k] for k in ("grid", "streams", "chunk")} == {
         k: o[k] for k in ("grid", "streams", "chunk")}
