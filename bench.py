@@ -296,7 +296,7 @@ def main() -> int:
         out["roofline"] = {
             "kernel": "k_bounce (closest hit + receiver/edge capture + reflect + compaction)",
             "bound": "alu",
-            "limiter": "latency of divergent traversal (dependent node loads; VALU issue about 78% of slots, 61% of lanes active)",
+            "limiter": "latency of divergent traversal (dependent node loads; VALU issue about 80% of slots, 61% of lanes active)",
             "achieved": round(achieved, 4),
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
