@@ -844,7 +844,11 @@ int32_t emrt_set_frame_host(emrt_ctx* c, const emrt_frame_desc* f) {
         d.obj_vel = put(f->obj_vel, 3 * nd);
     }
     HC(hipMemcpyAsync(c->f_stage, c->fr_pin, sizeof(double) * off, hipMemcpyHostToDevice, c->stream));
-    HC(hipEventRecord(c->ev_fr, c->stream));
+    const hipError_t er = hipEventRecord(c->ev_fr, c->stream);
+    if (er != hipSuccess) {  // no event to wait on: the pinned buffer is free once the stream is
+        (void)hipStreamSynchronize(c->stream);
+        return hip_check(c, er, "frame upload event");
+    }
     c->fr_pending = true;
     return frame_gather(c, &d);
 }
