@@ -337,8 +337,8 @@ int32_t emrt_batch_set_stream(emrt_batch* batch, void* stream);
 /* use_graph 0/1 (default 1), n_streams 1..16 (default 4), grid = workgroups
  * of the persistent multi-scene bounce launch (default 2048), chunk = rays a
  * wave takes per fetch from the launch's work counter: 32, 64 (default), 128,
- * 256, 512 or 1024 (EMRT_E_INVALID otherwise); bounce levels after the
- * second take at most 256. */
+ * 256, 512 or 1024 (EMRT_E_INVALID otherwise).  The primary rays' level
+ * takes twice that (at most 1024), levels after the second at most 256. */
 int32_t emrt_batch_set_options(emrt_batch* batch, int32_t use_graph, int32_t n_streams, int32_t grid, int32_t chunk);
 /* Step every member (discover as in emrt_step).  Errors: EMRT_E_STATE (a
  * member without frame, or members at different cache parities),
